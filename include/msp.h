@@ -1,0 +1,242 @@
+/*
+ * msp.h — masked sparse matrix-matrix products on AMD Instinct MI355X (gfx950).
+ *
+ * Computes C = M .* (A B) over a semiring (Section "Background and Notation":
+ * M is m x n, A is m x k, B is k x n, C is m x n), or C = !M .* (A B) with a
+ * complemented mask (Introduction; Section "Masked Sparse Accumulator" for
+ * the complemented accumulator). Only the pattern of M is used; M's values
+ * are never read.
+ *
+ * An entry C(i,j) exists iff the mask admits (i,j) and at least one k has
+ * both A(i,k) and B(k,j) stored, whatever the values (the accumulator's
+ * remove() returns "none" only when nothing was inserted, Section
+ * "Accumulator"). Its value folds the products a (x) b with (+). Rows of C
+ * are emitted in ascending column order for both mask modes.
+ *
+ * Conventions for every entry point:
+ *  - All matrix pointers are DEVICE pointers, borrowed: the caller owns them
+ *    and keeps them alive until the work enqueued on `stream` has finished.
+ *    Inputs are never modified.
+ *  - CSR: int64 row pointers (nrows+1 entries, rowptr[0] = 0,
+ *    rowptr[nrows] = nnz), int32 column indices, sorted ascending and
+ *    duplicate-free within each row, 0-based. `values` may be NULL: every
+ *    stored entry then holds the semiring's multiplicative one.
+ *    Violations are reported as MSP_ERR_INVALID_CSR when options->validate
+ *    is set and are undefined behaviour otherwise.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Kernels are
+ *    enqueued asynchronously; calls that return a host value say that they
+ *    synchronize the stream.
+ *  - No exception crosses the ABI. Every call returns an msp_status; the
+ *    thread-local msp_last_error() gives a message. An asynchronous device
+ *    fault surfaces as MSP_ERR_DEVICE at the next synchronizing call.
+ *  - Dimension rule: A.ncols == B.nrows, M.nrows == A.nrows,
+ *    M.ncols == B.ncols; a violation returns MSP_ERR_DIMENSION_MISMATCH.
+ *    Empty shapes (m, n or k = 0, nnz = 0) are valid and give an empty C.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum msp_status {
+    MSP_OK = 0,
+    MSP_ERR_INVALID_ARGUMENT = 1,
+    MSP_ERR_DIMENSION_MISMATCH = 2,
+    MSP_ERR_INVALID_CSR = 3,
+    MSP_ERR_UNSUPPORTED = 4,
+    MSP_ERR_INSUFFICIENT_CAPACITY = 5,
+    MSP_ERR_OUT_OF_MEMORY = 6,
+    MSP_ERR_DEVICE = 7
+} msp_status;
+
+/*
+ * Semirings (input value type -> output value type). The paper describes its
+ * accumulators on the arithmetic semiring and evaluates graph algorithms that
+ * use others (Section "Background and Notation"); these are the ones here:
+ *  PLUS_TIMES_F64  double -> double   IEEE binary64; sums may be reordered
+ *  PLUS_PAIR_I64   (values ignored) -> int64: counts contributing products
+ *  LOR_LAND_BOOL   uint8 -> uint8     (x) = a&&b, (+) = ||, result 0 or 1
+ *  PLUS_TIMES_I32  int32 -> int32     wrap-around mod 2^32
+ *  PLUS_TIMES_I64  int64 -> int64     wrap-around mod 2^64
+ */
+typedef enum msp_semiring {
+    MSP_PLUS_TIMES_F64 = 0,
+    MSP_PLUS_PAIR_I64 = 1,
+    MSP_LOR_LAND_BOOL = 2,
+    MSP_PLUS_TIMES_I32 = 3,
+    MSP_PLUS_TIMES_I64 = 4
+} msp_semiring;
+
+/*
+ * Accumulator kinds. The library picks one per row (or per column tile /
+ * mask chunk of a heavy row) unless options->force_kind is set.
+ *  DENSE    dense state over a column tile held in LDS: admitted bitmap,
+ *           inserted bitmap and values, emitted by a scan of the tile
+ *           (the masked sparse accumulator of Section "Masked Sparse
+ *           Accumulator", re-laid out per tile). Normal and complemented.
+ *  HASH     open-addressing table in LDS keyed by the mask's columns
+ *           (Section "Hash Accumulator"). Normal mask only.
+ *  MASKIDX  slot = rank of the column in the row of M, found by binary
+ *           search over the mask row staged in LDS (Section "Mask
+ *           Compressed Accumulator"). Normal mask only.
+ *  INNER    pull formulation: one sparse dot product of A(i,:) with B(:,j)
+ *           per admitted (i,j) (Section "Pull-based Algorithms"). Needs the
+ *           transpose of B, built by the plan unless options->b_transpose is
+ *           given. Normal mask only.
+ * Forcing MASKIDX, HASH or INNER together with a complemented mask returns
+ * MSP_ERR_UNSUPPORTED.
+ */
+typedef enum msp_kind {
+    MSP_KIND_AUTO = -1,
+    MSP_KIND_DENSE = 0,
+    MSP_KIND_HASH = 1,
+    MSP_KIND_MASKIDX = 2,
+    MSP_KIND_INNER = 3
+} msp_kind;
+
+/* Read-only CSR view of device memory (see the conventions above). */
+typedef struct msp_csr {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nnz;
+    const int64_t* rowptr;  /* device, nrows + 1 */
+    const int32_t* colidx;  /* device, nnz */
+    const void* values;     /* device, nnz of the semiring's input type, or NULL */
+} msp_csr;
+
+/*
+ * Output CSR, allocated by the caller. rowptr has nrows + 1 entries;
+ * colidx/values have `capacity` entries (values of the semiring's output
+ * type). On success the library writes rowptr (rowptr[nrows] = nnz(C)),
+ * and the first nnz(C) entries of colidx and values.
+ */
+typedef struct msp_csr_out {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t capacity;
+    int64_t* rowptr;
+    int32_t* colidx;
+    void* values;
+} msp_csr_out;
+
+typedef struct msp_options {
+    int32_t phase;        /* 1: one-phase (numeric into staging, then compaction,
+                             Section "Symbolic and Numeric Phases");
+                             2: two-phase (symbolic count, then numeric). 0 = 1. */
+    int32_t force_kind;   /* msp_kind; MSP_KIND_AUTO (-1) lets the binner choose */
+    int32_t validate;     /* nonzero: check the CSR invariants of A, B and M on
+                             the device at plan creation */
+    int32_t inner_ratio;  /* auto mode: use INNER for a row when its pull cost
+                             (sum over mask columns of nnz(B(:,j))) times this
+                             ratio is below its push cost (products). 0 = never
+                             choose INNER automatically. */
+    const msp_csr* b_transpose; /* optional CSR of B^T (n x k); NULL = built by the
+                                   plan when INNER is used */
+} msp_options;
+
+/* Fills `opt` with the defaults: phase 1, auto kind, no validation,
+   inner_ratio 0, no B^T. */
+void msp_options_default(msp_options* opt);
+
+/* Plan statistics, filled by msp_plan_info. */
+typedef struct msp_plan_info_t {
+    int64_t upper_bound;     /* sum over rows of min(admitted columns, products):
+                                the exact per-row output bound; a one-phase
+                                output needs capacity >= this */
+    int64_t products;        /* sum over rows of products (flops_i) */
+    int64_t units;           /* work units (rows or row tiles) */
+    int64_t staging;         /* staging entries used by one-phase execution */
+    int64_t mask_nnz;        /* nnz(M) */
+    int64_t kind_units[4];   /* units per msp_kind */
+} msp_plan_info_t;
+
+typedef struct msp_plan msp_plan;
+
+/*
+ * Analyse the operands and bind a plan to them (row analysis and row
+ * binning). Computes per row the product count
+ * flops_i = sum over stored A(i,k) of nnz(B(k,:)), the mask count, the
+ * output bound, and the accumulator kind and tiling; then places every work
+ * unit in its kind's bin. Allocates the plan's device workspace
+ * (stream-ordered) and SYNCHRONIZES `stream` once to read the sizes.
+ * The operands must stay alive and unchanged while the plan is used.
+ * `opt` may be NULL (defaults).
+ */
+msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
+                           int complement, msp_semiring semiring, const msp_options* opt,
+                           void* stream);
+
+/* Copies the plan's statistics into `info` (host). */
+msp_status msp_plan_info(const msp_plan* plan, msp_plan_info_t* info);
+
+/*
+ * Two-phase, symbolic step: counts nnz(C(i,:)) from indices only and writes
+ * the row pointers of C into C_rowptr (device, nrows + 1). If nnz_host is not
+ * NULL, SYNCHRONIZES and stores nnz(C) there.
+ */
+msp_status msp_symbolic(msp_plan* plan, int64_t* C_rowptr, int64_t* nnz_host, void* stream);
+
+/*
+ * Two-phase, numeric step (after msp_symbolic on the same plan, with the same
+ * C->rowptr): writes colidx and values of C. C->capacity must be >= nnz(C).
+ */
+msp_status msp_numeric(msp_plan* plan, msp_csr_out* C, void* stream);
+
+/*
+ * Runs the whole product on a plan: phase 1 (numeric into staging sized by
+ * the per-unit bounds, then prefix sum of the counts and compaction into C)
+ * or phase 2 (symbolic, prefix sum, numeric), as options->phase says.
+ * Phase 1 needs C->capacity >= info.upper_bound; phase 2 needs
+ * C->capacity >= nnz(C) and SYNCHRONIZES once to check it.
+ * If nnz_host is not NULL, SYNCHRONIZES and stores nnz(C) there.
+ * May be called repeatedly on one plan (e.g. after the values of A or B
+ * changed in place).
+ */
+msp_status msp_execute(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* stream);
+
+/* Releases the plan's device workspace (stream-ordered on the plan's stream). */
+void msp_plan_destroy(msp_plan* plan);
+
+/*
+ * One-shot product: plan, execute, destroy. C->capacity must be at least the
+ * upper bound (phase 1) or nnz(C) (phase 2); otherwise returns
+ * MSP_ERR_INSUFFICIENT_CAPACITY and writes the bound into *nnz_host when it
+ * is not NULL. SYNCHRONIZES.
+ */
+msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                             msp_semiring semiring, const msp_options* opt, msp_csr_out* C,
+                             int64_t* nnz_host, void* stream);
+
+/* Exact per-row output bound summed over rows (see msp_plan_info_t).
+   SYNCHRONIZES. */
+msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                           int64_t* upper_bound, void* stream);
+
+/*
+ * (+)-reduction of n output values of the semiring's output type into one
+ * value written to `result` (device, one element of the output type); the
+ * post-reduction of triangle counting (sum of L .* (L L), Section "Triangle
+ * Counting"). Deterministic for a given n. n = 0 writes the identity.
+ */
+msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result,
+                      void* stream);
+
+/* Static message for a status code. */
+const char* msp_status_string(msp_status status);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* msp_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int msp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSP_H */

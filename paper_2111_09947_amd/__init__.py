@@ -1,0 +1,253 @@
+"""Masked sparse matrix-matrix products C = M .* (A B) on AMD MI355X.
+
+Thin Python binding over the C-ABI library ``libmsp.so`` (include/msp.h):
+it only marshals torch device tensors and the current HIP stream; every step
+of the product runs in the library's HIP kernels. Importing works without a
+GPU; calling needs the built library and a GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+from . import _lib as L
+
+SEMIRINGS = {
+    "plus_times_f64": 0,
+    "plus_pair_i64": 1,
+    "lor_land_bool": 2,
+    "plus_times_i32": 3,
+    "plus_times_i64": 4,
+}
+KINDS = {None: -1, "auto": -1, "dense": 0, "hash": 1, "maskidx": 2, "inner": 3}
+STATUS = {0: "MSP_OK", 1: "MSP_ERR_INVALID_ARGUMENT", 2: "MSP_ERR_DIMENSION_MISMATCH",
+          3: "MSP_ERR_INVALID_CSR", 4: "MSP_ERR_UNSUPPORTED", 5: "MSP_ERR_INSUFFICIENT_CAPACITY",
+          6: "MSP_ERR_OUT_OF_MEMORY", 7: "MSP_ERR_DEVICE"}
+
+
+class MspError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = L.load()
+        detail = lib.msp_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({detail})")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def in_dtype(semiring: str):
+    t = _torch()
+    return {"plus_times_f64": t.float64, "plus_pair_i64": None, "lor_land_bool": t.uint8,
+            "plus_times_i32": t.int32, "plus_times_i64": t.int64}[semiring]
+
+
+def out_dtype(semiring: str):
+    t = _torch()
+    return {"plus_times_f64": t.float64, "plus_pair_i64": t.int64, "lor_land_bool": t.uint8,
+            "plus_times_i32": t.int32, "plus_times_i64": t.int64}[semiring]
+
+
+@dataclasses.dataclass
+class DeviceCSR:
+    """CSR on the GPU: int64 rowptr, int32 colidx (sorted, unique per row),
+    optional values."""
+
+    nrows: int
+    ncols: int
+    rowptr: "object"
+    colidx: "object"
+    values: "Optional[object]" = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colidx.numel())
+
+    @staticmethod
+    def from_host(X, device="cuda", values_dtype=None) -> "DeviceCSR":
+        """Upload a host CSR (numpy arrays: rowptr, colidx, values or None)."""
+        t = _torch()
+        rp = t.from_numpy(X.rowptr).to(device=device, dtype=t.int64)
+        ci = t.from_numpy(X.colidx).to(device=device, dtype=t.int32)
+        v = None
+        if X.values is not None and values_dtype is not None:
+            v = t.from_numpy(X.values).to(device=device, dtype=values_dtype)
+        return DeviceCSR(X.nrows, X.ncols, rp.contiguous(), ci.contiguous(), v)
+
+    def to_host(self):
+        """(rowptr, colidx, values) as numpy arrays."""
+        return (self.rowptr.cpu().numpy(), self.colidx.cpu().numpy(),
+                None if self.values is None else self.values.cpu().numpy())
+
+
+def _view(X: DeviceCSR, semiring: str, name: str) -> L.MspCsr:
+    t = _torch()
+    if X.rowptr.dtype != t.int64 or X.colidx.dtype != t.int32:
+        raise TypeError(f"{name}: rowptr must be int64 and colidx int32")
+    if not (X.rowptr.is_cuda and X.colidx.is_cuda):
+        raise ValueError(f"{name}: tensors must be on the GPU")
+    if not (X.rowptr.is_contiguous() and X.colidx.is_contiguous()):
+        raise ValueError(f"{name}: tensors must be contiguous")
+    vals = 0
+    want = in_dtype(semiring) if semiring is not None else None
+    if X.values is not None and want is not None:
+        if X.values.dtype != want:
+            raise TypeError(f"{name}: values must be {want} for {semiring}")
+        if not X.values.is_contiguous():
+            raise ValueError(f"{name}: values must be contiguous")
+        vals = X.values.data_ptr()
+    return L.MspCsr(X.nrows, X.ncols, X.colidx.numel(), X.rowptr.data_ptr(),
+                    X.colidx.data_ptr() if X.colidx.numel() else 0, vals)
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise MspError(st, where)
+
+
+def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio: int = 0,
+            b_transpose: Optional[L.MspCsr] = None) -> L.MspOptions:
+    o = L.MspOptions()
+    L.load().msp_options_default(ctypes.byref(o))
+    o.phase = int(phase)
+    o.force_kind = KINDS[force_kind]
+    o.validate = int(bool(validate))
+    o.inner_ratio = int(inner_ratio)
+    if b_transpose is not None:
+        o.b_transpose = ctypes.pointer(b_transpose)
+    return o
+
+
+class Plan:
+    """A plan binds the operands (row analysis + binning done once); execute
+    it one or more times. The operands must stay alive and unchanged in
+    pattern while the plan lives."""
+
+    def __init__(self, A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
+                 semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
+                 validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None):
+        lib = L.load()
+        self.semiring = semiring
+        self.A, self.B, self.M = A, B, M
+        self._views = (_view(A, semiring, "A"), _view(B, semiring, "B"), _view(M, None, "M"))
+        self._bt = None if b_transpose is None else _view(b_transpose, semiring, "B^T")
+        self._bt_keep = b_transpose
+        self._opt = options(phase, force_kind, validate, inner_ratio, self._bt)
+        self.phase = phase
+        self.nrows, self.ncols = A.nrows, B.ncols
+        h = ctypes.c_void_p()
+        st = lib.msp_plan_create(ctypes.byref(h), *(ctypes.byref(v) for v in self._views),
+                                 int(bool(complement)), SEMIRINGS[semiring], ctypes.byref(self._opt), _stream())
+        _check(st, "msp_plan_create")
+        self._h = h
+        info = L.MspPlanInfo()
+        _check(lib.msp_plan_info(self._h, ctypes.byref(info)), "msp_plan_info")
+        self.upper_bound = info.upper_bound
+        self.products = info.products
+        self.units = info.units
+        self.staging = info.staging
+        self.mask_nnz = info.mask_nnz
+        self.kind_units = {k: info.kind_units[i] for i, k in enumerate(["dense", "hash", "maskidx", "inner"])}
+
+    def _out(self, capacity: int):
+        t = _torch()
+        dev = self.A.rowptr.device
+        rp = t.empty(self.nrows + 1, dtype=t.int64, device=dev)
+        ci = t.empty(max(capacity, 1), dtype=t.int32, device=dev)
+        v = t.empty(max(capacity, 1), dtype=out_dtype(self.semiring), device=dev)
+        return rp, ci, v
+
+    def execute(self, nnz: bool = True) -> DeviceCSR:
+        """Runs the product. Phase 1 allocates C with the upper-bound capacity
+        and returns views trimmed to nnz(C) (one synchronization); phase 2
+        runs symbolic, allocates exactly, then numeric."""
+        lib = L.load()
+        s = _stream()
+        if self.phase == 2:
+            t = _torch()
+            rp = t.empty(self.nrows + 1, dtype=t.int64, device=self.A.rowptr.device)
+            n = ctypes.c_int64(0)
+            _check(lib.msp_symbolic(self._h, ctypes.c_void_p(rp.data_ptr()), ctypes.byref(n), s), "msp_symbolic")
+            nn = n.value
+            ci = t.empty(max(nn, 1), dtype=t.int32, device=rp.device)
+            v = t.empty(max(nn, 1), dtype=out_dtype(self.semiring), device=rp.device)
+            out = L.MspCsrOut(self.nrows, self.ncols, nn, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
+            _check(lib.msp_numeric(self._h, ctypes.byref(out), s), "msp_numeric")
+            return DeviceCSR(self.nrows, self.ncols, rp, ci[:nn], v[:nn])
+        rp, ci, v = self._out(self.upper_bound)
+        out = L.MspCsrOut(self.nrows, self.ncols, self.upper_bound, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
+        n = ctypes.c_int64(0)
+        _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if nnz else None, s), "msp_execute")
+        if not nnz:
+            return DeviceCSR(self.nrows, self.ncols, rp, ci, v)
+        nn = n.value
+        return DeviceCSR(self.nrows, self.ncols, rp, ci[:nn], v[:nn])
+
+    def execute_into(self, rowptr, colidx, values, capacity: int, sync_nnz: bool = False) -> int:
+        """Runs the product into caller-allocated buffers (no allocation);
+        returns nnz(C) if sync_nnz, else -1 (rowptr[-1] holds it on device)."""
+        lib = L.load()
+        out = L.MspCsrOut(self.nrows, self.ncols, capacity, rowptr.data_ptr(), colidx.data_ptr(),
+                          values.data_ptr())
+        n = ctypes.c_int64(-1)
+        _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if sync_nnz else None, _stream()),
+               "msp_execute")
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().msp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def masked_spgemm(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
+                  semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
+                  validate: bool = False, inner_ratio: int = 0,
+                  b_transpose: Optional[DeviceCSR] = None) -> DeviceCSR:
+    """C = M .* (A B) (or !M .* (A B)) over `semiring`, rows sorted."""
+    with Plan(A, B, M, complement, semiring, phase, force_kind, validate, inner_ratio, b_transpose) as p:
+        return p.execute()
+
+
+def upper_bound(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False) -> int:
+    lib = L.load()
+    vs = (_view(A, None, "A"), _view(B, None, "B"), _view(M, None, "M"))
+    ub = ctypes.c_int64(0)
+    _check(lib.msp_upper_bound(*(ctypes.byref(v) for v in vs), int(bool(complement)), ctypes.byref(ub), _stream()),
+           "msp_upper_bound")
+    return ub.value
+
+
+def reduce(values, semiring: str, out=None):
+    """(+)-reduction of output values into a one-element device tensor."""
+    t = _torch()
+    if values.dtype != out_dtype(semiring):
+        raise TypeError("values dtype does not match the semiring's output type")
+    if out is None:
+        out = t.empty(1, dtype=values.dtype, device=values.device)
+    _check(L.load().msp_reduce(ctypes.c_void_p(values.data_ptr() if values.numel() else 0), values.numel(),
+                               SEMIRINGS[semiring], ctypes.c_void_p(out.data_ptr()), _stream()), "msp_reduce")
+    return out
+
+
+def version() -> int:
+    return L.load().msp_version()

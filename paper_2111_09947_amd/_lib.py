@@ -1,0 +1,71 @@
+"""ctypes declarations for libmsp.so (include/msp.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsp.so")
+
+c_i32, c_i64, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+
+class MspCsr(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("nnz", c_i64),
+                ("rowptr", c_vp), ("colidx", c_vp), ("values", c_vp)]
+
+
+class MspCsrOut(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("capacity", c_i64),
+                ("rowptr", c_vp), ("colidx", c_vp), ("values", c_vp)]
+
+
+class MspOptions(ctypes.Structure):
+    _fields_ = [("phase", c_i32), ("force_kind", c_i32), ("validate", c_i32),
+                ("inner_ratio", c_i32), ("b_transpose", ctypes.POINTER(MspCsr))]
+
+
+class MspPlanInfo(ctypes.Structure):
+    _fields_ = [("upper_bound", c_i64), ("products", c_i64), ("units", c_i64),
+                ("staging", c_i64), ("mask_nnz", c_i64), ("kind_units", c_i64 * 4)]
+
+
+# every symbol include/msp.h declares, with its ctypes signature
+SIGNATURES = {
+    "msp_options_default": (None, [ctypes.POINTER(MspOptions)]),
+    "msp_plan_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
+                                       ctypes.POINTER(MspCsr), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(MspOptions), c_vp]),
+    "msp_plan_info": (ctypes.c_int, [c_vp, ctypes.POINTER(MspPlanInfo)]),
+    "msp_symbolic": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
+    "msp_numeric": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), c_vp]),
+    "msp_execute": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp]),
+    "msp_plan_destroy": (None, [c_vp]),
+    "msp_masked_spgemm": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
+                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(MspOptions),
+                                         ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp]),
+    "msp_upper_bound": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
+                                       ctypes.c_int, ctypes.POINTER(c_i64), c_vp]),
+    "msp_reduce": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_vp]),
+    "msp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "msp_last_error": (ctypes.c_char_p, []),
+    "msp_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the in-tree libmsp.so; raises if it has not been built. There is
+    no fallback: the masked product runs only in the HIP library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -m paper_2111_09947_amd.build or __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

@@ -1,0 +1,137 @@
+// Internal interface between the host runtime (msp_api.cpp) and the kernels
+// (msp_kernels.hip). Not installed; the public interface is include/msp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "msp.h"
+
+namespace mspk {
+
+// Work-unit bins. A unit is a row of C, or one tile of a heavy row: a chunk
+// of the row's mask entries (mask-keyed kinds) or a column window (dense).
+enum Bin : int {
+    BIN_DENSE_W = 0,    // one wave, dense state over <= DENSE_W_COLS columns
+    BIN_DENSE_B = 1,    // one block, dense state over a DENSE_B_COLS column tile
+    BIN_HASH_W = 2,     // one wave, hash table of <= HASH_W_CAP mask entries
+    BIN_HASH_B = 3,     // one block, hash table of <= HASH_B_CAP mask entries
+    BIN_MASKIDX_W = 4,  // one wave, binary search over <= MASKIDX_W_CAP mask entries
+    BIN_MASKIDX_B = 5,  // one block, binary search over <= MASKIDX_B_CAP mask entries
+    BIN_INNER_W = 6,    // one wave, dot products for <= INNER_CAP mask entries
+    NBINS = 7
+};
+
+constexpr int DENSE_W_COLS = 512;
+constexpr int DENSE_B_COLS = 4096;
+constexpr int HASH_W_CAP = 256;
+constexpr int HASH_B_CAP = 1024;
+constexpr int MASKIDX_W_CAP = 256;
+constexpr int MASKIDX_B_CAP = 4096;
+constexpr int INNER_CAP = 256;
+constexpr int INNER_ACAP = 512;   // A row staged in LDS up to this length
+constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
+constexpr int MASKIDX_SMALL = 32; // auto: binary search below this mask size, hash above
+
+// Device statistics written by the analysis kernel (one sync reads them).
+enum Stat : int {
+    ST_FLOPS = 0,
+    ST_UB = 1,
+    ST_UNITS = 2,
+    ST_STAGING = 3,
+    ST_MNNZ = 4,
+    ST_MAXFLOPS = 5,
+    ST_BIN0 = 6,                 // ST_BIN0 + b: units in bin b
+    ST_ERROR = ST_BIN0 + NBINS,  // nonzero: invalid CSR found by validation
+    ST_COUNT = ST_ERROR + 1
+};
+
+enum Mode : int { MODE_COUNT = 0, MODE_STAGE = 1, MODE_DIRECT = 2 };
+
+struct Operands {
+    int64_t m, k, n;
+    const int64_t* Arp; const int32_t* Aci; const void* Av;
+    const int64_t* Brp; const int32_t* Bci; const void* Bv;
+    const int64_t* Mrp; const int32_t* Mci;
+    const int64_t* BTrp; const int32_t* BTci; const void* BTv;  // B^T (inner kind)
+    int complement;
+};
+
+struct AnalysisArgs {
+    Operands op;
+    int force_kind;
+    int inner_ratio;
+    const int64_t* colcnt_rp;  // row pointers of B^T (column counts of B) or null
+    int64_t* flops;            // [m]
+    int64_t* tiles;            // [m+1], number of units per row (scanned later)
+    int8_t* bin;               // [m]
+    unsigned long long* stats; // [ST_COUNT]
+};
+
+struct UnitArgs {
+    Operands op;
+    const int64_t* flops;
+    const int64_t* unit_base;  // [m+1] exclusive scan of tiles
+    const int8_t* bin;
+    const int64_t* bin_off;    // [NBINS] start of each bin in bin_units (device)
+    unsigned long long* bin_cursor;  // [NBINS], zeroed
+    int32_t* unit_row;
+    int32_t* unit_tile;
+    int64_t* stg_size;         // [U+1] staging entries per unit (scanned later)
+    int32_t* bin_units;
+};
+
+struct NumArgs {
+    Operands op;
+    const int32_t* unit_row;
+    const int32_t* unit_tile;
+    const int32_t* units;      // this bin's units
+    int64_t nunits;
+    const int64_t* out_off;    // staging offsets (STAGE) or final offsets (DIRECT)
+    int64_t* cnt;              // per-unit output counts (COUNT, STAGE)
+    int32_t* out_col;
+    void* out_val;
+};
+
+struct CompactArgs {
+    int64_t m;
+    int64_t U;
+    const int64_t* unit_base;  // [m+1]
+    const int64_t* stg_off;    // [U+1]
+    const int64_t* out_off;    // [U+1] (scanned counts)
+    const int32_t* stg_col;
+    const void* stg_val;
+    int val_bytes;
+    int64_t* C_rowptr;
+    int32_t* C_col;
+    void* C_val;
+};
+
+// ---- launchers (msp_kernels.hip). All enqueue on `s` and return the launch error.
+hipError_t launch_validate(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int64_t nnz,
+                           unsigned long long* err, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s);
+hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s);
+// Exclusive scan of n int64 (in may equal out); writes n + 1 outputs.
+// `partial` needs scan_partial_elems(n) int64.
+int64_t scan_partial_elems(int64_t n);
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s);
+hipError_t launch_numeric(int semiring, int bin, int mode, const NumArgs& a, hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
+hipError_t launch_rowptr_from_units(int64_t m, const int64_t* unit_base, const int64_t* out_off,
+                                    int64_t* C_rowptr, hipStream_t s);
+// B^T construction: column counts -> scan -> scatter (rows of B^T unsorted).
+hipError_t launch_colcount(const int32_t* ci, int64_t nnz, int64_t* cnt, hipStream_t s);
+hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const void* v, int val_bytes,
+                                    int64_t nrows, const int64_t* trp, unsigned long long* cursor,
+                                    int32_t* tci, void* tv, hipStream_t s);
+// Deterministic (+)-reduction into one value.
+int64_t reduce_partial_elems();
+hipError_t launch_reduce(int semiring, const void* vals, int64_t n, void* partial, void* result,
+                         hipStream_t s);
+
+int out_bytes(int semiring);   // output value width
+int in_bytes(int semiring);    // input value width (0: values ignored)
+
+}  // namespace mspk

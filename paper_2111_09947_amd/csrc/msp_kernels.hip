@@ -1,0 +1,951 @@
+// HIP kernels (gfx950, wave64) of the masked SpGEMM hot path C = M .* (A B).
+//
+// Path (one product):
+//   analysis   per row: products flops_i = sum_k nnz(B(k,:)), mask count,
+//              exact output bound, accumulator kind and tiling
+//   units      expand rows into work units (row or row tile) and place them
+//              in per-kind bins
+//   scan       prefix sums (unit bases, staging offsets, output offsets)
+//   numeric    one kernel per non-empty bin: the accumulator kinds
+//   compaction one-phase staging -> final CSR
+//   reduce     optional (+)-reduction of the output values
+//
+// The row-wise push formulation (Section "Push-Based algorithms") streams,
+// for row i, every stored A(i,k) and the stanza B(k,:). Here a wavefront
+// flattens the stanzas of up to 64 A entries into one product sequence so
+// that all 64 lanes read consecutive B entries regardless of stanza lengths;
+// a product's B value is loaded only when the mask admits its column (the
+// lazy insert of the accumulator interface, Section "Accumulator").
+#include <hip/hip_runtime.h>
+
+#include "msp_device.hpp"
+#include "msp_internal.hpp"
+
+namespace mspk {
+
+int out_bytes(int sr) {
+    switch (sr) {
+    case MSP_PLUS_TIMES_F64: return 8;
+    case MSP_PLUS_PAIR_I64: return 8;
+    case MSP_LOR_LAND_BOOL: return 1;
+    case MSP_PLUS_TIMES_I32: return 4;
+    case MSP_PLUS_TIMES_I64: return 8;
+    default: return 0;
+    }
+}
+
+int in_bytes(int sr) {
+    switch (sr) {
+    case MSP_PLUS_TIMES_F64: return 8;
+    case MSP_PLUS_PAIR_I64: return 0;
+    case MSP_LOR_LAND_BOOL: return 1;
+    case MSP_PLUS_TIMES_I32: return 4;
+    case MSP_PLUS_TIMES_I64: return 8;
+    default: return 0;
+    }
+}
+
+static inline unsigned grid_for(int64_t n, int per_block, int64_t cap = 1 << 20) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- validation
+
+__global__ void k_validate(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, int64_t nrows,
+                           int64_t ncols, int64_t nnz, unsigned long long* err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nrows) return;
+    if (i == nrows) {
+        if (rp[nrows] != nnz || rp[0] != 0) atomicOr(err, 1ull);
+        return;
+    }
+    const int64_t a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || b > nnz) { atomicOr(err, 1ull); return; }
+    int64_t prev = -1;
+    for (int64_t p = a; p < b; ++p) {
+        const int64_t c = ci[p];
+        if (c <= prev || c >= ncols) { atomicOr(err, 1ull); return; }
+        prev = c;
+    }
+}
+
+hipError_t launch_validate(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int64_t nnz,
+                           unsigned long long* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(nrows + 1, 256, INT32_MAX)), dim3(256), 0, s, rp, ci, nrows,
+                       ncols, nnz, err);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        p[x] = v;
+}
+
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ analysis
+
+constexpr int ANA_T = 256;      // rows per block, threads per block
+constexpr int ANA_CHUNK = 2048; // nonzeros per streamed chunk (8 per thread)
+__device__ __forceinline__ int ana_idx(int e) { return e + (e >> 3); }  // pad: fewer LDS bank conflicts
+
+// For the rows [r0, r1) of a CSR pattern, each thread gets the sum over its
+// row (row r0 + threadIdx.x) of gather(column). The block streams the rows'
+// nonzeros in chunks: a coalesced gather into LDS, a block prefix sum, then
+// every row reads its overlap with the chunk as a difference of two prefix
+// values, so a row of any length costs O(1) per chunk.
+template <class G>
+__device__ int64_t csr_rowsum(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, int64_t r0,
+                              int64_t r1, G gather, int64_t* lds, int64_t* tmp) {
+    const int tid = threadIdx.x;
+    const int64_t r = r0 + tid;
+    const bool has = r < r1;
+    const int64_t rs = has ? rp[r] : 0, re = has ? rp[r + 1] : 0;
+    const int64_t p0 = rp[r0], p1 = rp[r1];
+    int64_t sum = 0;
+    for (int64_t cs = p0; cs < p1; cs += ANA_CHUNK) {
+        const int64_t ce = min(cs + (int64_t)ANA_CHUNK, p1);
+        for (int e = tid; e < ANA_CHUNK; e += ANA_T) {
+            const int64_t p = cs + e;
+            lds[ana_idx(e)] = p < ce ? gather(ci[p]) : 0;
+        }
+        __syncthreads();
+        int64_t loc[8];
+        int64_t run = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            run += lds[ana_idx(tid * 8 + j)];
+            loc[j] = run;
+        }
+        int64_t tot;
+        const int64_t off = block_excl_scan<ANA_T / WAVE>(run, tmp, tot);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[ana_idx(tid * 8 + j)] = loc[j] + off;
+        __syncthreads();
+        if (has) {
+            const int64_t a = max(rs, cs), b = min(re, ce);
+            if (a < b) {
+                const int64_t hi = lds[ana_idx((int)(b - cs - 1))];
+                const int64_t lo = (a > cs) ? lds[ana_idx((int)(a - cs - 1))] : 0;
+                sum += hi - lo;
+            }
+        }
+        __syncthreads();
+    }
+    return sum;
+}
+
+__device__ __forceinline__ int64_t cdiv(int64_t x, int64_t y) { return (x + y - 1) / y; }
+
+// Accumulator kind and tiling of one row (auto or forced).
+__device__ void classify(int64_t mnnz, int64_t flops, int64_t n, int comp, int force, int inner_ratio,
+                        int64_t icost, int& bin, int64_t& tiles) {
+    int kind = comp ? (int)MSP_KIND_DENSE : force;
+    if (kind == MSP_KIND_AUTO) {
+        if (inner_ratio > 0 && icost * (int64_t)inner_ratio < flops) kind = MSP_KIND_INNER;
+        else if (n <= DENSE_W_COLS) kind = MSP_KIND_DENSE;
+        else if (mnnz <= MASKIDX_SMALL) kind = MSP_KIND_MASKIDX;
+        else if (mnnz <= HASH_B_CAP) kind = MSP_KIND_HASH;
+        else kind = MSP_KIND_MASKIDX;
+    }
+    switch (kind) {
+    case MSP_KIND_DENSE:
+        if (n <= DENSE_W_COLS) { bin = BIN_DENSE_W; tiles = 1; }
+        else { bin = BIN_DENSE_B; tiles = cdiv(n, DENSE_B_COLS); }
+        break;
+    case MSP_KIND_HASH:
+        if (mnnz <= HASH_W_CAP) { bin = BIN_HASH_W; tiles = 1; }
+        else { bin = BIN_HASH_B; tiles = cdiv(mnnz, HASH_B_CAP); }
+        break;
+    case MSP_KIND_MASKIDX:
+        if (mnnz <= MASKIDX_W_CAP) { bin = BIN_MASKIDX_W; tiles = 1; }
+        else { bin = BIN_MASKIDX_B; tiles = cdiv(mnnz, MASKIDX_B_CAP); }
+        break;
+    default:
+        bin = BIN_INNER_W; tiles = cdiv(mnnz, INNER_CAP);
+        break;
+    }
+}
+
+// Staging entries of tile t of row i: min(admitted columns of the tile, products).
+__device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t, int64_t tiles, int64_t mnnz,
+                                int64_t flops) {
+    int64_t adm = 0;
+    switch (bin) {
+    case BIN_DENSE_W:
+        adm = o.complement ? o.n - mnnz : mnnz;
+        break;
+    case BIN_DENSE_B: {
+        const int64_t c0 = t * DENSE_B_COLS, c1 = min(c0 + DENSE_B_COLS, o.n);
+        int64_t mt = mnnz;
+        if (tiles > 1) {
+            const int64_t p0 = lower_bound_g(o.Mci, o.Mrp[i], o.Mrp[i + 1], c0);
+            mt = lower_bound_g(o.Mci, p0, o.Mrp[i + 1], c1) - p0;
+        }
+        adm = o.complement ? (c1 - c0) - mt : mt;
+        break;
+    }
+    case BIN_HASH_W: case BIN_MASKIDX_W: adm = mnnz; break;
+    case BIN_HASH_B: adm = min((int64_t)HASH_B_CAP, mnnz - t * HASH_B_CAP); break;
+    case BIN_MASKIDX_B: adm = min((int64_t)MASKIDX_B_CAP, mnnz - t * MASKIDX_B_CAP); break;
+    default: adm = min((int64_t)INNER_CAP, mnnz - t * INNER_CAP); break;
+    }
+    return min(adm, flops);
+}
+
+__global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
+    __shared__ int64_t lds[ANA_CHUNK + ANA_CHUNK / 8];
+    __shared__ int64_t tmp[ANA_T / WAVE];
+    __shared__ unsigned long long sst[ST_COUNT];
+    const Operands& o = a.op;
+    const int64_t r0 = (int64_t)blockIdx.x * ANA_T;
+    const int64_t r1 = min(r0 + ANA_T, o.m);
+    if (threadIdx.x < ST_COUNT) sst[threadIdx.x] = 0;
+    const int64_t* Brp = o.Brp;
+    const int64_t flops = csr_rowsum(o.Arp, o.Aci, r0, r1, [=](int32_t k) { return Brp[k + 1] - Brp[k]; }, lds, tmp);
+    int64_t icost = 0;
+    const bool need_icost = a.inner_ratio > 0 && !o.complement && a.colcnt_rp != nullptr &&
+                            a.force_kind == (int)MSP_KIND_AUTO;
+    if (need_icost) {
+        const int64_t* crp = a.colcnt_rp;
+        icost = csr_rowsum(o.Mrp, o.Mci, r0, r1, [=](int32_t j) { return crp[j + 1] - crp[j]; }, lds, tmp);
+    }
+    __syncthreads();
+    const int64_t i = r0 + threadIdx.x;
+    if (i < r1) {
+        const int64_t mnnz = o.Mrp[i + 1] - o.Mrp[i];
+        const int64_t adm = o.complement ? o.n - mnnz : mnnz;
+        const int64_t ub = min(adm, flops);
+        int bin = -1;
+        int64_t tiles = 0, stg = 0;
+        if (ub > 0) {
+            classify(mnnz, flops, o.n, o.complement, a.force_kind, a.inner_ratio, icost, bin, tiles);
+            for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
+            atomicAdd(&sst[ST_BIN0 + bin], (unsigned long long)tiles);
+        }
+        a.flops[i] = flops;
+        a.tiles[i] = tiles;
+        a.bin[i] = (int8_t)bin;
+        atomicAdd(&sst[ST_FLOPS], (unsigned long long)flops);
+        atomicAdd(&sst[ST_UB], (unsigned long long)ub);
+        atomicAdd(&sst[ST_UNITS], (unsigned long long)tiles);
+        atomicAdd(&sst[ST_STAGING], (unsigned long long)stg);
+        atomicAdd(&sst[ST_MNNZ], (unsigned long long)mnnz);
+        atomicMax(&sst[ST_MAXFLOPS], (unsigned long long)flops);
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_COUNT) {
+        const unsigned long long v = sst[threadIdx.x];
+        if (v) {
+            if (threadIdx.x == ST_MAXFLOPS) atomicMax(&a.stats[threadIdx.x], v);
+            else atomicAdd(&a.stats[threadIdx.x], v);
+        }
+    }
+}
+
+hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
+    if (a.op.m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_analysis, dim3(grid_for(a.op.m, ANA_T, INT32_MAX)), dim3(ANA_T), 0, s, a);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------- units
+
+__global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
+    const Operands& o = a.op;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool has = i < m;
+    int64_t base = 0, tiles = 0, mnnz = 0, flops = 0;
+    int bin = -1;
+    if (has) {
+        base = a.unit_base[i];
+        tiles = a.unit_base[i + 1] - base;
+        bin = a.bin[i];
+        mnnz = o.Mrp[i + 1] - o.Mrp[i];
+        flops = a.flops[i];
+        for (int64_t t = 0; t < tiles; ++t) {
+            a.unit_row[base + t] = (int32_t)i;
+            a.unit_tile[base + t] = (int32_t)t;
+            a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
+        }
+    }
+    // single-unit rows: one atomic per distinct bin per wave; rank inside the wave keeps row order
+    bool pending = has && tiles == 1;
+    while (true) {
+        const uint64_t pm = __ballot(pending);
+        if (pm == 0) break;
+        const int leader = __builtin_ctzll(pm);
+        const int b = __shfl(bin, leader, WAVE);
+        const uint64_t same = __ballot(pending && bin == b);
+        unsigned long long start = 0;
+        if (lane() == leader) start = atomicAdd(&a.bin_cursor[b], (unsigned long long)__popcll(same));
+        start = __shfl(start, leader, WAVE);
+        if (pending && bin == b) {
+            a.bin_units[a.bin_off[b] + (int64_t)start + rank_below(same)] = (int32_t)base;
+            pending = false;
+        }
+    }
+    if (has && tiles > 1) {
+        const unsigned long long start = atomicAdd(&a.bin_cursor[bin], (unsigned long long)tiles);
+        for (int64_t t = 0; t < tiles; ++t) a.bin_units[a.bin_off[bin] + (int64_t)start + t] = (int32_t)(base + t);
+    }
+}
+
+hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_units, dim3(grid_for(m, 256, INT32_MAX)), dim3(256), 0, s, a, m);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------- scan
+
+constexpr int SCAN_T = 256, SCAN_I = 8, SCAN_TILE = SCAN_T * SCAN_I;
+
+int64_t scan_partial_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const int64_t* __restrict__ in, int64_t n,
+                                                        int64_t* __restrict__ partial) {
+    __shared__ int64_t t[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; ++j) {
+        const int64_t e = base + threadIdx.x + (int64_t)j * SCAN_T;
+        if (e < n) s += in[e];
+    }
+    s = wave_sum(s);
+    if (lane() == 0) t[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t v = 0;
+        for (int w = 0; w < SCAN_T / WAVE; ++w) v += t[w];
+        partial[blockIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_partials(int64_t* partial, int64_t nb) {
+    __shared__ int64_t tmp[SCAN_T / WAVE];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_T) {
+        const int64_t idx = b0 + threadIdx.x;
+        const int64_t v = idx < nb ? partial[idx] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<SCAN_T / WAVE>(v, tmp, tot);
+        if (idx < nb) partial[idx] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_down(const int64_t* in, int64_t* out, int64_t n,
+                                                      const int64_t* __restrict__ partial) {
+    __shared__ int64_t tmp[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+    int64_t v[SCAN_I];
+    int64_t run = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; ++j) {
+        v[j] = (base + j < n) ? in[base + j] : 0;
+        run += v[j];
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan<SCAN_T / WAVE>(run, tmp, tot);
+    int64_t acc = partial[blockIdx.x] + ex;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; ++j) {
+        if (base + j < n) out[base + j] = acc;
+        acc += v[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = partial[blockIdx.x] + tot;
+}
+
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s) {
+    if (n <= 0) return launch_fill_i64(out, 1, 0, s);
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_T), 0, s, partial, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, (const int64_t*)partial);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- product streaming
+
+// Per-wave LDS for one batch of up to 64 A entries: for the s-th stanza with
+// a nonzero length (in A order), its start in the flattened product
+// sequence, the shift from flattened position to B position, and A's value.
+template <class T>
+struct StanzaLds {
+    int64_t start[WAVE];
+    int64_t delta[WAVE];
+    typename T::in_t a[WAVE];
+    unsigned long long S;
+};
+
+// Streams every product (k, j) of row i: for each stored A(i,k) and each
+// stored B(k,j) with lo <= j <= hi (when `window`), calls f(j, s, q) where
+// q is the position of B(k,j) and s indexes st.a for A(i,k). Wave `wv` of
+// `nw` waves processes the product blocks wv, wv + nw, ... of each batch.
+//
+// Lane-to-stanza mapping of a block of 64 consecutive products: every
+// stanza that starts inside the block sets bit (start - block base) of a
+// 64-bit word; a lane's stanza is then
+//   (#stanzas starting before the block) + popcount(word & bits <= lane) - 1.
+template <class T, class F>
+__device__ __forceinline__ void stream_products(const Operands& o, int64_t i, bool window, int32_t lo, int32_t hi,
+                                                int wv, int nw, StanzaLds<T>& st, F&& f) {
+    const int ln = lane();
+    const int64_t pa0 = o.Arp[i], pa1 = o.Arp[i + 1];
+    for (int64_t pb = pa0; pb < pa1; pb += WAVE) {
+        const int64_t p = pb + ln;
+        int64_t b0 = 0, b1 = 0;
+        typename T::in_t a = T::one();
+        if (p < pa1) {
+            const int32_t k = o.Aci[p];
+            b0 = o.Brp[k];
+            b1 = o.Brp[k + 1];
+            if (T::needs_values) a = T::load(o.Av, p);
+            if (window) {
+                b0 = lower_bound_g(o.Bci, b0, b1, lo);
+                b1 = lower_bound_g(o.Bci, b0, b1, (int64_t)hi + 1);
+            }
+        }
+        const int64_t len = b1 - b0;
+        const uint64_t nzm = __ballot(len > 0);
+        if (nzm == 0) continue;
+        const int nz = __popcll(nzm);
+        const int64_t incl = wave_incl_scan(len);
+        const int64_t total = __shfl(incl, WAVE - 1, WAVE);
+        if (len > 0) {
+            const int sl = rank_below(nzm);
+            st.start[sl] = incl - len;
+            st.delta[sl] = b0 - (incl - len);
+            if (T::needs_values) st.a[sl] = a;
+        }
+        wave_lds_sync();
+        const int64_t my_start = ln < nz ? st.start[ln] : INT64_MAX;
+        for (int64_t base = (int64_t)wv * WAVE; base < total; base += (int64_t)nw * WAVE) {
+            const int before = __popcll(__ballot(my_start < base));
+            const int64_t rel = my_start - base;
+            if (rel >= 0 && rel < WAVE) atomicOr(&st.S, 1ull << rel);
+            wave_lds_sync();
+            const unsigned long long S = st.S;
+            wave_lds_sync();
+            if (ln == 0) st.S = 0ull;
+            const int s = before + __popcll(S & ((2ull << ln) - 1ull)) - 1;
+            const int64_t pos = base + ln;
+            if (pos < total) {
+                const int64_t q = st.delta[s] + pos;
+                f(o.Bci[q], s, q);
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// Ordered compaction over [0, len) for a block of NW waves: calls
+// write(idx, position) for every idx with keep(idx), positions in idx order.
+template <int NW, class K, class W>
+__device__ __forceinline__ int64_t ordered_emit(int len, int64_t* tmp, K keep, W write) {
+    int64_t running = 0;
+    for (int base = 0; base < len; base += NW * WAVE) {
+        const int idx = base + (int)threadIdx.x;
+        const bool kp = idx < len && keep(idx);
+        const uint64_t bm = __ballot(kp);
+        int64_t before = 0, total = __popcll(bm);
+        if (NW > 1) {
+            const int w = threadIdx.x / WAVE;
+            if (lane() == 0) tmp[w] = total;
+            __syncthreads();
+            total = 0;
+#pragma unroll
+            for (int x = 0; x < NW; ++x) {
+                const int64_t c = tmp[x];
+                before += (x < w) ? c : 0;
+                total += c;
+            }
+            __syncthreads();
+        }
+        if (kp) write(idx, running + before + rank_below(bm));
+        running += total;
+    }
+    return running;
+}
+
+// ------------------------------------------------- dense-state accumulator
+// A column tile [c0, c0 + wt) of row i held densely in LDS: admitted bitmap
+// (normal: set from the mask row; complemented: all set, then cleared from
+// the mask row), values and (where the value cannot tell) inserted flags.
+// Emission scans the tile in column order, so rows come out sorted for both
+// mask modes.
+template <int SR, int MODE, int NW, int W>
+__global__ __launch_bounds__(NW * WAVE) void k_dense(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    constexpr bool FLAGS = COUNT || T::sep_flag;
+    constexpr int NWORDS = W / 32;
+    __shared__ uint32_t allowed[NWORDS];
+    __shared__ acc_t vals[COUNT ? 1 : W];
+    __shared__ uint8_t flags[FLAGS ? W : 1];
+    __shared__ StanzaLds<T> st[NW];
+    __shared__ int64_t tmp[NW];
+    const Operands& o = g.op;
+    const int tid = threadIdx.x, wv = tid / WAVE;
+    const int u = g.units[blockIdx.x];
+    const int64_t i = g.unit_row[u];
+    const int64_t c0 = (int64_t)g.unit_tile[u] * W;
+    const int wt = (int)min((int64_t)W, o.n - c0);
+    const bool tiled = o.n > W;
+    for (int x = tid; x < NWORDS; x += NW * WAVE) {
+        const int lo = x * 32;
+        const uint32_t valid = (lo + 32 <= wt) ? 0xFFFFFFFFu : (lo >= wt ? 0u : ((1u << (wt - lo)) - 1u));
+        allowed[x] = o.complement ? valid : 0u;
+    }
+    if (!COUNT) for (int x = tid; x < W; x += NW * WAVE) vals[x] = T::identity();
+    if (FLAGS) for (int x = tid; x < W; x += NW * WAVE) flags[x] = 0;
+    if (lane() == 0) st[wv].S = 0ull;
+    __syncthreads();
+    int64_t m0 = o.Mrp[i], m1 = o.Mrp[i + 1];
+    if (tiled) {
+        m0 = lower_bound_g(o.Mci, m0, m1, c0);
+        m1 = lower_bound_g(o.Mci, m0, m1, c0 + wt);
+    }
+    for (int64_t p = m0 + tid; p < m1; p += NW * WAVE) {
+        const int c = o.Mci[p] - (int)c0;
+        const uint32_t bit = 1u << (c & 31);
+        if (o.complement) atomicAnd(&allowed[c >> 5], ~bit);
+        else atomicOr(&allowed[c >> 5], bit);
+    }
+    __syncthreads();
+    StanzaLds<T>& S = st[wv];
+    stream_products<T>(o, i, tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
+                       [&](int32_t j, int s, int64_t q) {
+                           const int c = j - (int)c0;
+                           if (allowed[c >> 5] & (1u << (c & 31))) {
+                               if (FLAGS) flags[c] = 1;
+                               if (!COUNT) {
+                                   const typename T::in_t b = T::needs_values ? T::load(o.Bv, q) : T::one();
+                                   T::lds_add(&vals[c], T::term(S.a[s], b));
+                               }
+                           }
+                       });
+    __syncthreads();
+    const int64_t ob = COUNT ? 0 : g.out_off[u];
+    typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+    const int64_t total = ordered_emit<NW>(
+        wt, tmp,
+        [&](int c) { return FLAGS ? (flags[c] != 0) : T::is_set(vals[c]); },
+        [&](int c, int64_t pos) {
+            if (!COUNT) {
+                g.out_col[ob + pos] = (int32_t)(c0 + c);
+                ov[ob + pos] = T::finish(vals[c]);
+            }
+        });
+    if (tid == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
+}
+
+// ---------------------------------------------- mask-keyed accumulators
+// Accumulator slots indexed by the rank of the column within the row's mask
+// chunk (at most CAP mask entries, kept sorted in LDS). The rank comes from
+// an open-addressing hash table keyed by column (HASHED; load factor <= 1/2,
+// linear probing) or from a branch-free binary search over the sorted keys.
+// Emission walks the ranks in order, i.e. the mask's column order.
+__device__ __forceinline__ int rank_search(const int32_t* keys, int cnt, int top, int32_t j) {
+    int pos = 0;
+    for (int step = top; step > 0; step >>= 1) {
+        const int np = pos + step;
+        if (np <= cnt && keys[np - 1] < j) pos = np;
+    }
+    return (pos < cnt && keys[pos] == j) ? pos : -1;
+}
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t j, int tbits) {
+    return ((uint32_t)j * 0x9E3779B1u) >> (32 - tbits);
+}
+
+__device__ __forceinline__ int hash_find(const unsigned long long* table, uint32_t tmask, int tbits, int32_t j) {
+    uint32_t h = hash_slot(j, tbits);
+    while (true) {
+        const unsigned long long e = table[h];
+        const int32_t k = (int32_t)(uint32_t)e;
+        if (k == j) return (int)(e >> 32);
+        if (k == -1) return -1;
+        h = (h + 1) & tmask;
+    }
+}
+
+template <int SR, int MODE, int NW, int CAP, bool HASHED>
+__global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    constexpr bool FLAGS = COUNT || T::sep_flag;
+    constexpr int TS = HASHED ? 2 * CAP : 1;
+    __shared__ int32_t keys[CAP];
+    __shared__ unsigned long long table[TS];
+    __shared__ acc_t vals[COUNT ? 1 : CAP];
+    __shared__ uint8_t flags[FLAGS ? CAP : 1];
+    __shared__ StanzaLds<T> st[NW];
+    __shared__ int64_t tmp[NW];
+    const Operands& o = g.op;
+    const int tid = threadIdx.x, wv = tid / WAVE;
+    const int u = g.units[blockIdx.x];
+    const int64_t i = g.unit_row[u];
+    const int64_t r0 = (int64_t)g.unit_tile[u] * CAP;
+    const int64_t mrow = o.Mrp[i];
+    const int64_t mnnz = o.Mrp[i + 1] - mrow;
+    const int cnt = (int)min((int64_t)CAP, mnnz - r0);
+    const bool tiled = mnnz > CAP;
+    for (int x = tid; x < cnt; x += NW * WAVE) {
+        keys[x] = o.Mci[mrow + r0 + x];
+        if (!COUNT) vals[x] = T::identity();
+        if (FLAGS) flags[x] = 0;
+    }
+    int tbits = 1;
+    while ((1 << tbits) < 2 * cnt) ++tbits;
+    const uint32_t tmask = (1u << tbits) - 1u;
+    if (HASHED)
+        for (int x = tid; x <= (int)tmask; x += NW * WAVE) table[x] = ~0ull;
+    if (lane() == 0) st[wv].S = 0ull;
+    __syncthreads();
+    if (HASHED) {
+        for (int x = tid; x < cnt; x += NW * WAVE) {
+            const int32_t key = keys[x];
+            const unsigned long long e = ((unsigned long long)(uint32_t)x << 32) | (uint32_t)key;
+            uint32_t h = hash_slot(key, tbits);
+            while (atomicCAS(&table[h], ~0ull, e) != ~0ull) h = (h + 1) & tmask;
+        }
+        __syncthreads();
+    }
+    const int32_t lo = keys[0], hi = keys[cnt - 1];
+    const int top = 1 << (31 - __clz(cnt));
+    StanzaLds<T>& S = st[wv];
+    stream_products<T>(o, i, tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q) {
+        const int r = HASHED ? hash_find(table, tmask, tbits, j) : rank_search(keys, cnt, top, j);
+        if (r >= 0) {
+            if (FLAGS) flags[r] = 1;
+            if (!COUNT) {
+                const typename T::in_t b = T::needs_values ? T::load(o.Bv, q) : T::one();
+                T::lds_add(&vals[r], T::term(S.a[s], b));
+            }
+        }
+    });
+    __syncthreads();
+    const int64_t ob = COUNT ? 0 : g.out_off[u];
+    typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+    const int64_t total = ordered_emit<NW>(
+        cnt, tmp,
+        [&](int r) { return FLAGS ? (flags[r] != 0) : T::is_set(vals[r]); },
+        [&](int r, int64_t pos) {
+            if (!COUNT) {
+                g.out_col[ob + pos] = keys[r];
+                ov[ob + pos] = T::finish(vals[r]);
+            }
+        });
+    if (tid == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
+}
+
+// ----------------------------------------------------------- inner product
+// Pull formulation: lane x of the wave owns mask entry (i, j) and computes
+// the sparse dot product of A(i,:) with column j of B (row j of B^T) by
+// looking up every k of that column in A's row (staged in LDS when short,
+// else a binary search in global memory).
+template <int SR, int MODE, int CAP, int ACAP>
+__global__ __launch_bounds__(WAVE) void k_inner(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    using in_t = typename T::in_t;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    __shared__ int32_t akeys[ACAP];
+    __shared__ in_t avals[T::needs_values ? ACAP : 1];
+    const Operands& o = g.op;
+    const int ln = lane();
+    const int u = g.units[blockIdx.x];
+    const int64_t i = g.unit_row[u];
+    const int64_t r0 = (int64_t)g.unit_tile[u] * CAP;
+    const int64_t mrow = o.Mrp[i];
+    const int cnt = (int)min((int64_t)CAP, o.Mrp[i + 1] - mrow - r0);
+    const int64_t pa0 = o.Arp[i];
+    const int64_t alen = o.Arp[i + 1] - pa0;
+    const bool in_lds = alen <= ACAP;
+    if (in_lds) {
+        for (int x = ln; x < alen; x += WAVE) {
+            akeys[x] = o.Aci[pa0 + x];
+            if (T::needs_values && !COUNT) avals[x] = T::load(o.Av, pa0 + x);
+        }
+    }
+    __syncthreads();
+    const int top = in_lds && alen > 0 ? 1 << (31 - __clz((int)alen)) : 0;
+    const int64_t ob = COUNT ? 0 : g.out_off[u];
+    typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+    int64_t running = 0;
+    for (int base = 0; base < cnt; base += WAVE) {
+        const int x = base + ln;
+        bool set = false;
+        acc_t acc = T::identity();
+        int32_t j = 0;
+        if (x < cnt) {
+            j = o.Mci[mrow + r0 + x];
+            const int64_t q0 = o.BTrp[j], q1 = o.BTrp[j + 1];
+            for (int64_t q = q0; q < q1; ++q) {
+                const int32_t k = o.BTci[q];
+                int64_t idx;
+                if (in_lds) idx = rank_search(akeys, (int)alen, top, k);
+                else {
+                    const int64_t p = lower_bound_g(o.Aci, pa0, pa0 + alen, k);
+                    idx = (p < pa0 + alen && o.Aci[p] == k) ? p - pa0 : -1;
+                }
+                if (idx >= 0) {
+                    set = true;
+                    if (!COUNT) {
+                        const in_t a = T::needs_values ? (in_lds ? avals[idx] : T::load(o.Av, pa0 + idx)) : T::one();
+                        const in_t b = T::needs_values ? T::load(o.BTv, q) : T::one();
+                        acc = T::add(acc, T::term(a, b));
+                    }
+                }
+            }
+        }
+        const uint64_t bm = __ballot(set);
+        if (set && !COUNT) {
+            const int64_t pos = ob + running + rank_below(bm);
+            g.out_col[pos] = j;
+            ov[pos] = T::finish(acc);
+        }
+        running += __popcll(bm);
+    }
+    if (ln == 0 && MODE != MODE_DIRECT) g.cnt[u] = running;
+}
+
+template <int SR, int MODE>
+static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.nunits);
+    switch (bin) {
+    case BIN_DENSE_W:
+        hipLaunchKernelGGL((k_dense<SR, MODE, 1, DENSE_W_COLS>), grid, dim3(WAVE), 0, s, a);
+        break;
+    case BIN_DENSE_B:
+        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS>), grid, dim3(BLOCK_NW * WAVE), 0, s, a);
+        break;
+    case BIN_HASH_W:
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, true>), grid, dim3(WAVE), 0, s, a);
+        break;
+    case BIN_HASH_B:
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, true>), grid, dim3(BLOCK_NW * WAVE), 0, s, a);
+        break;
+    case BIN_MASKIDX_W:
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false>), grid, dim3(WAVE), 0, s, a);
+        break;
+    case BIN_MASKIDX_B:
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false>), grid, dim3(BLOCK_NW * WAVE), 0,
+                           s, a);
+        break;
+    case BIN_INNER_W:
+        hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP>), grid, dim3(WAVE), 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int SR>
+static hipError_t launch_numeric_sr(int bin, int mode, const NumArgs& a, hipStream_t s) {
+    switch (mode) {
+    case MODE_COUNT: return launch_numeric_t<SR, MODE_COUNT>(bin, a, s);
+    case MODE_STAGE: return launch_numeric_t<SR, MODE_STAGE>(bin, a, s);
+    case MODE_DIRECT: return launch_numeric_t<SR, MODE_DIRECT>(bin, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_numeric(int semiring, int bin, int mode, const NumArgs& a, hipStream_t s) {
+    if (a.nunits <= 0) return hipSuccess;
+    if (mode == MODE_COUNT) {
+        // symbolic counting does not depend on values: one instantiation per value layout suffices
+        switch (semiring) {
+        case MSP_PLUS_PAIR_I64: return launch_numeric_sr<MSP_PLUS_PAIR_I64>(bin, mode, a, s);
+        default: return launch_numeric_sr<MSP_PLUS_PAIR_I64>(bin, mode, a, s);
+        }
+    }
+    switch (semiring) {
+    case MSP_PLUS_TIMES_F64: return launch_numeric_sr<MSP_PLUS_TIMES_F64>(bin, mode, a, s);
+    case MSP_PLUS_PAIR_I64: return launch_numeric_sr<MSP_PLUS_PAIR_I64>(bin, mode, a, s);
+    case MSP_LOR_LAND_BOOL: return launch_numeric_sr<MSP_LOR_LAND_BOOL>(bin, mode, a, s);
+    case MSP_PLUS_TIMES_I32: return launch_numeric_sr<MSP_PLUS_TIMES_I32>(bin, mode, a, s);
+    case MSP_PLUS_TIMES_I64: return launch_numeric_sr<MSP_PLUS_TIMES_I64>(bin, mode, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------- compaction
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
+    const int64_t u = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (u >= a.U) return;
+    const int64_t src = a.stg_off[u], dst = a.out_off[u], n = a.out_off[u + 1] - dst;
+    const V* sv = static_cast<const V*>(a.stg_val);
+    V* dv = static_cast<V*>(a.C_val);
+    for (int64_t x = lane(); x < n; x += WAVE) {
+        a.C_col[dst + x] = a.stg_col[src + x];
+        dv[dst + x] = sv[src + x];
+    }
+}
+
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
+    if (a.U <= 0) return hipSuccess;
+    const dim3 grid(grid_for(a.U, 4, INT32_MAX));
+    switch (a.val_bytes) {
+    case 1: hipLaunchKernelGGL(k_compact<uint8_t>, grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_compact<uint32_t>, grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_compact<unsigned long long>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_rowptr(int64_t m, const int64_t* __restrict__ unit_base, const int64_t* __restrict__ out_off,
+                         int64_t* __restrict__ rp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= m) rp[i] = out_off[unit_base[i]];
+}
+
+hipError_t launch_rowptr_from_units(int64_t m, const int64_t* unit_base, const int64_t* out_off,
+                                    int64_t* C_rowptr, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowptr, dim3(grid_for(m + 1, 256, INT32_MAX)), dim3(256), 0, s, m, unit_base, out_off,
+                       C_rowptr);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- transpose
+
+__global__ void k_colcount(const int32_t* __restrict__ ci, int64_t nnz, int64_t* cnt) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[ci[p]]), 1ull);
+}
+
+hipError_t launch_colcount(const int32_t* ci, int64_t nnz, int64_t* cnt, hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colcount, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, s, ci, nnz, cnt);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_tscatter(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                  const uint8_t* __restrict__ v, int vb, int64_t nrows,
+                                                  const int64_t* __restrict__ trp, unsigned long long* cursor,
+                                                  int32_t* __restrict__ tci, uint8_t* __restrict__ tv) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (r >= nrows) return;
+    for (int64_t p = rp[r] + lane(); p < rp[r + 1]; p += WAVE) {
+        const int32_t c = ci[p];
+        const int64_t pos = trp[c] + (int64_t)atomicAdd(&cursor[c], 1ull);
+        tci[pos] = (int32_t)r;
+        for (int b = 0; b < vb; ++b) tv[pos * vb + b] = v[p * vb + b];
+    }
+}
+
+hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const void* v, int val_bytes,
+                                    int64_t nrows, const int64_t* trp, unsigned long long* cursor, int32_t* tci,
+                                    void* tv, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tscatter, dim3(grid_for(nrows, 4, INT32_MAX)), dim3(256), 0, s, rp, ci,
+                       static_cast<const uint8_t*>(v), v ? val_bytes : 0, nrows, trp, cursor, tci,
+                       static_cast<uint8_t*>(tv));
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- reduction
+
+constexpr int RED_BLOCKS = 1024, RED_T = 256;
+int64_t reduce_partial_elems() { return RED_BLOCKS; }
+
+template <int SR> struct Red;
+template <> struct Red<MSP_PLUS_TIMES_F64> {
+    using V = double; using A = double;
+    __device__ static A from(V v) { return v; }
+    __device__ static A op(A x, A y) { return x + y; }
+    __device__ static V out(A x) { return x; }
+};
+template <> struct Red<MSP_PLUS_PAIR_I64> {
+    using V = int64_t; using A = unsigned long long;
+    __device__ static A from(V v) { return (A)v; }
+    __device__ static A op(A x, A y) { return x + y; }
+    __device__ static V out(A x) { return (V)x; }
+};
+template <> struct Red<MSP_PLUS_TIMES_I64> : Red<MSP_PLUS_PAIR_I64> {};
+template <> struct Red<MSP_PLUS_TIMES_I32> {
+    using V = int32_t; using A = unsigned long long;
+    __device__ static A from(V v) { return (A)(uint32_t)v; }
+    __device__ static A op(A x, A y) { return (A)(uint32_t)(x + y); }
+    __device__ static V out(A x) { return (V)(uint32_t)x; }
+};
+template <> struct Red<MSP_LOR_LAND_BOOL> {
+    using V = uint8_t; using A = unsigned long long;
+    __device__ static A from(V v) { return v != 0; }
+    __device__ static A op(A x, A y) { return (x | y) != 0; }
+    __device__ static V out(A x) { return (V)(x != 0); }
+};
+
+template <int SR>
+__device__ typename Red<SR>::A block_reduce(typename Red<SR>::A v) {
+    using R = Red<SR>;
+    __shared__ typename R::A t[RED_T / WAVE];
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v = R::op(v, __shfl_xor(v, d, WAVE));
+    if (lane() == 0) t[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    typename R::A r = t[0];
+    for (int w = 1; w < RED_T / WAVE; ++w) r = R::op(r, t[w]);
+    return r;
+}
+
+template <int SR>
+__global__ __launch_bounds__(RED_T) void k_reduce_partial(const typename Red<SR>::V* __restrict__ v, int64_t n,
+                                                          typename Red<SR>::A* partial) {
+    using R = Red<SR>;
+    typename R::A acc = R::from(typename R::V(0));
+    for (int64_t x = (int64_t)blockIdx.x * RED_T + threadIdx.x; x < n; x += (int64_t)gridDim.x * RED_T)
+        acc = R::op(acc, R::from(v[x]));
+    acc = block_reduce<SR>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+template <int SR>
+__global__ __launch_bounds__(RED_T) void k_reduce_final(const typename Red<SR>::A* partial, int nb,
+                                                        typename Red<SR>::V* out) {
+    using R = Red<SR>;
+    typename R::A acc = R::from(typename R::V(0));
+    for (int x = threadIdx.x; x < nb; x += RED_T) acc = R::op(acc, partial[x]);
+    acc = block_reduce<SR>(acc);
+    if (threadIdx.x == 0) *out = R::out(acc);
+}
+
+template <int SR>
+static hipError_t launch_reduce_t(const void* vals, int64_t n, void* partial, void* result, hipStream_t s) {
+    using R = Red<SR>;
+    const int nb = (int)grid_for(n, RED_T * 8, RED_BLOCKS);
+    hipLaunchKernelGGL(k_reduce_partial<SR>, dim3(nb), dim3(RED_T), 0, s, static_cast<const typename R::V*>(vals), n,
+                       static_cast<typename R::A*>(partial));
+    hipLaunchKernelGGL(k_reduce_final<SR>, dim3(1), dim3(RED_T), 0, s, static_cast<const typename R::A*>(partial), nb,
+                       static_cast<typename R::V*>(result));
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int semiring, const void* vals, int64_t n, void* partial, void* result, hipStream_t s) {
+    switch (semiring) {
+    case MSP_PLUS_TIMES_F64: return launch_reduce_t<MSP_PLUS_TIMES_F64>(vals, n, partial, result, s);
+    case MSP_PLUS_PAIR_I64: return launch_reduce_t<MSP_PLUS_PAIR_I64>(vals, n, partial, result, s);
+    case MSP_LOR_LAND_BOOL: return launch_reduce_t<MSP_LOR_LAND_BOOL>(vals, n, partial, result, s);
+    case MSP_PLUS_TIMES_I32: return launch_reduce_t<MSP_PLUS_TIMES_I32>(vals, n, partial, result, s);
+    case MSP_PLUS_TIMES_I64: return launch_reduce_t<MSP_PLUS_TIMES_I64>(vals, n, partial, result, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mspk

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+rowptr/colidx bit-exact; integer values bit-exact; FP64 within 1e-12 relative."""
+import math
+
+import numpy as np
+import pytest
+
+import mspgen
+import oracle
+from tests.gpu_util import (assert_same, msp, rand_problem, run_and_check, torch_or_skip, up)
+
+pytestmark = pytest.mark.gpu
+
+SEMIRINGS = ["plus_times_f64", "plus_pair_i64", "lor_land_bool", "plus_times_i32", "plus_times_i64"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch_or_skip()
+
+
+# n = 400 fits the one-wave dense tile; n = 9000 needs three ragged 4096-column tiles
+SHAPES = {"narrow": (300, 200, 400, 5.0, 6.0, 30.0), "wide": (257, 300, 9000, 7.0, 9.0, 60.0)}
+
+
+@pytest.mark.parametrize("shape", sorted(SHAPES))
+@pytest.mark.parametrize("sr", SEMIRINGS)
+@pytest.mark.parametrize("kind", ["auto", "dense", "hash", "maskidx", "inner"])
+@pytest.mark.parametrize("phase", [1, 2])
+def test_forced_kinds_normal_mask(shape, sr, kind, phase):
+    A, B, M = rand_problem(hash((shape, sr)) % 1000, *SHAPES[shape], sr)
+    run_and_check(A, B, M, False, sr, force_kind=kind, phase=phase)
+
+
+@pytest.mark.parametrize("shape", sorted(SHAPES))
+@pytest.mark.parametrize("sr", SEMIRINGS)
+@pytest.mark.parametrize("phase", [1, 2])
+def test_complemented_mask(shape, sr, phase):
+    A, B, M = rand_problem(7 + len(shape), *SHAPES[shape], sr)
+    run_and_check(A, B, M, True, sr, phase=phase)
+
+
+@pytest.mark.parametrize("kind", ["auto", "hash", "maskidx", "dense", "inner"])
+def test_heavy_rows_span_several_tiles(kind):
+    """Mask rows longer than every LDS capacity (4096 mask entries, 1024 hash
+    entries, 4096-column tiles), A rows longer than one 64-entry batch and
+    B rows longer than a wave."""
+    rng = np.random.default_rng(5)
+    m, k, n = 40, 300, 20000
+    A = mspgen.er(m, k, 150.0, 11, "f64")
+    B = mspgen.er(k, n, 120.0, 12, "f64")
+    # mask rows of very different lengths: 0, tiny, ~1500, ~5000, ~12000
+    dens = rng.choice([0.0, 3.0, 1500.0, 5000.0, 12000.0], size=m)
+    rows, cols = [], []
+    for i, d in enumerate(dens):
+        c = np.unique(rng.integers(0, n, size=int(d)))
+        rows.append(np.full(len(c), i))
+        cols.append(c)
+    M = mspgen.from_coo(m, n, np.concatenate(rows), np.concatenate(cols))
+    run_and_check(A, B, M, False, "plus_times_f64", force_kind=kind)
+    run_and_check(A, B, M, False, "plus_pair_i64", force_kind=kind, phase=2)
+
+
+def test_complement_heavy_wide():
+    A = mspgen.er(50, 80, 30.0, 21, "i32")
+    B = mspgen.er(80, 10000, 200.0, 22, "i32")
+    M = mspgen.er(50, 10000, 3000.0, 23, None)
+    run_and_check(A, B, M, True, "plus_times_i32")
+    run_and_check(A, B, M, True, "lor_land_bool", phase=2)
+
+
+def _empty(m, n):
+    return mspgen.CSR(m, n, np.zeros(m + 1, np.int64), np.zeros(0, np.int32))
+
+
+def _full(m, n):
+    r, c = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    return mspgen.from_coo(m, n, r.ravel(), c.ravel())
+
+
+@pytest.mark.parametrize("case", ["m0", "n0", "k0", "emptyA", "emptyM", "fullM", "onecol", "rect"])
+@pytest.mark.parametrize("complement", [False, True])
+def test_edge_shapes(case, complement):
+    sr = "plus_times_f64"
+    if case == "m0":
+        A, B, M = mspgen.er(0, 30, 3, 1, "f64"), mspgen.er(30, 40, 3, 2, "f64"), _empty(0, 40)
+    elif case == "n0":
+        A, B, M = mspgen.er(30, 20, 3, 1, "f64"), mspgen.er(20, 0, 3, 2, "f64"), _empty(30, 0)
+    elif case == "k0":
+        A, B, M = mspgen.er(30, 0, 3, 1, "f64"), mspgen.er(0, 40, 3, 2, "f64"), mspgen.er(30, 40, 5, 3, None)
+    elif case == "emptyA":
+        A, B, M = _empty(30, 20), mspgen.er(20, 40, 3, 2, "f64"), mspgen.er(30, 40, 5, 3, None)
+        A = A.with_values(np.zeros(0))
+    elif case == "emptyM":
+        A, B, M = mspgen.er(30, 20, 3, 1, "f64"), mspgen.er(20, 40, 3, 2, "f64"), _empty(30, 40)
+    elif case == "fullM":
+        A, B, M = mspgen.er(30, 20, 3, 1, "f64"), mspgen.er(20, 600, 30, 2, "f64"), _full(30, 600)
+    elif case == "onecol":
+        A, B, M = mspgen.er(64, 50, 4, 1, "f64"), mspgen.er(50, 1, 0.5, 2, "f64"), mspgen.er(64, 1, 0.6, 3, None)
+    else:
+        A, B, M = mspgen.er(7, 1000, 40, 1, "f64"), mspgen.er(1000, 3, 1.5, 2, "f64"), mspgen.er(7, 3, 2, 3, None)
+    for phase in (1, 2):
+        run_and_check(A, B, M, complement, sr, phase=phase)
+
+
+def test_explicit_zeros_and_wraparound():
+    rng = np.random.default_rng(3)
+    A = mspgen.er(200, 150, 8, 31, "i32")
+    B = mspgen.er(150, 300, 8, 32, "i32")
+    A.values[rng.integers(0, A.nnz, 200)] = 0
+    A.values[:] = A.values * 40000  # products exceed 2^31 and wrap
+    B.values[:] = B.values * 30000
+    M = mspgen.er(200, 300, 40, 33, None)
+    for kind in ("auto", "dense", "hash", "maskidx", "inner"):
+        run_and_check(A, B, M, False, "plus_times_i32", force_kind=kind)
+    Af = mspgen.er(200, 150, 8, 34, "f64")
+    Af.values[::3] = 0.0
+    Bf = mspgen.er(150, 300, 8, 35, "f64")
+    run_and_check(Af, Bf, M, False, "plus_times_f64")
+    run_and_check(Af, Bf, M, True, "plus_times_f64")
+
+
+def test_iso_valued_operands():
+    A = mspgen.er(100, 90, 6, 41, None)
+    B = mspgen.er(90, 120, 6, 42, None)
+    M = mspgen.er(100, 120, 25, 43, None)
+    for sr in SEMIRINGS:
+        run_and_check(A, B, M, False, sr)
+
+
+@pytest.mark.parametrize("n", [3, 8, 40, 100])
+def test_complete_graph_triangles(n):
+    L = mspgen.tril_strict(mspgen.complete_graph(n))
+    dL = up(L)
+    C = msp().masked_spgemm(dL, dL, dL, semiring="plus_pair_i64")
+    rp, ci, v = C.to_host()
+    assert int(rp[-1]) == math.comb(n - 1, 2)
+    assert int(v.sum()) == math.comb(n, 3)
+    s = msp().reduce(C.values, "plus_pair_i64")
+    assert int(s.item()) == math.comb(n, 3)
+
+
+@pytest.mark.parametrize("scale", [10, 13])
+def test_triangle_counting_rmat(scale):
+    L = mspgen.triangle_input(scale, 16, scale)
+    dL = up(L)
+    R = oracle.masked_spgemm(L, L, L, False, "plus_pair_i64")
+    for kind in ("auto", "hash", "maskidx", "inner"):
+        for phase in (1, 2):
+            C = msp().masked_spgemm(dL, dL, dL, semiring="plus_pair_i64", force_kind=kind, phase=phase)
+            assert_same(C, R, "plus_pair_i64")
+    C = msp().masked_spgemm(dL, dL, dL, semiring="plus_pair_i64", inner_ratio=4)
+    assert_same(C, R, "plus_pair_i64")
+
+
+@pytest.mark.parametrize("sr,vals", [("lor_land_bool", "u8"), ("plus_times_i32", "i32")])
+def test_bfs_step(sr, vals):
+    G = mspgen.rmat_graph(12, 8, 12)
+    F, V, srcs, lv = mspgen.bfs_step_input(G, 512, seed=21, values=vals)
+    for phase in (1, 2):
+        run_and_check(G, F, V, True, sr, phase=phase)
+
+
+def test_er_small_workload_full():
+    """Erdos-Renyi n = 4096, 8 entries per row, U(0,1) FP64, normal mask."""
+    A = mspgen.er(4096, 4096, 8.0, 101, "f64")
+    B = mspgen.er(4096, 4096, 8.0, 102, "f64")
+    M = mspgen.er(4096, 4096, 8.0, 103, None)
+    for kind in ("auto", "hash", "maskidx", "dense", "inner"):
+        run_and_check(A, B, M, False, "plus_times_f64", force_kind=kind)
+
+
+def test_validation_rejects_bad_csr():
+    m = msp()
+    A = mspgen.er(50, 40, 5, 1, "f64")
+    B = mspgen.er(40, 60, 5, 2, "f64")
+    M = mspgen.er(50, 60, 5, 3, None)
+    bad = mspgen.CSR(B.nrows, B.ncols, B.rowptr.copy(), B.colidx.copy(), B.values)
+    r = int(np.argmax(np.diff(B.rowptr) >= 2))
+    p = B.rowptr[r]
+    bad.colidx[p], bad.colidx[p + 1] = bad.colidx[p + 1], bad.colidx[p]  # unsorted row
+    with pytest.raises(m.MspError) as e:
+        m.masked_spgemm(up(A, "plus_times_f64"), up(bad, "plus_times_f64"), up(M), validate=True)
+    assert e.value.status == 3
+    C = m.masked_spgemm(up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M), validate=True)
+    assert_same(C, oracle.masked_spgemm(A, B, M, False, "plus_times_f64"), "plus_times_f64")
+
+
+def test_plan_reuse_and_value_update():
+    torch = torch_or_skip()
+    m = msp()
+    A = mspgen.er(500, 400, 6, 51, "f64")
+    B = mspgen.er(400, 700, 6, 52, "f64")
+    M = mspgen.er(500, 700, 30, 53, None)
+    dA, dB, dM = up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M)
+    with m.Plan(dA, dB, dM, semiring="plus_times_f64") as p:
+        C1 = p.execute()
+        C2 = p.execute()
+        assert torch.equal(C1.colidx, C2.colidx)
+        dA.values.mul_(2.0)  # same pattern, new values: the plan stays valid
+        C3 = p.execute()
+    A2 = A.with_values(A.values * 2.0)
+    assert_same(C3, oracle.masked_spgemm(A2, B, M, False, "plus_times_f64"), "plus_times_f64")
+
+
+def test_integer_results_repeat_bit_exact():
+    torch = torch_or_skip()
+    L = mspgen.triangle_input(12, 16, 3)
+    dL = up(L)
+    a = msp().masked_spgemm(dL, dL, dL, semiring="plus_pair_i64")
+    b = msp().masked_spgemm(dL, dL, dL, semiring="plus_pair_i64", phase=2)
+    assert torch.equal(a.rowptr, b.rowptr) and torch.equal(a.colidx, b.colidx) and torch.equal(a.values, b.values)
+
+
+def test_reduce_semirings():
+    torch = torch_or_skip()
+    m = msp()
+    dev = torch.device("cuda:0")
+    x = torch.arange(1, 100001, dtype=torch.int64, device=dev)
+    assert int(m.reduce(x, "plus_pair_i64").item()) == 100000 * 100001 // 2
+    y = torch.rand(12345, dtype=torch.float64, device=dev)
+    assert abs(float(m.reduce(y, "plus_times_f64").item()) - float(y.sum().item())) <= 1e-10
+    z = torch.zeros(1000, dtype=torch.uint8, device=dev)
+    assert int(m.reduce(z, "lor_land_bool").item()) == 0
+    z[777] = 1
+    assert int(m.reduce(z, "lor_land_bool").item()) == 1
+    w = torch.full((1000,), 2**30, dtype=torch.int32, device=dev)
+    assert int(m.reduce(w, "plus_times_i32").item()) == 0  # 1000 * 2^30 mod 2^32
+    e = torch.zeros(0, dtype=torch.int64, device=dev)
+    assert int(m.reduce(e, "plus_pair_i64").item()) == 0
