@@ -153,7 +153,34 @@ typedef struct msp_plan_info_t {
     int64_t staging;         /* staging entries used by one-phase execution */
     int64_t mask_nnz;        /* nnz(M) */
     int64_t kind_units[4];   /* units per msp_kind */
+    int64_t bin_units[8];    /* units per kernel bin (MSP_BIN_*; 7 used) */
 } msp_plan_info_t;
+
+/*
+ * Kernel bins: every work unit runs in the numeric kernel of its bin. The
+ * "wave" bins give one wavefront per unit, the "block" bins one 256-thread
+ * workgroup per unit.
+ */
+enum {
+    MSP_BIN_DENSE_WAVE = 0,
+    MSP_BIN_DENSE_BLOCK = 1,
+    MSP_BIN_HASH_WAVE = 2,
+    MSP_BIN_HASH_BLOCK = 3,
+    MSP_BIN_MASKIDX_WAVE = 4,
+    MSP_BIN_MASKIDX_BLOCK = 5,
+    MSP_BIN_INNER_WAVE = 6,
+    MSP_NBINS = 7
+};
+
+/* Stage slots of msp_execute_profiled: 0..6 = numeric kernel of bin b,
+   then these. */
+enum {
+    MSP_STAGE_SYMBOLIC = 7,   /* all symbolic count kernels (two-phase) */
+    MSP_STAGE_SCAN = 8,       /* prefix sums of the unit counts */
+    MSP_STAGE_ROWPTR = 9,     /* row pointers of C */
+    MSP_STAGE_COMPACT = 10,   /* one-phase staging -> C */
+    MSP_NSTAGES = 11
+};
 
 typedef struct msp_plan msp_plan;
 
@@ -198,6 +225,19 @@ msp_status msp_numeric(msp_plan* plan, msp_csr_out* C, void* stream);
  * changed in place).
  */
 msp_status msp_execute(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* stream);
+
+/*
+ * msp_execute with timing: records HIP events on `stream` around every
+ * stage, SYNCHRONIZES, and ADDS each stage's elapsed milliseconds to
+ * stage_ms[MSP_NSTAGES] (host; stages that did not run add 0). For
+ * measurement; the results are those of msp_execute.
+ */
+msp_status msp_execute_profiled(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, double* stage_ms,
+                                void* stream);
+
+/* Copies the kernel bin of every row (MSP_BIN_*, or -1 for rows with no
+   possible output) into bins (host, nrows entries). SYNCHRONIZES. */
+msp_status msp_plan_row_bins(const msp_plan* plan, int8_t* bins, void* stream);
 
 /* Releases the plan's device workspace (stream-ordered on the plan's stream). */
 void msp_plan_destroy(msp_plan* plan);

@@ -20,6 +20,8 @@ SEMIRINGS = {
     "plus_times_i32": 3,
     "plus_times_i64": 4,
 }
+BIN_NAMES = L.BIN_NAMES
+STAGE_NAMES = L.STAGE_NAMES
 KINDS = {None: -1, "auto": -1, "dense": 0, "hash": 1, "maskidx": 2, "inner": 3}
 STATUS = {0: "MSP_OK", 1: "MSP_ERR_INVALID_ARGUMENT", 2: "MSP_ERR_DIMENSION_MISMATCH",
           3: "MSP_ERR_INVALID_CSR", 4: "MSP_ERR_UNSUPPORTED", 5: "MSP_ERR_INSUFFICIENT_CAPACITY",
@@ -155,6 +157,7 @@ class Plan:
         self.staging = info.staging
         self.mask_nnz = info.mask_nnz
         self.kind_units = {k: info.kind_units[i] for i, k in enumerate(["dense", "hash", "maskidx", "inner"])}
+        self.bin_units = {k: info.bin_units[i] for i, k in enumerate(L.BIN_NAMES)}
 
     def _out(self, capacity: int):
         t = _torch()
@@ -200,6 +203,29 @@ class Plan:
         _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if sync_nnz else None, _stream()),
                "msp_execute")
         return n.value
+
+    def execute_profiled(self, rowptr, colidx, values, capacity: int, stage_ms) -> int:
+        """Like execute_into, and adds each stage's HIP-event time (ms) to
+        stage_ms (float64 numpy array of len(STAGE_NAMES)); synchronizes and
+        returns nnz(C)."""
+        import numpy as np
+        lib = L.load()
+        assert stage_ms.dtype == np.float64 and len(stage_ms) == L.NSTAGES
+        out = L.MspCsrOut(self.nrows, self.ncols, capacity, rowptr.data_ptr(), colidx.data_ptr(),
+                          values.data_ptr())
+        n = ctypes.c_int64(-1)
+        _check(lib.msp_execute_profiled(self._h, ctypes.byref(out), ctypes.byref(n),
+                                        stage_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+               "msp_execute_profiled")
+        return n.value
+
+    def row_bins(self):
+        """Kernel bin of every row (numpy int8; -1 = no possible output)."""
+        import numpy as np
+        out = np.empty(self.nrows, dtype=np.int8)
+        _check(L.load().msp_plan_row_bins(self._h, out.ctypes.data_as(ctypes.c_void_p), _stream()),
+               "msp_plan_row_bins")
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -4,7 +4,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsp.so")
+# MSP_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MSP_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsp.so")
 
 c_i32, c_i64, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 
@@ -26,7 +27,14 @@ class MspOptions(ctypes.Structure):
 
 class MspPlanInfo(ctypes.Structure):
     _fields_ = [("upper_bound", c_i64), ("products", c_i64), ("units", c_i64),
-                ("staging", c_i64), ("mask_nnz", c_i64), ("kind_units", c_i64 * 4)]
+                ("staging", c_i64), ("mask_nnz", c_i64), ("kind_units", c_i64 * 4),
+                ("bin_units", c_i64 * 8)]
+
+
+BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wave", "maskidx_block",
+             "inner_wave"]
+STAGE_NAMES = BIN_NAMES + ["symbolic", "scan", "rowptr", "compact"]
+NSTAGES = len(STAGE_NAMES)
 
 
 # every symbol include/msp.h declares, with its ctypes signature
@@ -39,6 +47,9 @@ SIGNATURES = {
     "msp_symbolic": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
     "msp_numeric": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), c_vp]),
     "msp_execute": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp]),
+    "msp_execute_profiled": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64),
+                                            ctypes.POINTER(ctypes.c_double), c_vp]),
+    "msp_plan_row_bins": (ctypes.c_int, [c_vp, c_vp, c_vp]),
     "msp_plan_destroy": (None, [c_vp]),
     "msp_masked_spgemm": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(MspOptions),

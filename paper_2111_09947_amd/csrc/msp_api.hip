@@ -91,8 +91,9 @@ struct msp_plan {
     int64_t bin_count[NBINS] = {};
     int64_t bin_off[NBINS + 1] = {};
     // units
-    int64_t* bin_off_d = nullptr;
-    unsigned long long* bin_cursor = nullptr;
+    int64_t* seg_off_d = nullptr;
+    unsigned long long* seg_cursor = nullptr;
+    int64_t seg_off[NBINS * NBUCKET] = {};
     int32_t* unit_row = nullptr;
     int32_t* unit_tile = nullptr;
     int64_t* stg_off = nullptr;
@@ -276,18 +277,25 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
     P->U = (int64_t)P->stats[ST_UNITS];
     P->S = (int64_t)P->stats[ST_STAGING];
     P->ub = (int64_t)P->stats[ST_UB];
+    // bins in order; inside a bin, flops buckets from the heaviest down
     P->bin_off[0] = 0;
+    int64_t run = 0;
     for (int b = 0; b < NBINS; ++b) {
-        P->bin_count[b] = (int64_t)P->stats[ST_BIN0 + b];
-        P->bin_off[b + 1] = P->bin_off[b] + P->bin_count[b];
+        P->bin_off[b] = run;
+        for (int q = NBUCKET - 1; q >= 0; --q) {
+            P->seg_off[b * NBUCKET + q] = run;
+            run += (int64_t)P->stats[ST_BIN0 + b * NBUCKET + q];
+        }
+        P->bin_count[b] = run - P->bin_off[b];
     }
+    P->bin_off[NBINS] = run;
     if (P->bin_off[NBINS] != P->U) return fail(MSP_ERR_DEVICE, "inconsistent unit statistics");
     if (P->U >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many work units");
     if (P->bin_count[BIN_INNER_W] > 0 && !o.b_transpose) MSP_CHECK(build_transpose(P, true));
 
     const int64_t U = P->U;
-    MSP_CHECK(P->alloc_n(&P->bin_off_d, NBINS + 1));
-    MSP_CHECK(P->alloc_n(&P->bin_cursor, NBINS));
+    MSP_CHECK(P->alloc_n(&P->seg_off_d, NBINS * NBUCKET));
+    MSP_CHECK(P->alloc_n(&P->seg_cursor, NBINS * NBUCKET));
     MSP_CHECK(P->alloc_n(&P->unit_row, U));
     MSP_CHECK(P->alloc_n(&P->unit_tile, U));
     MSP_CHECK(P->alloc_n(&P->stg_off, U + 1));
@@ -298,15 +306,15 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
         MSP_CHECK(P->alloc_n(&part, scan_partial_elems(U + 1)));
         P->scan_partial = part;
     }
-    MSP_HIP(hipMemcpyAsync(P->bin_off_d, P->bin_off, sizeof(int64_t) * (NBINS + 1), hipMemcpyHostToDevice, s));
-    MSP_HIP(hipMemsetAsync(P->bin_cursor, 0, sizeof(unsigned long long) * NBINS, s));
+    MSP_HIP(hipMemcpyAsync(P->seg_off_d, P->seg_off, sizeof(int64_t) * NBINS * NBUCKET, hipMemcpyHostToDevice, s));
+    MSP_HIP(hipMemsetAsync(P->seg_cursor, 0, sizeof(unsigned long long) * NBINS * NBUCKET, s));
     UnitArgs ua{};
     ua.op = op;
     ua.flops = P->flops;
     ua.unit_base = P->unit_base;
     ua.bin = P->bin;
-    ua.bin_off = P->bin_off_d;
-    ua.bin_cursor = P->bin_cursor;
+    ua.seg_off = P->seg_off_d;
+    ua.seg_cursor = P->seg_cursor;
     ua.unit_row = P->unit_row;
     ua.unit_tile = P->unit_tile;
     ua.stg_size = P->stg_off;
@@ -349,6 +357,7 @@ msp_status msp_plan_info(const msp_plan* P, msp_plan_info_t* info) {
     info->kind_units[MSP_KIND_HASH] = P->bin_count[BIN_HASH_W] + P->bin_count[BIN_HASH_B];
     info->kind_units[MSP_KIND_MASKIDX] = P->bin_count[BIN_MASKIDX_W] + P->bin_count[BIN_MASKIDX_B];
     info->kind_units[MSP_KIND_INNER] = P->bin_count[BIN_INNER_W];
+    for (int b = 0; b < 8; ++b) info->bin_units[b] = b < NBINS ? P->bin_count[b] : 0;
     return MSP_OK;
 }
 
@@ -408,18 +417,82 @@ msp_status msp_numeric(msp_plan* P, msp_csr_out* C, void* stream) {
     return MSP_OK;
 }
 
-msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* stream) {
-    if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
-    MSP_CHECK(check_out(P, C));
-    hipStream_t s = (hipStream_t)stream;
+// Optional per-stage HIP event timing (msp_execute_profiled).
+struct StageTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    hipEvent_t open_ev = nullptr;
+    int open_stage = -1;
+    msp_status begin(int stage) {
+        if (!on) return MSP_OK;
+        hipEvent_t e;
+        MSP_HIP(hipEventCreate(&e));
+        MSP_HIP(hipEventRecord(e, s));
+        open_ev = e;
+        open_stage = stage;
+        return MSP_OK;
+    }
+    msp_status end() {
+        if (!on) return MSP_OK;
+        hipEvent_t e;
+        MSP_HIP(hipEventCreate(&e));
+        MSP_HIP(hipEventRecord(e, s));
+        marks.push_back({open_stage, {open_ev, e}});
+        return MSP_OK;
+    }
+    msp_status collect(double* ms) {
+        if (!on) return MSP_OK;
+        MSP_HIP(hipStreamSynchronize(s));
+        for (auto& mk : marks) {
+            float t = 0.f;
+            MSP_HIP(hipEventElapsedTime(&t, mk.second.first, mk.second.second));
+            ms[mk.first] += (double)t;
+        }
+        return MSP_OK;
+    }
+    ~StageTimer() {
+        for (auto& mk : marks) {
+            (void)hipEventDestroy(mk.second.first);
+            (void)hipEventDestroy(mk.second.second);
+        }
+    }
+};
+
+static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
     if (P->opt.phase == 2) {
         int64_t nnz = 0;
-        MSP_CHECK(msp_symbolic(P, C->rowptr, &nnz, stream));
+        MSP_CHECK(tm.begin(MSP_STAGE_SYMBOLIC));
+        for (int b = 0; b < NBINS; ++b) {
+            if (!P->bin_count[b]) continue;
+            NumArgs a = num_args(P, b);
+            a.cnt = P->cnt;
+            MSP_HIP(launch_numeric(P->sr, b, MODE_COUNT, a, s));
+        }
+        MSP_CHECK(tm.end());
+        MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
+        MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
+        MSP_CHECK(tm.end());
+        MSP_CHECK(tm.begin(MSP_STAGE_ROWPTR));
+        MSP_HIP(launch_rowptr_from_units(P->op.m, P->unit_base, P->cnt, C->rowptr, s));
+        MSP_CHECK(tm.end());
+        P->symbolic_done = true;
+        MSP_HIP(hipMemcpyAsync(&nnz, C->rowptr + P->op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
         if (C->capacity < nnz) {
             if (nnz_host) *nnz_host = nnz;
             return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "capacity below nnz(C)");
         }
-        MSP_CHECK(msp_numeric(P, C, stream));
+        for (int b = 0; b < NBINS; ++b) {
+            if (!P->bin_count[b]) continue;
+            NumArgs a = num_args(P, b);
+            a.out_off = P->cnt;
+            a.out_col = C->colidx;
+            a.out_val = C->values;
+            MSP_CHECK(tm.begin(b));
+            MSP_HIP(launch_numeric(P->sr, b, MODE_DIRECT, a, s));
+            MSP_CHECK(tm.end());
+        }
         if (nnz_host) *nnz_host = nnz;
         return MSP_OK;
     }
@@ -435,10 +508,16 @@ msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* str
         a.cnt = P->cnt;
         a.out_col = P->stg_col;
         a.out_val = P->stg_val;
+        MSP_CHECK(tm.begin(b));
         MSP_HIP(launch_numeric(P->sr, b, MODE_STAGE, a, s));
+        MSP_CHECK(tm.end());
     }
+    MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
     MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
+    MSP_CHECK(tm.end());
+    MSP_CHECK(tm.begin(MSP_STAGE_ROWPTR));
     MSP_HIP(launch_rowptr_from_units(P->op.m, P->unit_base, P->cnt, C->rowptr, s));
+    MSP_CHECK(tm.end());
     CompactArgs ca{};
     ca.m = P->op.m;
     ca.U = P->U;
@@ -451,11 +530,39 @@ msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* str
     ca.C_rowptr = C->rowptr;
     ca.C_col = C->colidx;
     ca.C_val = C->values;
+    MSP_CHECK(tm.begin(MSP_STAGE_COMPACT));
     MSP_HIP(launch_compact(ca, s));
+    MSP_CHECK(tm.end());
     if (nnz_host) {
         MSP_HIP(hipMemcpyAsync(nnz_host, C->rowptr + P->op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         MSP_HIP(hipStreamSynchronize(s));
     }
+    return MSP_OK;
+}
+
+msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* stream) {
+    if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
+    MSP_CHECK(check_out(P, C));
+    StageTimer none;
+    return execute_impl(P, C, nnz_host, (hipStream_t)stream, none);
+}
+
+msp_status msp_execute_profiled(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, double* stage_ms, void* stream) {
+    if (!P || !stage_ms) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    MSP_CHECK(check_out(P, C));
+    StageTimer tm;
+    tm.on = true;
+    tm.s = (hipStream_t)stream;
+    MSP_CHECK(execute_impl(P, C, nnz_host, tm.s, tm));
+    return tm.collect(stage_ms);
+}
+
+msp_status msp_plan_row_bins(const msp_plan* P, int8_t* bins, void* stream) {
+    if (!P || (!bins && P->op.m > 0)) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (P->op.m == 0) return MSP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    MSP_HIP(hipMemcpyAsync(bins, P->bin, (size_t)P->op.m, hipMemcpyDeviceToHost, s));
+    MSP_HIP(hipStreamSynchronize(s));
     return MSP_OK;
 }
 

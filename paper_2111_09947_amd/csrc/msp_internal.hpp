@@ -11,7 +11,7 @@ namespace mspk {
 
 // Work-unit bins. A unit is a row of C, or one tile of a heavy row: a chunk
 // of the row's mask entries (mask-keyed kinds) or a column window (dense).
-enum Bin : int {
+enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_DENSE_W = 0,    // one wave, dense state over <= DENSE_W_COLS columns
     BIN_DENSE_B = 1,    // one block, dense state over a DENSE_B_COLS column tile
     BIN_HASH_W = 2,     // one wave, hash table of <= HASH_W_CAP mask entries
@@ -25,13 +25,18 @@ enum Bin : int {
 constexpr int DENSE_W_COLS = 512;
 constexpr int DENSE_B_COLS = 4096;
 constexpr int HASH_W_CAP = 256;
-constexpr int HASH_B_CAP = 1024;
+constexpr int HASH_B_CAP = 512;
 constexpr int MASKIDX_W_CAP = 256;
 constexpr int MASKIDX_B_CAP = 4096;
 constexpr int INNER_CAP = 256;
 constexpr int INNER_ACAP = 512;   // A row staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 constexpr int MASKIDX_SMALL = 32; // auto: binary search below this mask size, hash above
+constexpr int64_t BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
+// Units of a bin are ordered by the product count of their row, heaviest
+// first (bucket b holds rows with 4^b <= flops < 4^(b+1)), so that the
+// longest units start first and do not form the tail of the launch.
+constexpr int NBUCKET = 12;
 
 // Device statistics written by the analysis kernel (one sync reads them).
 enum Stat : int {
@@ -41,8 +46,8 @@ enum Stat : int {
     ST_STAGING = 3,
     ST_MNNZ = 4,
     ST_MAXFLOPS = 5,
-    ST_BIN0 = 6,                 // ST_BIN0 + b: units in bin b
-    ST_ERROR = ST_BIN0 + NBINS,  // nonzero: invalid CSR found by validation
+    ST_BIN0 = 6,                 // ST_BIN0 + b * NBUCKET + bucket: units of bin b in a flops bucket
+    ST_ERROR = ST_BIN0 + NBINS * NBUCKET,  // nonzero: invalid CSR found by validation
     ST_COUNT = ST_ERROR + 1
 };
 
@@ -73,8 +78,8 @@ struct UnitArgs {
     const int64_t* flops;
     const int64_t* unit_base;  // [m+1] exclusive scan of tiles
     const int8_t* bin;
-    const int64_t* bin_off;    // [NBINS] start of each bin in bin_units (device)
-    unsigned long long* bin_cursor;  // [NBINS], zeroed
+    const int64_t* seg_off;    // [NBINS * NBUCKET] start of each (bin, bucket) segment in bin_units
+    unsigned long long* seg_cursor;  // [NBINS * NBUCKET], zeroed
     int32_t* unit_row;
     int32_t* unit_tile;
     int64_t* stg_size;         // [U+1] staging entries per unit (scanned later)
@@ -113,6 +118,11 @@ hipError_t launch_validate(const int64_t* rp, const int32_t* ci, int64_t nrows, 
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s);
 hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s);
+__host__ __device__ inline int flops_bucket(int64_t flops) {
+    int b = 0;
+    while (b < NBUCKET - 1 && flops >= (int64_t(4) << (2 * b))) ++b;
+    return b;
+}
 // Exclusive scan of n int64 (in may equal out); writes n + 1 outputs.
 // `partial` needs scan_partial_elems(n) int64.
 int64_t scan_partial_elems(int64_t n);

@@ -155,17 +155,18 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t n, int comp, int f
         else if (mnnz <= HASH_B_CAP) kind = MSP_KIND_HASH;
         else kind = MSP_KIND_MASKIDX;
     }
+    const bool heavy = flops > BLOCK_FLOPS;
     switch (kind) {
     case MSP_KIND_DENSE:
-        if (n <= DENSE_W_COLS) { bin = BIN_DENSE_W; tiles = 1; }
+        if (n <= DENSE_W_COLS && !heavy) { bin = BIN_DENSE_W; tiles = 1; }
         else { bin = BIN_DENSE_B; tiles = cdiv(n, DENSE_B_COLS); }
         break;
     case MSP_KIND_HASH:
-        if (mnnz <= HASH_W_CAP) { bin = BIN_HASH_W; tiles = 1; }
+        if (mnnz <= HASH_W_CAP && !heavy) { bin = BIN_HASH_W; tiles = 1; }
         else { bin = BIN_HASH_B; tiles = cdiv(mnnz, HASH_B_CAP); }
         break;
     case MSP_KIND_MASKIDX:
-        if (mnnz <= MASKIDX_W_CAP) { bin = BIN_MASKIDX_W; tiles = 1; }
+        if (mnnz <= MASKIDX_W_CAP && !heavy) { bin = BIN_MASKIDX_W; tiles = 1; }
         else { bin = BIN_MASKIDX_B; tiles = cdiv(mnnz, MASKIDX_B_CAP); }
         break;
     default:
@@ -183,7 +184,7 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
         adm = o.complement ? o.n - mnnz : mnnz;
         break;
     case BIN_DENSE_B: {
-        const int64_t c0 = t * DENSE_B_COLS, c1 = min(c0 + DENSE_B_COLS, o.n);
+        const int64_t c0 = t * DENSE_B_COLS, c1 = min(c0 + (int64_t)DENSE_B_COLS, o.n);
         int64_t mt = mnnz;
         if (tiles > 1) {
             const int64_t p0 = lower_bound_g(o.Mci, o.Mrp[i], o.Mrp[i + 1], c0);
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
         if (ub > 0) {
             classify(mnnz, flops, o.n, o.complement, a.force_kind, a.inner_ratio, icost, bin, tiles);
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
-            atomicAdd(&sst[ST_BIN0 + bin], (unsigned long long)tiles);
+            atomicAdd(&sst[ST_BIN0 + bin * NBUCKET + flops_bucket(flops)], (unsigned long long)tiles);
         }
         a.flops[i] = flops;
         a.tiles[i] = tiles;
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool has = i < m;
     int64_t base = 0, tiles = 0, mnnz = 0, flops = 0;
-    int bin = -1;
+    int bin = -1, seg = -1;
     if (has) {
         base = a.unit_base[i];
         tiles = a.unit_base[i + 1] - base;
@@ -275,26 +276,28 @@ __global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
             a.unit_tile[base + t] = (int32_t)t;
             a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
         }
+        if (tiles > 0) seg = bin * NBUCKET + flops_bucket(flops);
     }
-    // single-unit rows: one atomic per distinct bin per wave; rank inside the wave keeps row order
+    // single-unit rows: one atomic per distinct segment per wave; the rank
+    // inside the wave keeps row order within a segment
     bool pending = has && tiles == 1;
     while (true) {
         const uint64_t pm = __ballot(pending);
         if (pm == 0) break;
         const int leader = __builtin_ctzll(pm);
-        const int b = __shfl(bin, leader, WAVE);
-        const uint64_t same = __ballot(pending && bin == b);
+        const int b = __shfl(seg, leader, WAVE);
+        const uint64_t same = __ballot(pending && seg == b);
         unsigned long long start = 0;
-        if (lane() == leader) start = atomicAdd(&a.bin_cursor[b], (unsigned long long)__popcll(same));
+        if (lane() == leader) start = atomicAdd(&a.seg_cursor[b], (unsigned long long)__popcll(same));
         start = __shfl(start, leader, WAVE);
-        if (pending && bin == b) {
-            a.bin_units[a.bin_off[b] + (int64_t)start + rank_below(same)] = (int32_t)base;
+        if (pending && seg == b) {
+            a.bin_units[a.seg_off[b] + (int64_t)start + rank_below(same)] = (int32_t)base;
             pending = false;
         }
     }
     if (has && tiles > 1) {
-        const unsigned long long start = atomicAdd(&a.bin_cursor[bin], (unsigned long long)tiles);
-        for (int64_t t = 0; t < tiles; ++t) a.bin_units[a.bin_off[bin] + (int64_t)start + t] = (int32_t)(base + t);
+        const unsigned long long start = atomicAdd(&a.seg_cursor[seg], (unsigned long long)tiles);
+        for (int64_t t = 0; t < tiles; ++t) a.bin_units[a.seg_off[seg] + (int64_t)start + t] = (int32_t)(base + t);
     }
 }
 
@@ -376,31 +379,45 @@ hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* part
 
 // ------------------------------------------------------- product streaming
 
+// Products per lane per step of the product stream: each lane keeps this
+// many independent B loads in flight, a wave covers 64 * STREAM_U products.
+#ifndef MSP_STREAM_U
+#define MSP_STREAM_U 8
+#endif
+constexpr int STREAM_U = MSP_STREAM_U;
+
 // Per-wave LDS for one batch of up to 64 A entries: for the s-th stanza with
 // a nonzero length (in A order), its start in the flattened product
-// sequence, the shift from flattened position to B position, and A's value.
+// sequence, the shift from flattened position to B position, and A's value;
+// plus the start bitmap of the current window.
 template <class T>
 struct StanzaLds {
     int64_t start[WAVE];
     int64_t delta[WAVE];
     typename T::in_t a[WAVE];
-    unsigned long long S;
+    unsigned long long S[STREAM_U];
 };
 
 // Streams every product (k, j) of row i: for each stored A(i,k) and each
 // stored B(k,j) with lo <= j <= hi (when `window`), calls f(j, s, q) where
 // q is the position of B(k,j) and s indexes st.a for A(i,k). Wave `wv` of
-// `nw` waves processes the product blocks wv, wv + nw, ... of each batch.
+// `nw` waves processes the windows wv, wv + nw, ... of 64 * STREAM_U
+// products of each batch.
 //
-// Lane-to-stanza mapping of a block of 64 consecutive products: every
-// stanza that starts inside the block sets bit (start - block base) of a
-// 64-bit word; a lane's stanza is then
-//   (#stanzas starting before the block) + popcount(word & bits <= lane) - 1.
+// Lane-to-stanza mapping of a window: every stanza that starts inside the
+// window sets bit (start - window base) of a 64 * STREAM_U-bit map; the
+// stanza of the product at offset 64u + lane is then
+//   (#stanzas starting before the window)
+//   + popcount(map bits 0 .. 64u + lane) - 1.
+// The STREAM_U loads of a lane are issued back to back before any of them is
+// consumed, so a wave keeps STREAM_U stanza reads outstanding.
 template <class T, class F>
 __device__ __forceinline__ void stream_products(const Operands& o, int64_t i, bool window, int32_t lo, int32_t hi,
                                                 int wv, int nw, StanzaLds<T>& st, F&& f) {
     const int ln = lane();
+    const uint64_t le_mask = (2ull << ln) - 1ull;  // lanes 0..ln (wraps to all ones for lane 63)
     const int64_t pa0 = o.Arp[i], pa1 = o.Arp[i + 1];
+    constexpr int64_t WIN = (int64_t)WAVE * STREAM_U;
     for (int64_t pb = pa0; pb < pa1; pb += WAVE) {
         const int64_t p = pb + ln;
         int64_t b0 = 0, b1 = 0;
@@ -429,20 +446,42 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t i, bo
         }
         wave_lds_sync();
         const int64_t my_start = ln < nz ? st.start[ln] : INT64_MAX;
-        for (int64_t base = (int64_t)wv * WAVE; base < total; base += (int64_t)nw * WAVE) {
+        for (int64_t base = (int64_t)wv * WIN; base < total; base += (int64_t)nw * WIN) {
             const int before = __popcll(__ballot(my_start < base));
             const int64_t rel = my_start - base;
-            if (rel >= 0 && rel < WAVE) atomicOr(&st.S, 1ull << rel);
+            if (rel >= 0 && rel < WIN) atomicOr(&st.S[rel >> 6], 1ull << (rel & 63));
             wave_lds_sync();
-            const unsigned long long S = st.S;
+            unsigned long long Sw[STREAM_U];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) Sw[u] = st.S[u];
             wave_lds_sync();
-            if (ln == 0) st.S = 0ull;
-            const int s = before + __popcll(S & ((2ull << ln) - 1ull)) - 1;
-            const int64_t pos = base + ln;
-            if (pos < total) {
-                const int64_t q = st.delta[s] + pos;
-                f(o.Bci[q], s, q);
+            if (ln < STREAM_U) st.S[ln] = 0ull;
+            // all loads unconditional: an inactive slot reads stanza 0's offset and B position 0,
+            // which exists whenever the window is non-empty
+            int sidx[STREAM_U];
+            int64_t q[STREAM_U];
+            int32_t j[STREAM_U];
+            bool act[STREAM_U];
+            int cum = before;
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                const int sv = cum + __popcll(Sw[u] & le_mask) - 1;
+                cum += __popcll(Sw[u]);
+                sidx[u] = min(max(sv, 0), WAVE - 1);
             }
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) q[u] = st.delta[sidx[u]];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                const int64_t pos = base + (int64_t)(u * WAVE + ln);
+                act[u] = pos < total;
+                q[u] = act[u] ? q[u] + pos : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) j[u] = o.Bci[q[u]];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u)
+                if (act[u]) f(j[u], sidx[u], q[u]);
             wave_lds_sync();
         }
     }
@@ -509,7 +548,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_dense(NumArgs g) {
     }
     if (!COUNT) for (int x = tid; x < W; x += NW * WAVE) vals[x] = T::identity();
     if (FLAGS) for (int x = tid; x < W; x += NW * WAVE) flags[x] = 0;
-    if (lane() == 0) st[wv].S = 0ull;
+    if (lane() < STREAM_U) st[wv].S[lane()] = 0ull;
     __syncthreads();
     int64_t m0 = o.Mrp[i], m1 = o.Mrp[i + 1];
     if (tiled) {
@@ -569,12 +608,14 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t j, int tbits) {
     return ((uint32_t)j * 0x9E3779B1u) >> (32 - tbits);
 }
 
-__device__ __forceinline__ int hash_find(const unsigned long long* table, uint32_t tmask, int tbits, int32_t j) {
+// Linear probing over a key table (-1 = empty) holding at most 1/4 of its
+// slots; the mask rank of a key sits in a parallel table.
+__device__ __forceinline__ int hash_find(const int32_t* tkey, const uint16_t* trank, uint32_t tmask, int tbits,
+                                         int32_t j) {
     uint32_t h = hash_slot(j, tbits);
     while (true) {
-        const unsigned long long e = table[h];
-        const int32_t k = (int32_t)(uint32_t)e;
-        if (k == j) return (int)(e >> 32);
+        const int32_t k = tkey[h];
+        if (k == j) return (int)trank[h];
         if (k == -1) return -1;
         h = (h + 1) & tmask;
     }
@@ -586,9 +627,10 @@ __global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
     using acc_t = typename T::acc_t;
     constexpr bool COUNT = MODE == MODE_COUNT;
     constexpr bool FLAGS = COUNT || T::sep_flag;
-    constexpr int TS = HASHED ? 2 * CAP : 1;
+    constexpr int TS = HASHED ? 4 * CAP : 1;
     __shared__ int32_t keys[CAP];
-    __shared__ unsigned long long table[TS];
+    __shared__ int32_t tkey[TS];
+    __shared__ uint16_t trank[TS];
     __shared__ acc_t vals[COUNT ? 1 : CAP];
     __shared__ uint8_t flags[FLAGS ? CAP : 1];
     __shared__ StanzaLds<T> st[NW];
@@ -607,19 +649,19 @@ __global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
         if (!COUNT) vals[x] = T::identity();
         if (FLAGS) flags[x] = 0;
     }
-    int tbits = 1;
-    while ((1 << tbits) < 2 * cnt) ++tbits;
+    int tbits = 2;
+    while ((1 << tbits) < 4 * cnt) ++tbits;
     const uint32_t tmask = (1u << tbits) - 1u;
     if (HASHED)
-        for (int x = tid; x <= (int)tmask; x += NW * WAVE) table[x] = ~0ull;
-    if (lane() == 0) st[wv].S = 0ull;
+        for (int x = tid; x <= (int)tmask; x += NW * WAVE) tkey[x] = -1;
+    if (lane() < STREAM_U) st[wv].S[lane()] = 0ull;
     __syncthreads();
     if (HASHED) {
         for (int x = tid; x < cnt; x += NW * WAVE) {
             const int32_t key = keys[x];
-            const unsigned long long e = ((unsigned long long)(uint32_t)x << 32) | (uint32_t)key;
             uint32_t h = hash_slot(key, tbits);
-            while (atomicCAS(&table[h], ~0ull, e) != ~0ull) h = (h + 1) & tmask;
+            while (atomicCAS(&tkey[h], -1, key) != -1) h = (h + 1) & tmask;
+            trank[h] = (uint16_t)x;
         }
         __syncthreads();
     }
@@ -627,7 +669,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
     const int top = 1 << (31 - __clz(cnt));
     StanzaLds<T>& S = st[wv];
     stream_products<T>(o, i, tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q) {
-        const int r = HASHED ? hash_find(table, tmask, tbits, j) : rank_search(keys, cnt, top, j);
+        const int r = HASHED ? hash_find(tkey, trank, tmask, tbits, j) : rank_search(keys, cnt, top, j);
         if (r >= 0) {
             if (FLAGS) flags[r] = 1;
             if (!COUNT) {
