@@ -127,6 +127,27 @@ struct msp_plan {
     msp_status alloc_n(T** p, int64_t n) {
         return alloc(reinterpret_cast<void**>(p), (size_t)(n > 0 ? n : 1) * sizeof(T));
     }
+    // Carves several arrays out of one allocation (256-byte aligned pieces).
+    struct Carve {
+        std::vector<std::pair<void**, size_t>> parts;
+        template <class T>
+        void add(T** p, int64_t n) {
+            parts.push_back({reinterpret_cast<void**>(p), (size_t)(n > 0 ? n : 1) * sizeof(T)});
+        }
+        void add_bytes(void** p, size_t bytes) { parts.push_back({p, bytes > 0 ? bytes : 1}); }
+    };
+    msp_status alloc_carve(Carve& c) {
+        size_t total = 0;
+        for (auto& pt : c.parts) total += (pt.second + 255) & ~(size_t)255;
+        char* base = nullptr;
+        MSP_CHECK(alloc(reinterpret_cast<void**>(&base), total));
+        size_t off = 0;
+        for (auto& pt : c.parts) {
+            *pt.first = base + off;
+            off += (pt.second + 255) & ~(size_t)255;
+        }
+        return MSP_OK;
+    }
     void release() {
         for (void* p : allocs) {
             if (pooled) (void)hipFreeAsync(p, stream);
@@ -231,7 +252,16 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
     const int64_t m = op.m;
     hipStream_t s = stream;
 
-    MSP_CHECK(P->alloc_n(&P->stats_d, ST_COUNT));
+    // workspace sized by the operand shapes
+    {
+        msp_plan::Carve c;
+        c.add(&P->stats_d, ST_COUNT);
+        c.add(&P->flops, m);
+        c.add(&P->unit_base, m + 1);
+        c.add(&P->bin, m);
+        c.add(&P->scan_partial, scan_partial_elems(m + 1));
+        MSP_CHECK(P->alloc_carve(c));
+    }
     MSP_HIP(hipMemsetAsync(P->stats_d, 0, sizeof(unsigned long long) * ST_COUNT, s));
     if (o.validate) {
         unsigned long long* err = P->stats_d + ST_ERROR;
@@ -257,10 +287,6 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
         MSP_CHECK(build_transpose(P, o.force_kind == MSP_KIND_INNER));
     }
 
-    MSP_CHECK(P->alloc_n(&P->flops, m));
-    MSP_CHECK(P->alloc_n(&P->unit_base, m + 1));
-    MSP_CHECK(P->alloc_n(&P->bin, m));
-    MSP_CHECK(P->alloc_n(&P->scan_partial, scan_partial_elems(m + 1)));
     AnalysisArgs aa{};
     aa.op = op;
     aa.force_kind = o.force_kind;
@@ -294,17 +320,24 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
     if (P->bin_count[BIN_INNER_W] > 0 && !o.b_transpose) MSP_CHECK(build_transpose(P, true));
 
     const int64_t U = P->U;
-    MSP_CHECK(P->alloc_n(&P->seg_off_d, NBINS * NBUCKET));
-    MSP_CHECK(P->alloc_n(&P->seg_cursor, NBINS * NBUCKET));
-    MSP_CHECK(P->alloc_n(&P->unit_row, U));
-    MSP_CHECK(P->alloc_n(&P->unit_tile, U));
-    MSP_CHECK(P->alloc_n(&P->stg_off, U + 1));
-    MSP_CHECK(P->alloc_n(&P->cnt, U + 1));
-    MSP_CHECK(P->alloc_n(&P->bin_units, U));
-    if (U + 1 > m + 1) {
+    // workspace sized by the units (and the one-phase staging)
+    {
+        msp_plan::Carve c;
+        c.add(&P->seg_off_d, NBINS * NBUCKET);
+        c.add(&P->seg_cursor, NBINS * NBUCKET);
+        c.add(&P->unit_row, U);
+        c.add(&P->unit_tile, U);
+        c.add(&P->stg_off, U + 1);
+        c.add(&P->cnt, U + 1);
+        c.add(&P->bin_units, U);
         int64_t* part = nullptr;
-        MSP_CHECK(P->alloc_n(&part, scan_partial_elems(U + 1)));
-        P->scan_partial = part;
+        if (U + 1 > m + 1) c.add(&part, scan_partial_elems(U + 1));
+        if (want_staging && o.phase == 1) {
+            c.add(&P->stg_col, P->S);
+            c.add_bytes(&P->stg_val, (size_t)(P->S > 0 ? P->S : 1) * out_bytes(semiring));
+        }
+        MSP_CHECK(P->alloc_carve(c));
+        if (part) P->scan_partial = part;
     }
     MSP_HIP(hipMemcpyAsync(P->seg_off_d, P->seg_off, sizeof(int64_t) * NBINS * NBUCKET, hipMemcpyHostToDevice, s));
     MSP_HIP(hipMemsetAsync(P->seg_cursor, 0, sizeof(unsigned long long) * NBINS * NBUCKET, s));
@@ -320,12 +353,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
     ua.stg_size = P->stg_off;
     ua.bin_units = P->bin_units;
     MSP_HIP(launch_units(ua, m, s));
-    if (want_staging && o.phase == 1) {
-        MSP_HIP(launch_scan(P->stg_off, P->stg_off, U, P->scan_partial, s));
-        const int ob = out_bytes(semiring);
-        MSP_CHECK(P->alloc_n(&P->stg_col, P->S));
-        MSP_CHECK(P->alloc(&P->stg_val, (size_t)(P->S > 0 ? P->S : 1) * ob));
-    }
+    if (want_staging && o.phase == 1) MSP_HIP(launch_scan(P->stg_off, P->stg_off, U, P->scan_partial, s));
     return MSP_OK;
 }
 

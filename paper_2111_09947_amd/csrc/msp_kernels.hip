@@ -112,10 +112,18 @@ __device__ int64_t csr_rowsum(const int64_t* __restrict__ rp, const int32_t* __r
     int64_t sum = 0;
     for (int64_t cs = p0; cs < p1; cs += ANA_CHUNK) {
         const int64_t ce = min(cs + (int64_t)ANA_CHUNK, p1);
-        for (int e = tid; e < ANA_CHUNK; e += ANA_T) {
-            const int64_t p = cs + e;
-            lds[ana_idx(e)] = p < ce ? gather(ci[p]) : 0;
+        // 8 column loads, then 8 independent gathers, in flight together
+        int32_t col[ANA_CHUNK / ANA_T];
+#pragma unroll
+        for (int x = 0; x < ANA_CHUNK / ANA_T; ++x) {
+            const int64_t p = cs + tid + x * ANA_T;
+            col[x] = p < ce ? ci[p] : -1;
         }
+        int64_t gv[ANA_CHUNK / ANA_T];
+#pragma unroll
+        for (int x = 0; x < ANA_CHUNK / ANA_T; ++x) gv[x] = col[x] >= 0 ? gather(col[x]) : 0;
+#pragma unroll
+        for (int x = 0; x < ANA_CHUNK / ANA_T; ++x) lds[ana_idx(tid + x * ANA_T)] = gv[x];
         __syncthreads();
         int64_t loc[8];
         int64_t run = 0;
@@ -208,7 +216,7 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
     const Operands& o = a.op;
     const int64_t r0 = (int64_t)blockIdx.x * ANA_T;
     const int64_t r1 = min(r0 + ANA_T, o.m);
-    if (threadIdx.x < ST_COUNT) sst[threadIdx.x] = 0;
+    for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) sst[x] = 0;
     const int64_t* Brp = o.Brp;
     const int64_t flops = csr_rowsum(o.Arp, o.Aci, r0, r1, [=](int32_t k) { return Brp[k + 1] - Brp[k]; }, lds, tmp);
     int64_t icost = 0;
@@ -220,33 +228,54 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
     }
     __syncthreads();
     const int64_t i = r0 + threadIdx.x;
+    int64_t ub = 0, tiles = 0, stg = 0, mnnz = 0;
+    int seg = -1;
     if (i < r1) {
-        const int64_t mnnz = o.Mrp[i + 1] - o.Mrp[i];
+        mnnz = o.Mrp[i + 1] - o.Mrp[i];
         const int64_t adm = o.complement ? o.n - mnnz : mnnz;
-        const int64_t ub = min(adm, flops);
+        ub = min(adm, flops);
         int bin = -1;
-        int64_t tiles = 0, stg = 0;
         if (ub > 0) {
             classify(mnnz, flops, o.n, o.complement, a.force_kind, a.inner_ratio, icost, bin, tiles);
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
-            atomicAdd(&sst[ST_BIN0 + bin * NBUCKET + flops_bucket(flops)], (unsigned long long)tiles);
+            seg = bin * NBUCKET + flops_bucket(flops);
         }
         a.flops[i] = flops;
         a.tiles[i] = tiles;
         a.bin[i] = (int8_t)bin;
-        atomicAdd(&sst[ST_FLOPS], (unsigned long long)flops);
-        atomicAdd(&sst[ST_UB], (unsigned long long)ub);
-        atomicAdd(&sst[ST_UNITS], (unsigned long long)tiles);
-        atomicAdd(&sst[ST_STAGING], (unsigned long long)stg);
-        atomicAdd(&sst[ST_MNNZ], (unsigned long long)mnnz);
-        atomicMax(&sst[ST_MAXFLOPS], (unsigned long long)flops);
+    }
+    // per-segment unit counts: one LDS atomic per distinct segment per wave
+    bool pending = seg >= 0;
+    while (true) {
+        const uint64_t pm = __ballot(pending);
+        if (pm == 0) break;
+        const int leader = __builtin_ctzll(pm);
+        const int sg = __shfl(seg, leader, WAVE);
+        const bool mine = pending && seg == sg;
+        const int64_t cnt = wave_sum(mine ? tiles : 0);
+        if (lane() == leader) atomicAdd(&sst[ST_BIN0 + sg], (unsigned long long)cnt);
+        pending = pending && !mine;
+    }
+    // sums: wave reductions, then one LDS atomic per wave
+    const int64_t v_flops = wave_sum(i < r1 ? flops : 0);
+    const int64_t v_ub = wave_sum(ub), v_tiles = wave_sum(tiles), v_stg = wave_sum(stg), v_mnnz = wave_sum(mnnz);
+    int64_t v_max = i < r1 ? flops : 0;
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v_max = max(v_max, (int64_t)__shfl_xor(v_max, d, WAVE));
+    if (lane() == 0) {
+        atomicAdd(&sst[ST_FLOPS], (unsigned long long)v_flops);
+        atomicAdd(&sst[ST_UB], (unsigned long long)v_ub);
+        atomicAdd(&sst[ST_UNITS], (unsigned long long)v_tiles);
+        atomicAdd(&sst[ST_STAGING], (unsigned long long)v_stg);
+        atomicAdd(&sst[ST_MNNZ], (unsigned long long)v_mnnz);
+        atomicMax(&sst[ST_MAXFLOPS], (unsigned long long)v_max);
     }
     __syncthreads();
-    if (threadIdx.x < ST_COUNT) {
-        const unsigned long long v = sst[threadIdx.x];
+    for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) {
+        const unsigned long long v = sst[x];
         if (v) {
-            if (threadIdx.x == ST_MAXFLOPS) atomicMax(&a.stats[threadIdx.x], v);
-            else atomicAdd(&a.stats[threadIdx.x], v);
+            if (x == ST_MAXFLOPS) atomicMax(&a.stats[x], v);
+            else atomicAdd(&a.stats[x], v);
         }
     }
 }
@@ -260,44 +289,39 @@ hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
 // --------------------------------------------------------------------- units
 
 __global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
+    __shared__ unsigned int hist[NBINS * NBUCKET];
+    __shared__ unsigned long long seg_base[NBINS * NBUCKET];
     const Operands& o = a.op;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool has = i < m;
-    int64_t base = 0, tiles = 0, mnnz = 0, flops = 0;
-    int bin = -1, seg = -1;
+    for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x) hist[x] = 0;
+    __syncthreads();
+    int64_t base = 0, tiles = 0;
+    int seg = -1;
+    unsigned int rank = 0;
     if (has) {
         base = a.unit_base[i];
         tiles = a.unit_base[i + 1] - base;
-        bin = a.bin[i];
-        mnnz = o.Mrp[i + 1] - o.Mrp[i];
-        flops = a.flops[i];
-        for (int64_t t = 0; t < tiles; ++t) {
-            a.unit_row[base + t] = (int32_t)i;
-            a.unit_tile[base + t] = (int32_t)t;
-            a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
-        }
-        if (tiles > 0) seg = bin * NBUCKET + flops_bucket(flops);
-    }
-    // single-unit rows: one atomic per distinct segment per wave; the rank
-    // inside the wave keeps row order within a segment
-    bool pending = has && tiles == 1;
-    while (true) {
-        const uint64_t pm = __ballot(pending);
-        if (pm == 0) break;
-        const int leader = __builtin_ctzll(pm);
-        const int b = __shfl(seg, leader, WAVE);
-        const uint64_t same = __ballot(pending && seg == b);
-        unsigned long long start = 0;
-        if (lane() == leader) start = atomicAdd(&a.seg_cursor[b], (unsigned long long)__popcll(same));
-        start = __shfl(start, leader, WAVE);
-        if (pending && seg == b) {
-            a.bin_units[a.seg_off[b] + (int64_t)start + rank_below(same)] = (int32_t)base;
-            pending = false;
+        if (tiles > 0) {
+            const int bin = a.bin[i];
+            const int64_t mnnz = o.Mrp[i + 1] - o.Mrp[i];
+            const int64_t flops = a.flops[i];
+            for (int64_t t = 0; t < tiles; ++t) {
+                a.unit_row[base + t] = (int32_t)i;
+                a.unit_tile[base + t] = (int32_t)t;
+                a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
+            }
+            seg = bin * NBUCKET + flops_bucket(flops);
+            rank = atomicAdd(&hist[seg], (unsigned int)tiles);
         }
     }
-    if (has && tiles > 1) {
-        const unsigned long long start = atomicAdd(&a.seg_cursor[seg], (unsigned long long)tiles);
-        for (int64_t t = 0; t < tiles; ++t) a.bin_units[a.seg_off[seg] + (int64_t)start + t] = (int32_t)(base + t);
+    __syncthreads();
+    for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x)
+        if (hist[x]) seg_base[x] = atomicAdd(&a.seg_cursor[x], (unsigned long long)hist[x]);
+    __syncthreads();
+    if (seg >= 0) {
+        const int64_t pos = a.seg_off[seg] + (int64_t)seg_base[seg] + rank;
+        for (int64_t t = 0; t < tiles; ++t) a.bin_units[pos + t] = (int32_t)(base + t);
     }
 }
 
@@ -399,8 +423,9 @@ struct StanzaLds {
 };
 
 // Streams every product (k, j) of row i: for each stored A(i,k) and each
-// stored B(k,j) with lo <= j <= hi (when `window`), calls f(j, s, q) where
-// q is the position of B(k,j) and s indexes st.a for A(i,k). Wave `wv` of
+// stored B(k,j) with lo <= j <= hi (when `window`), calls f(j, s, q, true)
+// where q is the position of B(k,j) and s indexes st.a for A(i,k); slots
+// past the last product call f(j, s, q, false) with meaningless j, s, q. Wave `wv` of
 // `nw` waves processes the windows wv, wv + nw, ... of 64 * STREAM_U
 // products of each batch.
 //
@@ -415,7 +440,6 @@ template <class T, class F>
 __device__ __forceinline__ void stream_products(const Operands& o, int64_t i, bool window, int32_t lo, int32_t hi,
                                                 int wv, int nw, StanzaLds<T>& st, F&& f) {
     const int ln = lane();
-    const uint64_t le_mask = (2ull << ln) - 1ull;  // lanes 0..ln (wraps to all ones for lane 63)
     const int64_t pa0 = o.Arp[i], pa1 = o.Arp[i + 1];
     constexpr int64_t WIN = (int64_t)WAVE * STREAM_U;
     for (int64_t pb = pa0; pb < pa1; pb += WAVE) {
@@ -451,54 +475,58 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t i, bo
             const int64_t rel = my_start - base;
             if (rel >= 0 && rel < WIN) atomicOr(&st.S[rel >> 6], 1ull << (rel & 63));
             wave_lds_sync();
-            unsigned long long Sw[STREAM_U];
+            // the window's start bitmap is uniform: move it to scalar registers
+            uint64_t Sw[STREAM_U];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) Sw[u] = st.S[u];
+            for (int u = 0; u < STREAM_U; ++u) {
+                const unsigned long long v = st.S[u];
+                // readfirstlane returns int: go through uint32_t so that bit 31 does not sign-extend
+                const uint32_t vh = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+                const uint32_t vl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+                Sw[u] = ((uint64_t)vh << 32) | (uint64_t)vl;
+            }
             wave_lds_sync();
             if (ln < STREAM_U) st.S[ln] = 0ull;
-            // all loads unconditional: an inactive slot reads stanza 0's offset and B position 0,
-            // which exists whenever the window is non-empty
+            const int lim = (int)min(total - base, WIN);  // products left in this window
+            // stanza of the product at window offset 64u + lane:
+            //   (#stanzas starting before it) + (#starts at offsets <= 64u + lane) - 1
             int sidx[STREAM_U];
-            int64_t q[STREAM_U];
-            int32_t j[STREAM_U];
-            bool act[STREAM_U];
-            int cum = before;
+            int cum = before - 1;
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) {
-                const int sv = cum + __popcll(Sw[u] & le_mask) - 1;
+                sidx[u] = min(max(cum + (int)(Sw[u] & 1ull) + rank_below(Sw[u] >> 1), 0), WAVE - 1);
                 cum += __popcll(Sw[u]);
-                sidx[u] = min(max(sv, 0), WAVE - 1);
             }
+            int64_t q[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) q[u] = st.delta[sidx[u]];
+            // an inactive slot (past the window's products) reads B position 0, which exists
+            // whenever the window is non-empty, and is not passed on
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) {
-                const int64_t pos = base + (int64_t)(u * WAVE + ln);
-                act[u] = pos < total;
-                q[u] = act[u] ? q[u] + pos : 0;
-            }
+            for (int u = 0; u < STREAM_U; ++u) q[u] = (u * WAVE + ln < lim) ? q[u] + base + (u * WAVE + ln) : 0;
+            int32_t j[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) j[u] = o.Bci[q[u]];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u)
-                if (act[u]) f(j[u], sidx[u], q[u]);
+            for (int u = 0; u < STREAM_U; ++u) f(j[u], sidx[u], q[u], u * WAVE + ln < lim);
             wave_lds_sync();
         }
     }
 }
 
-// Ordered compaction over [0, len) for a block of NW waves: calls
-// write(idx, position) for every idx with keep(idx), positions in idx order.
+// Ordered compaction over [0, len) for the NW waves of one unit (unit-local
+// thread index ut): calls write(idx, position) for every idx with keep(idx),
+// positions in idx order.
 template <int NW, class K, class W>
-__device__ __forceinline__ int64_t ordered_emit(int len, int64_t* tmp, K keep, W write) {
+__device__ __forceinline__ int64_t ordered_emit(int len, int64_t* tmp, int ut, K keep, W write) {
     int64_t running = 0;
     for (int base = 0; base < len; base += NW * WAVE) {
-        const int idx = base + (int)threadIdx.x;
+        const int idx = base + ut;
         const bool kp = idx < len && keep(idx);
         const uint64_t bm = __ballot(kp);
         int64_t before = 0, total = __popcll(bm);
         if (NW > 1) {
-            const int w = threadIdx.x / WAVE;
+            const int w = ut / WAVE;
             if (lane() == 0) tmp[w] = total;
             __syncthreads();
             total = 0;
@@ -516,55 +544,72 @@ __device__ __forceinline__ int64_t ordered_emit(int len, int64_t* tmp, K keep, W
     return running;
 }
 
+// Barrier among the waves that work on one unit: the whole block when a unit
+// spans NW > 1 waves, only the wave itself otherwise (several independent
+// one-wave units may share a block).
+template <int NW>
+__device__ __forceinline__ void unit_sync() {
+    if (NW > 1) __syncthreads();
+    else wave_lds_sync();
+}
+
 // ------------------------------------------------- dense-state accumulator
 // A column tile [c0, c0 + wt) of row i held densely in LDS: admitted bitmap
 // (normal: set from the mask row; complemented: all set, then cleared from
 // the mask row), values and (where the value cannot tell) inserted flags.
 // Emission scans the tile in column order, so rows come out sorted for both
 // mask modes.
-template <int SR, int MODE, int NW, int W>
-__global__ __launch_bounds__(NW * WAVE) void k_dense(NumArgs g) {
+template <int SR, int MODE, int NW, int W, int WPB>
+__global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
+    static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     constexpr bool COUNT = MODE == MODE_COUNT;
     constexpr bool FLAGS = COUNT || T::sep_flag;
     constexpr int NWORDS = W / 32;
-    __shared__ uint32_t allowed[NWORDS];
-    __shared__ acc_t vals[COUNT ? 1 : W];
-    __shared__ uint8_t flags[FLAGS ? W : 1];
-    __shared__ StanzaLds<T> st[NW];
+    constexpr int UT = NW * WAVE;  // threads per unit
+    __shared__ uint32_t allowed_[WPB][NWORDS];
+    __shared__ acc_t vals_[WPB][COUNT ? 1 : W];
+    __shared__ uint8_t flags_[WPB][FLAGS ? W : 1];
+    __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
     const Operands& o = g.op;
-    const int tid = threadIdx.x, wv = tid / WAVE;
-    const int u = g.units[blockIdx.x];
+    const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
+    const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
+    if (uix >= g.nunits) return;  // only one-wave units can leave early (WPB > 1 implies NW == 1)
+    uint32_t* allowed = allowed_[gi];
+    acc_t* vals = vals_[gi];
+    uint8_t* flags = flags_[gi];
+    const int u = g.units[uix];
     const int64_t i = g.unit_row[u];
     const int64_t c0 = (int64_t)g.unit_tile[u] * W;
     const int wt = (int)min((int64_t)W, o.n - c0);
     const bool tiled = o.n > W;
-    for (int x = tid; x < NWORDS; x += NW * WAVE) {
+    for (int x = ut; x < NWORDS; x += UT) {
         const int lo = x * 32;
         const uint32_t valid = (lo + 32 <= wt) ? 0xFFFFFFFFu : (lo >= wt ? 0u : ((1u << (wt - lo)) - 1u));
         allowed[x] = o.complement ? valid : 0u;
     }
-    if (!COUNT) for (int x = tid; x < W; x += NW * WAVE) vals[x] = T::identity();
-    if (FLAGS) for (int x = tid; x < W; x += NW * WAVE) flags[x] = 0;
-    if (lane() < STREAM_U) st[wv].S[lane()] = 0ull;
-    __syncthreads();
+    if (!COUNT) for (int x = ut; x < W; x += UT) vals[x] = T::identity();
+    if (FLAGS) for (int x = ut; x < W; x += UT) flags[x] = 0;
+    if (lane() < STREAM_U) st[wave].S[lane()] = 0ull;
+    unit_sync<NW>();
     int64_t m0 = o.Mrp[i], m1 = o.Mrp[i + 1];
     if (tiled) {
         m0 = lower_bound_g(o.Mci, m0, m1, c0);
         m1 = lower_bound_g(o.Mci, m0, m1, c0 + wt);
     }
-    for (int64_t p = m0 + tid; p < m1; p += NW * WAVE) {
+    for (int64_t p = m0 + ut; p < m1; p += UT) {
         const int c = o.Mci[p] - (int)c0;
         const uint32_t bit = 1u << (c & 31);
         if (o.complement) atomicAnd(&allowed[c >> 5], ~bit);
         else atomicOr(&allowed[c >> 5], bit);
     }
-    __syncthreads();
-    StanzaLds<T>& S = st[wv];
+    unit_sync<NW>();
+    StanzaLds<T>& S = st[wave];
     stream_products<T>(o, i, tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
-                       [&](int32_t j, int s, int64_t q) {
+                       [&](int32_t j, int s, int64_t q, bool act) {
+                           if (!act) return;
                            const int c = j - (int)c0;
                            if (allowed[c >> 5] & (1u << (c & 31))) {
                                if (FLAGS) flags[c] = 1;
@@ -574,11 +619,11 @@ __global__ __launch_bounds__(NW * WAVE) void k_dense(NumArgs g) {
                                }
                            }
                        });
-    __syncthreads();
+    unit_sync<NW>();
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
     const int64_t total = ordered_emit<NW>(
-        wt, tmp,
+        wt, tmp, ut,
         [&](int c) { return FLAGS ? (flags[c] != 0) : T::is_set(vals[c]); },
         [&](int c, int64_t pos) {
             if (!COUNT) {
@@ -586,7 +631,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_dense(NumArgs g) {
                 ov[ob + pos] = T::finish(vals[c]);
             }
         });
-    if (tid == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
+    if (ut == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
 }
 
 // ---------------------------------------------- mask-keyed accumulators
@@ -608,68 +653,98 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t j, int tbits) {
     return ((uint32_t)j * 0x9E3779B1u) >> (32 - tbits);
 }
 
-// Linear probing over a key table (-1 = empty) holding at most 1/4 of its
-// slots; the mask rank of a key sits in a parallel table.
-__device__ __forceinline__ int hash_find(const int32_t* tkey, const uint16_t* trank, uint32_t tmask, int tbits,
-                                         int32_t j) {
-    uint32_t h = hash_slot(j, tbits);
-    while (true) {
-        const int32_t k = tkey[h];
-        if (k == j) return (int)trank[h];
-        if (k == -1) return -1;
-        h = (h + 1) & tmask;
-    }
+// Bucketed open addressing: buckets of 4 keys (16 bytes, -1 = empty) filled
+// in slot order, at most one key per bucket on average; the mask rank of a
+// key sits in a parallel table. One 16-byte LDS read settles a lookup unless
+// the home bucket is full without holding the key, in which case the next
+// buckets are read (linear probing over buckets).
+// All four compares are evaluated, so the bucket is one 16-byte LDS read.
+__device__ __forceinline__ int bucket_hit(int4 e, int32_t j) {
+    int h = (e.w == j) ? 3 : -1;
+    h = (e.z == j) ? 2 : h;
+    h = (e.y == j) ? 1 : h;
+    h = (e.x == j) ? 0 : h;
+    return h;
 }
 
-template <int SR, int MODE, int NW, int CAP, bool HASHED>
-__global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
+// j must not be -1 (the empty marker); a column below zero never matches.
+__device__ __forceinline__ int hash_find(const int4* tkey, const uint16_t* trank, uint32_t bmask, int bbits,
+                                         int32_t j) {
+    uint32_t b = hash_slot(j, bbits);
+    int4 e = tkey[b];
+    int h = bucket_hit(e, j);
+    while (h < 0 && e.w != -1) {  // full home bucket without the key: rare
+        b = (b + 1) & bmask;
+        e = tkey[b];
+        h = bucket_hit(e, j);
+    }
+    return h < 0 ? -1 : (int)trank[b * 4 + h];
+}
+
+template <int SR, int MODE, int NW, int CAP, bool HASHED, int WPB>
+__global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
+    static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     constexpr bool COUNT = MODE == MODE_COUNT;
     constexpr bool FLAGS = COUNT || T::sep_flag;
-    constexpr int TS = HASHED ? 4 * CAP : 1;
-    __shared__ int32_t keys[CAP];
-    __shared__ int32_t tkey[TS];
-    __shared__ uint16_t trank[TS];
-    __shared__ acc_t vals[COUNT ? 1 : CAP];
-    __shared__ uint8_t flags[FLAGS ? CAP : 1];
-    __shared__ StanzaLds<T> st[NW];
+    constexpr int NBK = HASHED ? CAP : 1;  // buckets (4 slots each)
+    constexpr int UT = NW * WAVE;
+    __shared__ int32_t keys_[WPB][CAP];
+    __shared__ int4 tkey_[WPB][NBK];
+    __shared__ uint16_t trank_[WPB][4 * NBK];
+    __shared__ acc_t vals_[WPB][COUNT ? 1 : CAP];
+    __shared__ uint8_t flags_[WPB][FLAGS ? CAP : 1];
+    __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
     const Operands& o = g.op;
-    const int tid = threadIdx.x, wv = tid / WAVE;
-    const int u = g.units[blockIdx.x];
+    const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
+    const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
+    if (uix >= g.nunits) return;  // only one-wave units can leave early (WPB > 1 implies NW == 1)
+    int32_t* keys = keys_[gi];
+    int4* tkey = tkey_[gi];
+    uint16_t* trank = trank_[gi];
+    acc_t* vals = vals_[gi];
+    uint8_t* flags = flags_[gi];
+    const int u = g.units[uix];
     const int64_t i = g.unit_row[u];
     const int64_t r0 = (int64_t)g.unit_tile[u] * CAP;
     const int64_t mrow = o.Mrp[i];
     const int64_t mnnz = o.Mrp[i + 1] - mrow;
     const int cnt = (int)min((int64_t)CAP, mnnz - r0);
     const bool tiled = mnnz > CAP;
-    for (int x = tid; x < cnt; x += NW * WAVE) {
+    for (int x = ut; x < cnt; x += UT) {
         keys[x] = o.Mci[mrow + r0 + x];
         if (!COUNT) vals[x] = T::identity();
         if (FLAGS) flags[x] = 0;
     }
-    int tbits = 2;
-    while ((1 << tbits) < 4 * cnt) ++tbits;
-    const uint32_t tmask = (1u << tbits) - 1u;
+    int bbits = 1;
+    while ((1 << bbits) < cnt) ++bbits;
+    const uint32_t bmask = (1u << bbits) - 1u;
     if (HASHED)
-        for (int x = tid; x <= (int)tmask; x += NW * WAVE) tkey[x] = -1;
-    if (lane() < STREAM_U) st[wv].S[lane()] = 0ull;
-    __syncthreads();
+        for (int x = ut; x <= (int)bmask; x += UT) tkey[x] = make_int4(-1, -1, -1, -1);
+    if (lane() < STREAM_U) st[wave].S[lane()] = 0ull;
+    unit_sync<NW>();
     if (HASHED) {
-        for (int x = tid; x < cnt; x += NW * WAVE) {
+        for (int x = ut; x < cnt; x += UT) {
             const int32_t key = keys[x];
-            uint32_t h = hash_slot(key, tbits);
-            while (atomicCAS(&tkey[h], -1, key) != -1) h = (h + 1) & tmask;
-            trank[h] = (uint16_t)x;
+            int32_t* slots = reinterpret_cast<int32_t*>(tkey);
+            uint32_t b = hash_slot(key, bbits);
+            int sl = 0;
+            while (atomicCAS(&slots[b * 4 + sl], -1, key) != -1) {
+                if (++sl == 4) { sl = 0; b = (b + 1) & bmask; }
+            }
+            trank[b * 4 + sl] = (uint16_t)x;
         }
-        __syncthreads();
+        unit_sync<NW>();
     }
     const int32_t lo = keys[0], hi = keys[cnt - 1];
     const int top = 1 << (31 - __clz(cnt));
-    StanzaLds<T>& S = st[wv];
-    stream_products<T>(o, i, tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q) {
-        const int r = HASHED ? hash_find(tkey, trank, tmask, tbits, j) : rank_search(keys, cnt, top, j);
+    StanzaLds<T>& S = st[wave];
+    stream_products<T>(o, i, tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q, bool act) {
+        // an inactive slot looks up a column that no mask holds (branch-free)
+        const int32_t jj = act ? j : INT32_MIN;
+        const int r = HASHED ? hash_find(tkey, trank, bmask, bbits, jj) : rank_search(keys, cnt, top, jj);
         if (r >= 0) {
             if (FLAGS) flags[r] = 1;
             if (!COUNT) {
@@ -678,11 +753,11 @@ __global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
             }
         }
     });
-    __syncthreads();
+    unit_sync<NW>();
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
     const int64_t total = ordered_emit<NW>(
-        cnt, tmp,
+        cnt, tmp, ut,
         [&](int r) { return FLAGS ? (flags[r] != 0) : T::is_set(vals[r]); },
         [&](int r, int64_t pos) {
             if (!COUNT) {
@@ -690,7 +765,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
                 ov[ob + pos] = T::finish(vals[r]);
             }
         });
-    if (tid == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
+    if (ut == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
 }
 
 // ----------------------------------------------------------- inner product
@@ -698,17 +773,22 @@ __global__ __launch_bounds__(NW * WAVE) void k_maskkey(NumArgs g) {
 // the sparse dot product of A(i,:) with column j of B (row j of B^T) by
 // looking up every k of that column in A's row (staged in LDS when short,
 // else a binary search in global memory).
-template <int SR, int MODE, int CAP, int ACAP>
-__global__ __launch_bounds__(WAVE) void k_inner(NumArgs g) {
+template <int SR, int MODE, int CAP, int ACAP, int WPB>
+__global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     using in_t = typename T::in_t;
     constexpr bool COUNT = MODE == MODE_COUNT;
-    __shared__ int32_t akeys[ACAP];
-    __shared__ in_t avals[T::needs_values ? ACAP : 1];
+    __shared__ int32_t akeys_[WPB][ACAP];
+    __shared__ in_t avals_[WPB][T::needs_values ? ACAP : 1];
     const Operands& o = g.op;
     const int ln = lane();
-    const int u = g.units[blockIdx.x];
+    const int gi = threadIdx.x / WAVE;
+    const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
+    if (uix >= g.nunits) return;
+    int32_t* akeys = akeys_[gi];
+    in_t* avals = avals_[gi];
+    const int u = g.units[uix];
     const int64_t i = g.unit_row[u];
     const int64_t r0 = (int64_t)g.unit_tile[u] * CAP;
     const int64_t mrow = o.Mrp[i];
@@ -722,7 +802,7 @@ __global__ __launch_bounds__(WAVE) void k_inner(NumArgs g) {
             if (T::needs_values && !COUNT) avals[x] = T::load(o.Av, pa0 + x);
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     const int top = in_lds && alen > 0 ? 1 << (31 - __clz((int)alen)) : 0;
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
@@ -764,31 +844,36 @@ __global__ __launch_bounds__(WAVE) void k_inner(NumArgs g) {
     if (ln == 0 && MODE != MODE_DIRECT) g.cnt[u] = running;
 }
 
+#ifndef MSP_WPB
+#define MSP_WPB 1
+#endif
+constexpr int WPB = MSP_WPB;  // independent one-wave units per block
+
 template <int SR, int MODE>
 static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)a.nunits);
+    const dim3 gw((unsigned)((a.nunits + WPB - 1) / WPB)), gb((unsigned)a.nunits);
+    const dim3 bw(WPB * WAVE), bb(BLOCK_NW * WAVE);
     switch (bin) {
     case BIN_DENSE_W:
-        hipLaunchKernelGGL((k_dense<SR, MODE, 1, DENSE_W_COLS>), grid, dim3(WAVE), 0, s, a);
+        hipLaunchKernelGGL((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB>), gw, bw, 0, s, a);
         break;
     case BIN_DENSE_B:
-        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS>), grid, dim3(BLOCK_NW * WAVE), 0, s, a);
+        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1>), gb, bb, 0, s, a);
         break;
     case BIN_HASH_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, true>), grid, dim3(WAVE), 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, true, WPB>), gw, bw, 0, s, a);
         break;
     case BIN_HASH_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, true>), grid, dim3(BLOCK_NW * WAVE), 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, true, 1>), gb, bb, 0, s, a);
         break;
     case BIN_MASKIDX_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false>), grid, dim3(WAVE), 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false, WPB>), gw, bw, 0, s, a);
         break;
     case BIN_MASKIDX_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false>), grid, dim3(BLOCK_NW * WAVE), 0,
-                           s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false, 1>), gb, bb, 0, s, a);
         break;
     case BIN_INNER_W:
-        hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP>), grid, dim3(WAVE), 0, s, a);
+        hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB>), gw, bw, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
