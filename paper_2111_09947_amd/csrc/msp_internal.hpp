@@ -31,7 +31,10 @@ constexpr int MASKIDX_B_CAP = 4096;
 constexpr int INNER_CAP = 256;
 constexpr int INNER_ACAP = 512;   // A row staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
-constexpr int MASKIDX_SMALL = 32; // auto: binary search below this mask size, hash above
+#ifndef MSP_MASKIDX_SMALL
+#define MSP_MASKIDX_SMALL 8
+#endif
+constexpr int MASKIDX_SMALL = MSP_MASKIDX_SMALL;  // auto: binary search up to this mask size, hash above
 constexpr int64_t BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
 // Units of a bin are ordered by the product count of their row, heaviest
 // first (bucket b holds rows with 4^b <= flops < 4^(b+1)), so that the
