@@ -137,10 +137,16 @@ typedef struct msp_options {
                              choose INNER automatically. */
     const msp_csr* b_transpose; /* optional CSR of B^T (n x k); NULL = built by the
                                    plan when INNER is used */
+    int32_t maskidx_max;  /* auto mode: rows whose mask has at most this many
+                             entries use MASKIDX, larger ones HASH (-1 = default 8) */
+    int32_t reserved;
+    int64_t block_flops;  /* rows with more products than this run on a whole
+                             256-thread workgroup instead of one wavefront
+                             (-1 = default 8192) */
 } msp_options;
 
 /* Fills `opt` with the defaults: phase 1, auto kind, no validation,
-   inner_ratio 0, no B^T. */
+   inner_ratio 0, no B^T, maskidx_max 8, block_flops 8192. */
 void msp_options_default(msp_options* opt);
 
 /* Plan statistics, filled by msp_plan_info. */
@@ -265,6 +271,47 @@ msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M,
  */
 msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result,
                       void* stream);
+
+/*
+ * ---- Batches: many products in one set of launches ----
+ * A batch is a plan over `count` products on one semiring (one-phase only).
+ * All products are analysed together; their work units are binned jointly,
+ * so each kernel bin runs ONE launch over the units of every product, then
+ * one prefix sum, one row-pointer and one compaction kernel serve all
+ * outputs. msp_plan_info, msp_plan_row_bins and msp_plan_destroy accept a
+ * batch; msp_execute/msp_symbolic/msp_numeric take single products only.
+ */
+typedef struct msp_problem {
+    msp_csr A, B, M;      /* device views, as for msp_plan_create */
+    int32_t complement;   /* 0 or 1 */
+    int32_t reserved;     /* 0 */
+} msp_problem;
+
+/* Analyses and bins all products (one synchronization). */
+msp_status msp_batch_create(msp_plan** batch, const msp_problem* problems, int64_t count,
+                            msp_semiring semiring, const msp_options* opt, void* stream);
+
+/* Number of products of a batch (1 for a single-product plan). */
+int64_t msp_batch_count(const msp_plan* batch);
+
+/* Statistics of product p (0 <= p < count), or of all products (p = -1). */
+msp_status msp_batch_info(const msp_plan* batch, int64_t p, msp_plan_info_t* info);
+
+/* Binds the outputs C[0..count) (capacity of C[p] >= its upper bound).
+   SYNCHRONIZES. Invalidates a previously captured graph. */
+msp_status msp_batch_bind(msp_plan* batch, const msp_csr_out* C, void* stream);
+
+/* Enqueues the whole batch on `stream`: kernels only, no allocation, no
+   memset and no synchronization, so the sequence may be captured. */
+msp_status msp_batch_execute(msp_plan* batch, void* stream);
+
+/* First call on a stream: captures msp_batch_execute into a HIP graph on
+   `stream` (which must not be the default stream) and instantiates it; every
+   call then launches the graph once. */
+msp_status msp_batch_graph_launch(msp_plan* batch, void* stream);
+
+/* nnz of every product's output into nnz[0..count) (host). SYNCHRONIZES. */
+msp_status msp_batch_nnz(const msp_plan* batch, int64_t* nnz, void* stream);
 
 /* Static message for a status code. */
 const char* msp_status_string(msp_status status);

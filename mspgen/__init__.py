@@ -111,22 +111,22 @@ def random_values(nnz: int, kind: Optional[str], rng: np.random.Generator) -> Op
 def er(nrows: int, ncols: int, d: float, seed: int, values: Optional[str] = "f64") -> CSR:
     """Erdos-Renyi G(nrows, ncols, p) with p = d / ncols: every cell is
     present independently, so each row has Binomial(ncols, p) entries at
-    distinct uniform columns. Sampled as a Binomial total and a uniform subset
-    of that size of all cells, which is the same distribution."""
+    distinct uniform columns. Rows are drawn in C by geometric skipping with a
+    counter-based random stream per row (mspgen/gen.c); values with numpy."""
+    from . import _native
     rng = np.random.default_rng(seed)
-    cells = nrows * ncols
-    if cells == 0:
-        return CSR(nrows, ncols, np.zeros(nrows + 1, np.int64), np.zeros(0, np.int32),
-                   random_values(0, values, rng))
-    p = min(1.0, d / ncols)
-    total = int(rng.binomial(cells, p))
-    pos = np.sort(rng.choice(cells, size=total, replace=False).astype(np.int64))
-    rows = pos // ncols
-    cols = pos - rows * ncols
-    counts = np.bincount(rows, minlength=nrows)
     rowptr = np.zeros(nrows + 1, dtype=np.int64)
-    np.cumsum(counts, out=rowptr[1:])
-    return CSR(nrows, ncols, rowptr, cols.astype(np.int32), random_values(total, values, rng))
+    if nrows == 0 or ncols == 0:
+        return CSR(nrows, ncols, rowptr, np.zeros(0, np.int32), random_values(0, values, rng))
+    p = min(1.0, d / ncols)
+    L = _native.lib()
+    cnt = np.zeros(nrows, dtype=np.int64)
+    s64 = int(rng.integers(0, 2**63 - 1))
+    L.gen_er_counts(nrows, ncols, p, s64, _native.ptr(cnt))
+    np.cumsum(cnt, out=rowptr[1:])
+    colidx = np.empty(int(rowptr[-1]), dtype=np.int32)
+    L.gen_er_fill(nrows, ncols, p, s64, _native.ptr(rowptr), _native.ptr(colidx))
+    return CSR(nrows, ncols, rowptr, colidx, random_values(len(colidx), values, rng))
 
 
 def rmat_edges(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
@@ -222,51 +222,6 @@ def complete_bipartite(p: int, q: int) -> CSR:
     return from_coo(n, n, rows, cols)
 
 
-def _bfs_levels(G: CSR, sources: np.ndarray, max_level: int):
-    """Level-synchronous BFS from each source independently (pattern only).
-    Returns, per source, the list of (vertex array, path-count array) per
-    level 0..max_level. Path counts are the number of shortest paths from the
-    source (summed over predecessors in the previous level). Uses plain numpy
-    gathers over the CSR pattern."""
-    n = G.nrows
-    rp, ci = G.rowptr, G.colidx.astype(np.int64)
-    out = []
-    dist = np.full(n, -1, dtype=np.int64)
-    sigma = np.zeros(n, dtype=np.int64)
-    for s in sources:
-        s = int(s)
-        dist[s] = 0
-        sigma[s] = 1
-        levels = [(np.array([s], dtype=np.int64), np.array([1], dtype=np.int64))]
-        touched = [np.array([s], dtype=np.int64)]
-        frontier = levels[0][0]
-        for lvl in range(1, max_level + 1):
-            starts, ends = rp[frontier], rp[frontier + 1]
-            lens = ends - starts
-            if lens.sum() == 0:
-                levels.append((np.zeros(0, np.int64), np.zeros(0, np.int64)))
-                frontier = levels[-1][0]
-                continue
-            src = np.repeat(frontier, lens)
-            idx = np.repeat(starts - np.cumsum(lens) + lens, lens) + np.arange(lens.sum())
-            nbr = ci[idx]
-            new = dist[nbr] == -1
-            fresh = nbr[new]
-            dist[fresh] = lvl
-            cand = nbr[dist[nbr] == lvl]
-            csrc = src[dist[nbr] == lvl]
-            np.add.at(sigma, cand, sigma[csrc])
-            verts = np.unique(fresh)
-            levels.append((verts, sigma[verts].copy()))
-            touched.append(verts)
-            frontier = verts
-        out.append(levels)
-        allv = np.concatenate(touched)
-        dist[allv] = -1
-        sigma[allv] = 0
-    return out
-
-
 def bfs_step_input(G: CSR, nsrc: int, seed: int, values: str = "u8",
                    levels: Optional[List[int]] = None):
     """Operands of one multi-source BFS step in the orientation C = !V .* (A F):
@@ -275,35 +230,49 @@ def bfs_step_input(G: CSR, nsrc: int, seed: int, values: str = "u8",
     V (n x nsrc) holds every vertex at distance <= l_s (the visited set).
 
     Sources are uniform among non-isolated vertices; l_s ~ U{1,2,3}
-    (or ``levels`` if given). Returns (F, V, sources, levels)."""
+    (or ``levels`` if given). The per-source BFS runs in C (mspgen/gen.c).
+    Returns (F, V, sources, levels)."""
+    from . import _native
     rng = np.random.default_rng(seed)
     deg = np.diff(G.rowptr)
     cand = np.nonzero(deg > 0)[0]
-    sources = rng.choice(cand, size=nsrc, replace=len(cand) < nsrc)
-    lv = np.asarray(levels if levels is not None else rng.integers(1, 4, size=nsrc), dtype=np.int64)
-    bfs = _bfs_levels(G, sources, int(lv.max()) if nsrc else 0)
-    fr, fc, fv, vr, vc = [], [], [], [], []
-    for s in range(nsrc):
-        L = int(lv[s])
-        verts, sig = bfs[s][L]
-        fr.append(verts)
-        fc.append(np.full(len(verts), s, np.int64))
-        fv.append(sig)
-        for lvl in range(L + 1):
-            vr.append(bfs[s][lvl][0])
-            vc.append(np.full(len(bfs[s][lvl][0]), s, np.int64))
+    sources = rng.choice(cand, size=nsrc, replace=len(cand) < nsrc).astype(np.int64)
+    lv = np.asarray(levels if levels is not None else rng.integers(1, 4, size=nsrc), dtype=np.int32)
     n = G.nrows
-    cat = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt)
-    fvals = cat(fv, np.int64)
+    L = _native.lib()
+    rp = np.ascontiguousarray(G.rowptr, np.int64)
+    ci = np.ascontiguousarray(G.colidx, np.int32)
+    fcnt = np.zeros(nsrc, np.int64)
+    vcnt = np.zeros(nsrc, np.int64)
+    P = _native.ptr
+    if L.gen_bfs_counts(n, P(rp), P(ci), nsrc, P(sources), P(lv), P(fcnt), P(vcnt)) != 0:
+        raise MemoryError("bfs counts")
+    foff = np.zeros(nsrc + 1, np.int64)
+    voff = np.zeros(nsrc + 1, np.int64)
+    np.cumsum(fcnt, out=foff[1:])
+    np.cumsum(vcnt, out=voff[1:])
+    fv = np.empty(int(foff[-1]), np.int32)
+    fs = np.empty(int(foff[-1]), np.int64)
+    vv = np.empty(int(voff[-1]), np.int32)
+    if L.gen_bfs_lists(n, P(rp), P(ci), nsrc, P(sources), P(lv), P(foff), P(fv), P(fs), P(voff), P(vv)) != 0:
+        raise MemoryError("bfs lists")
+    F_rp = np.empty(n + 1, np.int64)
+    F_ci = np.empty(len(fv), np.int32)
+    F_val = np.empty(len(fv), np.int64)
+    L.gen_lists_to_csr(n, nsrc, P(foff), P(fv), P(fs), P(F_rp), P(F_ci), P(F_val))
+    del fv, fs
+    V_rp = np.empty(n + 1, np.int64)
+    V_ci = np.empty(len(vv), np.int32)
+    L.gen_lists_to_csr(n, nsrc, P(voff), P(vv), None, P(V_rp), P(V_ci), None)
     if values == "u8":
-        fvals = np.ones(len(fvals), np.uint8)
+        fvals = np.ones(len(F_ci), np.uint8)
     elif values == "i32":
-        fvals = fvals.astype(np.int32)
-    elif values is None:
+        fvals = F_val.astype(np.int32)
+    elif values == "i64":
+        fvals = F_val
+    else:
         fvals = None
-    F = from_coo(n, nsrc, cat(fr, np.int64), cat(fc, np.int64), fvals, dedup=False)
-    V = from_coo(n, nsrc, cat(vr, np.int64), cat(vc, np.int64), dedup=False)
-    return F, V, sources, lv
+    return CSR(n, nsrc, F_rp, F_ci, fvals), CSR(n, nsrc, V_rp, V_ci), sources, lv.astype(np.int64)
 
 
 def batch_mix(count: int, seed: int, n_lo: int = 12, n_hi: int = 17,

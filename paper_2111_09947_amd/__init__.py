@@ -115,13 +115,16 @@ def _check(st: int, where: str):
 
 
 def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio: int = 0,
-            b_transpose: Optional[L.MspCsr] = None) -> L.MspOptions:
+            b_transpose: Optional[L.MspCsr] = None, maskidx_max: int = -1,
+            block_flops: int = -1) -> L.MspOptions:
     o = L.MspOptions()
     L.load().msp_options_default(ctypes.byref(o))
     o.phase = int(phase)
     o.force_kind = KINDS[force_kind]
     o.validate = int(bool(validate))
     o.inner_ratio = int(inner_ratio)
+    o.maskidx_max = int(maskidx_max)
+    o.block_flops = int(block_flops)
     if b_transpose is not None:
         o.b_transpose = ctypes.pointer(b_transpose)
     return o
@@ -134,14 +137,15 @@ class Plan:
 
     def __init__(self, A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
                  semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
-                 validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None):
+                 validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None,
+                 maskidx_max: int = -1, block_flops: int = -1):
         lib = L.load()
         self.semiring = semiring
         self.A, self.B, self.M = A, B, M
         self._views = (_view(A, semiring, "A"), _view(B, semiring, "B"), _view(M, None, "M"))
         self._bt = None if b_transpose is None else _view(b_transpose, semiring, "B^T")
         self._bt_keep = b_transpose
-        self._opt = options(phase, force_kind, validate, inner_ratio, self._bt)
+        self._opt = options(phase, force_kind, validate, inner_ratio, self._bt, maskidx_max, block_flops)
         self.phase = phase
         self.nrows, self.ncols = A.nrows, B.ncols
         h = ctypes.c_void_p()
@@ -277,3 +281,94 @@ def reduce(values, semiring: str, out=None):
 
 def version() -> int:
     return L.load().msp_version()
+
+
+class Batch:
+    """Many masked products on one semiring planned and run together: each
+    kernel bin is one launch over the units of every product; execute() can
+    be captured once into a HIP graph and replayed (graph_launch()).
+
+    problems: list of (A, B, M, complement) DeviceCSR triples."""
+
+    def __init__(self, problems, semiring: str = "plus_times_f64", force_kind=None, inner_ratio: int = 0,
+                 maskidx_max: int = -1, block_flops: int = -1):
+        lib = L.load()
+        self.semiring = semiring
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (L.MspProblem * n)()
+        for p, (A, B, M, comp) in enumerate(self.problems):
+            arr[p].A = _view(A, semiring, "A")
+            arr[p].B = _view(B, semiring, "B")
+            arr[p].M = _view(M, None, "M")
+            arr[p].complement = int(bool(comp))
+        self._arr = arr
+        self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops)
+        h = ctypes.c_void_p()
+        _check(lib.msp_batch_create(ctypes.byref(h), arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt),
+                                    _stream()), "msp_batch_create")
+        self._h = h
+        self.count = n
+        self.upper_bounds = []
+        self.products = []
+        for p in range(n):
+            info = L.MspPlanInfo()
+            _check(lib.msp_batch_info(h, p, ctypes.byref(info)), "msp_batch_info")
+            self.upper_bounds.append(info.upper_bound)
+            self.products.append(info.products)
+        info = L.MspPlanInfo()
+        _check(lib.msp_batch_info(h, -1, ctypes.byref(info)), "msp_batch_info")
+        self.units = info.units
+        self.bin_units = {k: info.bin_units[i] for i, k in enumerate(L.BIN_NAMES)}
+        self.outputs = None
+
+    def bind_new_outputs(self):
+        """Allocates every output with its upper-bound capacity and binds it."""
+        t = _torch()
+        outs = (L.MspCsrOut * self.count)()
+        self.outputs = []
+        for p, (A, B, M, _) in enumerate(self.problems):
+            dev = A.rowptr.device
+            cap = max(self.upper_bounds[p], 1)
+            rp = t.empty(A.nrows + 1, dtype=t.int64, device=dev)
+            ci = t.empty(cap, dtype=t.int32, device=dev)
+            v = t.empty(cap, dtype=out_dtype(self.semiring), device=dev)
+            self.outputs.append((rp, ci, v))
+            outs[p] = L.MspCsrOut(A.nrows, B.ncols, cap, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
+        _check(L.load().msp_batch_bind(self._h, outs, _stream()), "msp_batch_bind")
+        return self.outputs
+
+    def execute(self):
+        _check(L.load().msp_batch_execute(self._h, _stream()), "msp_batch_execute")
+
+    def graph_launch(self):
+        """Replays the captured graph (captures it on first use); the current
+        stream must not be the default stream."""
+        _check(L.load().msp_batch_graph_launch(self._h, _stream()), "msp_batch_graph_launch")
+
+    def results(self):
+        """Outputs trimmed to nnz (synchronizes)."""
+        n = (ctypes.c_int64 * self.count)()
+        _check(L.load().msp_batch_nnz(self._h, n, _stream()), "msp_batch_nnz")
+        res = []
+        for p, (rp, ci, v) in enumerate(self.outputs):
+            A, B = self.problems[p][0], self.problems[p][1]
+            res.append(DeviceCSR(A.nrows, B.ncols, rp, ci[:n[p]], v[:n[p]]))
+        return res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().msp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

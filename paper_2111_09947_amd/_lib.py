@@ -22,7 +22,8 @@ class MspCsrOut(ctypes.Structure):
 
 class MspOptions(ctypes.Structure):
     _fields_ = [("phase", c_i32), ("force_kind", c_i32), ("validate", c_i32),
-                ("inner_ratio", c_i32), ("b_transpose", ctypes.POINTER(MspCsr))]
+                ("inner_ratio", c_i32), ("b_transpose", ctypes.POINTER(MspCsr)),
+                ("maskidx_max", c_i32), ("reserved", c_i32), ("block_flops", c_i64)]
 
 
 class MspPlanInfo(ctypes.Structure):
@@ -35,6 +36,10 @@ BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wa
              "inner_wave"]
 STAGE_NAMES = BIN_NAMES + ["symbolic", "scan", "rowptr", "compact"]
 NSTAGES = len(STAGE_NAMES)
+
+
+class MspProblem(ctypes.Structure):
+    _fields_ = [("A", MspCsr), ("B", MspCsr), ("M", MspCsr), ("complement", c_i32), ("reserved", c_i32)]
 
 
 # every symbol include/msp.h declares, with its ctypes signature
@@ -57,6 +62,14 @@ SIGNATURES = {
     "msp_upper_bound": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
                                        ctypes.c_int, ctypes.POINTER(c_i64), c_vp]),
     "msp_reduce": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_vp]),
+    "msp_batch_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(MspProblem), c_i64, ctypes.c_int,
+                                        ctypes.POINTER(MspOptions), c_vp]),
+    "msp_batch_count": (c_i64, [c_vp]),
+    "msp_batch_info": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(MspPlanInfo)]),
+    "msp_batch_bind": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), c_vp]),
+    "msp_batch_execute": (ctypes.c_int, [c_vp, c_vp]),
+    "msp_batch_graph_launch": (ctypes.c_int, [c_vp, c_vp]),
+    "msp_batch_nnz": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i64), c_vp]),
     "msp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "msp_last_error": (ctypes.c_char_p, []),
     "msp_version": (ctypes.c_int, []),

@@ -1,12 +1,20 @@
 // Host runtime of the C-ABI (include/msp.h): argument checks, plan
 // workspace, kernel sequencing for the one-phase and two-phase paths
-// (Section "Symbolic and Numeric Phases").
+// (Section "Symbolic and Numeric Phases"), and batches of products that
+// share one set of launches.
+//
+// A plan covers P >= 1 products on one semiring. Their rows are numbered
+// globally (product p owns rows row_off_p .. row_off_p + m_p - 1) and their
+// work units share one unit space, so that each kernel bin runs one launch
+// over the units of all products; a unit finds its operands through a device
+// table. A single product (msp_plan_create) is the case P = 1.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "msp.h"
@@ -71,41 +79,66 @@ msp_status check_csr(const msp_csr* X, const char* name) {
     return MSP_OK;
 }
 
+msp_status check_triple(const msp_csr* A, const msp_csr* B, const msp_csr* M) {
+    MSP_CHECK(check_csr(A, "A"));
+    MSP_CHECK(check_csr(B, "B"));
+    MSP_CHECK(check_csr(M, "M"));
+    if (A->ncols != B->nrows || M->nrows != A->nrows || M->ncols != B->ncols)
+        return fail(MSP_ERR_DIMENSION_MISMATCH, "need A.ncols == B.nrows, M.nrows == A.nrows, M.ncols == B.ncols");
+    return MSP_OK;
+}
+
+struct Product {
+    Operands op{};
+    int64_t row_off = 0;
+    int64_t nnzB = 0;
+    int64_t* BTrp = nullptr;
+    int32_t* BTci = nullptr;
+    void* BTv = nullptr;
+    int64_t ub = 0, flops = 0, units = 0, staging = 0, mnnz = 0;
+    int64_t bin_units[NBINS] = {};
+};
+
 }  // namespace
 
 struct msp_plan {
     hipStream_t stream = nullptr;
-    Operands op{};
     int sr = 0;
     msp_options opt{};
-    int64_t nnzB = 0;
+    std::vector<Product> prods;
+    int64_t P = 0, R = 0, U = 0, S = 0, ub = 0;
     std::vector<void*> allocs;
     bool pooled = true;
-    // analysis
+    // analysis (global rows)
+    unsigned long long* stats_d = nullptr;  // [P * ST_COUNT]
+    std::vector<unsigned long long> stats;
     int64_t* flops = nullptr;
     int64_t* unit_base = nullptr;
     int8_t* bin = nullptr;
-    unsigned long long* stats_d = nullptr;
-    unsigned long long stats[ST_COUNT] = {};
-    int64_t U = 0, S = 0, ub = 0;
+    int64_t* scan_partial = nullptr;
+    // units (global)
     int64_t bin_count[NBINS] = {};
     int64_t bin_off[NBINS + 1] = {};
-    // units
+    int64_t seg_off[NBINS * NBUCKET] = {};
     int64_t* seg_off_d = nullptr;
     unsigned long long* seg_cursor = nullptr;
-    int64_t seg_off[NBINS * NBUCKET] = {};
     int32_t* unit_row = nullptr;
     int32_t* unit_tile = nullptr;
+    int32_t* unit_prob = nullptr;
     int64_t* stg_off = nullptr;
     int64_t* cnt = nullptr;
     int32_t* bin_units = nullptr;
     int32_t* stg_col = nullptr;
     void* stg_val = nullptr;
-    int64_t* scan_partial = nullptr;
-    // B^T
-    int64_t* BTrp = nullptr;
-    int32_t* BTci = nullptr;
-    void* BTv = nullptr;
+    // batch tables
+    Operands* ops_d = nullptr;
+    OutBind* outs_d = nullptr;
+    int64_t* ent_off_d = nullptr;
+    std::vector<OutBind> outs;
+    bool bound = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;
     bool symbolic_done = false;
 
     msp_status alloc(void** p, size_t bytes) {
@@ -149,6 +182,10 @@ struct msp_plan {
         return MSP_OK;
     }
     void release() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
         for (void* p : allocs) {
             if (pooled) (void)hipFreeAsync(p, stream);
             else (void)hipFree(p);
@@ -166,6 +203,9 @@ void msp_options_default(msp_options* opt) {
     opt->validate = 0;
     opt->inner_ratio = 0;
     opt->b_transpose = nullptr;
+    opt->maskidx_max = -1;
+    opt->reserved = 0;
+    opt->block_flops = -1;
 }
 
 const char* msp_status_string(msp_status s) {
@@ -184,90 +224,110 @@ const char* msp_status_string(msp_status s) {
 
 const char* msp_last_error(void) { return g_last_error.c_str(); }
 
-int msp_version(void) { return 100; }
+int msp_version(void) { return 200; }
 
-static msp_status build_transpose(msp_plan* P, bool scatter) {
-    const Operands& o = P->op;
+}  // extern "C"
+
+// B^T of product `pr`: column counts and their prefix sum (always), rows
+// scattered (when `scatter`). Rows of B^T come out in no particular order.
+static msp_status build_transpose(msp_plan* P, Product& pr, bool scatter) {
+    const Operands& o = pr.op;
     hipStream_t s = P->stream;
-    if (!P->BTrp) {
-        MSP_CHECK(P->alloc_n(&P->BTrp, o.n + 1));
-        MSP_HIP(launch_fill_i64(P->BTrp, o.n + 1, 0, s));
-        MSP_HIP(launch_colcount(o.Bci, P->nnzB, P->BTrp, s));
+    if (!pr.BTrp) {
+        MSP_CHECK(P->alloc_n(&pr.BTrp, o.n + 1));
+        MSP_HIP(launch_fill_i64(pr.BTrp, o.n + 1, 0, s));
+        MSP_HIP(launch_colcount(o.Bci, pr.nnzB, pr.BTrp, s));
         int64_t* part = nullptr;
         MSP_CHECK(P->alloc_n(&part, scan_partial_elems(o.n)));
-        MSP_HIP(launch_scan(P->BTrp, P->BTrp, o.n, part, s));
-        P->op.BTrp = P->BTrp;
+        MSP_HIP(launch_scan(pr.BTrp, pr.BTrp, o.n, part, s));
+        pr.op.BTrp = pr.BTrp;
     }
-    if (scatter && !P->BTci) {
+    if (scatter && !pr.BTci) {
         const int vb = in_bytes(P->sr);
-        MSP_CHECK(P->alloc_n(&P->BTci, P->nnzB));
-        if (vb && o.Bv) MSP_CHECK(P->alloc(&P->BTv, (size_t)(P->nnzB > 0 ? P->nnzB : 1) * vb));
+        MSP_CHECK(P->alloc_n(&pr.BTci, pr.nnzB));
+        if (vb && o.Bv) MSP_CHECK(P->alloc(&pr.BTv, (size_t)(pr.nnzB > 0 ? pr.nnzB : 1) * vb));
         unsigned long long* cursor = nullptr;
         MSP_CHECK(P->alloc_n(&cursor, o.n));
         MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(cursor), o.n, 0, s));
-        MSP_HIP(launch_transpose_scatter(o.Brp, o.Bci, o.Bv, vb, o.k, P->BTrp, cursor, P->BTci, P->BTv, s));
-        P->op.BTci = P->BTci;
-        P->op.BTv = P->BTv;
+        MSP_HIP(launch_transpose_scatter(o.Brp, o.Bci, o.Bv, vb, o.k, pr.BTrp, cursor, pr.BTci, pr.BTv, s));
+        pr.op.BTci = pr.BTci;
+        pr.op.BTv = pr.BTv;
     }
     return MSP_OK;
 }
 
-static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr* B, const msp_csr* M,
-                                   int complement, msp_semiring semiring, const msp_options* opt,
-                                   hipStream_t stream, bool want_staging) {
-    MSP_CHECK(check_csr(A, "A"));
-    MSP_CHECK(check_csr(B, "B"));
-    MSP_CHECK(check_csr(M, "M"));
+// Plans the products `probs` (count P). want_staging: allocate one-phase staging.
+static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_t count, msp_semiring semiring,
+                                   const msp_options* opt, hipStream_t stream, bool want_staging) {
+    if (count < 1) return fail(MSP_ERR_INVALID_ARGUMENT, "a plan needs at least one product");
+    if (!probs) return fail(MSP_ERR_INVALID_ARGUMENT, "problems is NULL");
     if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
-    if (complement != 0 && complement != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "complement must be 0 or 1");
-    if (A->ncols != B->nrows || M->nrows != A->nrows || M->ncols != B->ncols)
-        return fail(MSP_ERR_DIMENSION_MISMATCH, "need A.ncols == B.nrows, M.nrows == A.nrows, M.ncols == B.ncols");
     msp_options o;
     msp_options_default(&o);
     if (opt) o = *opt;
     if (o.phase == 0) o.phase = 1;
     if (o.phase != 1 && o.phase != 2) return fail(MSP_ERR_INVALID_ARGUMENT, "phase must be 1 or 2");
+    if (count > 1 && o.phase != 1) return fail(MSP_ERR_UNSUPPORTED, "a batch runs one-phase only");
     if (o.force_kind < MSP_KIND_AUTO || o.force_kind > MSP_KIND_INNER)
         return fail(MSP_ERR_INVALID_ARGUMENT, "unknown force_kind");
     if (o.inner_ratio < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "inner_ratio must be >= 0");
-    if (complement && o.force_kind != MSP_KIND_AUTO && o.force_kind != MSP_KIND_DENSE)
-        return fail(MSP_ERR_UNSUPPORTED, "a complemented mask supports only the dense kind");
+    if (o.maskidx_max < 0) o.maskidx_max = DEFAULT_MASKIDX_MAX;
+    if (o.block_flops < 0) o.block_flops = DEFAULT_BLOCK_FLOPS;
+    if (count > 1 && o.b_transpose) return fail(MSP_ERR_UNSUPPORTED, "b_transpose applies to a single product");
+    int64_t R = 0;
+    P->prods.resize((size_t)count);
+    for (int64_t p = 0; p < count; ++p) {
+        const msp_problem& q = probs[p];
+        MSP_CHECK(check_triple(&q.A, &q.B, &q.M));
+        if (q.complement != 0 && q.complement != 1)
+            return fail(MSP_ERR_INVALID_ARGUMENT, "complement must be 0 or 1");
+        if (q.complement && o.force_kind != MSP_KIND_AUTO && o.force_kind != MSP_KIND_DENSE)
+            return fail(MSP_ERR_UNSUPPORTED, "a complemented mask supports only the dense kind");
+        Product& pr = P->prods[(size_t)p];
+        Operands& op = pr.op;
+        op.m = q.A.nrows; op.k = q.A.ncols; op.n = q.B.ncols;
+        op.Arp = q.A.rowptr; op.Aci = q.A.colidx; op.Av = q.A.values;
+        op.Brp = q.B.rowptr; op.Bci = q.B.colidx; op.Bv = q.B.values;
+        op.Mrp = q.M.rowptr; op.Mci = q.M.colidx;
+        op.complement = q.complement;
+        pr.nnzB = q.B.nnz;
+        pr.row_off = R;
+        R += op.m;
+    }
+    if (R >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many rows in one plan");
     if (o.b_transpose) {
         MSP_CHECK(check_csr(o.b_transpose, "B^T"));
-        if (o.b_transpose->nrows != B->ncols || o.b_transpose->ncols != B->nrows ||
-            o.b_transpose->nnz != B->nnz)
+        const msp_csr& B = probs[0].B;
+        if (o.b_transpose->nrows != B.ncols || o.b_transpose->ncols != B.nrows || o.b_transpose->nnz != B.nnz)
             return fail(MSP_ERR_DIMENSION_MISMATCH, "B^T must be B.ncols x B.nrows with nnz(B) entries");
     }
     configure_pool();
     P->stream = stream;
     P->sr = semiring;
     P->opt = o;
-    P->nnzB = B->nnz;
-    Operands& op = P->op;
-    op.m = A->nrows; op.k = A->ncols; op.n = B->ncols;
-    op.Arp = A->rowptr; op.Aci = A->colidx; op.Av = A->values;
-    op.Brp = B->rowptr; op.Bci = B->colidx; op.Bv = B->values;
-    op.Mrp = M->rowptr; op.Mci = M->colidx;
-    op.complement = complement;
-    const int64_t m = op.m;
+    P->P = count;
+    P->R = R;
     hipStream_t s = stream;
 
     // workspace sized by the operand shapes
     {
         msp_plan::Carve c;
-        c.add(&P->stats_d, ST_COUNT);
-        c.add(&P->flops, m);
-        c.add(&P->unit_base, m + 1);
-        c.add(&P->bin, m);
-        c.add(&P->scan_partial, scan_partial_elems(m + 1));
+        c.add(&P->stats_d, count * ST_COUNT);
+        c.add(&P->flops, R);
+        c.add(&P->unit_base, R + 1);
+        c.add(&P->bin, R);
+        c.add(&P->scan_partial, scan_partial_elems(R + 1));
         MSP_CHECK(P->alloc_carve(c));
     }
-    MSP_HIP(hipMemsetAsync(P->stats_d, 0, sizeof(unsigned long long) * ST_COUNT, s));
+    MSP_HIP(hipMemsetAsync(P->stats_d, 0, sizeof(unsigned long long) * ST_COUNT * count, s));
     if (o.validate) {
         unsigned long long* err = P->stats_d + ST_ERROR;
-        MSP_HIP(launch_validate(A->rowptr, A->colidx, A->nrows, A->ncols, A->nnz, err, s));
-        MSP_HIP(launch_validate(B->rowptr, B->colidx, B->nrows, B->ncols, B->nnz, err, s));
-        MSP_HIP(launch_validate(M->rowptr, M->colidx, M->nrows, M->ncols, M->nnz, err, s));
+        for (int64_t p = 0; p < count; ++p) {
+            const msp_problem& q = probs[p];
+            MSP_HIP(launch_validate(q.A.rowptr, q.A.colidx, q.A.nrows, q.A.ncols, q.A.nnz, err, s));
+            MSP_HIP(launch_validate(q.B.rowptr, q.B.colidx, q.B.nrows, q.B.ncols, q.B.nnz, err, s));
+            MSP_HIP(launch_validate(q.M.rowptr, q.M.colidx, q.M.nrows, q.M.ncols, q.M.nnz, err, s));
+        }
         if (o.b_transpose)
             MSP_HIP(launch_validate(o.b_transpose->rowptr, o.b_transpose->colidx, o.b_transpose->nrows,
                                     o.b_transpose->ncols, o.b_transpose->nnz, err, s));
@@ -277,47 +337,78 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
         MSP_HIP(hipStreamSynchronize(s));
         if (e) return fail(MSP_ERR_INVALID_CSR, "an operand violates the CSR invariants");
     }
-    const bool inner_possible = !complement && (o.force_kind == MSP_KIND_INNER ||
-                                                (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0));
-    if (o.b_transpose) {
-        op.BTrp = o.b_transpose->rowptr;
-        op.BTci = o.b_transpose->colidx;
-        op.BTv = o.b_transpose->values;
-    } else if (inner_possible) {
-        MSP_CHECK(build_transpose(P, o.force_kind == MSP_KIND_INNER));
+    const bool inner_any = o.force_kind == MSP_KIND_INNER || (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0);
+    for (int64_t p = 0; p < count; ++p) {
+        Product& pr = P->prods[(size_t)p];
+        if (pr.op.complement || !inner_any) continue;
+        if (o.b_transpose) {
+            pr.op.BTrp = o.b_transpose->rowptr;
+            pr.op.BTci = o.b_transpose->colidx;
+            pr.op.BTv = o.b_transpose->values;
+        } else {
+            MSP_CHECK(build_transpose(P, pr, o.force_kind == MSP_KIND_INNER));
+        }
     }
-
-    AnalysisArgs aa{};
-    aa.op = op;
-    aa.force_kind = o.force_kind;
-    aa.inner_ratio = inner_possible ? o.inner_ratio : 0;
-    aa.colcnt_rp = op.BTrp;
-    aa.flops = P->flops;
-    aa.tiles = P->unit_base;
-    aa.bin = P->bin;
-    aa.stats = P->stats_d;
-    MSP_HIP(launch_analysis(aa, s));
-    MSP_HIP(launch_scan(P->unit_base, P->unit_base, m, P->scan_partial, s));
-    MSP_HIP(hipMemcpyAsync(P->stats, P->stats_d, sizeof(P->stats), hipMemcpyDeviceToHost, s));
+    for (int64_t p = 0; p < count; ++p) {
+        Product& pr = P->prods[(size_t)p];
+        AnalysisArgs aa{};
+        aa.op = pr.op;
+        aa.row_off = pr.row_off;
+        aa.force_kind = o.force_kind;
+        aa.inner_ratio = (!pr.op.complement && inner_any) ? o.inner_ratio : 0;
+        aa.maskidx_max = o.maskidx_max;
+        aa.block_flops = o.block_flops;
+        aa.colcnt_rp = pr.op.BTrp;
+        aa.flops = P->flops;
+        aa.tiles = P->unit_base;
+        aa.bin = P->bin;
+        aa.stats = P->stats_d + p * ST_COUNT;
+        MSP_HIP(launch_analysis(aa, s));
+    }
+    MSP_HIP(launch_scan(P->unit_base, P->unit_base, R, P->scan_partial, s));
+    P->stats.assign((size_t)(count * ST_COUNT), 0ull);
+    MSP_HIP(hipMemcpyAsync(P->stats.data(), P->stats_d, sizeof(unsigned long long) * ST_COUNT * count,
+                           hipMemcpyDeviceToHost, s));
     MSP_HIP(hipStreamSynchronize(s));
-    P->U = (int64_t)P->stats[ST_UNITS];
-    P->S = (int64_t)P->stats[ST_STAGING];
-    P->ub = (int64_t)P->stats[ST_UB];
-    // bins in order; inside a bin, flops buckets from the heaviest down
-    P->bin_off[0] = 0;
+
+    // totals; bins in order, inside a bin the flops buckets from the heaviest down
+    std::vector<int64_t> segc(NBINS * NBUCKET, 0);
+    for (int64_t p = 0; p < count; ++p) {
+        Product& pr = P->prods[(size_t)p];
+        const unsigned long long* st = &P->stats[(size_t)(p * ST_COUNT)];
+        pr.ub = (int64_t)st[ST_UB];
+        pr.flops = (int64_t)st[ST_FLOPS];
+        pr.units = (int64_t)st[ST_UNITS];
+        pr.staging = (int64_t)st[ST_STAGING];
+        pr.mnnz = (int64_t)st[ST_MNNZ];
+        for (int b = 0; b < NBINS; ++b) {
+            int64_t t = 0;
+            for (int q = 0; q < NBUCKET; ++q) {
+                t += (int64_t)st[ST_BIN0 + b * NBUCKET + q];
+                segc[(size_t)(b * NBUCKET + q)] += (int64_t)st[ST_BIN0 + b * NBUCKET + q];
+            }
+            pr.bin_units[b] = t;
+        }
+        P->U += pr.units;
+        P->S += pr.staging;
+        P->ub += pr.ub;
+    }
     int64_t run = 0;
     for (int b = 0; b < NBINS; ++b) {
         P->bin_off[b] = run;
         for (int q = NBUCKET - 1; q >= 0; --q) {
             P->seg_off[b * NBUCKET + q] = run;
-            run += (int64_t)P->stats[ST_BIN0 + b * NBUCKET + q];
+            run += segc[(size_t)(b * NBUCKET + q)];
         }
         P->bin_count[b] = run - P->bin_off[b];
     }
     P->bin_off[NBINS] = run;
-    if (P->bin_off[NBINS] != P->U) return fail(MSP_ERR_DEVICE, "inconsistent unit statistics");
+    if (run != P->U) return fail(MSP_ERR_DEVICE, "inconsistent unit statistics");
     if (P->U >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many work units");
-    if (P->bin_count[BIN_INNER_W] > 0 && !o.b_transpose) MSP_CHECK(build_transpose(P, true));
+    for (int64_t p = 0; p < count; ++p) {
+        Product& pr = P->prods[(size_t)p];
+        if (pr.bin_units[BIN_INNER_W] > 0 && !o.b_transpose) MSP_CHECK(build_transpose(P, pr, true));
+    }
 
     const int64_t U = P->U;
     // workspace sized by the units (and the one-phase staging)
@@ -327,43 +418,67 @@ static msp_status plan_create_impl(msp_plan* P, const msp_csr* A, const msp_csr*
         c.add(&P->seg_cursor, NBINS * NBUCKET);
         c.add(&P->unit_row, U);
         c.add(&P->unit_tile, U);
+        c.add(&P->unit_prob, U);
         c.add(&P->stg_off, U + 1);
         c.add(&P->cnt, U + 1);
         c.add(&P->bin_units, U);
         int64_t* part = nullptr;
-        if (U + 1 > m + 1) c.add(&part, scan_partial_elems(U + 1));
+        if (U + 1 > R + 1) c.add(&part, scan_partial_elems(U + 1));
         if (want_staging && o.phase == 1) {
             c.add(&P->stg_col, P->S);
             c.add_bytes(&P->stg_val, (size_t)(P->S > 0 ? P->S : 1) * out_bytes(semiring));
+        }
+        if (count > 1) {
+            c.add(&P->ops_d, count);
+            c.add(&P->outs_d, count);
+            c.add(&P->ent_off_d, count + 1);
         }
         MSP_CHECK(P->alloc_carve(c));
         if (part) P->scan_partial = part;
     }
     MSP_HIP(hipMemcpyAsync(P->seg_off_d, P->seg_off, sizeof(int64_t) * NBINS * NBUCKET, hipMemcpyHostToDevice, s));
     MSP_HIP(hipMemsetAsync(P->seg_cursor, 0, sizeof(unsigned long long) * NBINS * NBUCKET, s));
-    UnitArgs ua{};
-    ua.op = op;
-    ua.flops = P->flops;
-    ua.unit_base = P->unit_base;
-    ua.bin = P->bin;
-    ua.seg_off = P->seg_off_d;
-    ua.seg_cursor = P->seg_cursor;
-    ua.unit_row = P->unit_row;
-    ua.unit_tile = P->unit_tile;
-    ua.stg_size = P->stg_off;
-    ua.bin_units = P->bin_units;
-    MSP_HIP(launch_units(ua, m, s));
+    if (count > 1) {
+        std::vector<Operands> ops((size_t)count);
+        std::vector<int64_t> ent((size_t)count + 1, 0);
+        for (int64_t p = 0; p < count; ++p) {
+            ops[(size_t)p] = P->prods[(size_t)p].op;
+            ent[(size_t)p + 1] = ent[(size_t)p] + P->prods[(size_t)p].op.m + 1;
+        }
+        MSP_HIP(hipMemcpyAsync(P->ops_d, ops.data(), sizeof(Operands) * count, hipMemcpyHostToDevice, s));
+        MSP_HIP(hipMemcpyAsync(P->ent_off_d, ent.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s));
+        MSP_HIP(hipStreamSynchronize(s));  // the host staging vectors go out of scope
+    }
+    for (int64_t p = 0; p < count; ++p) {
+        Product& pr = P->prods[(size_t)p];
+        if (pr.op.m == 0) continue;
+        UnitArgs ua{};
+        ua.op = pr.op;
+        ua.row_off = pr.row_off;
+        ua.prob = (int32_t)p;
+        ua.flops = P->flops;
+        ua.unit_base = P->unit_base;
+        ua.bin = P->bin;
+        ua.seg_off = P->seg_off_d;
+        ua.seg_cursor = P->seg_cursor;
+        ua.unit_row = P->unit_row;
+        ua.unit_tile = P->unit_tile;
+        ua.unit_prob = P->unit_prob;
+        ua.stg_size = P->stg_off;
+        ua.bin_units = P->bin_units;
+        MSP_HIP(launch_units(ua, pr.op.m, s));
+    }
     if (want_staging && o.phase == 1) MSP_HIP(launch_scan(P->stg_off, P->stg_off, U, P->scan_partial, s));
     return MSP_OK;
 }
 
-msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
-                           int complement, msp_semiring semiring, const msp_options* opt, void* stream) {
+static msp_status create_common(msp_plan** plan, const msp_problem* probs, int64_t count, msp_semiring semiring,
+                                const msp_options* opt, void* stream, bool want_staging) {
     if (!plan) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
     *plan = nullptr;
     msp_plan* P = new (std::nothrow) msp_plan();
     if (!P) return fail(MSP_ERR_OUT_OF_MEMORY, "host allocation");
-    const msp_status st = plan_create_impl(P, A, B, M, complement, semiring, opt, (hipStream_t)stream, true);
+    const msp_status st = plan_create_impl(P, probs, count, semiring, opt, (hipStream_t)stream, want_staging);
     if (st != MSP_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         P->release();
@@ -374,24 +489,11 @@ msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, 
     return MSP_OK;
 }
 
-msp_status msp_plan_info(const msp_plan* P, msp_plan_info_t* info) {
-    if (!P || !info) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
-    info->upper_bound = P->ub;
-    info->products = (int64_t)P->stats[ST_FLOPS];
-    info->units = P->U;
-    info->staging = P->S;
-    info->mask_nnz = (int64_t)P->stats[ST_MNNZ];
-    info->kind_units[MSP_KIND_DENSE] = P->bin_count[BIN_DENSE_W] + P->bin_count[BIN_DENSE_B];
-    info->kind_units[MSP_KIND_HASH] = P->bin_count[BIN_HASH_W] + P->bin_count[BIN_HASH_B];
-    info->kind_units[MSP_KIND_MASKIDX] = P->bin_count[BIN_MASKIDX_W] + P->bin_count[BIN_MASKIDX_B];
-    info->kind_units[MSP_KIND_INNER] = P->bin_count[BIN_INNER_W];
-    for (int b = 0; b < 8; ++b) info->bin_units[b] = b < NBINS ? P->bin_count[b] : 0;
-    return MSP_OK;
-}
-
 static NumArgs num_args(const msp_plan* P, int b) {
     NumArgs a{};
-    a.op = P->op;
+    a.op = P->prods[0].op;
+    a.ops = P->P > 1 ? P->ops_d : nullptr;
+    a.unit_prob = P->unit_prob;
     a.unit_row = P->unit_row;
     a.unit_tile = P->unit_tile;
     a.units = P->bin_units + P->bin_off[b];
@@ -399,10 +501,9 @@ static NumArgs num_args(const msp_plan* P, int b) {
     return a;
 }
 
-static msp_status check_out(const msp_plan* P, const msp_csr_out* C) {
+static msp_status check_out(const Product& pr, const msp_csr_out* C) {
     if (!C) return fail(MSP_ERR_INVALID_ARGUMENT, "C is NULL");
-    if (C->nrows != P->op.m || C->ncols != P->op.n)
-        return fail(MSP_ERR_DIMENSION_MISMATCH, "C must be A.nrows x B.ncols");
+    if (C->nrows != pr.op.m || C->ncols != pr.op.n) return fail(MSP_ERR_DIMENSION_MISMATCH, "C must be A.nrows x B.ncols");
     if (!C->rowptr) return fail(MSP_ERR_INVALID_ARGUMENT, "C.rowptr is NULL");
     if (C->capacity < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "negative capacity");
     if (C->capacity > 0 && (!C->colidx || !C->values))
@@ -410,39 +511,19 @@ static msp_status check_out(const msp_plan* P, const msp_csr_out* C) {
     return MSP_OK;
 }
 
-msp_status msp_symbolic(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, void* stream) {
-    if (!P || !C_rowptr) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
-    hipStream_t s = (hipStream_t)stream;
-    for (int b = 0; b < NBINS; ++b) {
-        if (!P->bin_count[b]) continue;
-        NumArgs a = num_args(P, b);
-        a.cnt = P->cnt;
-        MSP_HIP(launch_numeric(P->sr, b, MODE_COUNT, a, s));
-    }
-    MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
-    MSP_HIP(launch_rowptr_from_units(P->op.m, P->unit_base, P->cnt, C_rowptr, s));
-    P->symbolic_done = true;
-    if (nnz_host) {
-        MSP_HIP(hipMemcpyAsync(nnz_host, C_rowptr + P->op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-    }
-    return MSP_OK;
-}
-
-msp_status msp_numeric(msp_plan* P, msp_csr_out* C, void* stream) {
-    if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
-    MSP_CHECK(check_out(P, C));
-    if (!P->symbolic_done) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric needs msp_symbolic first");
-    hipStream_t s = (hipStream_t)stream;
-    for (int b = 0; b < NBINS; ++b) {
-        if (!P->bin_count[b]) continue;
-        NumArgs a = num_args(P, b);
-        a.out_off = P->cnt;
-        a.out_col = C->colidx;
-        a.out_val = C->values;
-        MSP_HIP(launch_numeric(P->sr, b, MODE_DIRECT, a, s));
-    }
-    return MSP_OK;
+static OutBind bind_of(const msp_plan* P, const msp_csr_out* C, int64_t p) {
+    const Product& pr = P->prods[(size_t)p];
+    OutBind ob{};
+    ob.rowptr = C->rowptr;
+    ob.col = C->colidx;
+    ob.val = C->values;
+    ob.row_off = pr.row_off;
+    ob.nrows = pr.op.m;
+    // units of earlier products come first in the global unit numbering
+    int64_t first = 0;
+    for (int64_t q = 0; q < p; ++q) first += P->prods[(size_t)q].units;
+    ob.unit_first = first;
+    return ob;
 }
 
 // Optional per-stage HIP event timing (msp_execute_profiled).
@@ -487,47 +568,10 @@ struct StageTimer {
     }
 };
 
-static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
-    if (P->opt.phase == 2) {
-        int64_t nnz = 0;
-        MSP_CHECK(tm.begin(MSP_STAGE_SYMBOLIC));
-        for (int b = 0; b < NBINS; ++b) {
-            if (!P->bin_count[b]) continue;
-            NumArgs a = num_args(P, b);
-            a.cnt = P->cnt;
-            MSP_HIP(launch_numeric(P->sr, b, MODE_COUNT, a, s));
-        }
-        MSP_CHECK(tm.end());
-        MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
-        MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
-        MSP_CHECK(tm.end());
-        MSP_CHECK(tm.begin(MSP_STAGE_ROWPTR));
-        MSP_HIP(launch_rowptr_from_units(P->op.m, P->unit_base, P->cnt, C->rowptr, s));
-        MSP_CHECK(tm.end());
-        P->symbolic_done = true;
-        MSP_HIP(hipMemcpyAsync(&nnz, C->rowptr + P->op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-        if (C->capacity < nnz) {
-            if (nnz_host) *nnz_host = nnz;
-            return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "capacity below nnz(C)");
-        }
-        for (int b = 0; b < NBINS; ++b) {
-            if (!P->bin_count[b]) continue;
-            NumArgs a = num_args(P, b);
-            a.out_off = P->cnt;
-            a.out_col = C->colidx;
-            a.out_val = C->values;
-            MSP_CHECK(tm.begin(b));
-            MSP_HIP(launch_numeric(P->sr, b, MODE_DIRECT, a, s));
-            MSP_CHECK(tm.end());
-        }
-        if (nnz_host) *nnz_host = nnz;
-        return MSP_OK;
-    }
-    if (C->capacity < P->ub) {
-        if (nnz_host) *nnz_host = P->ub;
-        return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "one-phase output capacity below the upper bound");
-    }
+// The one-phase sequence over all products: numeric into staging, prefix sum
+// of the unit counts, row pointers, compaction. Kernels only (no allocation,
+// no memset, no synchronization), so it can be captured in a HIP graph.
+static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, StageTimer& tm) {
     if (!P->stg_col) return fail(MSP_ERR_INVALID_ARGUMENT, "plan has no one-phase staging");
     for (int b = 0; b < NBINS; ++b) {
         if (!P->bin_count[b]) continue;
@@ -543,41 +587,135 @@ static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, h
     MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
     MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
     MSP_CHECK(tm.end());
+    const OutBind* outs = P->P > 1 ? P->outs_d : nullptr;
+    const int64_t entries = P->P > 1 ? P->R + P->P : P->prods[0].op.m + 1;
     MSP_CHECK(tm.begin(MSP_STAGE_ROWPTR));
-    MSP_HIP(launch_rowptr_from_units(P->op.m, P->unit_base, P->cnt, C->rowptr, s));
+    MSP_HIP(launch_rowptr(P->P, entries, P->ent_off_d, outs, one, P->unit_base, P->cnt, s));
     MSP_CHECK(tm.end());
     CompactArgs ca{};
-    ca.m = P->op.m;
     ca.U = P->U;
-    ca.unit_base = P->unit_base;
     ca.stg_off = P->stg_off;
     ca.out_off = P->cnt;
+    ca.unit_prob = P->unit_prob;
     ca.stg_col = P->stg_col;
     ca.stg_val = P->stg_val;
     ca.val_bytes = out_bytes(P->sr);
-    ca.C_rowptr = C->rowptr;
-    ca.C_col = C->colidx;
-    ca.C_val = C->values;
+    ca.one = one;
+    ca.outs = outs;
     MSP_CHECK(tm.begin(MSP_STAGE_COMPACT));
     MSP_HIP(launch_compact(ca, s));
     MSP_CHECK(tm.end());
+    return MSP_OK;
+}
+
+static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
+    const Product& pr = P->prods[0];
+    MSP_CHECK(tm.begin(MSP_STAGE_SYMBOLIC));
+    for (int b = 0; b < NBINS; ++b) {
+        if (!P->bin_count[b]) continue;
+        NumArgs a = num_args(P, b);
+        a.cnt = P->cnt;
+        MSP_HIP(launch_numeric(P->sr, b, MODE_COUNT, a, s));
+    }
+    MSP_CHECK(tm.end());
+    MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
+    MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
+    MSP_CHECK(tm.end());
+    OutBind one{};
+    one.rowptr = C_rowptr;
+    one.nrows = pr.op.m;
+    MSP_CHECK(tm.begin(MSP_STAGE_ROWPTR));
+    MSP_HIP(launch_rowptr(1, pr.op.m + 1, nullptr, nullptr, one, P->unit_base, P->cnt, s));
+    MSP_CHECK(tm.end());
+    P->symbolic_done = true;
     if (nnz_host) {
-        MSP_HIP(hipMemcpyAsync(nnz_host, C->rowptr + P->op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipMemcpyAsync(nnz_host, C_rowptr + pr.op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         MSP_HIP(hipStreamSynchronize(s));
     }
     return MSP_OK;
 }
 
+static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, hipStream_t s, StageTimer& tm) {
+    for (int b = 0; b < NBINS; ++b) {
+        if (!P->bin_count[b]) continue;
+        NumArgs a = num_args(P, b);
+        a.out_off = P->cnt;
+        a.out_col = C->colidx;
+        a.out_val = C->values;
+        MSP_CHECK(tm.begin(b));
+        MSP_HIP(launch_numeric(P->sr, b, MODE_DIRECT, a, s));
+        MSP_CHECK(tm.end());
+    }
+    return MSP_OK;
+}
+
+static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
+    if (P->P != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_execute takes a single-product plan; use msp_batch_*");
+    const Product& pr = P->prods[0];
+    MSP_CHECK(check_out(pr, C));
+    if (P->opt.phase == 2) {
+        int64_t nnz = 0;
+        MSP_CHECK(symbolic_impl(P, C->rowptr, &nnz, s, tm));
+        if (C->capacity < nnz) {
+            if (nnz_host) *nnz_host = nnz;
+            return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "capacity below nnz(C)");
+        }
+        MSP_CHECK(numeric_impl(P, C, s, tm));
+        if (nnz_host) *nnz_host = nnz;
+        return MSP_OK;
+    }
+    if (C->capacity < P->ub) {
+        if (nnz_host) *nnz_host = P->ub;
+        return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "one-phase output capacity below the upper bound");
+    }
+    const OutBind one = bind_of(P, C, 0);
+    MSP_CHECK(run_one_phase(P, one, s, tm));
+    if (nnz_host) {
+        MSP_HIP(hipMemcpyAsync(nnz_host, C->rowptr + pr.op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+    }
+    return MSP_OK;
+}
+
+extern "C" {
+
+msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
+                           int complement, msp_semiring semiring, const msp_options* opt, void* stream) {
+    if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
+    msp_problem pb{};
+    pb.A = *A;
+    pb.B = *B;
+    pb.M = *M;
+    pb.complement = complement;
+    return create_common(plan, &pb, 1, semiring, opt, stream, true);
+}
+
+msp_status msp_plan_info(const msp_plan* P, msp_plan_info_t* info) { return msp_batch_info(P, -1, info); }
+
+msp_status msp_symbolic(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, void* stream) {
+    if (!P || !C_rowptr) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (P->P != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_symbolic takes a single-product plan");
+    StageTimer none;
+    return symbolic_impl(P, C_rowptr, nnz_host, (hipStream_t)stream, none);
+}
+
+msp_status msp_numeric(msp_plan* P, msp_csr_out* C, void* stream) {
+    if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (P->P != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric takes a single-product plan");
+    MSP_CHECK(check_out(P->prods[0], C));
+    if (!P->symbolic_done) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric needs msp_symbolic first");
+    StageTimer none;
+    return numeric_impl(P, C, (hipStream_t)stream, none);
+}
+
 msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* stream) {
     if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
-    MSP_CHECK(check_out(P, C));
     StageTimer none;
     return execute_impl(P, C, nnz_host, (hipStream_t)stream, none);
 }
 
 msp_status msp_execute_profiled(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, double* stage_ms, void* stream) {
     if (!P || !stage_ms) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
-    MSP_CHECK(check_out(P, C));
     StageTimer tm;
     tm.on = true;
     tm.s = (hipStream_t)stream;
@@ -586,10 +724,10 @@ msp_status msp_execute_profiled(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, 
 }
 
 msp_status msp_plan_row_bins(const msp_plan* P, int8_t* bins, void* stream) {
-    if (!P || (!bins && P->op.m > 0)) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (P->op.m == 0) return MSP_OK;
+    if (!P || (!bins && P->R > 0)) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (P->R == 0) return MSP_OK;
     hipStream_t s = (hipStream_t)stream;
-    MSP_HIP(hipMemcpyAsync(bins, P->bin, (size_t)P->op.m, hipMemcpyDeviceToHost, s));
+    MSP_HIP(hipMemcpyAsync(bins, P->bin, (size_t)P->R, hipMemcpyDeviceToHost, s));
     MSP_HIP(hipStreamSynchronize(s));
     return MSP_OK;
 }
@@ -614,17 +752,18 @@ msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* 
 msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
                            int64_t* upper_bound, void* stream) {
     if (!upper_bound) return fail(MSP_ERR_INVALID_ARGUMENT, "upper_bound is NULL");
-    msp_plan* P = new (std::nothrow) msp_plan();
-    if (!P) return fail(MSP_ERR_OUT_OF_MEMORY, "host allocation");
-    msp_options o;
-    msp_options_default(&o);
-    const msp_status st = plan_create_impl(P, A, B, M, complement, MSP_PLUS_PAIR_I64, &o, (hipStream_t)stream,
-                                           false);
-    if (st == MSP_OK) *upper_bound = P->ub;
+    if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
+    msp_problem pb{};
+    pb.A = *A;
+    pb.B = *B;
+    pb.M = *M;
+    pb.complement = complement;
+    msp_plan* P = nullptr;
+    MSP_CHECK(create_common(&P, &pb, 1, MSP_PLUS_PAIR_I64, nullptr, stream, false));
+    *upper_bound = P->ub;
     (void)hipStreamSynchronize((hipStream_t)stream);
-    P->release();
-    delete P;
-    return st;
+    msp_plan_destroy(P);
+    return MSP_OK;
 }
 
 msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result, void* stream) {
@@ -642,6 +781,104 @@ msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void
     if (pooled) (void)hipFreeAsync(partial, s);
     else { (void)hipStreamSynchronize(s); (void)hipFree(partial); }
     MSP_HIP(le);
+    return MSP_OK;
+}
+
+// ------------------------------------------------------------------- batches
+
+msp_status msp_batch_create(msp_plan** batch, const msp_problem* problems, int64_t count, msp_semiring semiring,
+                            const msp_options* opt, void* stream) {
+    return create_common(batch, problems, count, semiring, opt, stream, true);
+}
+
+int64_t msp_batch_count(const msp_plan* P) { return P ? P->P : 0; }
+
+msp_status msp_batch_info(const msp_plan* P, int64_t p, msp_plan_info_t* info) {
+    if (!P || !info) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (p < -1 || p >= P->P) return fail(MSP_ERR_INVALID_ARGUMENT, "product index out of range");
+    std::memset(info, 0, sizeof(*info));
+    for (int64_t q = 0; q < P->P; ++q) {
+        if (p >= 0 && q != p) continue;
+        const Product& pr = P->prods[(size_t)q];
+        info->upper_bound += pr.ub;
+        info->products += pr.flops;
+        info->units += pr.units;
+        info->staging += pr.staging;
+        info->mask_nnz += pr.mnnz;
+        info->kind_units[MSP_KIND_DENSE] += pr.bin_units[BIN_DENSE_W] + pr.bin_units[BIN_DENSE_B];
+        info->kind_units[MSP_KIND_HASH] += pr.bin_units[BIN_HASH_W] + pr.bin_units[BIN_HASH_B];
+        info->kind_units[MSP_KIND_MASKIDX] += pr.bin_units[BIN_MASKIDX_W] + pr.bin_units[BIN_MASKIDX_B];
+        info->kind_units[MSP_KIND_INNER] += pr.bin_units[BIN_INNER_W];
+        for (int b = 0; b < NBINS; ++b) info->bin_units[b] += pr.bin_units[b];
+    }
+    return MSP_OK;
+}
+
+msp_status msp_batch_bind(msp_plan* P, const msp_csr_out* C, void* stream) {
+    if (!P || !C) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::vector<OutBind> outs((size_t)P->P);
+    for (int64_t p = 0; p < P->P; ++p) {
+        const Product& pr = P->prods[(size_t)p];
+        MSP_CHECK(check_out(pr, &C[p]));
+        if (C[p].capacity < pr.ub) return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "output capacity below its upper bound");
+        outs[(size_t)p] = bind_of(P, &C[p], p);
+    }
+    if (P->P > 1) {
+        hipStream_t s = (hipStream_t)stream;
+        MSP_HIP(hipMemcpyAsync(P->outs_d, outs.data(), sizeof(OutBind) * P->P, hipMemcpyHostToDevice, s));
+        MSP_HIP(hipStreamSynchronize(s));
+    }
+    P->outs = std::move(outs);
+    // a captured graph refers to the previous outputs
+    if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+    if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+    P->bound = true;
+    return MSP_OK;
+}
+
+msp_status msp_batch_execute(msp_plan* P, void* stream) {
+    if (!P || !P->bound) return fail(MSP_ERR_INVALID_ARGUMENT, "batch outputs are not bound");
+    StageTimer none;
+    return run_one_phase(P, P->outs[0], (hipStream_t)stream, none);
+}
+
+msp_status msp_batch_graph_launch(msp_plan* P, void* stream) {
+    if (!P || !P->bound) return fail(MSP_ERR_INVALID_ARGUMENT, "batch outputs are not bound");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(MSP_ERR_INVALID_ARGUMENT, "graph capture needs a non-default stream");
+    if (P->gexec && P->graph_stream != s) {
+        (void)hipGraphExecDestroy(P->gexec);
+        (void)hipGraphDestroy(P->graph);
+        P->gexec = nullptr;
+        P->graph = nullptr;
+    }
+    if (!P->gexec) {
+        MSP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        StageTimer none;
+        const msp_status st = run_one_phase(P, P->outs[0], s, none);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s, &g);
+        if (st != MSP_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        MSP_HIP(ee);
+        P->graph = g;
+        MSP_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+        P->graph_stream = s;
+    }
+    MSP_HIP(hipGraphLaunch(P->gexec, s));
+    return MSP_OK;
+}
+
+msp_status msp_batch_nnz(const msp_plan* P, int64_t* nnz, void* stream) {
+    if (!P || !nnz || !P->bound) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument or unbound batch");
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t p = 0; p < P->P; ++p) {
+        const OutBind& ob = P->outs[(size_t)p];
+        MSP_HIP(hipMemcpyAsync(&nnz[p], ob.rowptr + ob.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
+    MSP_HIP(hipStreamSynchronize(s));
     return MSP_OK;
 }
 

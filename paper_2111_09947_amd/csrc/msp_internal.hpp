@@ -31,11 +31,8 @@ constexpr int MASKIDX_B_CAP = 4096;
 constexpr int INNER_CAP = 256;
 constexpr int INNER_ACAP = 512;   // A row staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
-#ifndef MSP_MASKIDX_SMALL
-#define MSP_MASKIDX_SMALL 8
-#endif
-constexpr int MASKIDX_SMALL = MSP_MASKIDX_SMALL;  // auto: binary search up to this mask size, hash above
-constexpr int64_t BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
+constexpr int DEFAULT_MASKIDX_MAX = 8;       // auto: binary search up to this mask size, hash above
+constexpr int64_t DEFAULT_BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
 // Units of a bin are ordered by the product count of their row, heaviest
 // first (bucket b holds rows with 4^b <= flops < 4^(b+1)), so that the
 // longest units start first and do not form the tail of the launch.
@@ -67,30 +64,38 @@ struct Operands {
 
 struct AnalysisArgs {
     Operands op;
+    int64_t row_off;           // first global row of this product
     int force_kind;
     int inner_ratio;
+    int maskidx_max;
+    int64_t block_flops;
     const int64_t* colcnt_rp;  // row pointers of B^T (column counts of B) or null
-    int64_t* flops;            // [m]
-    int64_t* tiles;            // [m+1], number of units per row (scanned later)
-    int8_t* bin;               // [m]
-    unsigned long long* stats; // [ST_COUNT]
+    int64_t* flops;            // [R] global rows
+    int64_t* tiles;            // [R+1], number of units per row (scanned later)
+    int8_t* bin;               // [R]
+    unsigned long long* stats; // [ST_COUNT] of this product
 };
 
 struct UnitArgs {
     Operands op;
+    int64_t row_off;           // first global row of this product
+    int32_t prob;              // product index
     const int64_t* flops;
-    const int64_t* unit_base;  // [m+1] exclusive scan of tiles
+    const int64_t* unit_base;  // [R+1] exclusive scan of tiles over global rows
     const int8_t* bin;
     const int64_t* seg_off;    // [NBINS * NBUCKET] start of each (bin, bucket) segment in bin_units
     unsigned long long* seg_cursor;  // [NBINS * NBUCKET], zeroed
-    int32_t* unit_row;
+    int32_t* unit_row;         // local row within the product
     int32_t* unit_tile;
+    int32_t* unit_prob;        // product of the unit
     int64_t* stg_size;         // [U+1] staging entries per unit (scanned later)
     int32_t* bin_units;
 };
 
 struct NumArgs {
-    Operands op;
+    Operands op;               // operands when ops == nullptr (single product)
+    const Operands* ops;       // per-product operands (device), or nullptr
+    const int32_t* unit_prob;  // product of each unit (with ops)
     const int32_t* unit_row;
     const int32_t* unit_tile;
     const int32_t* units;      // this bin's units
@@ -101,18 +106,26 @@ struct NumArgs {
     void* out_val;
 };
 
+// Per-product output binding (device table entry when batched).
+struct OutBind {
+    int64_t* rowptr;
+    int32_t* col;
+    void* val;
+    int64_t row_off;     // first global row
+    int64_t nrows;
+    int64_t unit_first;  // first global unit (= unit_base[row_off])
+};
+
 struct CompactArgs {
-    int64_t m;
     int64_t U;
-    const int64_t* unit_base;  // [m+1]
     const int64_t* stg_off;    // [U+1]
     const int64_t* out_off;    // [U+1] (scanned counts)
+    const int32_t* unit_prob;  // [U] (batched) or nullptr
     const int32_t* stg_col;
     const void* stg_val;
     int val_bytes;
-    int64_t* C_rowptr;
-    int32_t* C_col;
-    void* C_val;
+    OutBind one;               // single product
+    const OutBind* outs;       // per product (device) or nullptr
 };
 
 // ---- launchers (msp_kernels.hip). All enqueue on `s` and return the launch error.
@@ -132,8 +145,10 @@ int64_t scan_partial_elems(int64_t n);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s);
 hipError_t launch_numeric(int semiring, int bin, int mode, const NumArgs& a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
-hipError_t launch_rowptr_from_units(int64_t m, const int64_t* unit_base, const int64_t* out_off,
-                                    int64_t* C_rowptr, hipStream_t s);
+// Row pointers of every product: C_p.rowptr[i] = out_off[unit_base[row_off_p + i]] - out_off[unit_first_p].
+// `outs` (device, P entries) or `one` (P == 1); `ent_off` (device, P + 1) = row_off_p + p.
+hipError_t launch_rowptr(int64_t P, int64_t total_entries, const int64_t* ent_off, const OutBind* outs,
+                         const OutBind& one, const int64_t* unit_base, const int64_t* out_off, hipStream_t s);
 // B^T construction: column counts -> scan -> scatter (rows of B^T unsorted).
 hipError_t launch_colcount(const int32_t* ci, int64_t nnz, int64_t* cnt, hipStream_t s);
 hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const void* v, int val_bytes,

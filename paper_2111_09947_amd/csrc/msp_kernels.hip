@@ -154,16 +154,16 @@ __device__ __forceinline__ int64_t cdiv(int64_t x, int64_t y) { return (x + y - 
 
 // Accumulator kind and tiling of one row (auto or forced).
 __device__ void classify(int64_t mnnz, int64_t flops, int64_t n, int comp, int force, int inner_ratio,
-                        int64_t icost, int& bin, int64_t& tiles) {
+                        int maskidx_max, int64_t block_flops, int64_t icost, int& bin, int64_t& tiles) {
     int kind = comp ? (int)MSP_KIND_DENSE : force;
     if (kind == MSP_KIND_AUTO) {
         if (inner_ratio > 0 && icost * (int64_t)inner_ratio < flops) kind = MSP_KIND_INNER;
         else if (n <= DENSE_W_COLS) kind = MSP_KIND_DENSE;
-        else if (mnnz <= MASKIDX_SMALL) kind = MSP_KIND_MASKIDX;
+        else if (mnnz <= maskidx_max) kind = MSP_KIND_MASKIDX;
         else if (mnnz <= HASH_B_CAP) kind = MSP_KIND_HASH;
         else kind = MSP_KIND_MASKIDX;
     }
-    const bool heavy = flops > BLOCK_FLOPS;
+    const bool heavy = flops > block_flops;
     switch (kind) {
     case MSP_KIND_DENSE:
         if (n <= DENSE_W_COLS && !heavy) { bin = BIN_DENSE_W; tiles = 1; }
@@ -236,13 +236,14 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
         ub = min(adm, flops);
         int bin = -1;
         if (ub > 0) {
-            classify(mnnz, flops, o.n, o.complement, a.force_kind, a.inner_ratio, icost, bin, tiles);
+            classify(mnnz, flops, o.n, o.complement, a.force_kind, a.inner_ratio, a.maskidx_max, a.block_flops,
+                     icost, bin, tiles);
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
             seg = bin * NBUCKET + flops_bucket(flops);
         }
-        a.flops[i] = flops;
-        a.tiles[i] = tiles;
-        a.bin[i] = (int8_t)bin;
+        a.flops[a.row_off + i] = flops;
+        a.tiles[a.row_off + i] = tiles;
+        a.bin[a.row_off + i] = (int8_t)bin;
     }
     // per-segment unit counts: one LDS atomic per distinct segment per wave
     bool pending = seg >= 0;
@@ -300,15 +301,17 @@ __global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
     int seg = -1;
     unsigned int rank = 0;
     if (has) {
-        base = a.unit_base[i];
-        tiles = a.unit_base[i + 1] - base;
+        const int64_t gr = a.row_off + i;
+        base = a.unit_base[gr];
+        tiles = a.unit_base[gr + 1] - base;
         if (tiles > 0) {
-            const int bin = a.bin[i];
+            const int bin = a.bin[gr];
             const int64_t mnnz = o.Mrp[i + 1] - o.Mrp[i];
-            const int64_t flops = a.flops[i];
+            const int64_t flops = a.flops[gr];
             for (int64_t t = 0; t < tiles; ++t) {
                 a.unit_row[base + t] = (int32_t)i;
                 a.unit_tile[base + t] = (int32_t)t;
+                a.unit_prob[base + t] = a.prob;
                 a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
             }
             seg = bin * NBUCKET + flops_bucket(flops);
@@ -559,7 +562,7 @@ __device__ __forceinline__ void unit_sync() {
 // the mask row), values and (where the value cannot tell) inserted flags.
 // Emission scans the tile in column order, so rows come out sorted for both
 // mask modes.
-template <int SR, int MODE, int NW, int W, int WPB>
+template <int SR, int MODE, int NW, int W, int WPB, bool BATCH>
 __global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
     static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
@@ -573,14 +576,15 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
     __shared__ uint8_t flags_[WPB][FLAGS ? W : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
-    const Operands& o = g.op;
     const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;  // only one-wave units can leave early (WPB > 1 implies NW == 1)
     uint32_t* allowed = allowed_[gi];
     acc_t* vals = vals_[gi];
     uint8_t* flags = flags_[gi];
-    const int u = g.units[uix];
+    // the unit is the same for every lane of the wave
+    const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
+    const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
     const int64_t i = g.unit_row[u];
     const int64_t c0 = (int64_t)g.unit_tile[u] * W;
     const int wt = (int)min((int64_t)W, o.n - c0);
@@ -681,7 +685,7 @@ __device__ __forceinline__ int hash_find(const int4* tkey, const uint16_t* trank
     return h < 0 ? -1 : (int)trank[b * 4 + h];
 }
 
-template <int SR, int MODE, int NW, int CAP, bool HASHED, int WPB>
+template <int SR, int MODE, int NW, int CAP, bool HASHED, int WPB, bool BATCH>
 __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
     static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
@@ -697,7 +701,6 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
     __shared__ uint8_t flags_[WPB][FLAGS ? CAP : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
-    const Operands& o = g.op;
     const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;  // only one-wave units can leave early (WPB > 1 implies NW == 1)
@@ -706,7 +709,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
     uint16_t* trank = trank_[gi];
     acc_t* vals = vals_[gi];
     uint8_t* flags = flags_[gi];
-    const int u = g.units[uix];
+    // the unit is the same for every lane of the wave
+    const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
+    const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
     const int64_t i = g.unit_row[u];
     const int64_t r0 = (int64_t)g.unit_tile[u] * CAP;
     const int64_t mrow = o.Mrp[i];
@@ -773,7 +778,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
 // the sparse dot product of A(i,:) with column j of B (row j of B^T) by
 // looking up every k of that column in A's row (staged in LDS when short,
 // else a binary search in global memory).
-template <int SR, int MODE, int CAP, int ACAP, int WPB>
+template <int SR, int MODE, int CAP, int ACAP, int WPB, bool BATCH>
 __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
@@ -781,14 +786,15 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     constexpr bool COUNT = MODE == MODE_COUNT;
     __shared__ int32_t akeys_[WPB][ACAP];
     __shared__ in_t avals_[WPB][T::needs_values ? ACAP : 1];
-    const Operands& o = g.op;
     const int ln = lane();
     const int gi = threadIdx.x / WAVE;
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;
     int32_t* akeys = akeys_[gi];
     in_t* avals = avals_[gi];
-    const int u = g.units[uix];
+    // the unit is the same for every lane of the wave
+    const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
+    const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
     const int64_t i = g.unit_row[u];
     const int64_t r0 = (int64_t)g.unit_tile[u] * CAP;
     const int64_t mrow = o.Mrp[i];
@@ -849,31 +855,31 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
 #endif
 constexpr int WPB = MSP_WPB;  // independent one-wave units per block
 
-template <int SR, int MODE>
+template <int SR, int MODE, bool BATCH>
 static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
     const dim3 gw((unsigned)((a.nunits + WPB - 1) / WPB)), gb((unsigned)a.nunits);
     const dim3 bw(WPB * WAVE), bb(BLOCK_NW * WAVE);
     switch (bin) {
     case BIN_DENSE_W:
-        hipLaunchKernelGGL((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB>), gw, bw, 0, s, a);
+        hipLaunchKernelGGL((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_DENSE_B:
-        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1>), gb, bb, 0, s, a);
+        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_HASH_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, true, WPB>), gw, bw, 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, true, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_HASH_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, true, 1>), gb, bb, 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, true, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_MASKIDX_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false, WPB>), gw, bw, 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_MASKIDX_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false, 1>), gb, bb, 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_INNER_W:
-        hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB>), gw, bw, 0, s, a);
+        hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -883,10 +889,12 @@ static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
 
 template <int SR>
 static hipError_t launch_numeric_sr(int bin, int mode, const NumArgs& a, hipStream_t s) {
+    // batches (per-unit operands) run one-phase only
+    if (a.ops) return mode == MODE_STAGE ? launch_numeric_t<SR, MODE_STAGE, true>(bin, a, s) : hipErrorInvalidValue;
     switch (mode) {
-    case MODE_COUNT: return launch_numeric_t<SR, MODE_COUNT>(bin, a, s);
-    case MODE_STAGE: return launch_numeric_t<SR, MODE_STAGE>(bin, a, s);
-    case MODE_DIRECT: return launch_numeric_t<SR, MODE_DIRECT>(bin, a, s);
+    case MODE_COUNT: return launch_numeric_t<SR, MODE_COUNT, false>(bin, a, s);
+    case MODE_STAGE: return launch_numeric_t<SR, MODE_STAGE, false>(bin, a, s);
+    case MODE_DIRECT: return launch_numeric_t<SR, MODE_DIRECT, false>(bin, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -916,11 +924,13 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
     const int64_t u = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
     if (u >= a.U) return;
-    const int64_t src = a.stg_off[u], dst = a.out_off[u], n = a.out_off[u + 1] - dst;
+    const OutBind& ob = a.outs ? a.outs[a.unit_prob[u]] : a.one;
+    const int64_t src = a.stg_off[u], n = a.out_off[u + 1] - a.out_off[u];
+    const int64_t dst = a.out_off[u] - a.out_off[ob.unit_first];
     const V* sv = static_cast<const V*>(a.stg_val);
-    V* dv = static_cast<V*>(a.C_val);
+    V* dv = static_cast<V*>(ob.val);
     for (int64_t x = lane(); x < n; x += WAVE) {
-        a.C_col[dst + x] = a.stg_col[src + x];
+        ob.col[dst + x] = a.stg_col[src + x];
         dv[dst + x] = sv[src + x];
     }
 }
@@ -937,16 +947,30 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_rowptr(int64_t m, const int64_t* __restrict__ unit_base, const int64_t* __restrict__ out_off,
-                         int64_t* __restrict__ rp) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= m) rp[i] = out_off[unit_base[i]];
+// One thread per row pointer entry of every product (nrows_p + 1 entries each).
+__global__ void k_rowptr(int64_t P, int64_t total, const int64_t* __restrict__ ent_off, const OutBind* outs,
+                         OutBind one, const int64_t* __restrict__ unit_base, const int64_t* __restrict__ out_off) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    int64_t p = 0;
+    if (outs) {  // product of entry t: last p with ent_off[p] <= t
+        int64_t lo = 0, hi = P - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (ent_off[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        p = lo;
+    }
+    const OutBind& ob = outs ? outs[p] : one;
+    const int64_t i = t - (outs ? ent_off[p] : 0);
+    ob.rowptr[i] = out_off[unit_base[ob.row_off + i]] - out_off[ob.unit_first];
 }
 
-hipError_t launch_rowptr_from_units(int64_t m, const int64_t* unit_base, const int64_t* out_off,
-                                    int64_t* C_rowptr, hipStream_t s) {
-    hipLaunchKernelGGL(k_rowptr, dim3(grid_for(m + 1, 256, INT32_MAX)), dim3(256), 0, s, m, unit_base, out_off,
-                       C_rowptr);
+hipError_t launch_rowptr(int64_t P, int64_t total_entries, const int64_t* ent_off, const OutBind* outs,
+                         const OutBind& one, const int64_t* unit_base, const int64_t* out_off, hipStream_t s) {
+    if (total_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rowptr, dim3(grid_for(total_entries, 256, INT32_MAX)), dim3(256), 0, s, P, total_entries,
+                       ent_off, outs, one, unit_base, out_off);
     return hipGetLastError();
 }
 

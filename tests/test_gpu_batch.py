@@ -1,0 +1,90 @@
+"""GPU parity of batches: every product of a batch (one launch per kernel bin
+for all products, optionally replayed from a captured HIP graph) equals the
+oracle and the same product run alone."""
+import numpy as np
+import pytest
+
+import mspgen
+import oracle
+from tests.gpu_util import assert_same, msp, torch_or_skip, up
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_problems(seed, sr="plus_times_f64"):
+    vk = {"plus_times_f64": "f64", "plus_pair_i64": "f64", "plus_times_i32": "i32", "lor_land_bool": "u8"}[sr]
+    rng = np.random.default_rng(seed)
+    probs = []
+    shapes = [(300, 200, 400, 5, 6, 30, False), (150, 700, 9000, 9, 7, 80, False), (1, 5, 5, 2, 2, 2, False),
+              (0, 10, 10, 1, 1, 1, False), (400, 300, 500, 4, 5, 50, True), (200, 100, 20000, 30, 40, 3000, False),
+              (64, 64, 64, 8, 8, 8, True), (100, 50, 3000, 20, 100, 10, False)]
+    for t, (m, k, n, da, db, dm, comp) in enumerate(shapes):
+        s = int(rng.integers(1, 10**6))
+        A = mspgen.er(m, k, da, s + 1, vk)
+        B = mspgen.er(k, n, db, s + 2, vk)
+        M = mspgen.er(m, n, dm, s + 3, None)
+        probs.append((A, B, M, comp))
+    return probs
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64", "plus_times_i32", "lor_land_bool"])
+def test_batch_matches_oracle_and_single(sr):
+    torch = torch_or_skip()
+    m = msp()
+    probs = _mixed_problems(7, sr)
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    with m.Batch(dev, semiring=sr) as b:
+        b.bind_new_outputs()
+        b.execute()
+        res = b.results()
+        for (A, B, M, c), C, d in zip(probs, res, dev):
+            R = oracle.masked_spgemm(A, B, M, c, sr)
+            assert_same(C, R, sr)
+            single = m.masked_spgemm(d[0], d[1], d[2], complement=c, semiring=sr)
+            assert torch.equal(single.rowptr, C.rowptr) and torch.equal(single.colidx, C.colidx)
+            if sr != "plus_times_f64":
+                assert torch.equal(single.values, C.values)
+
+
+def test_batch_graph_replays():
+    """The captured graph replayed several times, with unrelated eager work
+    and synchronizations in between, gives the oracle's result every time."""
+    torch = torch_or_skip()
+    m = msp()
+    sr = "plus_times_f64"
+    probs = _mixed_problems(11, sr)
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    refs = [oracle.masked_spgemm(A, B, M, c, sr) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr) as b:
+            outs = b.bind_new_outputs()
+            for rep in range(4):
+                for (rp, ci, v) in outs:  # poison the outputs between replays
+                    rp.fill_(-1)
+                    ci.fill_(-1)
+                    v.fill_(float("nan"))
+                b.graph_launch()
+                x = torch.ones(1 << 20, device="cuda") * rep  # eager work on the same stream
+                s.synchronize()
+                assert float(x.sum().item()) == float(rep * (1 << 20))
+                for C, R in zip(b.results(), refs):
+                    assert_same(C, R, sr)
+
+
+def test_batch_rebind_changes_outputs():
+    torch = torch_or_skip()
+    m = msp()
+    sr = "plus_pair_i64"
+    probs = _mixed_problems(13, sr)
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr) as b:
+            b.bind_new_outputs()
+            b.graph_launch()
+            first = [(C.colidx.clone(), C.values.clone()) for C in b.results()]
+            b.bind_new_outputs()
+            b.graph_launch()
+            for (ci, v), C in zip(first, b.results()):
+                assert torch.equal(ci, C.colidx) and torch.equal(v, C.values)
