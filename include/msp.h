@@ -143,10 +143,14 @@ typedef struct msp_options {
     int64_t block_flops;  /* rows with more products than this run on a whole
                              256-thread workgroup instead of one wavefront
                              (-1 = default 8192) */
+    int64_t split_flops;  /* dense-kind rows (at most 4096 columns) with more
+                             products than this are split over several
+                             workgroups by chunks of A's row (-1 = default
+                             262144; 0 = never split) */
 } msp_options;
 
 /* Fills `opt` with the defaults: phase 1, auto kind, no validation,
-   inner_ratio 0, no B^T, maskidx_max 8, block_flops 8192. */
+   inner_ratio 0, no B^T, maskidx_max 8, block_flops 8192, split_flops 262144. */
 void msp_options_default(msp_options* opt);
 
 /* Plan statistics, filled by msp_plan_info. */
@@ -159,7 +163,7 @@ typedef struct msp_plan_info_t {
     int64_t staging;         /* staging entries used by one-phase execution */
     int64_t mask_nnz;        /* nnz(M) */
     int64_t kind_units[4];   /* units per msp_kind */
-    int64_t bin_units[8];    /* units per kernel bin (MSP_BIN_*; 7 used) */
+    int64_t bin_units[16];   /* units per kernel bin (MSP_BIN_*; MSP_NBINS used) */
 } msp_plan_info_t;
 
 /*
@@ -175,17 +179,21 @@ enum {
     MSP_BIN_MASKIDX_WAVE = 4,
     MSP_BIN_MASKIDX_BLOCK = 5,
     MSP_BIN_INNER_WAVE = 6,
-    MSP_NBINS = 7
+    MSP_BIN_DENSE_BLOCK_NARROW = 7,  /* dense state over <= 512 columns, one workgroup per row */
+    MSP_BIN_DENSE_SPLIT = 8,         /* rows with many products: one workgroup per chunk of the
+                                        row of A, merged into a per-row accumulator */
+    MSP_NBINS = 9
 };
 
-/* Stage slots of msp_execute_profiled: 0..6 = numeric kernel of bin b,
+/* Stage slots of msp_execute_profiled: 0..15 = numeric kernel of bin b,
    then these. */
 enum {
-    MSP_STAGE_SYMBOLIC = 7,   /* all symbolic count kernels (two-phase) */
-    MSP_STAGE_SCAN = 8,       /* prefix sums of the unit counts */
-    MSP_STAGE_ROWPTR = 9,     /* row pointers of C */
-    MSP_STAGE_COMPACT = 10,   /* one-phase staging -> C */
-    MSP_NSTAGES = 11
+    MSP_STAGE_SYMBOLIC = 16,  /* all symbolic count kernels (two-phase) */
+    MSP_STAGE_SCAN = 17,      /* prefix sums of the unit counts */
+    MSP_STAGE_ROWPTR = 18,    /* row pointers of C */
+    MSP_STAGE_COMPACT = 19,   /* one-phase staging -> C */
+    MSP_STAGE_SPLIT_EMIT = 20,  /* emission of the split rows */
+    MSP_NSTAGES = 21
 };
 
 typedef struct msp_plan msp_plan;

@@ -116,7 +116,7 @@ def _check(st: int, where: str):
 
 def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio: int = 0,
             b_transpose: Optional[L.MspCsr] = None, maskidx_max: int = -1,
-            block_flops: int = -1) -> L.MspOptions:
+            block_flops: int = -1, split_flops: int = -1) -> L.MspOptions:
     o = L.MspOptions()
     L.load().msp_options_default(ctypes.byref(o))
     o.phase = int(phase)
@@ -125,6 +125,7 @@ def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio
     o.inner_ratio = int(inner_ratio)
     o.maskidx_max = int(maskidx_max)
     o.block_flops = int(block_flops)
+    o.split_flops = int(split_flops)
     if b_transpose is not None:
         o.b_transpose = ctypes.pointer(b_transpose)
     return o
@@ -138,14 +139,15 @@ class Plan:
     def __init__(self, A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
                  semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
                  validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None,
-                 maskidx_max: int = -1, block_flops: int = -1):
+                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1):
         lib = L.load()
         self.semiring = semiring
         self.A, self.B, self.M = A, B, M
         self._views = (_view(A, semiring, "A"), _view(B, semiring, "B"), _view(M, None, "M"))
         self._bt = None if b_transpose is None else _view(b_transpose, semiring, "B^T")
         self._bt_keep = b_transpose
-        self._opt = options(phase, force_kind, validate, inner_ratio, self._bt, maskidx_max, block_flops)
+        self._opt = options(phase, force_kind, validate, inner_ratio, self._bt, maskidx_max, block_flops,
+                            split_flops)
         self.phase = phase
         self.nrows, self.ncols = A.nrows, B.ncols
         h = ctypes.c_void_p()
@@ -252,9 +254,11 @@ class Plan:
 def masked_spgemm(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
                   semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
                   validate: bool = False, inner_ratio: int = 0,
-                  b_transpose: Optional[DeviceCSR] = None) -> DeviceCSR:
-    """C = M .* (A B) (or !M .* (A B)) over `semiring`, rows sorted."""
-    with Plan(A, B, M, complement, semiring, phase, force_kind, validate, inner_ratio, b_transpose) as p:
+                  b_transpose: Optional[DeviceCSR] = None, **tuning) -> DeviceCSR:
+    """C = M .* (A B) (or !M .* (A B)) over `semiring`, rows sorted.
+    `tuning`: maskidx_max, block_flops, split_flops (binner thresholds)."""
+    with Plan(A, B, M, complement, semiring, phase, force_kind, validate, inner_ratio, b_transpose,
+              **tuning) as p:
         return p.execute()
 
 
@@ -291,7 +295,7 @@ class Batch:
     problems: list of (A, B, M, complement) DeviceCSR triples."""
 
     def __init__(self, problems, semiring: str = "plus_times_f64", force_kind=None, inner_ratio: int = 0,
-                 maskidx_max: int = -1, block_flops: int = -1):
+                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1):
         lib = L.load()
         self.semiring = semiring
         self.problems = list(problems)
@@ -303,7 +307,7 @@ class Batch:
             arr[p].M = _view(M, None, "M")
             arr[p].complement = int(bool(comp))
         self._arr = arr
-        self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops)
+        self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops, split_flops)
         h = ctypes.c_void_p()
         _check(lib.msp_batch_create(ctypes.byref(h), arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt),
                                     _stream()), "msp_batch_create")

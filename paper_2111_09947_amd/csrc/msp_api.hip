@@ -130,6 +130,13 @@ struct msp_plan {
     int32_t* bin_units = nullptr;
     int32_t* stg_col = nullptr;
     void* stg_val = nullptr;
+    // split rows
+    int64_t nsplit = 0;
+    unsigned long long* split_counter = nullptr;
+    int32_t* unit_aux = nullptr;
+    int32_t* split_first = nullptr;
+    int32_t* split_nchunk = nullptr;
+    unsigned int* gacc = nullptr;  // [nsplit] x (inserted bits, slots)
     // batch tables
     Operands* ops_d = nullptr;
     OutBind* outs_d = nullptr;
@@ -206,6 +213,7 @@ void msp_options_default(msp_options* opt) {
     opt->maskidx_max = -1;
     opt->reserved = 0;
     opt->block_flops = -1;
+    opt->split_flops = -1;
 }
 
 const char* msp_status_string(msp_status s) {
@@ -273,6 +281,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     if (o.inner_ratio < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "inner_ratio must be >= 0");
     if (o.maskidx_max < 0) o.maskidx_max = DEFAULT_MASKIDX_MAX;
     if (o.block_flops < 0) o.block_flops = DEFAULT_BLOCK_FLOPS;
+    if (o.split_flops < 0) o.split_flops = DEFAULT_SPLIT_FLOPS;
     if (count > 1 && o.b_transpose) return fail(MSP_ERR_UNSUPPORTED, "b_transpose applies to a single product");
     int64_t R = 0;
     P->prods.resize((size_t)count);
@@ -358,6 +367,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.inner_ratio = (!pr.op.complement && inner_any) ? o.inner_ratio : 0;
         aa.maskidx_max = o.maskidx_max;
         aa.block_flops = o.block_flops;
+        aa.split_flops = o.split_flops;
         aa.colcnt_rp = pr.op.BTrp;
         aa.flops = P->flops;
         aa.tiles = P->unit_base;
@@ -392,6 +402,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         P->U += pr.units;
         P->S += pr.staging;
         P->ub += pr.ub;
+        P->nsplit += (int64_t)st[ST_SPLITROWS];
     }
     int64_t run = 0;
     for (int b = 0; b < NBINS; ++b) {
@@ -415,13 +426,17 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     {
         msp_plan::Carve c;
         c.add(&P->seg_off_d, NBINS * NBUCKET);
-        c.add(&P->seg_cursor, NBINS * NBUCKET);
+        c.add(&P->seg_cursor, NBINS * NBUCKET + 1);  // + the split-row counter
         c.add(&P->unit_row, U);
         c.add(&P->unit_tile, U);
         c.add(&P->unit_prob, U);
         c.add(&P->stg_off, U + 1);
         c.add(&P->cnt, U + 1);
         c.add(&P->bin_units, U);
+        c.add(&P->unit_aux, U);
+        c.add(&P->split_first, P->nsplit);
+        c.add(&P->split_nchunk, P->nsplit);
+        c.add_bytes(reinterpret_cast<void**>(&P->gacc), (size_t)(P->nsplit > 0 ? P->nsplit : 1) * split_acc_bytes(semiring));
         int64_t* part = nullptr;
         if (U + 1 > R + 1) c.add(&part, scan_partial_elems(U + 1));
         if (want_staging && o.phase == 1) {
@@ -437,7 +452,8 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         if (part) P->scan_partial = part;
     }
     MSP_HIP(hipMemcpyAsync(P->seg_off_d, P->seg_off, sizeof(int64_t) * NBINS * NBUCKET, hipMemcpyHostToDevice, s));
-    MSP_HIP(hipMemsetAsync(P->seg_cursor, 0, sizeof(unsigned long long) * NBINS * NBUCKET, s));
+    MSP_HIP(hipMemsetAsync(P->seg_cursor, 0, sizeof(unsigned long long) * (NBINS * NBUCKET + 1), s));
+    P->split_counter = P->seg_cursor + NBINS * NBUCKET;
     if (count > 1) {
         std::vector<Operands> ops((size_t)count);
         std::vector<int64_t> ent((size_t)count + 1, 0);
@@ -466,6 +482,10 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         ua.unit_prob = P->unit_prob;
         ua.stg_size = P->stg_off;
         ua.bin_units = P->bin_units;
+        ua.split_counter = P->split_counter;
+        ua.unit_aux = P->unit_aux;
+        ua.split_first = P->split_first;
+        ua.split_nchunk = P->split_nchunk;
         MSP_HIP(launch_units(ua, pr.op.m, s));
     }
     if (want_staging && o.phase == 1) MSP_HIP(launch_scan(P->stg_off, P->stg_off, U, P->scan_partial, s));
@@ -498,7 +518,28 @@ static NumArgs num_args(const msp_plan* P, int b) {
     a.unit_tile = P->unit_tile;
     a.units = P->bin_units + P->bin_off[b];
     a.nunits = P->bin_count[b];
+    a.unit_aux = P->unit_aux;
+    a.split_first = P->split_first;
+    a.split_nchunk = P->split_nchunk;
+    a.nsplit = P->nsplit;
+    a.gset = P->gacc;
+    a.gval = P->gacc + (size_t)P->nsplit * (DENSE_B_COLS / 32);
     return a;
+}
+
+// Split rows: clear their global accumulators before the numeric kernels.
+static msp_status split_clear(msp_plan* P, hipStream_t s) {
+    if (P->nsplit <= 0) return MSP_OK;
+    MSP_HIP(launch_fill_u32(P->gacc, (int64_t)(P->nsplit * split_acc_bytes(P->sr) / 4), s));
+    return MSP_OK;
+}
+
+// Split rows: ordered emission after all numeric kernels.
+static msp_status split_emit(msp_plan* P, int mode, const NumArgs& base, hipStream_t s) {
+    if (P->nsplit <= 0) return MSP_OK;
+    NumArgs a = base;
+    MSP_HIP(launch_split_emit(P->sr, mode, a, s));
+    return MSP_OK;
 }
 
 static msp_status check_out(const Product& pr, const msp_csr_out* C) {
@@ -573,17 +614,24 @@ struct StageTimer {
 // no memset, no synchronization), so it can be captured in a HIP graph.
 static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, StageTimer& tm) {
     if (!P->stg_col) return fail(MSP_ERR_INVALID_ARGUMENT, "plan has no one-phase staging");
+    MSP_CHECK(split_clear(P, s));
+    NumArgs a = num_args(P, 0);
+    a.out_off = P->stg_off;
+    a.cnt = P->cnt;
+    a.out_col = P->stg_col;
+    a.out_val = P->stg_val;
     for (int b = 0; b < NBINS; ++b) {
         if (!P->bin_count[b]) continue;
-        NumArgs a = num_args(P, b);
-        a.out_off = P->stg_off;
-        a.cnt = P->cnt;
-        a.out_col = P->stg_col;
-        a.out_val = P->stg_val;
+        NumArgs ab = a;
+        ab.units = P->bin_units + P->bin_off[b];
+        ab.nunits = P->bin_count[b];
         MSP_CHECK(tm.begin(b));
-        MSP_HIP(launch_numeric(P->sr, b, MODE_STAGE, a, s));
+        MSP_HIP(launch_numeric(P->sr, b, MODE_STAGE, ab, s));
         MSP_CHECK(tm.end());
     }
+    MSP_CHECK(tm.begin(MSP_STAGE_SPLIT_EMIT));
+    MSP_CHECK(split_emit(P, MODE_STAGE, a, s));
+    MSP_CHECK(tm.end());
     MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
     MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
     MSP_CHECK(tm.end());
@@ -611,11 +659,17 @@ static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, 
 static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
     const Product& pr = P->prods[0];
     MSP_CHECK(tm.begin(MSP_STAGE_SYMBOLIC));
+    MSP_CHECK(split_clear(P, s));
     for (int b = 0; b < NBINS; ++b) {
         if (!P->bin_count[b]) continue;
         NumArgs a = num_args(P, b);
         a.cnt = P->cnt;
         MSP_HIP(launch_numeric(P->sr, b, MODE_COUNT, a, s));
+    }
+    {
+        NumArgs a = num_args(P, 0);
+        a.cnt = P->cnt;
+        MSP_CHECK(split_emit(P, MODE_COUNT, a, s));
     }
     MSP_CHECK(tm.end());
     MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
@@ -636,6 +690,7 @@ static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_hos
 }
 
 static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, hipStream_t s, StageTimer& tm) {
+    MSP_CHECK(split_clear(P, s));
     for (int b = 0; b < NBINS; ++b) {
         if (!P->bin_count[b]) continue;
         NumArgs a = num_args(P, b);
@@ -646,6 +701,13 @@ static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, hipStream_t s, Stage
         MSP_HIP(launch_numeric(P->sr, b, MODE_DIRECT, a, s));
         MSP_CHECK(tm.end());
     }
+    NumArgs a = num_args(P, 0);
+    a.out_off = P->cnt;
+    a.out_col = C->colidx;
+    a.out_val = C->values;
+    MSP_CHECK(tm.begin(MSP_STAGE_SPLIT_EMIT));
+    MSP_CHECK(split_emit(P, MODE_DIRECT, a, s));
+    MSP_CHECK(tm.end());
     return MSP_OK;
 }
 

@@ -108,6 +108,7 @@ template <> struct SRT<MSP_PLUS_TIMES_F64> {
     __device__ static acc_t identity() { return -0.0; }
     __device__ static acc_t term(in_t a, in_t b) { return __dmul_rn(a, b); }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicAdd(slot, t); }
+    __device__ static void merge(acc_t* slot, acc_t part) { atomicAdd(slot, part); }
     __device__ static acc_t add(acc_t x, acc_t t) { return __dadd_rn(x, t); }
     __device__ static bool is_set(acc_t) { return false; }
     __device__ static out_t finish(acc_t x) { return x; }
@@ -124,6 +125,7 @@ template <> struct SRT<MSP_PLUS_PAIR_I64> {
     __device__ static acc_t identity() { return 0ull; }
     __device__ static acc_t term(in_t, in_t) { return 1ull; }
     __device__ static void lds_add(acc_t* slot, acc_t) { atomicAdd(slot, 1ull); }
+    __device__ static void merge(acc_t* slot, acc_t part) { atomicAdd(slot, part); }
     __device__ static acc_t add(acc_t x, acc_t) { return x + 1ull; }
     __device__ static bool is_set(acc_t x) { return x != 0ull; }
     __device__ static out_t finish(acc_t x) { return (int64_t)x; }
@@ -142,6 +144,7 @@ template <> struct SRT<MSP_LOR_LAND_BOOL> {
     __device__ static acc_t identity() { return 0u; }
     __device__ static acc_t term(in_t a, in_t b) { return 2u | (a & b); }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicOr(slot, t); }
+    __device__ static void merge(acc_t* slot, acc_t part) { atomicOr(slot, part); }
     __device__ static acc_t add(acc_t x, acc_t t) { return x | t; }
     __device__ static bool is_set(acc_t x) { return x != 0u; }
     __device__ static out_t finish(acc_t x) { return (uint8_t)(x & 1u); }
@@ -160,6 +163,7 @@ template <> struct SRT<MSP_PLUS_TIMES_I32> {
     __device__ static acc_t identity() { return 0ull; }
     __device__ static acc_t term(in_t a, in_t b) { return (1ull << 32) | (unsigned long long)(a * b); }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicAdd(slot, t); }
+    __device__ static void merge(acc_t* slot, acc_t part) { atomicAdd(slot, part); }
     __device__ static acc_t add(acc_t x, acc_t t) { return x + t; }
     __device__ static bool is_set(acc_t x) { return x != 0ull; }
     __device__ static out_t finish(acc_t x) { return (int32_t)(uint32_t)x; }
@@ -178,6 +182,7 @@ template <> struct SRT<MSP_PLUS_TIMES_I64> {
     __device__ static acc_t identity() { return 0ull; }
     __device__ static acc_t term(in_t a, in_t b) { return a * b; }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicAdd(slot, t); }
+    __device__ static void merge(acc_t* slot, acc_t part) { atomicAdd(slot, part); }
     __device__ static acc_t add(acc_t x, acc_t t) { return x + t; }
     __device__ static bool is_set(acc_t) { return false; }
     __device__ static out_t finish(acc_t x) { return (int64_t)x; }

@@ -19,7 +19,10 @@ enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_MASKIDX_W = 4,  // one wave, binary search over <= MASKIDX_W_CAP mask entries
     BIN_MASKIDX_B = 5,  // one block, binary search over <= MASKIDX_B_CAP mask entries
     BIN_INNER_W = 6,    // one wave, dot products for <= INNER_CAP mask entries
-    NBINS = 7
+    BIN_DENSE_BN = 7,   // one block, dense state over <= DENSE_W_COLS columns (product-heavy rows)
+    BIN_DENSE_SPLIT = 8,  // one block per chunk of A's row, dense state over <= DENSE_B_COLS
+                          // columns, merged into a per-row accumulator in global memory
+    NBINS = 9
 };
 
 constexpr int DENSE_W_COLS = 512;
@@ -29,10 +32,11 @@ constexpr int HASH_B_CAP = 512;
 constexpr int MASKIDX_W_CAP = 256;
 constexpr int MASKIDX_B_CAP = 4096;
 constexpr int INNER_CAP = 256;
-constexpr int INNER_ACAP = 512;   // A row staged in LDS up to this length
+constexpr int INNER_ACAP = 1024;  // A row (column indices) staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 constexpr int DEFAULT_MASKIDX_MAX = 8;       // auto: binary search up to this mask size, hash above
 constexpr int64_t DEFAULT_BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
+constexpr int64_t DEFAULT_SPLIT_FLOPS = 262144;  // dense rows with more products split over several blocks
 // Units of a bin are ordered by the product count of their row, heaviest
 // first (bucket b holds rows with 4^b <= flops < 4^(b+1)), so that the
 // longest units start first and do not form the tail of the launch.
@@ -48,7 +52,8 @@ enum Stat : int {
     ST_MAXFLOPS = 5,
     ST_BIN0 = 6,                 // ST_BIN0 + b * NBUCKET + bucket: units of bin b in a flops bucket
     ST_ERROR = ST_BIN0 + NBINS * NBUCKET,  // nonzero: invalid CSR found by validation
-    ST_COUNT = ST_ERROR + 1
+    ST_SPLITROWS = ST_ERROR + 1,           // rows split over several blocks
+    ST_COUNT = ST_SPLITROWS + 1
 };
 
 enum Mode : int { MODE_COUNT = 0, MODE_STAGE = 1, MODE_DIRECT = 2 };
@@ -69,6 +74,7 @@ struct AnalysisArgs {
     int inner_ratio;
     int maskidx_max;
     int64_t block_flops;
+    int64_t split_flops;
     const int64_t* colcnt_rp;  // row pointers of B^T (column counts of B) or null
     int64_t* flops;            // [R] global rows
     int64_t* tiles;            // [R+1], number of units per row (scanned later)
@@ -90,6 +96,11 @@ struct UnitArgs {
     int32_t* unit_prob;        // product of the unit
     int64_t* stg_size;         // [U+1] staging entries per unit (scanned later)
     int32_t* bin_units;
+    // split rows
+    unsigned long long* split_counter;
+    int32_t* unit_aux;         // split row index of a split unit
+    int32_t* split_first;      // first unit of each split row
+    int32_t* split_nchunk;     // chunks (units) of each split row
 };
 
 struct NumArgs {
@@ -104,6 +115,13 @@ struct NumArgs {
     int64_t* cnt;              // per-unit output counts (COUNT, STAGE)
     int32_t* out_col;
     void* out_val;
+    // split rows
+    const int32_t* unit_aux;
+    const int32_t* split_first;
+    const int32_t* split_nchunk;
+    int64_t nsplit;
+    unsigned int* gset;        // [nsplit][DENSE_B_COLS / 32] inserted bits
+    void* gval;                // [nsplit][DENSE_B_COLS] accumulator slots
 };
 
 // Per-product output binding (device table entry when batched).
@@ -144,6 +162,11 @@ __host__ __device__ inline int flops_bucket(int64_t flops) {
 int64_t scan_partial_elems(int64_t n);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s);
 hipError_t launch_numeric(int semiring, int bin, int mode, const NumArgs& a, hipStream_t s);
+// Ordered emission of the split rows' global accumulators (after all numeric kernels).
+hipError_t launch_split_emit(int semiring, int mode, const NumArgs& a, hipStream_t s);
+// Bytes of the global accumulator per split row.
+size_t split_acc_bytes(int semiring);
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 // Row pointers of every product: C_p.rowptr[i] = out_off[unit_base[row_off_p + i]] - out_off[unit_first_p].
 // `outs` (device, P entries) or `one` (P == 1); `ent_off` (device, P + 1) = row_off_p + p.

@@ -152,9 +152,10 @@ __device__ int64_t csr_rowsum(const int64_t* __restrict__ rp, const int32_t* __r
 
 __device__ __forceinline__ int64_t cdiv(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
-// Accumulator kind and tiling of one row (auto or forced).
-__device__ void classify(int64_t mnnz, int64_t flops, int64_t n, int comp, int force, int inner_ratio,
-                        int maskidx_max, int64_t block_flops, int64_t icost, int& bin, int64_t& tiles) {
+// Accumulator kind and tiling of one row (auto or forced). alen = nnz(A(i,:)).
+__device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, int comp, int force, int inner_ratio,
+                        int maskidx_max, int64_t block_flops, int64_t split_flops, int64_t icost, int& bin,
+                        int64_t& tiles) {
     int kind = comp ? (int)MSP_KIND_DENSE : force;
     if (kind == MSP_KIND_AUTO) {
         if (inner_ratio > 0 && icost * (int64_t)inner_ratio < flops) kind = MSP_KIND_INNER;
@@ -164,9 +165,12 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t n, int comp, int f
         else kind = MSP_KIND_MASKIDX;
     }
     const bool heavy = flops > block_flops;
+    const bool split = split_flops > 0 && flops > split_flops && alen > 1;
     switch (kind) {
     case MSP_KIND_DENSE:
-        if (n <= DENSE_W_COLS && !heavy) { bin = BIN_DENSE_W; tiles = 1; }
+        tiles = 1;
+        if (n <= DENSE_B_COLS && split) { bin = BIN_DENSE_SPLIT; tiles = min(cdiv(flops, split_flops), alen); }
+        else if (n <= DENSE_W_COLS) bin = heavy ? BIN_DENSE_BN : BIN_DENSE_W;
         else { bin = BIN_DENSE_B; tiles = cdiv(n, DENSE_B_COLS); }
         break;
     case MSP_KIND_HASH:
@@ -188,8 +192,11 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
                                 int64_t flops) {
     int64_t adm = 0;
     switch (bin) {
-    case BIN_DENSE_W:
+    case BIN_DENSE_W: case BIN_DENSE_BN:
         adm = o.complement ? o.n - mnnz : mnnz;
+        break;
+    case BIN_DENSE_SPLIT:  // the first chunk emits the whole row
+        adm = t == 0 ? (o.complement ? o.n - mnnz : mnnz) : 0;
         break;
     case BIN_DENSE_B: {
         const int64_t c0 = t * DENSE_B_COLS, c1 = min(c0 + (int64_t)DENSE_B_COLS, o.n);
@@ -236,8 +243,9 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
         ub = min(adm, flops);
         int bin = -1;
         if (ub > 0) {
-            classify(mnnz, flops, o.n, o.complement, a.force_kind, a.inner_ratio, a.maskidx_max, a.block_flops,
-                     icost, bin, tiles);
+            classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
+                     a.maskidx_max, a.block_flops, a.split_flops, icost, bin, tiles);
+            if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
             seg = bin * NBUCKET + flops_bucket(flops);
         }
@@ -316,6 +324,12 @@ __global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
             }
             seg = bin * NBUCKET + flops_bucket(flops);
             rank = atomicAdd(&hist[seg], (unsigned int)tiles);
+            if (bin == BIN_DENSE_SPLIT) {
+                const int32_t sidx = (int32_t)atomicAdd(a.split_counter, 1ull);
+                a.split_first[sidx] = (int32_t)base;
+                a.split_nchunk[sidx] = (int32_t)tiles;
+                for (int64_t t = 0; t < tiles; ++t) a.unit_aux[base + t] = sidx;
+            }
         }
     }
     __syncthreads();
@@ -425,7 +439,7 @@ struct StanzaLds {
     unsigned long long S[STREAM_U];
 };
 
-// Streams every product (k, j) of row i: for each stored A(i,k) and each
+// Streams every product (k, j) of the A entries [pa0, pa1) of one row: for each stored A(i,k) and each
 // stored B(k,j) with lo <= j <= hi (when `window`), calls f(j, s, q, true)
 // where q is the position of B(k,j) and s indexes st.a for A(i,k); slots
 // past the last product call f(j, s, q, false) with meaningless j, s, q. Wave `wv` of
@@ -440,10 +454,9 @@ struct StanzaLds {
 // The STREAM_U loads of a lane are issued back to back before any of them is
 // consumed, so a wave keeps STREAM_U stanza reads outstanding.
 template <class T, class F>
-__device__ __forceinline__ void stream_products(const Operands& o, int64_t i, bool window, int32_t lo, int32_t hi,
-                                                int wv, int nw, StanzaLds<T>& st, F&& f) {
+__device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, int64_t pa1, bool window, int32_t lo,
+                                                int32_t hi, int wv, int nw, StanzaLds<T>& st, F&& f) {
     const int ln = lane();
-    const int64_t pa0 = o.Arp[i], pa1 = o.Arp[i + 1];
     constexpr int64_t WIN = (int64_t)WAVE * STREAM_U;
     for (int64_t pb = pa0; pb < pa1; pb += WAVE) {
         const int64_t p = pb + ln;
@@ -611,7 +624,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
     }
     unit_sync<NW>();
     StanzaLds<T>& S = st[wave];
-    stream_products<T>(o, i, tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
+    stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
                        [&](int32_t j, int s, int64_t q, bool act) {
                            if (!act) return;
                            const int c = j - (int)c0;
@@ -636,6 +649,107 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
             }
         });
     if (ut == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
+}
+
+// ------------------------------------------------------------- split rows
+// A dense-kind row with very many products is cut into chunks of its A row;
+// each chunk (one unit, one 256-thread block) accumulates its products in an
+// LDS tile as k_dense does, then merges the tile into the row's accumulator
+// in global memory with atomics (inserted bits, and values with the
+// semiring's (+)); a second kernel emits every split row in column order.
+// Integer semirings stay exact; FP64 sums are reordered (within tolerance).
+template <int SR, int MODE, bool BATCH>
+__global__ __launch_bounds__(BLOCK_NW * WAVE) void k_dense_split(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    constexpr int W = DENSE_B_COLS;
+    constexpr int NW = BLOCK_NW;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    constexpr bool FLAGS = COUNT || T::sep_flag;
+    constexpr int NWORDS = W / 32;
+    constexpr int UT = NW * WAVE;
+    __shared__ uint32_t allowed[NWORDS];
+    __shared__ acc_t vals[COUNT ? 1 : W];
+    __shared__ uint8_t flags[FLAGS ? W : 1];
+    __shared__ StanzaLds<T> st[NW];
+    const int wv = threadIdx.x / WAVE, ut = threadIdx.x;
+    const int u = __builtin_amdgcn_readfirstlane(g.units[blockIdx.x]);
+    const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
+    const int64_t i = g.unit_row[u];
+    const int t = g.unit_tile[u];
+    const int sidx = g.unit_aux[u];
+    const int nchunk = g.split_nchunk[sidx];
+    const int wt = (int)o.n;  // <= W: split rows have a single column tile
+    for (int x = ut; x < NWORDS; x += UT) {
+        const int lo = x * 32;
+        const uint32_t valid = (lo + 32 <= wt) ? 0xFFFFFFFFu : (lo >= wt ? 0u : ((1u << (wt - lo)) - 1u));
+        allowed[x] = o.complement ? valid : 0u;
+    }
+    if (!COUNT) for (int x = ut; x < wt; x += UT) vals[x] = T::identity();
+    if (FLAGS) for (int x = ut; x < wt; x += UT) flags[x] = 0;
+    if (lane() < STREAM_U) st[wv].S[lane()] = 0ull;
+    __syncthreads();
+    for (int64_t p = o.Mrp[i] + ut; p < o.Mrp[i + 1]; p += UT) {
+        const int c = o.Mci[p];
+        const uint32_t bit = 1u << (c & 31);
+        if (o.complement) atomicAnd(&allowed[c >> 5], ~bit);
+        else atomicOr(&allowed[c >> 5], bit);
+    }
+    __syncthreads();
+    const int64_t ra0 = o.Arp[i], alen = o.Arp[i + 1] - ra0;
+    const int64_t chunk = (alen + nchunk - 1) / nchunk;
+    const int64_t a0 = ra0 + min((int64_t)t * chunk, alen), a1 = ra0 + min((int64_t)(t + 1) * chunk, alen);
+    StanzaLds<T>& S = st[wv];
+    stream_products<T>(o, a0, a1, false, 0, 0, wv, NW, S, [&](int32_t j, int s, int64_t q, bool act) {
+        if (!act) return;
+        if (allowed[j >> 5] & (1u << (j & 31))) {
+            if (FLAGS) flags[j] = 1;
+            if (!COUNT) {
+                const typename T::in_t b = T::needs_values ? T::load(o.Bv, q) : T::one();
+                T::lds_add(&vals[j], T::term(S.a[s], b));
+            }
+        }
+    });
+    __syncthreads();
+    unsigned int* gset = g.gset + (int64_t)sidx * NWORDS;
+    acc_t* gval = static_cast<acc_t*>(g.gval) + (int64_t)sidx * W;
+    for (int c = ut; c < wt; c += UT) {
+        const bool set = FLAGS ? (flags[c] != 0) : T::is_set(vals[c]);
+        if (set) {
+            atomicOr(&gset[c >> 5], 1u << (c & 31));
+            if (!COUNT) T::merge(&gval[c], vals[c]);
+        }
+    }
+    if (ut == 0 && MODE != MODE_DIRECT) g.cnt[u] = 0;  // the row's output is emitted by k_split_emit
+}
+
+// One block per split row: ordered emission from the global accumulator
+// into the output place of the row's first unit.
+template <int SR, int MODE, bool BATCH>
+__global__ __launch_bounds__(BLOCK_NW * WAVE) void k_split_emit(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    constexpr int W = DENSE_B_COLS;
+    constexpr int NW = BLOCK_NW;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    __shared__ int64_t tmp[NW];
+    const int sidx = blockIdx.x;
+    const int u = g.split_first[sidx];
+    const Operands& o = BATCH ? g.ops[g.unit_prob[u]] : g.op;
+    const int wt = (int)o.n;
+    const unsigned int* gset = g.gset + (int64_t)sidx * (W / 32);
+    const acc_t* gval = static_cast<const acc_t*>(g.gval) + (int64_t)sidx * W;
+    const int64_t ob = COUNT ? 0 : g.out_off[u];
+    typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+    const int64_t total = ordered_emit<NW>(
+        wt, tmp, (int)threadIdx.x, [&](int c) { return (gset[c >> 5] >> (c & 31)) & 1u; },
+        [&](int c, int64_t pos) {
+            if (!COUNT) {
+                g.out_col[ob + pos] = c;
+                ov[ob + pos] = T::finish(gval[c]);
+            }
+        });
+    if (threadIdx.x == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
 }
 
 // ---------------------------------------------- mask-keyed accumulators
@@ -746,7 +860,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
     const int32_t lo = keys[0], hi = keys[cnt - 1];
     const int top = 1 << (31 - __clz(cnt));
     StanzaLds<T>& S = st[wave];
-    stream_products<T>(o, i, tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q, bool act) {
+    stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q, bool act) {
         // an inactive slot looks up a column that no mask holds (branch-free)
         const int32_t jj = act ? j : INT32_MIN;
         const int r = HASHED ? hash_find(tkey, trank, bmask, bbits, jj) : rank_search(keys, cnt, top, jj);
@@ -776,8 +890,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
 // ----------------------------------------------------------- inner product
 // Pull formulation: lane x of the wave owns mask entry (i, j) and computes
 // the sparse dot product of A(i,:) with column j of B (row j of B^T) by
-// looking up every k of that column in A's row (staged in LDS when short,
-// else a binary search in global memory).
+// looking up every k of that column in A's row (column indices staged in LDS
+// up to ACAP entries, else a binary search in global memory); A's value is
+// read only for a match.
 template <int SR, int MODE, int CAP, int ACAP, int WPB, bool BATCH>
 __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     using T = SRT<SR>;
@@ -785,13 +900,11 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     using in_t = typename T::in_t;
     constexpr bool COUNT = MODE == MODE_COUNT;
     __shared__ int32_t akeys_[WPB][ACAP];
-    __shared__ in_t avals_[WPB][T::needs_values ? ACAP : 1];
     const int ln = lane();
     const int gi = threadIdx.x / WAVE;
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;
     int32_t* akeys = akeys_[gi];
-    in_t* avals = avals_[gi];
     // the unit is the same for every lane of the wave
     const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
     const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
@@ -803,10 +916,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     const int64_t alen = o.Arp[i + 1] - pa0;
     const bool in_lds = alen <= ACAP;
     if (in_lds) {
-        for (int x = ln; x < alen; x += WAVE) {
-            akeys[x] = o.Aci[pa0 + x];
-            if (T::needs_values && !COUNT) avals[x] = T::load(o.Av, pa0 + x);
-        }
+        for (int x = ln; x < alen; x += WAVE) akeys[x] = o.Aci[pa0 + x];
     }
     wave_lds_sync();
     const int top = in_lds && alen > 0 ? 1 << (31 - __clz((int)alen)) : 0;
@@ -832,7 +942,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
                 if (idx >= 0) {
                     set = true;
                     if (!COUNT) {
-                        const in_t a = T::needs_values ? (in_lds ? avals[idx] : T::load(o.Av, pa0 + idx)) : T::one();
+                        const in_t a = T::needs_values ? T::load(o.Av, pa0 + idx) : T::one();
                         const in_t b = T::needs_values ? T::load(o.BTv, q) : T::one();
                         acc = T::add(acc, T::term(a, b));
                     }
@@ -881,9 +991,61 @@ static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
     case BIN_INNER_W:
         hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB, BATCH>), gw, bw, 0, s, a);
         break;
+    case BIN_DENSE_BN:
+        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH>), gb, bb, 0, s, a);
+        break;
+    case BIN_DENSE_SPLIT:
+        hipLaunchKernelGGL((k_dense_split<SR, MODE, BATCH>), gb, bb, 0, s, a);
+        break;
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <int SR, int MODE>
+static hipError_t launch_split_emit_t(const NumArgs& a, hipStream_t s) {
+    if (a.ops) hipLaunchKernelGGL((k_split_emit<SR, MODE, true>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
+    else hipLaunchKernelGGL((k_split_emit<SR, MODE, false>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int SR>
+static hipError_t launch_split_emit_sr(int mode, const NumArgs& a, hipStream_t s) {
+    switch (mode) {
+    case MODE_COUNT: return launch_split_emit_t<SR, MODE_COUNT>(a, s);
+    case MODE_STAGE: return launch_split_emit_t<SR, MODE_STAGE>(a, s);
+    case MODE_DIRECT: return launch_split_emit_t<SR, MODE_DIRECT>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_split_emit(int semiring, int mode, const NumArgs& a, hipStream_t s) {
+    if (a.nsplit <= 0) return hipSuccess;
+    if (mode == MODE_COUNT) return launch_split_emit_sr<MSP_PLUS_PAIR_I64>(mode, a, s);
+    switch (semiring) {
+    case MSP_PLUS_TIMES_F64: return launch_split_emit_sr<MSP_PLUS_TIMES_F64>(mode, a, s);
+    case MSP_PLUS_PAIR_I64: return launch_split_emit_sr<MSP_PLUS_PAIR_I64>(mode, a, s);
+    case MSP_LOR_LAND_BOOL: return launch_split_emit_sr<MSP_LOR_LAND_BOOL>(mode, a, s);
+    case MSP_PLUS_TIMES_I32: return launch_split_emit_sr<MSP_PLUS_TIMES_I32>(mode, a, s);
+    case MSP_PLUS_TIMES_I64: return launch_split_emit_sr<MSP_PLUS_TIMES_I64>(mode, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t split_acc_bytes(int) {
+    // inserted bits plus DENSE_B_COLS slots of at most 8 bytes
+    return (size_t)DENSE_B_COLS / 32 * 4 + (size_t)DENSE_B_COLS * 8;
+}
+
+__global__ void k_fill_u32(unsigned int* p, int64_t n) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        p[x] = 0u;
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

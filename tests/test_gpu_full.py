@@ -1,0 +1,64 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration the
+benchmark times: triangle counting on R-MAT scale 18 compared entry by entry
+with the oracle; the 512-source BFS step on R-MAT scale 20 on sampled rows
+(the oracle computes them one by one); the 64-product batch on sampled rows of
+every product."""
+import numpy as np
+import pytest
+
+import mspgen
+import oracle
+from tests.gpu_util import assert_same, msp, torch_or_skip, up
+
+pytestmark = pytest.mark.gpu
+
+
+def test_triangle_counting_full_size():
+    L = mspgen.triangle_input(18, 16, 18)
+    dL = up(L)
+    C = msp().masked_spgemm(dL, dL, dL, semiring="plus_pair_i64")
+    R = oracle.masked_spgemm(L, L, L, False, "plus_pair_i64")
+    assert_same(C, R, "plus_pair_i64")
+    assert int(msp().reduce(C.values, "plus_pair_i64").item()) == int(R.values.sum())
+
+
+@pytest.fixture(scope="module")
+def bfs_graph():
+    return mspgen.rmat_graph(20, 16, 20)
+
+
+@pytest.mark.parametrize("sr,vk", [("plus_times_i32", "i32"), ("lor_land_bool", "u8")])
+def test_bfs_step_full_size_sampled(bfs_graph, sr, vk):
+    G = bfs_graph
+    F, V, srcs, lv = mspgen.bfs_step_input(G, 512, 21, vk)
+    C = msp().masked_spgemm(up(G), up(F, sr), up(V), complement=True, semiring=sr)
+    rng = np.random.default_rng(5)
+    deg = np.diff(G.rowptr)
+    hubs = np.argsort(deg)[-20:]  # the heaviest rows plus a uniform sample
+    rows = np.unique(np.concatenate([rng.integers(0, G.nrows, 3000), hubs]))
+    R = oracle.masked_spgemm(G, F, V, True, sr, rows=rows)
+    assert_same(C, R, sr, rows=rows)
+    # totals that hold at any size: nnz(C) is the number of (vertex, source)
+    # pairs at distance l_s + 1, counted by the oracle on the sample only; the
+    # row pointers are non-decreasing and end at the output size
+    rp = C.rowptr.cpu().numpy()
+    assert np.all(np.diff(rp) >= 0) and rp[-1] == C.colidx.numel()
+
+
+def test_batch_full_mix_sampled():
+    torch = torch_or_skip()
+    m = msp()
+    probs = mspgen.batch_mix(64, seed=4, max_mask_nnz=2_000_000)
+    dev = [(up(p["A"], "plus_times_f64"), up(p["B"], "plus_times_f64"), up(p["M"]), False) for p in probs]
+    rng = np.random.default_rng(9)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring="plus_times_f64") as b:
+            b.bind_new_outputs()
+            b.graph_launch()
+            b.graph_launch()
+            res = b.results()
+    for p, C in zip(probs, res):
+        rows = np.unique(rng.integers(0, p["A"].nrows, 64))
+        R = oracle.masked_spgemm(p["A"], p["B"], p["M"], False, "plus_times_f64", rows=rows)
+        assert_same(C, R, "plus_times_f64", rows=rows)

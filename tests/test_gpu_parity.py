@@ -228,3 +228,39 @@ def test_reduce_semirings():
     assert int(m.reduce(w, "plus_times_i32").item()) == 0  # 1000 * 2^30 mod 2^32
     e = torch.zeros(0, dtype=torch.int64, device=dev)
     assert int(m.reduce(e, "plus_pair_i64").item()) == 0
+
+
+@pytest.mark.parametrize("sr", SEMIRINGS)
+@pytest.mark.parametrize("complement", [False, True])
+@pytest.mark.parametrize("phase", [1, 2])
+@pytest.mark.parametrize("ncols", [300, 3000])
+def test_split_rows(sr, complement, phase, ncols):
+    """Rows split over several workgroups by chunks of A's row (forced with a
+    tiny threshold), merged through the global per-row accumulator."""
+    A = mspgen.er(120, 400, 60.0, 61, {"plus_times_f64": "f64", "plus_pair_i64": "f64", "lor_land_bool": "u8",
+                                      "plus_times_i32": "i32", "plus_times_i64": "i64"}[sr])
+    B = mspgen.er(400, ncols, 25.0, 62, A.values is not None and {"plus_times_f64": "f64", "plus_pair_i64": "f64",
+                  "lor_land_bool": "u8", "plus_times_i32": "i32", "plus_times_i64": "i64"}[sr] or None)
+    M = mspgen.er(120, ncols, ncols / 6.0, 63, None)
+    C, R = run_and_check(A, B, M, complement, sr, phase=phase, force_kind="dense", split_flops=300)
+
+
+def test_split_rows_in_batch():
+    torch = torch_or_skip()
+    m = msp()
+    sr = "plus_times_i32"
+    probs = []
+    for t in range(3):
+        A = mspgen.er(90, 300, 50.0, 70 + t, "i32")
+        B = mspgen.er(300, 500, 30.0, 80 + t, "i32")
+        M = mspgen.er(90, 500, 60.0, 90 + t, None)
+        probs.append((A, B, M, t % 2 == 1))
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr, split_flops=200) as b:
+            b.bind_new_outputs()
+            for _ in range(2):
+                b.graph_launch()
+            for (A, B, M, c), C in zip(probs, b.results()):
+                assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
