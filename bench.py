@@ -85,13 +85,15 @@ def main():
     ap.add_argument("--force-kind", default=None, choices=(None, "dense", "hash", "maskidx", "inner"))
     ap.add_argument("--inner-ratio", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs"),
+    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve"),
                     help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
                          "batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mask-cap", type=int, default=20_000_000,
                     help="batch: cap on one product's mask entries (host memory of the generator)")
     ap.add_argument("--tune", action="store_true", help="batch: autotune the binner thresholds first")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent execution slots")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -103,6 +105,8 @@ def main():
         return run_batch(args)
     if args.workload == "bfs":
         return run_bfs(args)
+    if args.workload == "serve":
+        return run_serve(args)
     run_tc(args)
 
 
@@ -313,6 +317,137 @@ def run_bfs(args):
                                   "(headline) and boolean"},
            "roofline": head["roofline"], "semirings": results}
     print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Poisson stream of masked products drawn uniformly from a pool of the
+    benchmark shapes (Erdos-Renyi n = 4096 with fresh seeds, triangle counting
+    on R-MAT scale 18, a 512-source BFS step on R-MAT scale 18, and the 64
+    mixed products with masks capped at 2e6 entries), plus-pair int64 for
+    triangle counting and 50/50 plus-pair int64 or FP64 plus-times otherwise;
+    operands resident on the GPU. Arrival rate = 0.8 x the capacity measured
+    in a closed loop. Continuous batching (slots on their own streams, same-
+    semiring mini-batches, memory admission) against a FIFO server that runs
+    one product at a time."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+    from paper_2111_09947_amd import serve
+    from paper_2111_09947_amd.autotune import same_output
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    t0 = time.time()
+
+    def up(X, f64):
+        return msp.DeviceCSR.from_host(X, dev, torch.float64 if f64 else None)
+
+    pool = []
+    for s in range(4):
+        A = mspgen.er(4096, 4096, 8.0, 101 + 10 * s, "f64")
+        B = mspgen.er(4096, 4096, 8.0, 102 + 10 * s, "f64")
+        M = mspgen.er(4096, 4096, 8.0, 103 + 10 * s, None)
+        pool.append(dict(name="er4096", ops=(up(A, True), up(B, True), up(M, False), False), f64=True))
+    L = mspgen.triangle_input(18, 16, 18)
+    dL = up(L, False)
+    pool.append(dict(name="tc_rmat18", ops=(dL, dL, dL, False), f64=False))
+    G = mspgen.rmat_graph(18, 16, 20)
+    F, V, _, _ = mspgen.bfs_step_input(G, 512, 21, "i64")
+    F = F.with_values(F.values.astype(np.float64))
+    G = G.with_values(np.ones(G.nnz))
+    pool.append(dict(name="bfs_rmat18", ops=(up(G, True), up(F, True), up(V, False), True), f64=True))
+    for q in mspgen.batch_mix(64, seed=4, max_mask_nnz=2_000_000):
+        pool.append(dict(name="mix", ops=(up(q["A"], True), up(q["B"], True), up(q["M"], False), False), f64=True))
+    print(f"[bench] serving pool of {len(pool)} items ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    for it in pool:  # admitted-product count per item (semiring independent)
+        A, B, M, c = it["ops"]
+        with msp.Plan(A, B, M, complement=c, semiring="plus_pair_i64") as p:
+            C = p.execute()
+            it["useful"] = int(C.values.sum().item())
+        it["est"] = {sr: serve.estimate_bytes(A, B, M, c, 8) for sr in ("plus_pair_i64", "plus_times_f64")}
+
+    def draw(n, seed):
+        r = np.random.default_rng(seed)
+        items = r.integers(0, len(pool), size=n)
+        coin = r.random(n) < 0.5
+        return [(int(k), "plus_pair_i64" if (not pool[k]["f64"] or coin[x]) else "plus_times_f64")
+                for x, k in enumerate(items)]
+
+    def make(seq):
+        def mk(i):
+            k, sr = seq[i]
+            it = pool[k]
+            return serve.Request(rid=i, semiring=sr, operands=it["ops"], est_bytes=it["est"][sr])
+        return mk
+
+    mem_budget = 64 << 30
+    # capacity: closed loop, everything queued at once
+    cap_seq = draw(400, 7)
+    srv = serve.Server(serve.GpuExecutor(args.slots), slots=args.slots, max_batch=8, mem_budget=mem_budget)
+    tc0 = time.perf_counter()
+    reqs = serve.run_trace(srv, make(cap_seq), [0.0] * len(cap_seq))
+    capacity = len(reqs) / (max(r.t_done for r in reqs) - tc0)
+    print(f"[bench] capacity {capacity:.1f} req/s", file=sys.stderr, flush=True)
+
+    warm = 200
+    n = warm + args.requests
+    seq = draw(n, 11)
+    lam = 0.8 * capacity
+    arrivals = list(np.cumsum(rng.exponential(1.0 / lam, size=n)))
+    keep = set(int(x) for x in np.random.default_rng(3).choice(np.arange(warm, n), size=24, replace=False))
+
+    def run(continuous):
+        srv = serve.Server(serve.GpuExecutor(args.slots), slots=args.slots, max_batch=8, mem_budget=mem_budget,
+                           continuous=continuous)
+        mk = make(seq)
+
+        def mk2(i):
+            r = mk(i)
+            r.keep = continuous and i in keep
+            return r
+        t_begin = time.perf_counter()
+        rs = serve.run_trace(srv, mk2, arrivals, timeout=900)
+        meas = rs[warm:]
+        errs = [r for r in rs if r.error]
+        span = max(r.t_done for r in meas) - min(r.t_arrival for r in meas)
+        useful = sum(pool[seq[r.rid][0]]["useful"] for r in meas)
+        lat = [r.latency * 1e3 for r in meas]
+        pc = serve.percentiles(lat)
+        return rs, {"requests": len(meas), "errors": len(errs), "throughput_req_s": round(len(meas) / span, 2),
+                    "useful_gflops": round(2 * useful / span / 1e9, 3), "p50_ms": round(pc["p50"], 3),
+                    "p99_ms": round(pc["p99"], 3), "wall_s": round(time.perf_counter() - t_begin, 2)}
+
+    rs_c, cont = run(True)
+    print(f"[bench] continuous {cont}", file=sys.stderr, flush=True)
+    _, fifo = run(False)
+    print(f"[bench] fifo {fifo}", file=sys.stderr, flush=True)
+
+    # each kept result alone (a fresh single-product run) equals the result in the mix
+    same = True
+    for r in rs_c:
+        if not r.keep or r.error:
+            continue
+        A, B, M, c = r.operands
+        alone = msp.masked_spgemm(A, B, M, complement=c, semiring=r.semiring)
+        ok = same_output(r.result.rowptr, r.result.colidx, r.result.values, alone.rowptr, alone.colidx, alone.values,
+                         r.semiring == "plus_times_f64")
+        same = same and ok
+    out = {"metric": "useful_masked_gflops", "value": cont["useful_gflops"], "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.requests, "warmup": warm, "ms_per_step": round(1e3 / cont["throughput_req_s"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "mixed(i64,f64)",
+           "data": "synthetic",
+           "config": {"workload": "serving: Poisson arrivals at 0.8 x measured capacity over a pool of "
+                                  f"{len(pool)} products (Erdos-Renyi n=4096, triangle counting R-MAT 18, BFS "
+                                  "step R-MAT 18 x 512 sources, 64 mixed products), plus-pair int64 / FP64",
+                      "slots": args.slots, "max_batch": 8, "mem_budget_bytes": mem_budget,
+                      "capacity_req_s": round(capacity, 2), "lambda_req_s": round(lam, 2)},
+           "serving": {"continuous": cont, "fifo_one_at_a_time": fifo,
+                       "speedup_throughput": round(cont["throughput_req_s"] / max(fifo["throughput_req_s"], 1e-9), 3),
+                       "alone_equals_mix": same}}
+    print(json.dumps(out), flush=True)
+    if not same:
+        sys.exit(1)
 
 
 def _timed(fn, steps, warmup, stream=None):
