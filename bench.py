@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--force-kind", default=None, choices=(None, "dense", "hash", "maskidx", "inner"))
     ap.add_argument("--inner-ratio", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve"),
+    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "copy"),
                     help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
                          "batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -94,8 +94,16 @@ def main():
     ap.add_argument("--tune", action="store_true", help="batch: autotune the binner thresholds first")
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent execution slots")
+    ap.add_argument("--summarize-traffic", metavar="DIR", default=None,
+                    help="turn the FETCH_SIZE / WRITE_SIZE counter runs under DIR (copy_FETCH_SIZE, copy_WRITE_SIZE, "
+                         "tc_FETCH_SIZE, tc_WRITE_SIZE) into profiles/traffic_tc_rmat18.json for --bin/--kernel")
+    ap.add_argument("--bin", default="hash_block", help="with --summarize-traffic: the kernel bin")
+    ap.add_argument("--kernel", default="k_maskkey<1, 1, 4, 512, true, 1, false>",
+                    help="with --summarize-traffic: the kernel name (substring) of that bin")
     args = ap.parse_args()
 
+    if args.summarize_traffic:
+        return summarize_traffic(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               "(the row-sharded multi-GPU design is described, not implemented)", file=sys.stderr)
@@ -107,6 +115,8 @@ def main():
         return run_bfs(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "copy":
+        return run_copy(args)
     run_tc(args)
 
 
@@ -448,6 +458,60 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
     if not same:
         sys.exit(1)
+
+
+def _counter_kib(csv_dir, counter, kernel_substr):
+    """Mean per-dispatch value (KiB) of one counter for the kernels whose name
+    contains kernel_substr, from a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+    vals = []
+    for f in glob.glob(os.path.join(csv_dir, "*_counter_collection.csv")):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and kernel_substr in r["Kernel_Name"]:
+                    vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} samples for '{kernel_substr}' under {csv_dir}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def summarize_traffic(args):
+    """HBM bytes per launch of one kernel from two counter runs, each scaled by
+    what the same counter reads for a plain 1 GiB device copy (1 GiB read and
+    1 GiB written per launch)."""
+    d = args.summarize_traffic
+    gib_kib = float(1 << 20)
+    cf, _ = _counter_kib(os.path.join(d, "copy_FETCH_SIZE"), "FETCH_SIZE", "copyBuffer")
+    cw, _ = _counter_kib(os.path.join(d, "copy_WRITE_SIZE"), "WRITE_SIZE", "copyBuffer")
+    kf, nf = _counter_kib(os.path.join(d, "tc_FETCH_SIZE"), "FETCH_SIZE", args.kernel)
+    kw, nw = _counter_kib(os.path.join(d, "tc_WRITE_SIZE"), "WRITE_SIZE", args.kernel)
+    f_scale, w_scale = gib_kib / cf, gib_kib / cw
+    read_b = kf * 1024 * f_scale
+    write_b = kw * 1024 * w_scale
+    out = {"kernel_hash": kernel_source_hash(), "bin": args.bin, "kernel": args.kernel,
+           "hbm_bytes_per_launch": int(round(read_b + write_b)),
+           "read_bytes": int(round(read_b)), "write_bytes": int(round(write_b)),
+           "fetch_kib_raw": round(kf, 3), "write_kib_raw": round(kw, 3), "dispatches": [nf, nw],
+           "copy_fetch_kib_per_gib": round(cf, 3), "copy_write_kib_per_gib": round(cw, 3),
+           "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)}
+    path = os.path.join(ROOT, "profiles", "traffic_tc_rmat18.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out))
+
+
+def run_copy(args):
+    """Calibration for the HBM byte counters: a plain device copy of 1 GiB
+    (1 GiB read, 1 GiB written per launch), timed like the other kernels."""
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    ms = _timed(lambda: dst.copy_(src), args.steps, args.warmup)
+    print(json.dumps({"metric": "copy_gbs", "value": round(2 * n / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+                      "bytes_read": n, "bytes_written": n, "ms_per_copy": round(ms, 4)}), flush=True)
 
 
 def _timed(fn, steps, warmup, stream=None):
