@@ -41,6 +41,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def tuning_kw(args):
+    """Binner thresholds given on the command line (0 keeps the library's)."""
+    kw = {}
+    for name in ("maskidx_max", "block_flops", "split_flops"):
+        v = getattr(args, name, 0)
+        if v:
+            kw[name] = v
+    return kw
+
+
 def row_quantities(L):
     """Per-row counts of the push method for A = B = M = L: A row length,
     products flops_i = sum over k in row i of nnz(L(k,:)), mask length."""
@@ -84,6 +94,12 @@ def main():
     ap.add_argument("--phase", type=int, default=1, choices=(1, 2))
     ap.add_argument("--force-kind", default=None, choices=(None, "dense", "hash", "maskidx", "inner"))
     ap.add_argument("--inner-ratio", type=int, default=0)
+    ap.add_argument("--maskidx-max", type=int, default=0, help="binner: mask rows up to this length use the "
+                    "search kind (0: library default)")
+    ap.add_argument("--block-flops", type=int, default=0, help="binner: products per row above which a row "
+                    "takes a workgroup (0: library default)")
+    ap.add_argument("--split-flops", type=int, default=0, help="binner: products per row above which a dense "
+                    "row is split over workgroups (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "copy"),
                     help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
@@ -137,7 +153,8 @@ def run_tc(args):
     stage_ms = np.zeros(len(msp.STAGE_NAMES), dtype=np.float64)
     sr = "plus_pair_i64"
     total_dev = torch.empty(1, dtype=torch.int64, device=dev)
-    kw = dict(semiring=sr, phase=args.phase, force_kind=args.force_kind, inner_ratio=args.inner_ratio)
+    kw = dict(semiring=sr, phase=args.phase, force_kind=args.force_kind, inner_ratio=args.inner_ratio,
+              **tuning_kw(args))
 
     plan_ms = [0.0]
 
@@ -271,7 +288,7 @@ def run_bfs(args):
         stage_ms = np.zeros(len(msp.STAGE_NAMES))
 
         def step(record):
-            with msp.Plan(dA, dF, dV, complement=True, semiring=sr) as p:
+            with msp.Plan(dA, dF, dV, complement=True, semiring=sr, **tuning_kw(args)) as p:
                 cap = max(p.upper_bound, 1)
                 rp = torch.empty(G.nrows + 1, dtype=torch.int64, device=dev)
                 ci = torch.empty(cap, dtype=torch.int32, device=dev)

@@ -18,6 +18,8 @@
 // lazy insert of the accumulator interface, Section "Accumulator").
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "msp_device.hpp"
 #include "msp_internal.hpp"
 
@@ -422,10 +424,22 @@ hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* part
 
 // Products per lane per step of the product stream: each lane keeps this
 // many independent B loads in flight, a wave covers 64 * STREAM_U products.
+// Minimum waves per SIMD the compiler must leave room for (register
+// budget) in the multi-wave (block) and one-wave numeric kernels.
+#ifndef MSP_MINW_BLOCK
+#define MSP_MINW_BLOCK 1
+#endif
+#ifndef MSP_MINW_WAVE
+#define MSP_MINW_WAVE 1
+#endif
 #ifndef MSP_STREAM_U
 #define MSP_STREAM_U 8
 #endif
 constexpr int STREAM_U = MSP_STREAM_U;
+
+// An int32 in global memory (addresses rebuilt from integers keep their
+// address space, so the loads stay global rather than flat).
+typedef __attribute__((address_space(1))) const int32_t gint32_t;
 
 // Per-wave LDS for one batch of up to 64 A entries: for the s-th stanza with
 // a nonzero length (in A order), its start in the flattened product
@@ -434,17 +448,23 @@ constexpr int STREAM_U = MSP_STREAM_U;
 template <class T>
 struct StanzaLds {
     int64_t start[WAVE];
-    int64_t delta[WAVE];
+    uint64_t ptr[WAVE];  // byte address that flattened position 0 would have in B's column indices
     typename T::in_t a[WAVE];
     unsigned long long S[STREAM_U];
 };
 
+
 // Streams every product (k, j) of the A entries [pa0, pa1) of one row: for each stored A(i,k) and each
-// stored B(k,j) with lo <= j <= hi (when `window`), calls f(j, s, q, true)
-// where q is the position of B(k,j) and s indexes st.a for A(i,k); slots
-// past the last product call f(j, s, q, false) with meaningless j, s, q. Wave `wv` of
-// `nw` waves processes the windows wv, wv + nw, ... of 64 * STREAM_U
-// products of each batch.
+// stored B(k,j) with lo <= j <= hi (when `window`). The products reach the
+// caller one window at a time: f(j, s, q, act) gets STREAM_U products per
+// lane, where for slot u, q[u] is the position of B(k,j), j[u] its column and
+// s[u] indexes st.a for A(i,k); slots past the last product have act[u] ==
+// false and meaningless j, s, q. Handing over a whole window lets the caller
+// issue the LDS (and value) reads of all its slots before waiting for any.
+// Wave `wv` of `nw` waves processes the windows wv, wv + nw, ... of
+// 64 * STREAM_U products of each batch; batch_end() runs after the last
+// window of every batch of 64 A entries, while st.a and st.ptr still
+// describe that batch.
 //
 // Lane-to-stanza mapping of a window: every stanza that starts inside the
 // window sets bit (start - window base) of a 64 * STREAM_U-bit map; the
@@ -453,9 +473,9 @@ struct StanzaLds {
 //   + popcount(map bits 0 .. 64u + lane) - 1.
 // The STREAM_U loads of a lane are issued back to back before any of them is
 // consumed, so a wave keeps STREAM_U stanza reads outstanding.
-template <class T, class F>
+template <class T, class F, class E>
 __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, int64_t pa1, bool window, int32_t lo,
-                                                int32_t hi, int wv, int nw, StanzaLds<T>& st, F&& f) {
+                                                int32_t hi, int wv, int nw, StanzaLds<T>& st, F&& f, E&& batch_end) {
     const int ln = lane();
     constexpr int64_t WIN = (int64_t)WAVE * STREAM_U;
     for (int64_t pb = pa0; pb < pa1; pb += WAVE) {
@@ -481,7 +501,7 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
         if (len > 0) {
             const int sl = rank_below(nzm);
             st.start[sl] = incl - len;
-            st.delta[sl] = b0 - (incl - len);
+            st.ptr[sl] = (uint64_t)(o.Bci + b0) - 4ull * (uint64_t)(incl - len);
             if (T::needs_values) st.a[sl] = a;
         }
         wave_lds_sync();
@@ -505,27 +525,68 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
             if (ln < STREAM_U) st.S[ln] = 0ull;
             const int lim = (int)min(total - base, WIN);  // products left in this window
             // stanza of the product at window offset 64u + lane:
-            //   (#stanzas starting before it) + (#starts at offsets <= 64u + lane) - 1
+            //   (#stanzas starting before it) + (#starts at offsets <= 64u + lane) - 1,
+            // which lies in [0, nz): stanza 0 starts at position 0
             int sidx[STREAM_U];
             int cum = before - 1;
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) {
-                sidx[u] = min(max(cum + (int)(Sw[u] & 1ull) + rank_below(Sw[u] >> 1), 0), WAVE - 1);
+                sidx[u] = cum + (int)(Sw[u] & 1ull) + rank_below(Sw[u] >> 1);
                 cum += __popcll(Sw[u]);
             }
+            // the product at flattened position x of stanza s sits at byte st.ptr[s] + 4x
+            // (slot u adds 64u entries: an immediate offset of the load)
+            const uint64_t pos4 = 4ull * (uint64_t)(base + ln);
+            const gint32_t* bp[STREAM_U];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) bp[u] = reinterpret_cast<const gint32_t*>(st.ptr[sidx[u]] + pos4);
             int64_t q[STREAM_U];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) q[u] = st.delta[sidx[u]];
-            // an inactive slot (past the window's products) reads B position 0, which exists
-            // whenever the window is non-empty, and is not passed on
+            for (int u = 0; u < STREAM_U; ++u)
+                q[u] = (int64_t)(((uint64_t)(bp[u] + u * WAVE) - (uint64_t)o.Bci) >> 2);
+            // a full window (every slot holds a product) and the batch's last, partial one take
+            // separate straight-line copies of the window's work
+            auto run = [&](auto full) {
+                constexpr bool FULL = decltype(full)::value;
+                bool act[STREAM_U];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) q[u] = (u * WAVE + ln < lim) ? q[u] + base + (u * WAVE + ln) : 0;
-            int32_t j[STREAM_U];
+                for (int u = 0; u < STREAM_U; ++u) act[u] = FULL || u * WAVE + ln < lim;
+                int32_t j[STREAM_U];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) j[u] = o.Bci[q[u]];
-#pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) f(j[u], sidx[u], q[u], u * WAVE + ln < lim);
+                for (int u = 0; u < STREAM_U; ++u) j[u] = (FULL || act[u]) ? bp[u][u * WAVE] : 0;
+                f(j, sidx, q, act);
+            };
+            if (lim == WIN) run(std::integral_constant<bool, true>{});
+            else run(std::integral_constant<bool, false>{});
             wave_lds_sync();
+        }
+        batch_end();
+        wave_lds_sync();
+    }
+}
+
+// Folds the admitted products of one window into the LDS accumulator: slot
+// u goes to vals[slot[u]] when hit[u]. B values are loaded only for admitted
+// products; all loads of the window are issued before the first LDS update.
+template <class T, bool FLAGS, bool COUNT>
+__device__ __forceinline__ void window_accumulate(const bool* hit, const int* slot, const int* s, const int64_t* q,
+                                                  const Operands& o, const StanzaLds<T>& st,
+                                                  typename T::acc_t* vals, uint8_t* flags) {
+    typename T::in_t b[STREAM_U], a[STREAM_U];
+    if (!COUNT) {
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) {
+            b[u] = T::one();
+            if (T::needs_values && hit[u]) b[u] = T::load(o.Bv, q[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) a[u] = T::needs_values ? st.a[s[u]] : T::one();
+    }
+#pragma unroll
+    for (int u = 0; u < STREAM_U; ++u) {
+        if (hit[u]) {
+            if (FLAGS) flags[slot[u]] = 1;
+            if (!COUNT) T::lds_add(&vals[slot[u]], T::term(a[u], b[u]));
         }
     }
 }
@@ -576,7 +637,7 @@ __device__ __forceinline__ void unit_sync() {
 // Emission scans the tile in column order, so rows come out sorted for both
 // mask modes.
 template <int SR, int MODE, int NW, int W, int WPB, bool BATCH>
-__global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
+__global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW_WAVE) void k_dense(NumArgs g) {
     static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
@@ -625,17 +686,20 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
     unit_sync<NW>();
     StanzaLds<T>& S = st[wave];
     stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
-                       [&](int32_t j, int s, int64_t q, bool act) {
-                           if (!act) return;
-                           const int c = j - (int)c0;
-                           if (allowed[c >> 5] & (1u << (c & 31))) {
-                               if (FLAGS) flags[c] = 1;
-                               if (!COUNT) {
-                                   const typename T::in_t b = T::needs_values ? T::load(o.Bv, q) : T::one();
-                                   T::lds_add(&vals[c], T::term(S.a[s], b));
-                               }
+                       [&](const int32_t* j, const int* s, const int64_t* q, const bool* act) {
+                           int c[STREAM_U];
+                           uint32_t w[STREAM_U];
+                           bool hit[STREAM_U];
+#pragma unroll
+                           for (int u = 0; u < STREAM_U; ++u) {
+                               c[u] = act[u] ? j[u] - (int)c0 : 0;  // column 0 of the tile always exists
+                               w[u] = allowed[c[u] >> 5];
                            }
-                       });
+#pragma unroll
+                           for (int u = 0; u < STREAM_U; ++u) hit[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u);
+                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, q, o, S, vals, flags);
+                       },
+                       [] {});
     unit_sync<NW>();
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
@@ -659,7 +723,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_dense(NumArgs g) {
 // semiring's (+)); a second kernel emits every split row in column order.
 // Integer semirings stay exact; FP64 sums are reordered (within tolerance).
 template <int SR, int MODE, bool BATCH>
-__global__ __launch_bounds__(BLOCK_NW * WAVE) void k_dense_split(NumArgs g) {
+__global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split(NumArgs g) {
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     constexpr int W = DENSE_B_COLS;
@@ -700,16 +764,21 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE) void k_dense_split(NumArgs g) {
     const int64_t chunk = (alen + nchunk - 1) / nchunk;
     const int64_t a0 = ra0 + min((int64_t)t * chunk, alen), a1 = ra0 + min((int64_t)(t + 1) * chunk, alen);
     StanzaLds<T>& S = st[wv];
-    stream_products<T>(o, a0, a1, false, 0, 0, wv, NW, S, [&](int32_t j, int s, int64_t q, bool act) {
-        if (!act) return;
-        if (allowed[j >> 5] & (1u << (j & 31))) {
-            if (FLAGS) flags[j] = 1;
-            if (!COUNT) {
-                const typename T::in_t b = T::needs_values ? T::load(o.Bv, q) : T::one();
-                T::lds_add(&vals[j], T::term(S.a[s], b));
-            }
-        }
-    });
+    stream_products<T>(o, a0, a1, false, 0, 0, wv, NW, S,
+                       [&](const int32_t* j, const int* s, const int64_t* q, const bool* act) {
+                           int c[STREAM_U];
+                           uint32_t w[STREAM_U];
+                           bool hit[STREAM_U];
+#pragma unroll
+                           for (int u = 0; u < STREAM_U; ++u) {
+                               c[u] = act[u] ? j[u] : 0;
+                               w[u] = allowed[c[u] >> 5];
+                           }
+#pragma unroll
+                           for (int u = 0; u < STREAM_U; ++u) hit[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u);
+                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, q, o, S, vals, flags);
+                       },
+                       [] {});
     __syncthreads();
     unsigned int* gset = g.gset + (int64_t)sidx * NWORDS;
     acc_t* gval = static_cast<acc_t*>(g.gval) + (int64_t)sidx * W;
@@ -799,20 +868,49 @@ __device__ __forceinline__ int hash_find(const int4* tkey, const uint16_t* trank
     return h < 0 ? -1 : (int)trank[b * 4 + h];
 }
 
+// Most products of a row miss its mask, so a lookup is preceded by a
+// membership filter: a bitmap of FILTER_WORDS * 32 bits with bit (j mod
+// bits) set for every key. A product that passes (a key, or a rare false
+// positive) goes to a per-wave ring of candidates; whenever a wave has 64
+// candidates it looks them up together, one per lane, so the lookup runs at
+// full lane occupancy instead of once per product. The ring is drained at
+// the end of every batch of A entries (candidates refer to that batch's A
+// values).
+template <int CAP, bool QVAL>
+struct MaskKeyCfg {
+    static constexpr int FILTER_WORDS = CAP < 1024 ? CAP : 1024;  // <= 1 key per 32 bits up to 1024 keys
+    // candidates are appended DRAIN slots at a time before full rounds are looked up, so the
+    // ring holds up to 63 waiting + 64 * DRAIN new ones (entries with value positions are larger)
+    static constexpr int DRAIN = QVAL ? 1 : 2;
+    static constexpr int QCAP = DRAIN == 1 ? 2 * WAVE : (DRAIN == 2 ? 4 * WAVE : 8 * WAVE);
+    static_assert(WAVE - 1 + WAVE * DRAIN <= QCAP, "candidate ring too small");
+};
+
 template <int SR, int MODE, int NW, int CAP, bool HASHED, int WPB, bool BATCH>
-__global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
+__global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW_WAVE) void k_maskkey(NumArgs g) {
     static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     constexpr bool COUNT = MODE == MODE_COUNT;
     constexpr bool FLAGS = COUNT || T::sep_flag;
-    constexpr int NBK = HASHED ? CAP : 1;  // buckets (4 slots each)
+    constexpr bool QVAL = !COUNT && T::needs_values;  // candidates carry the positions of their values
+    constexpr int NBK = HASHED ? CAP : 1;             // buckets (4 slots each)
     constexpr int UT = NW * WAVE;
+    constexpr int FW = MaskKeyCfg<CAP, QVAL>::FILTER_WORDS;
+    constexpr int FW_BITS = __builtin_ctz(FW);
+    static_assert((FW & (FW - 1)) == 0, "filter words: a power of two");
+    constexpr int QCAP = MaskKeyCfg<CAP, QVAL>::QCAP;
+    constexpr int DRAIN = MaskKeyCfg<CAP, QVAL>::DRAIN;
+    static_assert(STREAM_U % DRAIN == 0, "slots per window: a multiple of the drain group");
     __shared__ int32_t keys_[WPB][CAP];
     __shared__ int4 tkey_[WPB][NBK];
     __shared__ uint16_t trank_[WPB][4 * NBK];
     __shared__ acc_t vals_[WPB][COUNT ? 1 : CAP];
     __shared__ uint8_t flags_[WPB][FLAGS ? CAP : 1];
+    __shared__ uint32_t filt_[WPB][FW];
+    __shared__ int32_t qj_[WPB * NW][QCAP + WAVE];
+    __shared__ int64_t qq_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];
+    __shared__ uint8_t qs_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
     const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
@@ -823,6 +921,10 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
     uint16_t* trank = trank_[gi];
     acc_t* vals = vals_[gi];
     uint8_t* flags = flags_[gi];
+    uint32_t* filt = filt_[gi];
+    int32_t* qj = qj_[wave];
+    int64_t* qq = qq_[QVAL ? wave : 0];
+    uint8_t* qs = qs_[QVAL ? wave : 0];
     // the unit is the same for every lane of the wave
     const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
     const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
@@ -840,13 +942,17 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
     int bbits = 1;
     while ((1 << bbits) < cnt) ++bbits;
     const uint32_t bmask = (1u << bbits) - 1u;
+    // the filter uses about one word (32 bits) per key: at most 1 bit in 32 set
+    const int fwb = min(bbits, FW_BITS);
+    for (int x = ut; x < (1 << fwb); x += UT) filt[x] = 0u;
     if (HASHED)
         for (int x = ut; x <= (int)bmask; x += UT) tkey[x] = make_int4(-1, -1, -1, -1);
     if (lane() < STREAM_U) st[wave].S[lane()] = 0ull;
     unit_sync<NW>();
-    if (HASHED) {
-        for (int x = ut; x < cnt; x += UT) {
-            const int32_t key = keys[x];
+    for (int x = ut; x < cnt; x += UT) {
+        const int32_t key = keys[x];
+        atomicOr(&filt[(key >> 5) & ((1 << fwb) - 1)], 1u << (key & 31));
+        if (HASHED) {
             int32_t* slots = reinterpret_cast<int32_t*>(tkey);
             uint32_t b = hash_slot(key, bbits);
             int sl = 0;
@@ -855,23 +961,78 @@ __global__ __launch_bounds__(NW * WPB * WAVE) void k_maskkey(NumArgs g) {
             }
             trank[b * 4 + sl] = (uint16_t)x;
         }
-        unit_sync<NW>();
     }
+    unit_sync<NW>();
     const int32_t lo = keys[0], hi = keys[cnt - 1];
     const int top = 1 << (31 - __clz(cnt));
     StanzaLds<T>& S = st[wave];
-    stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, lo, hi, wv, NW, S, [&](int32_t j, int s, int64_t q, bool act) {
-        // an inactive slot looks up a column that no mask holds (branch-free)
-        const int32_t jj = act ? j : INT32_MIN;
-        const int r = HASHED ? hash_find(tkey, trank, bmask, bbits, jj) : rank_search(keys, cnt, top, jj);
+    // candidate ring of this wave: entries [qh, qn) (mod QCAP) wait for a lookup; qh, qn are wave-uniform
+    uint32_t qh = 0, qn = 0;
+    // looks up `count` <= 64 candidates starting at ring entry `base`, one per lane
+    auto lookup_round = [&](uint32_t base, int count) {
+        const int x = lane();
+        const int e = (int)((base + (uint32_t)x) & (QCAP - 1));
+        const int32_t jv = x < count ? qj[e] : INT32_MIN;  // an idle lane looks up a column no mask holds
+        const int r = HASHED ? hash_find(tkey, trank, bmask, bbits, jv) : rank_search(keys, cnt, top, jv);
         if (r >= 0) {
             if (FLAGS) flags[r] = 1;
             if (!COUNT) {
-                const typename T::in_t b = T::needs_values ? T::load(o.Bv, q) : T::one();
-                T::lds_add(&vals[r], T::term(S.a[s], b));
+                typename T::in_t av = T::one(), bv = T::one();
+                if (QVAL) {
+                    bv = T::load(o.Bv, qq[e]);
+                    av = S.a[qs[e]];
+                }
+                T::lds_add(&vals[r], T::term(av, bv));
             }
         }
-    });
+    };
+    stream_products<T>(
+        o, o.Arp[i], o.Arp[i + 1], tiled, lo, hi, wv, NW, S,
+        [&](const int32_t* j, const int* s, const int64_t* q, const bool* act) {
+            uint32_t w[STREAM_U];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) w[u] = filt[__builtin_amdgcn_ubfe((uint32_t)j[u], 5, (uint32_t)fwb)];
+            bool pass[STREAM_U];
+            uint64_t m[STREAM_U];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                pass[u] = act[u] & (__builtin_amdgcn_ubfe(w[u], (uint32_t)j[u], 1) != 0u);
+                m[u] = __ballot(pass[u]);
+            }
+            // append the window's candidates to the ring, DRAIN slots at a time, and look up every
+            // full round of 64; the ring indices are wave-uniform
+            uint32_t cum = (uint32_t)__builtin_amdgcn_readfirstlane((int)qn);
+            uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane((int)qh);
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                // every lane writes (branch-free): a rejected product to its own spare entry past the ring
+                const int ea = (int)((cum + (uint32_t)rank_below(m[u])) & (QCAP - 1));
+                const int e = pass[u] ? ea : QCAP + lane();
+                qj[e] = j[u];
+                if (QVAL) {
+                    qq[e] = q[u];
+                    qs[e] = (uint8_t)s[u];
+                }
+                cum += (uint32_t)__popcll(m[u]);
+                if ((u + 1) % DRAIN == 0 && cum - h >= (uint32_t)WAVE) {
+                    wave_lds_sync();
+                    do {
+                        lookup_round(h, WAVE);
+                        h += WAVE;
+                    } while (cum - h >= (uint32_t)WAVE);
+                    wave_lds_sync();  // the round's reads come before later appends reuse its entries
+                }
+            }
+            qn = cum;
+            qh = h;
+        },
+        [&] {
+            if (qn != qh) {
+                wave_lds_sync();
+                lookup_round(qh, (int)(qn - qh));
+                qh = qn;
+            }
+        });
     unit_sync<NW>();
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
