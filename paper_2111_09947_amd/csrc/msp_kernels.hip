@@ -159,14 +159,17 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
                         int maskidx_max, int64_t block_flops, int64_t split_flops, int64_t icost, int& bin,
                         int64_t& tiles) {
     int kind = comp ? (int)MSP_KIND_DENSE : force;
+    const bool heavy = flops > block_flops;
     if (kind == MSP_KIND_AUTO) {
+        // Every mask-keyed lookup is behind the membership filter, so a light row is looked up
+        // by search in the smaller (higher-occupancy) kernel; a heavy row with a mid-size mask
+        // has more candidates per lookup round and takes the hash table of a workgroup.
         if (inner_ratio > 0 && icost * (int64_t)inner_ratio < flops) kind = MSP_KIND_INNER;
         else if (n <= DENSE_W_COLS) kind = MSP_KIND_DENSE;
-        else if (mnnz <= maskidx_max) kind = MSP_KIND_MASKIDX;
+        else if (mnnz <= maskidx_max || (mnnz <= MASKIDX_W_CAP && !heavy)) kind = MSP_KIND_MASKIDX;
         else if (mnnz <= HASH_B_CAP) kind = MSP_KIND_HASH;
         else kind = MSP_KIND_MASKIDX;
     }
-    const bool heavy = flops > block_flops;
     const bool split = split_flops > 0 && flops > split_flops && alen > 1;
     switch (kind) {
     case MSP_KIND_DENSE:
@@ -637,7 +640,8 @@ __device__ __forceinline__ void unit_sync() {
 // Emission scans the tile in column order, so rows come out sorted for both
 // mask modes.
 template <int SR, int MODE, int NW, int W, int WPB, bool BATCH>
-__global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW_WAVE) void k_dense(NumArgs g) {
+__global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SRT<SR>::sep_flag ? 5 : MSP_MINW_BLOCK)
+                                                    : MSP_MINW_WAVE) void k_dense(NumArgs g) {
     static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
@@ -1121,6 +1125,9 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     if (ln == 0 && MODE != MODE_DIRECT) g.cnt[u] = running;
 }
 
+#ifndef MSP_HASH_LOOKUP
+#define MSP_HASH_LOOKUP 1
+#endif
 #ifndef MSP_WPB
 #define MSP_WPB 1
 #endif
@@ -1138,10 +1145,10 @@ static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_HASH_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, true, WPB, BATCH>), gw, bw, 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, MSP_HASH_LOOKUP != 0, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_HASH_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, true, 1, BATCH>), gb, bb, 0, s, a);
+        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, MSP_HASH_LOOKUP != 0, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_MASKIDX_W:
         hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false, WPB, BATCH>), gw, bw, 0, s, a);
