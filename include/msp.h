@@ -84,6 +84,10 @@ typedef enum msp_semiring {
  *  MASKIDX  slot = rank of the column in the row of M, found by binary
  *           search over the mask row staged in LDS (Section "Mask
  *           Compressed Accumulator"). Normal mask only.
+ *           HASH and MASKIDX first test each product's column against a
+ *           bitmap filter of the mask row in LDS; only products that pass
+ *           are looked up (the accumulator still holds one slot per mask
+ *           entry, as in the paper).
  *  INNER    pull formulation: one sparse dot product of A(i,:) with B(:,j)
  *           per admitted (i,j) (Section "Pull-based Algorithms"). Needs the
  *           transpose of B, built by the plan unless options->b_transpose is
@@ -138,7 +142,10 @@ typedef struct msp_options {
     const msp_csr* b_transpose; /* optional CSR of B^T (n x k); NULL = built by the
                                    plan when INNER is used */
     int32_t maskidx_max;  /* auto mode: rows whose mask has at most this many
-                             entries use MASKIDX, larger ones HASH (-1 = default 8) */
+                             entries use MASKIDX whatever their product count;
+                             light rows (at most block_flops products) with at
+                             most 256 mask entries use MASKIDX too, other rows
+                             with at most 512 use HASH (-1 = default 8) */
     int32_t reserved;
     int64_t block_flops;  /* rows with more products than this run on a whole
                              256-thread workgroup instead of one wavefront
