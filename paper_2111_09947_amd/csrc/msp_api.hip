@@ -10,11 +10,13 @@
 // table. A single product (msp_plan_create) is the case P = 1.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <utility>
+#include <map>
 #include <vector>
 
 #include "msp.h"
@@ -121,6 +123,7 @@ struct msp_plan {
     int64_t bin_off[NBINS + 1] = {};
     int64_t seg_off[NBINS * NBUCKET] = {};
     int64_t* seg_off_d = nullptr;
+    int64_t* icost = nullptr;
     unsigned long long* seg_cursor = nullptr;
     int32_t* unit_row = nullptr;
     int32_t* unit_tile = nullptr;
@@ -265,6 +268,57 @@ static msp_status build_transpose(msp_plan* P, Product& pr, bool scatter) {
 }
 
 // Plans the products `probs` (count P). want_staging: allocate one-phase staging.
+// Pinned host staging for the small device-to-host reads (statistics and
+// output counts): page-locked buffers are reused through a process-wide pool,
+// so a read is one DMA transfer instead of a staged pageable copy.
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    static std::mutex& mu() {
+        static std::mutex m;
+        return m;
+    }
+    static std::multimap<size_t, void*>& pool() {
+        static std::multimap<size_t, void*> free_list;
+        return free_list;
+    }
+    msp_status get(size_t bytes) {
+        {
+            std::lock_guard<std::mutex> lk(mu());
+            auto it = pool().lower_bound(bytes);
+            if (it != pool().end()) {
+                cap = it->first;
+                p = it->second;
+                pool().erase(it);
+                return MSP_OK;
+            }
+        }
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return fail(MSP_ERR_OUT_OF_MEMORY, "pinned host allocation");
+        }
+        cap = c;
+        return MSP_OK;
+    }
+    ~PinnedBuf() {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu());
+        pool().emplace(cap, p);
+    }
+};
+
+// Reads one int64 from device memory after the stream's work (synchronizes).
+static msp_status read_back_i64(int64_t* dst, const int64_t* src, hipStream_t s) {
+    PinnedBuf pin;
+    MSP_CHECK(pin.get(sizeof(int64_t)));
+    MSP_HIP(hipMemcpyAsync(pin.p, src, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MSP_HIP(hipStreamSynchronize(s));
+    std::memcpy(dst, pin.p, sizeof(int64_t));
+    return MSP_OK;
+}
+
 static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_t count, msp_semiring semiring,
                                    const msp_options* opt, hipStream_t stream, bool want_staging) {
     if (count < 1) return fail(MSP_ERR_INVALID_ARGUMENT, "a plan needs at least one product");
@@ -318,6 +372,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     P->R = R;
     hipStream_t s = stream;
 
+    const bool inner_any = o.force_kind == MSP_KIND_INNER || (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0);
     // workspace sized by the operand shapes
     {
         msp_plan::Carve c;
@@ -326,6 +381,13 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         c.add(&P->unit_base, R + 1);
         c.add(&P->bin, R);
         c.add(&P->scan_partial, scan_partial_elems(R + 1));
+        c.add(&P->seg_off_d, NBINS * NBUCKET);
+        c.add(&P->seg_cursor, NBINS * NBUCKET + 1);  // + the split-row counter
+        if (inner_any) {  // pull cost per row, one product at a time (stream order)
+            int64_t mmax = 0;
+            for (const Product& pr : P->prods) mmax = std::max(mmax, pr.op.m);
+            c.add(&P->icost, mmax);
+        }
         MSP_CHECK(P->alloc_carve(c));
     }
     MSP_HIP(hipMemsetAsync(P->stats_d, 0, sizeof(unsigned long long) * ST_COUNT * count, s));
@@ -346,7 +408,6 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         MSP_HIP(hipStreamSynchronize(s));
         if (e) return fail(MSP_ERR_INVALID_CSR, "an operand violates the CSR invariants");
     }
-    const bool inner_any = o.force_kind == MSP_KIND_INNER || (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0);
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
         if (pr.op.complement || !inner_any) continue;
@@ -369,6 +430,9 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.block_flops = o.block_flops;
         aa.split_flops = o.split_flops;
         aa.colcnt_rp = pr.op.BTrp;
+        aa.a_nnz = probs[p].A.nnz;
+        aa.m_nnz = probs[p].M.nnz;
+        aa.icost = (aa.inner_ratio > 0 && aa.colcnt_rp && o.force_kind == MSP_KIND_AUTO) ? P->icost : nullptr;
         aa.flops = P->flops;
         aa.tiles = P->unit_base;
         aa.bin = P->bin;
@@ -376,10 +440,17 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         MSP_HIP(launch_analysis(aa, s));
     }
     MSP_HIP(launch_scan(P->unit_base, P->unit_base, R, P->scan_partial, s));
-    P->stats.assign((size_t)(count * ST_COUNT), 0ull);
-    MSP_HIP(hipMemcpyAsync(P->stats.data(), P->stats_d, sizeof(unsigned long long) * ST_COUNT * count,
-                           hipMemcpyDeviceToHost, s));
-    MSP_HIP(hipStreamSynchronize(s));
+    MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, P->seg_cursor, s));
+    {
+        // the one synchronization of plan creation: the statistics size the unit arrays
+        const size_t sb = sizeof(unsigned long long) * ST_COUNT * (size_t)count;
+        PinnedBuf pin;
+        MSP_CHECK(pin.get(sb));
+        MSP_HIP(hipMemcpyAsync(pin.p, P->stats_d, sb, hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+        P->stats.assign((size_t)(count * ST_COUNT), 0ull);
+        std::memcpy(P->stats.data(), pin.p, sb);
+    }
 
     // totals; bins in order, inside a bin the flops buckets from the heaviest down
     std::vector<int64_t> segc(NBINS * NBUCKET, 0);
@@ -425,8 +496,6 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     // workspace sized by the units (and the one-phase staging)
     {
         msp_plan::Carve c;
-        c.add(&P->seg_off_d, NBINS * NBUCKET);
-        c.add(&P->seg_cursor, NBINS * NBUCKET + 1);  // + the split-row counter
         c.add(&P->unit_row, U);
         c.add(&P->unit_tile, U);
         c.add(&P->unit_prob, U);
@@ -451,8 +520,6 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         MSP_CHECK(P->alloc_carve(c));
         if (part) P->scan_partial = part;
     }
-    MSP_HIP(hipMemcpyAsync(P->seg_off_d, P->seg_off, sizeof(int64_t) * NBINS * NBUCKET, hipMemcpyHostToDevice, s));
-    MSP_HIP(hipMemsetAsync(P->seg_cursor, 0, sizeof(unsigned long long) * (NBINS * NBUCKET + 1), s));
     P->split_counter = P->seg_cursor + NBINS * NBUCKET;
     if (count > 1) {
         std::vector<Operands> ops((size_t)count);
@@ -568,27 +635,45 @@ static OutBind bind_of(const msp_plan* P, const msp_csr_out* C, int64_t p) {
 }
 
 // Optional per-stage HIP event timing (msp_execute_profiled).
+// Per-thread, per-device pool of timing events (created once, reused).
+static std::vector<hipEvent_t>& event_pool() {
+    thread_local std::map<int, std::vector<hipEvent_t>> pools;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return pools[dev];
+}
+
+// Stage times from events attached to the stage's own kernel launches
+// (hipExtLaunchKernel): begin() arms a start/stop pair, end() disarms it.
 struct StageTimer {
     bool on = false;
     hipStream_t s = nullptr;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-    hipEvent_t open_ev = nullptr;
+    std::vector<hipEvent_t> held;  // taken from the pool, returned at destruction
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     int open_stage = -1;
+    msp_status take(hipEvent_t* e) {
+        auto& pool = event_pool();
+        if (pool.empty()) {
+            MSP_HIP(hipEventCreate(e));
+        } else {
+            *e = pool.back();
+            pool.pop_back();
+        }
+        held.push_back(*e);
+        return MSP_OK;
+    }
     msp_status begin(int stage) {
         if (!on) return MSP_OK;
-        hipEvent_t e;
-        MSP_HIP(hipEventCreate(&e));
-        MSP_HIP(hipEventRecord(e, s));
-        open_ev = e;
+        MSP_CHECK(take(&ev_start));
+        MSP_CHECK(take(&ev_stop));
         open_stage = stage;
+        timing_arm(ev_start, ev_stop);
         return MSP_OK;
     }
     msp_status end() {
         if (!on) return MSP_OK;
-        hipEvent_t e;
-        MSP_HIP(hipEventCreate(&e));
-        MSP_HIP(hipEventRecord(e, s));
-        marks.push_back({open_stage, {open_ev, e}});
+        if (timing_disarm()) marks.push_back({open_stage, {ev_start, ev_stop}});
         return MSP_OK;
     }
     msp_status collect(double* ms) {
@@ -602,10 +687,9 @@ struct StageTimer {
         return MSP_OK;
     }
     ~StageTimer() {
-        for (auto& mk : marks) {
-            (void)hipEventDestroy(mk.second.first);
-            (void)hipEventDestroy(mk.second.second);
-        }
+        (void)timing_disarm();
+        auto& pool = event_pool();
+        for (hipEvent_t e : held) pool.push_back(e);
     }
 };
 
@@ -682,10 +766,7 @@ static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_hos
     MSP_HIP(launch_rowptr(1, pr.op.m + 1, nullptr, nullptr, one, P->unit_base, P->cnt, s));
     MSP_CHECK(tm.end());
     P->symbolic_done = true;
-    if (nnz_host) {
-        MSP_HIP(hipMemcpyAsync(nnz_host, C_rowptr + pr.op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-    }
+    if (nnz_host) MSP_CHECK(read_back_i64(nnz_host, C_rowptr + pr.op.m, s));
     return MSP_OK;
 }
 
@@ -732,10 +813,7 @@ static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, h
     }
     const OutBind one = bind_of(P, C, 0);
     MSP_CHECK(run_one_phase(P, one, s, tm));
-    if (nnz_host) {
-        MSP_HIP(hipMemcpyAsync(nnz_host, C->rowptr + pr.op.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-    }
+    if (nnz_host) MSP_CHECK(read_back_i64(nnz_host, C->rowptr + pr.op.m, s));
     return MSP_OK;
 }
 

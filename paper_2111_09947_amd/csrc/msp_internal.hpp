@@ -76,6 +76,9 @@ struct AnalysisArgs {
     int64_t block_flops;
     int64_t split_flops;
     const int64_t* colcnt_rp;  // row pointers of B^T (column counts of B) or null
+    int64_t a_nnz;             // nnz(A), nnz(M)
+    int64_t m_nnz;
+    int64_t* icost;            // [m] pull cost per row (auto INNER choice) or null
     int64_t* flops;            // [R] global rows
     int64_t* tiles;            // [R+1], number of units per row (scanned later)
     int8_t* bin;               // [R]
@@ -181,6 +184,18 @@ hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const 
 int64_t reduce_partial_elems();
 hipError_t launch_reduce(int semiring, const void* vals, int64_t n, void* partial, void* result,
                          hipStream_t s);
+
+// Unit-list segment offsets from the per-product statistics; zeroes the
+// placement cursors (NBINS * NBUCKET + 1 entries).
+hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
+                         unsigned long long* cursor, hipStream_t s);
+
+// Stage timing: between timing_arm(start, stop) and timing_disarm(), the
+// launches of this thread record `start` at the beginning of the first kernel
+// and `stop` at the end of the last one. timing_disarm() returns whether any
+// kernel was launched (otherwise the events were not recorded).
+void timing_arm(hipEvent_t start, hipEvent_t stop);
+bool timing_disarm();
 
 int out_bytes(int semiring);   // output value width
 int in_bytes(int semiring);    // input value width (0: values ignored)

@@ -16,12 +16,52 @@
 // that all 64 lanes read consecutive B entries regardless of stanza lengths;
 // a product's B value is loaded only when the mask admits its column (the
 // lazy insert of the accumulator interface, Section "Accumulator").
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
 
 #include "msp_device.hpp"
 #include "msp_internal.hpp"
+
+namespace mspk {
+
+// Kernel-attached timing. While a stage is armed (timing_arm), every launch
+// goes through hipExtLaunchKernel with the stage's events: the first launch
+// of the stage records `start` when it begins and every launch records `stop`
+// when it ends, so the pair spans exactly the stage's kernels. No marker
+// packets are inserted between kernels, unlike separate event records.
+namespace {
+thread_local hipEvent_t tl_start = nullptr;
+thread_local hipEvent_t tl_stop = nullptr;
+thread_local bool tl_launched = false;
+}  // namespace
+
+void timing_arm(hipEvent_t start, hipEvent_t stop) {
+    tl_start = start;
+    tl_stop = stop;
+    tl_launched = false;
+}
+
+bool timing_disarm() {
+    const bool launched = tl_launched;
+    tl_start = tl_stop = nullptr;
+    tl_launched = false;
+    return launched;
+}
+
+}  // namespace mspk
+
+#define MSP_LAUNCH(K, G, B, SH, S, ...)                                                                    \
+    do {                                                                                                 \
+        if (::mspk::tl_stop) {                                                                           \
+            hipExtLaunchKernelGGL(K, G, B, SH, S, ::mspk::tl_launched ? nullptr : ::mspk::tl_start,      \
+                                  ::mspk::tl_stop, 0u, __VA_ARGS__);                                      \
+            ::mspk::tl_launched = true;                                                                  \
+        } else {                                                                                         \
+            hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                             \
+        }                                                                                                \
+    } while (0)
 
 namespace mspk {
 
@@ -76,7 +116,7 @@ __global__ void k_validate(const int64_t* __restrict__ rp, const int32_t* __rest
 
 hipError_t launch_validate(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int64_t nnz,
                            unsigned long long* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(nrows + 1, 256, INT32_MAX)), dim3(256), 0, s, rp, ci, nrows,
+    MSP_LAUNCH(k_validate, dim3(grid_for(nrows + 1, 256, INT32_MAX)), dim3(256), 0, s, rp, ci, nrows,
                        ncols, nnz, err);
     return hipGetLastError();
 }
@@ -88,68 +128,87 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    MSP_LAUNCH(k_fill_i64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ analysis
 
-constexpr int ANA_T = 256;      // rows per block, threads per block
-constexpr int ANA_CHUNK = 2048; // nonzeros per streamed chunk (8 per thread)
-__device__ __forceinline__ int ana_idx(int e) { return e + (e >> 3); }  // pad: fewer LDS bank conflicts
+constexpr int ANA_T = 256;             // threads per block (analysis and row sums)
+constexpr int RS_PER = 8;              // nonzeros per thread in a row-sum block
+constexpr int RS_CHUNK = RS_PER * ANA_T;
+__device__ __forceinline__ int rs_idx(int e) { return e + (e >> 3); }  // pad: fewer LDS bank conflicts
 
-// For the rows [r0, r1) of a CSR pattern, each thread gets the sum over its
-// row (row r0 + threadIdx.x) of gather(column). The block streams the rows'
-// nonzeros in chunks: a coalesced gather into LDS, a block prefix sum, then
-// every row reads its overlap with the chunk as a difference of two prefix
-// values, so a row of any length costs O(1) per chunk.
-template <class G>
-__device__ int64_t csr_rowsum(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, int64_t r0,
-                              int64_t r1, G gather, int64_t* lds, int64_t* tmp) {
-    const int tid = threadIdx.x;
-    const int64_t r = r0 + tid;
-    const bool has = r < r1;
-    const int64_t rs = has ? rp[r] : 0, re = has ? rp[r + 1] : 0;
-    const int64_t p0 = rp[r0], p1 = rp[r1];
-    int64_t sum = 0;
-    for (int64_t cs = p0; cs < p1; cs += ANA_CHUNK) {
-        const int64_t ce = min(cs + (int64_t)ANA_CHUNK, p1);
-        // 8 column loads, then 8 independent gathers, in flight together
-        int32_t col[ANA_CHUNK / ANA_T];
-#pragma unroll
-        for (int x = 0; x < ANA_CHUNK / ANA_T; ++x) {
-            const int64_t p = cs + tid + x * ANA_T;
-            col[x] = p < ce ? ci[p] : -1;
-        }
-        int64_t gv[ANA_CHUNK / ANA_T];
-#pragma unroll
-        for (int x = 0; x < ANA_CHUNK / ANA_T; ++x) gv[x] = col[x] >= 0 ? gather(col[x]) : 0;
-#pragma unroll
-        for (int x = 0; x < ANA_CHUNK / ANA_T; ++x) lds[ana_idx(tid + x * ANA_T)] = gv[x];
-        __syncthreads();
-        int64_t loc[8];
-        int64_t run = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            run += lds[ana_idx(tid * 8 + j)];
-            loc[j] = run;
-        }
-        int64_t tot;
-        const int64_t off = block_excl_scan<ANA_T / WAVE>(run, tmp, tot);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) lds[ana_idx(tid * 8 + j)] = loc[j] + off;
-        __syncthreads();
-        if (has) {
-            const int64_t a = max(rs, cs), b = min(re, ce);
-            if (a < b) {
-                const int64_t hi = lds[ana_idx((int)(b - cs - 1))];
-                const int64_t lo = (a > cs) ? lds[ana_idx((int)(a - cs - 1))] : 0;
-                sum += hi - lo;
-            }
-        }
-        __syncthreads();
+// Largest r in [0, nrows) with rp[r] <= c (rp[0] = 0 <= c), by a 64-ary
+// search of one wave: every round narrows the range 64-fold.
+__device__ int64_t row_of(const int64_t* __restrict__ rp, int64_t nrows, int64_t c) {
+    int64_t lo = 0, hi = nrows - 1;  // rp[lo] <= c, answer <= hi
+    while (lo < hi) {
+        const int64_t step = (hi - lo + WAVE) / WAVE;  // >= 1
+        const int64_t r = lo + (int64_t)lane() * step;
+        const bool ok = r <= hi && rp[r] <= c;
+        const int cnt = __popcll(__ballot(ok));        // lane 0 (r = lo) always holds
+        const int64_t nlo = lo + (int64_t)(cnt - 1) * step;
+        hi = min(hi, nlo + step - 1);
+        lo = nlo;
     }
-    return sum;
+    return lo;
+}
+
+// out[r] += sum over the stored entries (r, c) of rp/ci of (grp[c+1] - grp[c])
+// for every row r, with `out` zeroed beforehand. Work is split by nonzeros,
+// not rows, so a block of very long rows costs the same as any other: block b
+// takes the entries [b * RS_CHUNK, (b+1) * RS_CHUNK), gathers the lengths
+// into LDS, prefix-sums them, and every row overlapping the range adds its
+// overlap (a plain store when the row lies wholly in the range, an atomic add
+// when it spans blocks).
+__global__ __launch_bounds__(ANA_T) void k_rowsum(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                  int64_t nrows, int64_t nnz, const int64_t* __restrict__ grp,
+                                                  int64_t* __restrict__ out) {
+    __shared__ int64_t lds[RS_CHUNK + RS_CHUNK / 8];
+    __shared__ int64_t tmp[ANA_T / WAVE];
+    __shared__ int64_t rows[2];
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * RS_CHUNK;
+    const int64_t c1 = min(c0 + (int64_t)RS_CHUNK, nnz);
+    const int w = tid / WAVE;
+    if (w < 2) {  // wave 0 finds the row of the first entry, wave 1 that of the last
+        const int64_t r = row_of(rp, nrows, w == 0 ? c0 : c1 - 1);
+        if (lane() == 0) rows[w] = r;
+    }
+    int32_t col[RS_PER];
+#pragma unroll
+    for (int x = 0; x < RS_PER; ++x) {
+        const int64_t p = c0 + tid + x * ANA_T;
+        col[x] = p < c1 ? ci[p] : -1;
+    }
+    int64_t gv[RS_PER];
+#pragma unroll
+    for (int x = 0; x < RS_PER; ++x) gv[x] = col[x] >= 0 ? grp[col[x] + 1] - grp[col[x]] : 0;
+#pragma unroll
+    for (int x = 0; x < RS_PER; ++x) lds[rs_idx(tid + x * ANA_T)] = gv[x];
+    __syncthreads();
+    int64_t loc[RS_PER];
+    int64_t run = 0;
+#pragma unroll
+    for (int j = 0; j < RS_PER; ++j) {
+        run += lds[rs_idx(tid * RS_PER + j)];
+        loc[j] = run;
+    }
+    int64_t tot;
+    const int64_t off = block_excl_scan<ANA_T / WAVE>(run, tmp, tot);
+#pragma unroll
+    for (int j = 0; j < RS_PER; ++j) lds[rs_idx(tid * RS_PER + j)] = loc[j] + off;  // inclusive prefix
+    __syncthreads();
+    const int64_t ra = rows[0], rb = rows[1];
+    for (int64_t r = ra + tid; r <= rb; r += ANA_T) {
+        const int64_t rs = rp[r], re = rp[r + 1];
+        const int64_t a = max(rs, c0), b = min(re, c1);
+        if (a >= b) continue;
+        const int64_t v = lds[rs_idx((int)(b - c0 - 1))] - (a > c0 ? lds[rs_idx((int)(a - c0 - 1))] : 0);
+        if (rs >= c0 && re <= c1) out[r] = v;
+        else atomicAdd(reinterpret_cast<unsigned long long*>(&out[r]), (unsigned long long)v);
+    }
 }
 
 __device__ __forceinline__ int64_t cdiv(int64_t x, int64_t y) { return (x + y - 1) / y; }
@@ -222,24 +281,16 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
 }
 
 __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
-    __shared__ int64_t lds[ANA_CHUNK + ANA_CHUNK / 8];
-    __shared__ int64_t tmp[ANA_T / WAVE];
     __shared__ unsigned long long sst[ST_COUNT];
     const Operands& o = a.op;
     const int64_t r0 = (int64_t)blockIdx.x * ANA_T;
     const int64_t r1 = min(r0 + ANA_T, o.m);
     for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) sst[x] = 0;
-    const int64_t* Brp = o.Brp;
-    const int64_t flops = csr_rowsum(o.Arp, o.Aci, r0, r1, [=](int32_t k) { return Brp[k + 1] - Brp[k]; }, lds, tmp);
-    int64_t icost = 0;
-    const bool need_icost = a.inner_ratio > 0 && !o.complement && a.colcnt_rp != nullptr &&
-                            a.force_kind == (int)MSP_KIND_AUTO;
-    if (need_icost) {
-        const int64_t* crp = a.colcnt_rp;
-        icost = csr_rowsum(o.Mrp, o.Mci, r0, r1, [=](int32_t j) { return crp[j + 1] - crp[j]; }, lds, tmp);
-    }
     __syncthreads();
     const int64_t i = r0 + threadIdx.x;
+    // products per row (and the pull cost), summed beforehand by k_rowsum
+    const int64_t flops = i < r1 ? a.flops[a.row_off + i] : 0;
+    const int64_t icost = (i < r1 && a.icost) ? a.icost[i] : 0;
     int64_t ub = 0, tiles = 0, stg = 0, mnnz = 0;
     int seg = -1;
     if (i < r1) {
@@ -254,7 +305,6 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
             seg = bin * NBUCKET + flops_bucket(flops);
         }
-        a.flops[a.row_off + i] = flops;
         a.tiles[a.row_off + i] = tiles;
         a.bin[a.row_off + i] = (int8_t)bin;
     }
@@ -294,9 +344,54 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
     }
 }
 
+
+
 hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
     if (a.op.m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_analysis, dim3(grid_for(a.op.m, ANA_T, INT32_MAX)), dim3(ANA_T), 0, s, a);
+    // products per row: sum over A(i,:) of nnz(B(k,:)); pull cost: sum over M(i,:) of nnz(B(:,j))
+    hipError_t e = launch_fill_i64(a.flops + a.row_off, a.op.m, 0, s);
+    if (e != hipSuccess) return e;
+    if (a.a_nnz > 0)
+        MSP_LAUNCH(k_rowsum, dim3(grid_for(a.a_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Arp, a.op.Aci,
+                   a.op.m, a.a_nnz, a.op.Brp, a.flops + a.row_off);
+    if (a.icost) {
+        e = launch_fill_i64(a.icost, a.op.m, 0, s);
+        if (e != hipSuccess) return e;
+        if (a.m_nnz > 0)
+            MSP_LAUNCH(k_rowsum, dim3(grid_for(a.m_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Mrp,
+                       a.op.Mci, a.op.m, a.m_nnz, a.colcnt_rp, a.icost);
+    }
+    MSP_LAUNCH(k_analysis, dim3(grid_for(a.op.m, ANA_T, INT32_MAX)), dim3(ANA_T), 0, s, a);
+    return hipGetLastError();
+}
+
+// Segment offsets of the unit list (bins in order, inside a bin the flops
+// buckets from the heaviest down), summed over the products of a plan, and
+// the zeroed placement cursors (+ the split-row counter). The host derives
+// the same offsets from the statistics it reads back.
+__global__ __launch_bounds__(128) void k_segoff(const unsigned long long* __restrict__ stats, int64_t count,
+                                                int64_t* __restrict__ seg_off, unsigned long long* cursor) {
+    __shared__ int64_t segc[NBINS * NBUCKET];
+    for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x) {
+        int64_t c = 0;
+        for (int64_t p = 0; p < count; ++p) c += (int64_t)stats[p * ST_COUNT + ST_BIN0 + x];
+        segc[x] = c;
+    }
+    for (int x = threadIdx.x; x < NBINS * NBUCKET + 1; x += blockDim.x) cursor[x] = 0ull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int b = 0; b < NBINS; ++b)
+            for (int q = NBUCKET - 1; q >= 0; --q) {
+                seg_off[b * NBUCKET + q] = run;
+                run += segc[b * NBUCKET + q];
+            }
+    }
+}
+
+hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
+                         unsigned long long* cursor, hipStream_t s) {
+    MSP_LAUNCH(k_segoff, dim3(1), dim3(128), 0, s, stats, count, seg_off, cursor);
     return hipGetLastError();
 }
 
@@ -349,7 +444,7 @@ __global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
 
 hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_units, dim3(grid_for(m, 256, INT32_MAX)), dim3(256), 0, s, a, m);
+    MSP_LAUNCH(k_units, dim3(grid_for(m, 256, INT32_MAX)), dim3(256), 0, s, a, m);
     return hipGetLastError();
 }
 
@@ -417,9 +512,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(const int64_t* in, int64_t
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s) {
     if (n <= 0) return launch_fill_i64(out, 1, 0, s);
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_T), 0, s, partial, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, (const int64_t*)partial);
+    MSP_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, partial);
+    MSP_LAUNCH(k_scan_partials, dim3(1), dim3(SCAN_T), 0, s, partial, nb);
+    MSP_LAUNCH(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, (const int64_t*)partial);
     return hipGetLastError();
 }
 
@@ -1139,31 +1234,31 @@ static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
     const dim3 bw(WPB * WAVE), bb(BLOCK_NW * WAVE);
     switch (bin) {
     case BIN_DENSE_W:
-        hipLaunchKernelGGL((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB, BATCH>), gw, bw, 0, s, a);
+        MSP_LAUNCH((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_DENSE_B:
-        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1, BATCH>), gb, bb, 0, s, a);
+        MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_HASH_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, HASH_W_CAP, MSP_HASH_LOOKUP != 0, WPB, BATCH>), gw, bw, 0, s, a);
+        MSP_LAUNCH((k_maskkey<SR, MODE, 1, HASH_W_CAP, MSP_HASH_LOOKUP != 0, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_HASH_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, MSP_HASH_LOOKUP != 0, 1, BATCH>), gb, bb, 0, s, a);
+        MSP_LAUNCH((k_maskkey<SR, MODE, BLOCK_NW, HASH_B_CAP, MSP_HASH_LOOKUP != 0, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_MASKIDX_W:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false, WPB, BATCH>), gw, bw, 0, s, a);
+        MSP_LAUNCH((k_maskkey<SR, MODE, 1, MASKIDX_W_CAP, false, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_MASKIDX_B:
-        hipLaunchKernelGGL((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false, 1, BATCH>), gb, bb, 0, s, a);
+        MSP_LAUNCH((k_maskkey<SR, MODE, BLOCK_NW, MASKIDX_B_CAP, false, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_INNER_W:
-        hipLaunchKernelGGL((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB, BATCH>), gw, bw, 0, s, a);
+        MSP_LAUNCH((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_DENSE_BN:
-        hipLaunchKernelGGL((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH>), gb, bb, 0, s, a);
+        MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_DENSE_SPLIT:
-        hipLaunchKernelGGL((k_dense_split<SR, MODE, BATCH>), gb, bb, 0, s, a);
+        MSP_LAUNCH((k_dense_split<SR, MODE, BATCH>), gb, bb, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1173,8 +1268,8 @@ static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
 
 template <int SR, int MODE>
 static hipError_t launch_split_emit_t(const NumArgs& a, hipStream_t s) {
-    if (a.ops) hipLaunchKernelGGL((k_split_emit<SR, MODE, true>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
-    else hipLaunchKernelGGL((k_split_emit<SR, MODE, false>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
+    if (a.ops) MSP_LAUNCH((k_split_emit<SR, MODE, true>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
+    else MSP_LAUNCH((k_split_emit<SR, MODE, false>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1213,7 +1308,7 @@ __global__ void k_fill_u32(unsigned int* p, int64_t n) {
 
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n);
+    MSP_LAUNCH(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -1269,9 +1364,9 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
     if (a.U <= 0) return hipSuccess;
     const dim3 grid(grid_for(a.U, 4, INT32_MAX));
     switch (a.val_bytes) {
-    case 1: hipLaunchKernelGGL(k_compact<uint8_t>, grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_compact<uint32_t>, grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_compact<unsigned long long>, grid, dim3(256), 0, s, a); break;
+    case 1: MSP_LAUNCH(k_compact<uint8_t>, grid, dim3(256), 0, s, a); break;
+    case 4: MSP_LAUNCH(k_compact<uint32_t>, grid, dim3(256), 0, s, a); break;
+    case 8: MSP_LAUNCH(k_compact<unsigned long long>, grid, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1299,7 +1394,7 @@ __global__ void k_rowptr(int64_t P, int64_t total, const int64_t* __restrict__ e
 hipError_t launch_rowptr(int64_t P, int64_t total_entries, const int64_t* ent_off, const OutBind* outs,
                          const OutBind& one, const int64_t* unit_base, const int64_t* out_off, hipStream_t s) {
     if (total_entries <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowptr, dim3(grid_for(total_entries, 256, INT32_MAX)), dim3(256), 0, s, P, total_entries,
+    MSP_LAUNCH(k_rowptr, dim3(grid_for(total_entries, 256, INT32_MAX)), dim3(256), 0, s, P, total_entries,
                        ent_off, outs, one, unit_base, out_off);
     return hipGetLastError();
 }
@@ -1313,7 +1408,7 @@ __global__ void k_colcount(const int32_t* __restrict__ ci, int64_t nnz, int64_t*
 
 hipError_t launch_colcount(const int32_t* ci, int64_t nnz, int64_t* cnt, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_colcount, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, s, ci, nnz, cnt);
+    MSP_LAUNCH(k_colcount, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, s, ci, nnz, cnt);
     return hipGetLastError();
 }
 
@@ -1335,7 +1430,7 @@ hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const 
                                     int64_t nrows, const int64_t* trp, unsigned long long* cursor, int32_t* tci,
                                     void* tv, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tscatter, dim3(grid_for(nrows, 4, INT32_MAX)), dim3(256), 0, s, rp, ci,
+    MSP_LAUNCH(k_tscatter, dim3(grid_for(nrows, 4, INT32_MAX)), dim3(256), 0, s, rp, ci,
                        static_cast<const uint8_t*>(v), v ? val_bytes : 0, nrows, trp, cursor, tci,
                        static_cast<uint8_t*>(tv));
     return hipGetLastError();
@@ -1411,9 +1506,9 @@ template <int SR>
 static hipError_t launch_reduce_t(const void* vals, int64_t n, void* partial, void* result, hipStream_t s) {
     using R = Red<SR>;
     const int nb = (int)grid_for(n, RED_T * 8, RED_BLOCKS);
-    hipLaunchKernelGGL(k_reduce_partial<SR>, dim3(nb), dim3(RED_T), 0, s, static_cast<const typename R::V*>(vals), n,
+    MSP_LAUNCH(k_reduce_partial<SR>, dim3(nb), dim3(RED_T), 0, s, static_cast<const typename R::V*>(vals), n,
                        static_cast<typename R::A*>(partial));
-    hipLaunchKernelGGL(k_reduce_final<SR>, dim3(1), dim3(RED_T), 0, s, static_cast<const typename R::A*>(partial), nb,
+    MSP_LAUNCH(k_reduce_final<SR>, dim3(1), dim3(RED_T), 0, s, static_cast<const typename R::A*>(partial), nb,
                        static_cast<typename R::V*>(result));
     return hipGetLastError();
 }
