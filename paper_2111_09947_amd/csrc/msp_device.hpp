@@ -138,11 +138,13 @@ template <> struct SRT<MSP_LOR_LAND_BOOL> {
     static constexpr bool needs_values = true;
     static constexpr bool sep_flag = false;
     __device__ static in_t one() { return 1u; }
+    // the raw byte: any nonzero byte is true (tested in term(), so that a load
+    // is not waited for until the product is formed)
     __device__ static in_t load(const void* v, int64_t p) {
-        return v ? (uint32_t)(static_cast<const uint8_t*>(v)[p] != 0) : 1u;
+        return v ? (uint32_t)static_cast<const uint8_t*>(v)[p] : 1u;
     }
     __device__ static acc_t identity() { return 0u; }
-    __device__ static acc_t term(in_t a, in_t b) { return 2u | (a & b); }
+    __device__ static acc_t term(in_t a, in_t b) { return 2u | (uint32_t)((a != 0u) & (b != 0u)); }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicOr(slot, t); }
     __device__ static void merge(acc_t* slot, acc_t part) { atomicOr(slot, part); }
     __device__ static acc_t add(acc_t x, acc_t t) { return x | t; }

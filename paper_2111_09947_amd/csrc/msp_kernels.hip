@@ -749,7 +749,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
     __shared__ uint8_t flags_[WPB][FLAGS ? W : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
-    const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
+    // the wave index is the same on every lane: keep it (and what derives from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;  // only one-wave units can leave early (WPB > 1 implies NW == 1)
     uint32_t* allowed = allowed_[gi];
@@ -835,7 +837,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
     __shared__ acc_t vals[COUNT ? 1 : W];
     __shared__ uint8_t flags[FLAGS ? W : 1];
     __shared__ StanzaLds<T> st[NW];
-    const int wv = threadIdx.x / WAVE, ut = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)), ut = threadIdx.x;
     const int u = __builtin_amdgcn_readfirstlane(g.units[blockIdx.x]);
     const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
     const int64_t i = g.unit_row[u];
@@ -1012,7 +1014,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     __shared__ uint8_t qs_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
-    const int wave = threadIdx.x / WAVE, gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
+    // the wave index is the same on every lane: keep it (and what derives from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;  // only one-wave units can leave early (WPB > 1 implies NW == 1)
     int32_t* keys = keys_[gi];
@@ -1161,7 +1165,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     constexpr bool COUNT = MODE == MODE_COUNT;
     __shared__ int32_t akeys_[WPB][ACAP];
     const int ln = lane();
-    const int gi = threadIdx.x / WAVE;
+    const int gi = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int64_t uix = (int64_t)blockIdx.x * WPB + gi;
     if (uix >= g.nunits) return;
     int32_t* akeys = akeys_[gi];
@@ -1347,7 +1351,7 @@ hipError_t launch_numeric(int semiring, int bin, int mode, const NumArgs& a, hip
 
 template <typename V>
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
-    const int64_t u = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    const int64_t u = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     if (u >= a.U) return;
     const OutBind& ob = a.outs ? a.outs[a.unit_prob[u]] : a.one;
     const int64_t src = a.stg_off[u], n = a.out_off[u + 1] - a.out_off[u];
@@ -1416,7 +1420,7 @@ __global__ __launch_bounds__(256) void k_tscatter(const int64_t* __restrict__ rp
                                                   const uint8_t* __restrict__ v, int vb, int64_t nrows,
                                                   const int64_t* __restrict__ trp, unsigned long long* cursor,
                                                   int32_t* __restrict__ tci, uint8_t* __restrict__ tv) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     if (r >= nrows) return;
     for (int64_t p = rp[r] + lane(); p < rp[r + 1]; p += WAVE) {
         const int32_t c = ci[p];
