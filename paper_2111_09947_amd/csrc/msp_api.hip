@@ -268,11 +268,12 @@ static msp_status build_transpose(msp_plan* P, Product& pr, bool scatter) {
 }
 
 // Plans the products `probs` (count P). want_staging: allocate one-phase staging.
-// Pinned host staging for the small device-to-host reads (statistics and
-// output counts): page-locked buffers are reused through a process-wide pool,
-// so a read is one DMA transfer instead of a staged pageable copy.
+// Page-locked, device-mapped host words for the small device-to-host reads
+// (statistics and output counts), reused through a process-wide pool. A
+// kernel writes them directly, so a read costs no copy-engine pass.
 struct PinnedBuf {
-    void* p = nullptr;
+    void* p = nullptr;    // host address
+    void* dev = nullptr;  // the same memory as the device addresses it
     size_t cap = 0;
     static std::mutex& mu() {
         static std::mutex m;
@@ -290,16 +291,25 @@ struct PinnedBuf {
                 cap = it->first;
                 p = it->second;
                 pool().erase(it);
-                return MSP_OK;
+                return map_dev();
             }
         }
         size_t c = 4096;
         while (c < bytes) c <<= 1;
-        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+        // mapped and coherent: kernels write into it directly, and the host reads it after a
+        // stream synchronization
+        if (hipHostMalloc(&p, c, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
             p = nullptr;
             return fail(MSP_ERR_OUT_OF_MEMORY, "pinned host allocation");
         }
         cap = c;
+        return map_dev();
+    }
+    msp_status map_dev() {
+        if (hipHostGetDevicePointer(&dev, p, 0) != hipSuccess) {
+            dev = nullptr;
+            return fail(MSP_ERR_DEVICE, "no device address for page-locked host memory");
+        }
         return MSP_OK;
     }
     ~PinnedBuf() {
@@ -313,7 +323,7 @@ struct PinnedBuf {
 static msp_status read_back_i64(int64_t* dst, const int64_t* src, hipStream_t s) {
     PinnedBuf pin;
     MSP_CHECK(pin.get(sizeof(int64_t)));
-    MSP_HIP(hipMemcpyAsync(pin.p, src, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MSP_HIP(launch_peek(src, static_cast<int64_t*>(pin.dev), s));
     MSP_HIP(hipStreamSynchronize(s));
     std::memcpy(dst, pin.p, sizeof(int64_t));
     return MSP_OK;
@@ -440,13 +450,13 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         MSP_HIP(launch_analysis(aa, s));
     }
     MSP_HIP(launch_scan(P->unit_base, P->unit_base, R, P->scan_partial, s));
-    MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, P->seg_cursor, s));
     {
         // the one synchronization of plan creation: the statistics size the unit arrays
         const size_t sb = sizeof(unsigned long long) * ST_COUNT * (size_t)count;
         PinnedBuf pin;
         MSP_CHECK(pin.get(sb));
-        MSP_HIP(hipMemcpyAsync(pin.p, P->stats_d, sb, hipMemcpyDeviceToHost, s));
+        MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, P->seg_cursor,
+                              static_cast<unsigned long long*>(pin.dev), s));
         MSP_HIP(hipStreamSynchronize(s));
         P->stats.assign((size_t)(count * ST_COUNT), 0ull);
         std::memcpy(P->stats.data(), pin.p, sb);

@@ -186,9 +186,12 @@ hipError_t launch_reduce(int semiring, const void* vals, int64_t n, void* partia
                          hipStream_t s);
 
 // Unit-list segment offsets from the per-product statistics; zeroes the
-// placement cursors (NBINS * NBUCKET + 1 entries).
+// placement cursors (NBINS * NBUCKET + 1 entries); copies the statistics to
+// `host_stats` (device-visible page-locked host memory) unless it is null.
 hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
-                         unsigned long long* cursor, hipStream_t s);
+                         unsigned long long* cursor, unsigned long long* host_stats, hipStream_t s);
+// *host_dst = *src, with host_dst device-visible page-locked host memory.
+hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s);
 
 // Stage timing: between timing_arm(start, stop) and timing_disarm(), the
 // launches of this thread record `start` at the beginning of the first kernel

@@ -370,8 +370,12 @@ hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
 // the zeroed placement cursors (+ the split-row counter). The host derives
 // the same offsets from the statistics it reads back.
 __global__ __launch_bounds__(128) void k_segoff(const unsigned long long* __restrict__ stats, int64_t count,
-                                                int64_t* __restrict__ seg_off, unsigned long long* cursor) {
+                                                int64_t* __restrict__ seg_off, unsigned long long* cursor,
+                                                unsigned long long* host_stats) {
     __shared__ int64_t segc[NBINS * NBUCKET];
+    // the statistics also go straight to the caller's page-locked host buffer (no copy engine pass)
+    if (host_stats)
+        for (int64_t x = threadIdx.x; x < count * ST_COUNT; x += blockDim.x) host_stats[x] = stats[x];
     for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x) {
         int64_t c = 0;
         for (int64_t p = 0; p < count; ++p) c += (int64_t)stats[p * ST_COUNT + ST_BIN0 + x];
@@ -390,8 +394,16 @@ __global__ __launch_bounds__(128) void k_segoff(const unsigned long long* __rest
 }
 
 hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
-                         unsigned long long* cursor, hipStream_t s) {
-    MSP_LAUNCH(k_segoff, dim3(1), dim3(128), 0, s, stats, count, seg_off, cursor);
+                         unsigned long long* cursor, unsigned long long* host_stats, hipStream_t s) {
+    MSP_LAUNCH(k_segoff, dim3(1), dim3(128), 0, s, stats, count, seg_off, cursor, host_stats);
+    return hipGetLastError();
+}
+
+// One int64 from device memory into a device-visible page-locked host word.
+__global__ void k_peek(const int64_t* __restrict__ src, int64_t* dst) { *dst = *src; }
+
+hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s) {
+    MSP_LAUNCH(k_peek, dim3(1), dim3(1), 0, s, src, host_dst);
     return hipGetLastError();
 }
 
