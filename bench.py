@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--split-flops", type=int, default=0, help="binner: products per row above which a dense "
                     "row is split over workgroups (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "copy"),
+    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "bc", "copy"),
                     help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
                          "batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -129,6 +129,8 @@ def main():
         return run_batch(args)
     if args.workload == "bfs":
         return run_bfs(args)
+    if args.workload == "bc":
+        return run_bc(args)
     if args.workload == "serve":
         return run_serve(args)
     if args.workload == "copy":
@@ -343,6 +345,74 @@ def run_bfs(args):
                                   "512 sources at depth 1..3, complemented visited mask; int32 path counts "
                                   "(headline) and boolean"},
            "roofline": head["roofline"], "semirings": results}
+    print(json.dumps(out), flush=True)
+
+
+def run_bc(args):
+    """Batched betweenness-centrality dependencies: 512 random non-isolated
+    sources on the symmetric R-MAT graph (scale --scale, edge factor
+    --edge-factor), the whole two-stage computation (forward multi-source BFS
+    with complemented masks, backward sweep with normal masks) per step.
+    Metric: TEPS = batch x undirected edges / time (Section "Betweenness
+    Centrality")."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    G = mspgen.rmat_graph(args.scale, args.edge_factor, 20)
+    deg = np.diff(G.rowptr)
+    rng = np.random.default_rng(21)
+    srcs = rng.choice(np.nonzero(deg > 0)[0], size=512, replace=False).astype(np.int32)
+    dG = msp.DeviceCSR.from_host(G.with_values(None), dev)
+    edges = G.nnz // 2
+    print(f"[bench] bc input: R-MAT scale {args.scale} ef {args.edge_factor}: n={G.nrows} undirected edges={edges} "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    bc = torch.zeros(G.nrows, dtype=torch.float64, device=dev)
+    info = None
+    for _ in range(args.warmup):
+        bc.zero_()
+        _, info = msp.bc_batch(dG, srcs, bc)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd = bwd = 0.0
+    for _ in range(args.steps):
+        bc.zero_()
+        _, info = msp.bc_batch(dG, srcs, bc)
+        fwd += info["forward_ms"]
+        bwd += info["backward_ms"]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) / args.steps * 1e3
+    teps = 512 * edges / (ms * 1e-3)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = min(16, len(os.sched_getaffinity(0)))
+        k = 64
+        c0 = time.perf_counter()
+        ref = oracle.bc(G, srcs[:k], nthreads=nthreads)
+        t_cpu = time.perf_counter() - c0
+        bc.zero_()
+        got, _ = msp.bc_batch(dG, srcs[:k], bc)
+        err = float(np.max(np.abs(got.cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0)))
+        if err > 1e-9:
+            print(f"[bench] MISMATCH against the oracle: max relative error {err:.3g}", file=sys.stderr)
+            sys.exit(1)
+        cpu = {"value": round(k * edges / t_cpu / 1e6, 2), "unit": "MTEPS", "cores": nthreads, "kind": "oracle",
+               "sample": f"{k} of the 512 sources (Brandes per source), {t_cpu:.2f} s; checked against the GPU "
+                         f"result for the same {k} sources (max relative error {err:.2g})"}
+    out = {
+        "metric": "bc_mteps", "value": round(teps / 1e6, 1), "unit": "MTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"betweenness-centrality dependencies, 512 sources, R-MAT scale {args.scale} edge "
+                               f"factor {args.edge_factor} (symmetrized)", "n": G.nrows, "undirected_edges": edges,
+                   **info},
+        "stages_ms": {"forward": round(fwd / args.steps, 3), "backward": round(bwd / args.steps, 3)},
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
 
 

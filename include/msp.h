@@ -328,6 +328,41 @@ msp_status msp_batch_graph_launch(msp_plan* batch, void* stream);
 /* nnz of every product's output into nnz[0..count) (host). SYNCHRONIZES. */
 msp_status msp_batch_nnz(const msp_plan* batch, int64_t* nnz, void* stream);
 
+/*
+ * Betweenness-centrality dependencies of a batch of sources (Section
+ * "Betweenness Centrality": the multi-source two-stage algorithm of Brandes
+ * on masked products). Forward stage, level d = 1, 2, ... until the frontier
+ * is empty: F_d = !V_{d-1} .* (A F_{d-1}) with a complemented mask, F_0 holding
+ * column j = source j with value 1, V = the union of the frontiers so far;
+ * F_d's values are the shortest-path counts. Backward stage, d = D..2:
+ * delta_{d-1} = sigma_{d-1} .* (F_{d-1} .* (A ((1 + delta_d) ./ sigma_d)))
+ * with a normal mask. All products use PLUS_TIMES_F64.
+ *
+ *  A        n x n device CSR holding the SYMMETRIC pattern of an unweighted
+ *           undirected graph; its values are ignored.
+ *  sources  HOST array of nsrc vertex ids in [0, n) (repeats allowed: each
+ *           entry is its own column).
+ *  bc       DEVICE array of n doubles; the library ADDS, for every vertex v,
+ *           the sum over the batch's sources s != v of delta_s(v) (not
+ *           halved). The caller zeroes it for a fresh result.
+ *  info     optional host struct filled with level and product counts and
+ *           the wall time of each stage.
+ * Allocates its working memory on `stream`; SYNCHRONIZES (every level sizes
+ * the next). Errors: MSP_ERR_DIMENSION_MISMATCH (A not square),
+ * MSP_ERR_INVALID_ARGUMENT (NULL pointers, a source out of range).
+ */
+typedef struct msp_bc_info {
+    int64_t levels;            /* D: frontiers F_1..F_D were non-empty */
+    int64_t frontier_nnz;      /* sum of nnz(F_d), d >= 1 */
+    int64_t forward_products;  /* products of the forward masked products */
+    int64_t backward_products; /* products of the backward masked products */
+    double forward_ms;         /* host wall time of each stage */
+    double backward_ms;
+} msp_bc_info_t;
+
+msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int64_t nsrc, double* bc,
+                        msp_bc_info_t* info, void* stream);
+
 /* Static message for a status code. */
 const char* msp_status_string(msp_status status);
 

@@ -22,6 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "msp_oracle.c")
+_SRC_BC = os.path.join(_HERE, "bc_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 SEMIRINGS = {
@@ -49,7 +50,7 @@ class _Result(ctypes.Structure):
 def build() -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no FP contraction)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", _SRC, "-o", _LIB_PATH + ".tmp"]
+           "-Wall", _SRC, _SRC_BC, "-o", _LIB_PATH + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
@@ -71,6 +72,8 @@ def _load():
             vp, vp, vp, vp, vp, vp, vp, vp,
             ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, ctypes.c_int]
         lib.oracle_free.argtypes = [ctypes.POINTER(_Result)]
+        lib.oracle_bc.restype = ctypes.c_int
+        lib.oracle_bc.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -150,3 +153,21 @@ def masked_spgemm(A, B, M, complement: bool = False, semiring: str = "plus_times
     finally:
         lib.oracle_free(r)
     return Result(nsel, B.ncols, rowptr, colidx, values, useful, sel)
+
+
+def bc(G, sources, nthreads: int = 0) -> np.ndarray:
+    """Betweenness-centrality dependencies of a batch of sources on the
+    unweighted undirected graph G (symmetric CSR pattern): bc[v] = sum over
+    the sources s != v of delta_s(v) (Brandes; see bc_oracle.c)."""
+    lib = _load()
+    if G.nrows != G.ncols:
+        raise ValueError("G must be square")
+    rp = np.ascontiguousarray(G.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(G.colidx, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.zeros(G.nrows, dtype=np.float64)
+    st = lib.oracle_bc(G.nrows, rp.ctypes.data, ci.ctypes.data, len(src), src.ctypes.data, out.ctypes.data,
+                       int(nthreads))
+    if st != 0:
+        raise ValueError("oracle_bc failed (bad source or out of memory)")
+    return out

@@ -283,6 +283,24 @@ def reduce(values, semiring: str, out=None):
     return out
 
 
+def bc_batch(A: DeviceCSR, sources, bc=None):
+    """Betweenness-centrality dependencies of a batch of sources on the
+    unweighted undirected graph A (symmetric pattern, values ignored):
+    adds sum over sources s != v of delta_s(v) into bc (a float64 device
+    tensor of A.nrows, zeros if None). Returns (bc, info dict)."""
+    import numpy as np
+    t = _torch()
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    if bc is None:
+        bc = t.zeros(A.nrows, dtype=t.float64, device=A.rowptr.device)
+    view = _view(A, None, "A")
+    info = L.MspBcInfo()
+    _check(L.load().msp_bc_batch(ctypes.byref(view), ctypes.c_void_p(src.ctypes.data if len(src) else 0),
+                                 len(src), ctypes.c_void_p(bc.data_ptr() if bc.numel() else 0),
+                                 ctypes.byref(info), _stream()), "msp_bc_batch")
+    return bc, {f: getattr(info, f) for f, _ in L.MspBcInfo._fields_}
+
+
 def version() -> int:
     return L.load().msp_version()
 

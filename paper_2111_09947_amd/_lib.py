@@ -32,6 +32,11 @@ class MspPlanInfo(ctypes.Structure):
                 ("bin_units", c_i64 * 16)]
 
 
+class MspBcInfo(ctypes.Structure):
+    _fields_ = [("levels", c_i64), ("frontier_nnz", c_i64), ("forward_products", c_i64),
+                ("backward_products", c_i64), ("forward_ms", ctypes.c_double), ("backward_ms", ctypes.c_double)]
+
+
 BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wave", "maskidx_block",
              "inner_wave", "dense_block_narrow", "dense_split"]
 STAGE_NAMES = BIN_NAMES + [f"bin{b}" for b in range(len(BIN_NAMES), 16)] + [
@@ -71,6 +76,7 @@ SIGNATURES = {
     "msp_batch_execute": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_graph_launch": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_nnz": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i64), c_vp]),
+    "msp_bc_batch": (ctypes.c_int, [ctypes.POINTER(MspCsr), c_vp, c_i64, c_vp, ctypes.POINTER(MspBcInfo), c_vp]),
     "msp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "msp_last_error": (ctypes.c_char_p, []),
     "msp_version": (ctypes.c_int, []),

@@ -68,6 +68,12 @@ void configure_pool() {
     });
 }
 
+}  // namespace
+
+msp_status mspk::set_error(msp_status st, const char* msg) { return fail(st, msg); }
+
+namespace {
+
 bool valid_sr(int s) { return s >= MSP_PLUS_TIMES_F64 && s <= MSP_PLUS_TIMES_I64; }
 
 msp_status check_csr(const msp_csr* X, const char* name) {

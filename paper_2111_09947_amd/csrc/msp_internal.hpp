@@ -193,6 +193,9 @@ hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t
 // *host_dst = *src, with host_dst device-visible page-locked host memory.
 hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s);
 
+// Records `msg` as the thread's last error (msp_last_error) and returns `st`.
+msp_status set_error(msp_status st, const char* msg);
+
 // Stage timing: between timing_arm(start, stop) and timing_disarm(), the
 // launches of this thread record `start` at the beginning of the first kernel
 // and `stop` at the end of the last one. timing_disarm() returns whether any
