@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--split-flops", type=int, default=0, help="binner: products per row above which a dense "
                     "row is split over workgroups (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "bc", "copy"),
+    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "bc", "ktruss", "copy"),
                     help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
                          "batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -131,6 +131,8 @@ def main():
         return run_bfs(args)
     if args.workload == "bc":
         return run_bc(args)
+    if args.workload == "ktruss":
+        return run_ktruss(args)
     if args.workload == "serve":
         return run_serve(args)
     if args.workload == "copy":
@@ -411,6 +413,54 @@ def run_bc(args):
                                f"factor {args.edge_factor} (symmetrized)", "n": G.nrows, "undirected_edges": edges,
                    **info},
         "stages_ms": {"forward": round(fwd / args.steps, 3), "backward": round(bwd / args.steps, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_ktruss(args):
+    """5-truss of the symmetric R-MAT graph (scale --scale, edge factor
+    --edge-factor) by repeated masked products with pruning. Metric as in
+    Section "k-truss": the flops of all masked products (2 per product)
+    divided by the total time of the whole computation."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+
+    dev = torch.device("cuda:0")
+    k = 5
+    G = mspgen.rmat_graph(args.scale, args.edge_factor, 18)
+    dG = msp.DeviceCSR.from_host(G.with_values(None), dev)
+    info = None
+    for _ in range(args.warmup):
+        C, info = msp.ktruss(dG, k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        C, info = msp.ktruss(dG, k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) / args.steps * 1e3
+    value = 2 * info["products"] / (ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        c0 = time.perf_counter()
+        erp, eci, esup = oracle.ktruss(G, k)
+        t_cpu = time.perf_counter() - c0
+        rp, ci, sup = C.to_host()
+        if not (np.array_equal(rp, erp) and np.array_equal(ci, eci) and np.array_equal(sup, esup)):
+            print("[bench] MISMATCH: the GPU truss differs from the oracle's", file=sys.stderr)
+            sys.exit(1)
+        cpu = {"value": round(2 * info["products"] / t_cpu / 1e9, 3), "unit": "GFLOP/s",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"the whole {k}-truss ({t_cpu:.2f} s), result identical to the GPU's"}
+    out = {
+        "metric": "ktruss_gflops", "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"{k}-truss, R-MAT scale {args.scale} edge factor {args.edge_factor} (symmetrized)",
+                   "n": G.nrows, "nnz": G.nnz, "truss_nnz": int(C.colidx.numel()), **info},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -363,6 +363,35 @@ typedef struct msp_bc_info {
 msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int64_t nsrc, double* bc,
                         msp_bc_info_t* info, void* stream);
 
+/*
+ * k-truss (Section "Experimental Setup": the edges supported by at least
+ * k - 2 triangles, found by masked products repeated while pruning changes
+ * the graph): C = A; repeat S = C .* (C C) over PLUS_PAIR_I64 (the support
+ * of every edge: its triangles inside C), C = the entries of S with support
+ * >= k - 2; until no edge is removed.
+ *
+ *  A          n x n device CSR of an undirected graph (symmetric pattern,
+ *             no self loops); values ignored.
+ *  k          >= 3 runs the iteration; k <= 2 returns A (every edge
+ *             qualifies) with supports 0.
+ *  C_rowptr   device, n + 1 entries; C_colidx (int32) and C_support (int64)
+ *             device arrays of at least nnz(A) entries, caller-allocated.
+ *             The truss is written there, rows sorted, each edge with its
+ *             support inside the truss.
+ *  nnz_host   host: nnz of the truss.
+ *  info       optional: iterations, products summed over all iterations,
+ *             wall time.
+ * Allocates its working memory on `stream`; SYNCHRONIZES every iteration.
+ */
+typedef struct msp_ktruss_info {
+    int64_t iterations;
+    int64_t products;  /* products of all masked products */
+    double ms;
+} msp_ktruss_info_t;
+
+msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr, int32_t* C_colidx, int64_t* C_support,
+                      int64_t* nnz_host, msp_ktruss_info_t* info, void* stream);
+
 /* Static message for a status code. */
 const char* msp_status_string(msp_status status);
 

@@ -171,3 +171,36 @@ def bc(G, sources, nthreads: int = 0) -> np.ndarray:
     if st != 0:
         raise ValueError("oracle_bc failed (bad source or out of memory)")
     return out
+
+
+def ktruss(G, k: int):
+    """k-truss of the undirected graph G (symmetric pattern) by the paper's
+    iteration (Section "Experimental Setup"): repeat S = C .* (C C) under
+    plus-pair with the oracle's masked product, keep the entries with
+    support >= k - 2, until no edge is removed. k <= 2 returns G with
+    supports 0. Returns (rowptr, colidx, support) as numpy arrays."""
+    n = G.nrows
+    rp = np.asarray(G.rowptr, dtype=np.int64)
+    ci = np.asarray(G.colidx, dtype=np.int32)
+    if k <= 2 or len(ci) == 0:
+        return rp.copy(), ci.copy(), np.zeros(len(ci), dtype=np.int64)
+
+    class _C:  # duck-typed CSR for masked_spgemm
+        def __init__(self, rp, ci):
+            self.nrows, self.ncols, self.rowptr, self.colidx, self.values = n, n, rp, ci, None
+
+    sup = np.zeros(len(ci), dtype=np.int64)
+    while True:
+        C = _C(rp, ci)
+        S = masked_spgemm(C, C, C, False, "plus_pair_i64")
+        keep = S.values >= k - 2
+        rows = np.repeat(np.arange(n), np.diff(S.rowptr))[keep]
+        nrp = np.zeros(n + 1, dtype=np.int64)
+        np.add.at(nrp, rows + 1, 1)
+        nrp = np.cumsum(nrp)
+        nci = S.colidx[keep].astype(np.int32)
+        sup = S.values[keep].astype(np.int64)
+        done = len(nci) == len(ci)
+        rp, ci = nrp, nci
+        if done or len(ci) == 0:
+            return rp, ci, sup

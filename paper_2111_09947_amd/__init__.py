@@ -301,6 +301,27 @@ def bc_batch(A: DeviceCSR, sources, bc=None):
     return bc, {f: getattr(info, f) for f, _ in L.MspBcInfo._fields_}
 
 
+def ktruss(A: DeviceCSR, k: int):
+    """k-truss of the undirected graph A (symmetric pattern): the edges with
+    at least k - 2 triangles inside the truss, by repeated masked products.
+    Returns (DeviceCSR of the truss with int64 supports as values, info)."""
+    t = _torch()
+    dev = A.rowptr.device
+    rp = t.empty(A.nrows + 1, dtype=t.int64, device=dev)
+    cap = max(A.colidx.numel(), 1)
+    ci = t.empty(cap, dtype=t.int32, device=dev)
+    sup = t.empty(cap, dtype=t.int64, device=dev)
+    view = _view(A, None, "A")
+    n = ctypes.c_int64(0)
+    info = L.MspKtrussInfo()
+    _check(L.load().msp_ktruss(ctypes.byref(view), int(k), ctypes.c_void_p(rp.data_ptr()),
+                               ctypes.c_void_p(ci.data_ptr()), ctypes.c_void_p(sup.data_ptr()), ctypes.byref(n),
+                               ctypes.byref(info), _stream()), "msp_ktruss")
+    nn = n.value
+    return (DeviceCSR(A.nrows, A.ncols, rp, ci[:nn], sup[:nn]),
+            {f: getattr(info, f) for f, _ in L.MspKtrussInfo._fields_})
+
+
 def version() -> int:
     return L.load().msp_version()
 

@@ -37,6 +37,10 @@ class MspBcInfo(ctypes.Structure):
                 ("backward_products", c_i64), ("forward_ms", ctypes.c_double), ("backward_ms", ctypes.c_double)]
 
 
+class MspKtrussInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_i64), ("products", c_i64), ("ms", ctypes.c_double)]
+
+
 BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wave", "maskidx_block",
              "inner_wave", "dense_block_narrow", "dense_split"]
 STAGE_NAMES = BIN_NAMES + [f"bin{b}" for b in range(len(BIN_NAMES), 16)] + [
@@ -76,6 +80,8 @@ SIGNATURES = {
     "msp_batch_execute": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_graph_launch": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_nnz": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i64), c_vp]),
+    "msp_ktruss": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64),
+                                  ctypes.POINTER(MspKtrussInfo), c_vp]),
     "msp_bc_batch": (ctypes.c_int, [ctypes.POINTER(MspCsr), c_vp, c_i64, c_vp, ctypes.POINTER(MspBcInfo), c_vp]),
     "msp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "msp_last_error": (ctypes.c_char_p, []),

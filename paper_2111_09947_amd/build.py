@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmsp.so")
-SOURCES = ["msp_kernels.hip", "msp_api.hip", "msp_bc.hip"]
+SOURCES = ["msp_kernels.hip", "msp_api.hip", "msp_bc.hip", "msp_ktruss.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
