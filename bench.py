@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--split-flops", type=int, default=0, help="binner: products per row above which a dense "
                     "row is split over workgroups (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "bc", "ktruss", "copy"),
+    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "bc", "ktruss", "heatmap", "copy"),
                     help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
                          "batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -133,6 +133,8 @@ def main():
         return run_bc(args)
     if args.workload == "ktruss":
         return run_ktruss(args)
+    if args.workload == "heatmap":
+        return run_heatmap(args)
     if args.workload == "serve":
         return run_serve(args)
     if args.workload == "copy":
@@ -463,6 +465,67 @@ def run_ktruss(args):
                    "n": G.nrows, "nnz": G.nnz, "truss_nnz": int(C.colidx.numel()), **info},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_heatmap(args):
+    """Best accumulator kind against input and mask density (the GPU analogue
+    of Section "Effect of Input Matrix and Mask Density"): Erdos-Renyi A, B
+    (degree d) and M (degree dm), n = 2^12 .. 2^20, FP64 plus-times, normal
+    mask. Every kind (and the automatic binner) runs the whole product (plan
+    creation included; the inner kind builds B^T inside it), best of 3; all
+    kinds must give the same result (pattern exact, values within 1e-12).
+    Cells with more than 2^31 products are skipped, and the dense kind is
+    run only up to n = 2^14 (its 4096-column tiles restream a row once per
+    tile)."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+
+    dev = torch.device("cuda:0")
+    kinds = [None, "dense", "hash", "maskidx", "inner"]
+    grid = []
+    for lg in (12, 14, 16, 18, 20):
+        n = 1 << lg
+        for d in (1, 4, 16, 64):
+            if n * d * d > (1 << 31):
+                continue
+            A = msp.DeviceCSR.from_host(mspgen.er(n, n, d, 1000 + lg, "f64"), dev, torch.float64)
+            B = msp.DeviceCSR.from_host(mspgen.er(n, n, d, 2000 + lg, "f64"), dev, torch.float64)
+            for dm in (1, 4, 16, 64, 256):
+                M = msp.DeviceCSR.from_host(mspgen.er(n, n, dm, 3000 + lg, None), dev)
+                cell = {"n": n, "d": d, "dm": dm, "ms": {}}
+                ref = None
+                for kind in kinds:
+                    if kind == "dense" and lg > 14:
+                        continue
+                    best = float("inf")
+                    for _ in range(3):
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        C = msp.masked_spgemm(A, B, M, semiring="plus_times_f64", force_kind=kind)
+                        torch.cuda.synchronize()
+                        best = min(best, (time.perf_counter() - t) * 1e3)
+                    h = C.to_host()
+                    if ref is None:
+                        ref = h
+                    elif not (np.array_equal(h[0], ref[0]) and np.array_equal(h[1], ref[1])
+                              and np.allclose(h[2], ref[2], rtol=1e-12, atol=0)):
+                        print(f"[bench] MISMATCH kind={kind} n={n} d={d} dm={dm}", file=sys.stderr)
+                        sys.exit(1)
+                    cell["ms"][kind or "auto"] = round(best, 4)
+                forced = {k: v for k, v in cell["ms"].items() if k != "auto"}
+                cell["best"] = min(forced, key=forced.get)
+                cell["auto_over_best"] = round(cell["ms"]["auto"] / forced[cell["best"]], 3)
+                grid.append(cell)
+                print(f"[bench] n=2^{lg} d={d} dm={dm}: best {cell['best']} {cell['ms']}", file=sys.stderr,
+                      flush=True)
+    ratios = [c["auto_over_best"] for c in grid]
+    out = {"metric": "heatmap_auto_over_best_median", "value": round(float(np.median(ratios)), 3),
+           "unit": "ratio", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "ER n=2^12..2^20, input degree 1..64, mask degree 1..256, FP64 plus-times"},
+           "worst_auto_over_best": round(float(np.max(ratios)), 3), "cells": grid}
     print(json.dumps(out), flush=True)
 
 
