@@ -1107,12 +1107,14 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
             uint32_t w[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) w[u] = filt[__builtin_amdgcn_ubfe((uint32_t)j[u], 5, (uint32_t)fwb)];
-            bool pass[STREAM_U];
+            // pass[u] is 0 or 1 (an integer, so that it selects the ring entry arithmetically
+            // below instead of through a lane mask)
+            uint32_t pass[STREAM_U];
             uint64_t m[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) {
-                pass[u] = act[u] & (__builtin_amdgcn_ubfe(w[u], (uint32_t)j[u], 1) != 0u);
-                m[u] = __ballot(pass[u]);
+                pass[u] = __builtin_amdgcn_ubfe(w[u], (uint32_t)j[u], 1) & (uint32_t)act[u];
+                m[u] = __ballot(pass[u] != 0u);
             }
             // append the window's candidates to the ring, DRAIN slots at a time, and look up every
             // full round of 64; the ring indices are wave-uniform
@@ -1122,7 +1124,8 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
             for (int u = 0; u < STREAM_U; ++u) {
                 // every lane writes (branch-free): a rejected product to its own spare entry past the ring
                 const int ea = (int)((cum + (uint32_t)rank_below(m[u])) & (QCAP - 1));
-                const int e = pass[u] ? ea : QCAP + lane();
+                const int eb = QCAP + lane();
+                const int e = eb + (int)pass[u] * (ea - eb);
                 qj[e] = j[u];
                 if (QVAL) {
                     qq[e] = q[u];
