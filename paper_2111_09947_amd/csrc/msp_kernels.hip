@@ -1379,8 +1379,59 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
     }
 }
 
+// Single-product compaction, CG consecutive units per wave: the group's
+// outputs are contiguous (units are numbered in row order), so the wave
+// walks them as one run of coalesced writes; each element finds its unit
+// among the group's (scalar) offsets and reads from that unit's staging run.
+constexpr int CG = 4;
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_compact_group(CompactArgs a) {
+    const int64_t grp = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int64_t u0 = grp * CG;
+    if (u0 >= a.U) return;
+    const int nk = (int)min((int64_t)CG, a.U - u0);
+    const int l = lane();
+    const int64_t oo = l <= nk ? a.out_off[u0 + l] : 0;
+    const int64_t so = l < nk ? a.stg_off[u0 + l] : 0;
+    int64_t o[CG + 1], st[CG];
+#pragma unroll
+    for (int k = 0; k <= CG; ++k) o[k] = readlane64(oo, min(k, nk));
+#pragma unroll
+    for (int k = 0; k < CG; ++k) st[k] = readlane64(so, min(k, nk - 1));
+    const int64_t base = o[0];
+    const int64_t total = o[nk] - base;
+    const int64_t dst0 = base - a.out_off[a.one.unit_first];
+    const V* sv = static_cast<const V*>(a.stg_val);
+    V* dv = static_cast<V*>(a.one.val);
+    for (int64_t x = l; x < total; x += WAVE) {
+        int64_t src = st[0] + x;
+#pragma unroll
+        for (int k = 1; k < CG; ++k)
+            if (k < nk && o[k] - base <= x) src = st[k] + (x - (o[k] - base));
+        a.one.col[dst0 + x] = a.stg_col[src];
+        dv[dst0 + x] = sv[src];
+    }
+}
+
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
     if (a.U <= 0) return hipSuccess;
+    if (!a.outs) {
+        const dim3 g(grid_for(a.U, 4 * CG, INT32_MAX));
+        switch (a.val_bytes) {
+        case 1: MSP_LAUNCH(k_compact_group<uint8_t>, g, dim3(256), 0, s, a); break;
+        case 4: MSP_LAUNCH(k_compact_group<uint32_t>, g, dim3(256), 0, s, a); break;
+        case 8: MSP_LAUNCH(k_compact_group<unsigned long long>, g, dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid(grid_for(a.U, 4, INT32_MAX));
     switch (a.val_bytes) {
     case 1: MSP_LAUNCH(k_compact<uint8_t>, grid, dim3(256), 0, s, a); break;
