@@ -92,6 +92,16 @@ typedef enum msp_semiring {
  *           per admitted (i,j) (Section "Pull-based Algorithms"). Needs the
  *           transpose of B, built by the plan unless options->b_transpose is
  *           given. Normal mask only.
+ *  HEAP     one lane per row: a k-way merge of the rows of B selected by
+ *           A(i,:), ordered by a min-heap of row iterators in LDS keyed by
+ *           (column, position in A's row), so that products of one column
+ *           come out consecutively and the row is emitted sorted without a
+ *           sort (Section "Masked Heap SpGEVM Algorithm"). Before an
+ *           iterator enters the heap it is advanced past columns the mask
+ *           does not admit (a binary search of the mask row per product),
+ *           so only admitted products are merged. Normal and complemented.
+ *           Rows whose row of A has more than 8 entries, or with 2^24
+ *           products or more, take the automatic choice instead.
  * Forcing MASKIDX, HASH or INNER together with a complemented mask returns
  * MSP_ERR_UNSUPPORTED.
  */
@@ -100,7 +110,8 @@ typedef enum msp_kind {
     MSP_KIND_DENSE = 0,
     MSP_KIND_HASH = 1,
     MSP_KIND_MASKIDX = 2,
-    MSP_KIND_INNER = 3
+    MSP_KIND_INNER = 3,
+    MSP_KIND_HEAP = 4
 } msp_kind;
 
 /* Read-only CSR view of device memory (see the conventions above). */
@@ -146,7 +157,16 @@ typedef struct msp_options {
                              light rows (at most block_flops products) with at
                              most 256 mask entries use MASKIDX too, other rows
                              with at most 512 use HASH (-1 = default 8) */
-    int32_t reserved;
+    int32_t heap_flops;   /* auto mode: rows whose row of A has at most 8
+                             entries use HEAP when they have at most this many
+                             products, or at most 8 times as many and a mask
+                             row with at least 8 entries per product, or, under
+                             a complemented mask with more than 4096 columns,
+                             whatever their product count (-1 = default 32;
+                             0 = never). An automatic heap bin of at most 32768
+                             rows whose mask rows (normal) hold at most 256
+                             entries runs in the MASKIDX wave kernel instead:
+                             a small heap launch costs more than it saves. */
     int64_t block_flops;  /* rows with more products than this run on a whole
                              256-thread workgroup instead of one wavefront
                              (-1 = default 8192) */
@@ -157,7 +177,8 @@ typedef struct msp_options {
 } msp_options;
 
 /* Fills `opt` with the defaults: phase 1, auto kind, no validation,
-   inner_ratio 0, no B^T, maskidx_max 8, block_flops 8192, split_flops 262144. */
+   inner_ratio 0, no B^T, maskidx_max 8, heap_flops 32, block_flops 8192,
+   split_flops 262144. */
 void msp_options_default(msp_options* opt);
 
 /* Plan statistics, filled by msp_plan_info. */
@@ -169,7 +190,7 @@ typedef struct msp_plan_info_t {
     int64_t units;           /* work units (rows or row tiles) */
     int64_t staging;         /* staging entries used by one-phase execution */
     int64_t mask_nnz;        /* nnz(M) */
-    int64_t kind_units[4];   /* units per msp_kind */
+    int64_t kind_units[8];   /* units per msp_kind (5 used) */
     int64_t bin_units[16];   /* units per kernel bin (MSP_BIN_*; MSP_NBINS used) */
 } msp_plan_info_t;
 
@@ -189,7 +210,8 @@ enum {
     MSP_BIN_DENSE_BLOCK_NARROW = 7,  /* dense state over <= 512 columns, one workgroup per row */
     MSP_BIN_DENSE_SPLIT = 8,         /* rows with many products: one workgroup per chunk of the
                                         row of A, merged into a per-row accumulator */
-    MSP_NBINS = 9
+    MSP_BIN_HEAP_LANE = 9,           /* one lane per row, k-way merge (HEAP kind) */
+    MSP_NBINS = 10
 };
 
 /* Stage slots of msp_execute_profiled: 0..15 = numeric kernel of bin b,

@@ -22,7 +22,7 @@ SEMIRINGS = {
 }
 BIN_NAMES = L.BIN_NAMES
 STAGE_NAMES = L.STAGE_NAMES
-KINDS = {None: -1, "auto": -1, "dense": 0, "hash": 1, "maskidx": 2, "inner": 3}
+KINDS = {None: -1, "auto": -1, "dense": 0, "hash": 1, "maskidx": 2, "inner": 3, "heap": 4}
 STATUS = {0: "MSP_OK", 1: "MSP_ERR_INVALID_ARGUMENT", 2: "MSP_ERR_DIMENSION_MISMATCH",
           3: "MSP_ERR_INVALID_CSR", 4: "MSP_ERR_UNSUPPORTED", 5: "MSP_ERR_INSUFFICIENT_CAPACITY",
           6: "MSP_ERR_OUT_OF_MEMORY", 7: "MSP_ERR_DEVICE"}
@@ -116,7 +116,7 @@ def _check(st: int, where: str):
 
 def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio: int = 0,
             b_transpose: Optional[L.MspCsr] = None, maskidx_max: int = -1,
-            block_flops: int = -1, split_flops: int = -1) -> L.MspOptions:
+            block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1) -> L.MspOptions:
     o = L.MspOptions()
     L.load().msp_options_default(ctypes.byref(o))
     o.phase = int(phase)
@@ -126,6 +126,7 @@ def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio
     o.maskidx_max = int(maskidx_max)
     o.block_flops = int(block_flops)
     o.split_flops = int(split_flops)
+    o.heap_flops = int(heap_flops)
     if b_transpose is not None:
         o.b_transpose = ctypes.pointer(b_transpose)
     return o
@@ -139,7 +140,7 @@ class Plan:
     def __init__(self, A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
                  semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
                  validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None,
-                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1):
+                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1):
         lib = L.load()
         self.semiring = semiring
         self.A, self.B, self.M = A, B, M
@@ -147,7 +148,7 @@ class Plan:
         self._bt = None if b_transpose is None else _view(b_transpose, semiring, "B^T")
         self._bt_keep = b_transpose
         self._opt = options(phase, force_kind, validate, inner_ratio, self._bt, maskidx_max, block_flops,
-                            split_flops)
+                            split_flops, heap_flops)
         self.phase = phase
         self.nrows, self.ncols = A.nrows, B.ncols
         h = ctypes.c_void_p()
@@ -162,7 +163,7 @@ class Plan:
         self.units = info.units
         self.staging = info.staging
         self.mask_nnz = info.mask_nnz
-        self.kind_units = {k: info.kind_units[i] for i, k in enumerate(["dense", "hash", "maskidx", "inner"])}
+        self.kind_units = {k: info.kind_units[i] for i, k in enumerate(["dense", "hash", "maskidx", "inner", "heap"])}
         self.bin_units = {k: info.bin_units[i] for i, k in enumerate(L.BIN_NAMES)}
 
     def _out(self, capacity: int):
@@ -256,7 +257,7 @@ def masked_spgemm(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = F
                   validate: bool = False, inner_ratio: int = 0,
                   b_transpose: Optional[DeviceCSR] = None, **tuning) -> DeviceCSR:
     """C = M .* (A B) (or !M .* (A B)) over `semiring`, rows sorted.
-    `tuning`: maskidx_max, block_flops, split_flops (binner thresholds)."""
+    `tuning`: maskidx_max, block_flops, split_flops, heap_flops (binner thresholds)."""
     with Plan(A, B, M, complement, semiring, phase, force_kind, validate, inner_ratio, b_transpose,
               **tuning) as p:
         return p.execute()
@@ -334,7 +335,7 @@ class Batch:
     problems: list of (A, B, M, complement) DeviceCSR triples."""
 
     def __init__(self, problems, semiring: str = "plus_times_f64", force_kind=None, inner_ratio: int = 0,
-                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1):
+                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1):
         lib = L.load()
         self.semiring = semiring
         self.problems = list(problems)
@@ -346,7 +347,8 @@ class Batch:
             arr[p].M = _view(M, None, "M")
             arr[p].complement = int(bool(comp))
         self._arr = arr
-        self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops, split_flops)
+        self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops, split_flops,
+                            heap_flops)
         h = ctypes.c_void_p()
         _check(lib.msp_batch_create(ctypes.byref(h), arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt),
                                     _stream()), "msp_batch_create")

@@ -23,12 +23,12 @@ class MspCsrOut(ctypes.Structure):
 class MspOptions(ctypes.Structure):
     _fields_ = [("phase", c_i32), ("force_kind", c_i32), ("validate", c_i32),
                 ("inner_ratio", c_i32), ("b_transpose", ctypes.POINTER(MspCsr)),
-                ("maskidx_max", c_i32), ("reserved", c_i32), ("block_flops", c_i64), ("split_flops", c_i64)]
+                ("maskidx_max", c_i32), ("heap_flops", c_i32), ("block_flops", c_i64), ("split_flops", c_i64)]
 
 
 class MspPlanInfo(ctypes.Structure):
     _fields_ = [("upper_bound", c_i64), ("products", c_i64), ("units", c_i64),
-                ("staging", c_i64), ("mask_nnz", c_i64), ("kind_units", c_i64 * 4),
+                ("staging", c_i64), ("mask_nnz", c_i64), ("kind_units", c_i64 * 8),
                 ("bin_units", c_i64 * 16)]
 
 
@@ -42,7 +42,7 @@ class MspKtrussInfo(ctypes.Structure):
 
 
 BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wave", "maskidx_block",
-             "inner_wave", "dense_block_narrow", "dense_split"]
+             "inner_wave", "dense_block_narrow", "dense_split", "heap_lane"]
 STAGE_NAMES = BIN_NAMES + [f"bin{b}" for b in range(len(BIN_NAMES), 16)] + [
     "symbolic", "scan", "rowptr", "compact", "split_emit"]
 NSTAGES = len(STAGE_NAMES)

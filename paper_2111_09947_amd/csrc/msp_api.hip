@@ -127,6 +127,7 @@ struct msp_plan {
     // units (global)
     int64_t bin_count[NBINS] = {};
     int64_t bin_off[NBINS + 1] = {};
+    bool heap_fold = false;  // the heap units run in the mask-indexed wave kernel's launch
     int64_t seg_off[NBINS * NBUCKET] = {};
     int64_t* seg_off_d = nullptr;
     int64_t* icost = nullptr;
@@ -220,7 +221,7 @@ void msp_options_default(msp_options* opt) {
     opt->inner_ratio = 0;
     opt->b_transpose = nullptr;
     opt->maskidx_max = -1;
-    opt->reserved = 0;
+    opt->heap_flops = -1;
     opt->block_flops = -1;
     opt->split_flops = -1;
 }
@@ -346,12 +347,13 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     if (o.phase == 0) o.phase = 1;
     if (o.phase != 1 && o.phase != 2) return fail(MSP_ERR_INVALID_ARGUMENT, "phase must be 1 or 2");
     if (count > 1 && o.phase != 1) return fail(MSP_ERR_UNSUPPORTED, "a batch runs one-phase only");
-    if (o.force_kind < MSP_KIND_AUTO || o.force_kind > MSP_KIND_INNER)
+    if (o.force_kind < MSP_KIND_AUTO || o.force_kind > MSP_KIND_HEAP)
         return fail(MSP_ERR_INVALID_ARGUMENT, "unknown force_kind");
     if (o.inner_ratio < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "inner_ratio must be >= 0");
     if (o.maskidx_max < 0) o.maskidx_max = DEFAULT_MASKIDX_MAX;
     if (o.block_flops < 0) o.block_flops = DEFAULT_BLOCK_FLOPS;
     if (o.split_flops < 0) o.split_flops = DEFAULT_SPLIT_FLOPS;
+    if (o.heap_flops < 0) o.heap_flops = DEFAULT_HEAP_FLOPS;
     if (count > 1 && o.b_transpose) return fail(MSP_ERR_UNSUPPORTED, "b_transpose applies to a single product");
     int64_t R = 0;
     P->prods.resize((size_t)count);
@@ -360,8 +362,9 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         MSP_CHECK(check_triple(&q.A, &q.B, &q.M));
         if (q.complement != 0 && q.complement != 1)
             return fail(MSP_ERR_INVALID_ARGUMENT, "complement must be 0 or 1");
-        if (q.complement && o.force_kind != MSP_KIND_AUTO && o.force_kind != MSP_KIND_DENSE)
-            return fail(MSP_ERR_UNSUPPORTED, "a complemented mask supports only the dense kind");
+        if (q.complement && o.force_kind != MSP_KIND_AUTO && o.force_kind != MSP_KIND_DENSE &&
+            o.force_kind != MSP_KIND_HEAP)
+            return fail(MSP_ERR_UNSUPPORTED, "a complemented mask supports only the dense and heap kinds");
         Product& pr = P->prods[(size_t)p];
         Operands& op = pr.op;
         op.m = q.A.nrows; op.k = q.A.ncols; op.n = q.B.ncols;
@@ -445,6 +448,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.maskidx_max = o.maskidx_max;
         aa.block_flops = o.block_flops;
         aa.split_flops = o.split_flops;
+        aa.heap_flops = o.heap_flops;
         aa.colcnt_rp = pr.op.BTrp;
         aa.a_nnz = probs[p].A.nnz;
         aa.m_nnz = probs[p].M.nnz;
@@ -470,6 +474,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
 
     // totals; bins in order, inside a bin the flops buckets from the heaviest down
     std::vector<int64_t> segc(NBINS * NBUCKET, 0);
+    int64_t heap_apart = 0;
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
         const unsigned long long* st = &P->stats[(size_t)(p * ST_COUNT)];
@@ -490,9 +495,11 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         P->S += pr.staging;
         P->ub += pr.ub;
         P->nsplit += (int64_t)st[ST_SPLITROWS];
+        heap_apart += (int64_t)st[ST_HEAP_APART];
     }
     int64_t run = 0;
-    for (int b = 0; b < NBINS; ++b) {
+    for (int x = 0; x < NBINS; ++x) {  // the layout of the unit list (the device computed the same)
+        const int b = bin_at(x);
         P->bin_off[b] = run;
         for (int q = NBUCKET - 1; q >= 0; --q) {
             P->seg_off[b * NBUCKET + q] = run;
@@ -502,6 +509,8 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     }
     P->bin_off[NBINS] = run;
     if (run != P->U) return fail(MSP_ERR_DEVICE, "inconsistent unit statistics");
+    P->heap_fold = o.force_kind == MSP_KIND_AUTO && P->bin_count[BIN_HEAP_L] > 0 &&
+                   P->bin_count[BIN_HEAP_L] <= HEAP_FOLD_MAX && heap_apart == 0;
     if (P->U >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many work units");
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
@@ -709,6 +718,24 @@ struct StageTimer {
     }
 };
 
+// Numeric kernels of every non-empty bin, in bin order on `s`, in `mode`,
+// with `a` giving the outputs. A folded heap bin (heap_fold) runs as part of
+// the mask-indexed wave launch: its units directly follow that bin's.
+static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream_t s, StageTimer* tm) {
+    for (int b = 0; b < NBINS; ++b) {
+        const bool fold_in = P->heap_fold && b == BIN_MASKIDX_W;
+        if (P->heap_fold && b == BIN_HEAP_L) continue;
+        if (!P->bin_count[b] && !fold_in) continue;
+        NumArgs ab = a;
+        ab.units = P->bin_units + P->bin_off[b];  // a folded heap bin starts where this one ends
+        ab.nunits = P->bin_count[b] + (fold_in ? P->bin_count[BIN_HEAP_L] : 0);
+        if (tm) MSP_CHECK(tm->begin(b));
+        MSP_HIP(launch_numeric(P->sr, b, mode, ab, s));
+        if (tm) MSP_CHECK(tm->end());
+    }
+    return MSP_OK;
+}
+
 // The one-phase sequence over all products: numeric into staging, prefix sum
 // of the unit counts, row pointers, compaction. Kernels only (no allocation,
 // no memset, no synchronization), so it can be captured in a HIP graph.
@@ -720,15 +747,7 @@ static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, 
     a.cnt = P->cnt;
     a.out_col = P->stg_col;
     a.out_val = P->stg_val;
-    for (int b = 0; b < NBINS; ++b) {
-        if (!P->bin_count[b]) continue;
-        NumArgs ab = a;
-        ab.units = P->bin_units + P->bin_off[b];
-        ab.nunits = P->bin_count[b];
-        MSP_CHECK(tm.begin(b));
-        MSP_HIP(launch_numeric(P->sr, b, MODE_STAGE, ab, s));
-        MSP_CHECK(tm.end());
-    }
+    MSP_CHECK(launch_bins(P, MODE_STAGE, a, s, &tm));
     MSP_CHECK(tm.begin(MSP_STAGE_SPLIT_EMIT));
     MSP_CHECK(split_emit(P, MODE_STAGE, a, s));
     MSP_CHECK(tm.end());
@@ -760,11 +779,10 @@ static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_hos
     const Product& pr = P->prods[0];
     MSP_CHECK(tm.begin(MSP_STAGE_SYMBOLIC));
     MSP_CHECK(split_clear(P, s));
-    for (int b = 0; b < NBINS; ++b) {
-        if (!P->bin_count[b]) continue;
-        NumArgs a = num_args(P, b);
+    {
+        NumArgs a = num_args(P, 0);
         a.cnt = P->cnt;
-        MSP_HIP(launch_numeric(P->sr, b, MODE_COUNT, a, s));
+        MSP_CHECK(launch_bins(P, MODE_COUNT, a, s, nullptr));
     }
     {
         NumArgs a = num_args(P, 0);
@@ -788,20 +806,11 @@ static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_hos
 
 static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, hipStream_t s, StageTimer& tm) {
     MSP_CHECK(split_clear(P, s));
-    for (int b = 0; b < NBINS; ++b) {
-        if (!P->bin_count[b]) continue;
-        NumArgs a = num_args(P, b);
-        a.out_off = P->cnt;
-        a.out_col = C->colidx;
-        a.out_val = C->values;
-        MSP_CHECK(tm.begin(b));
-        MSP_HIP(launch_numeric(P->sr, b, MODE_DIRECT, a, s));
-        MSP_CHECK(tm.end());
-    }
     NumArgs a = num_args(P, 0);
     a.out_off = P->cnt;
     a.out_col = C->colidx;
     a.out_val = C->values;
+    MSP_CHECK(launch_bins(P, MODE_DIRECT, a, s, &tm));
     MSP_CHECK(tm.begin(MSP_STAGE_SPLIT_EMIT));
     MSP_CHECK(split_emit(P, MODE_DIRECT, a, s));
     MSP_CHECK(tm.end());
@@ -961,10 +970,12 @@ msp_status msp_batch_info(const msp_plan* P, int64_t p, msp_plan_info_t* info) {
         info->units += pr.units;
         info->staging += pr.staging;
         info->mask_nnz += pr.mnnz;
-        info->kind_units[MSP_KIND_DENSE] += pr.bin_units[BIN_DENSE_W] + pr.bin_units[BIN_DENSE_B];
+        info->kind_units[MSP_KIND_DENSE] += pr.bin_units[BIN_DENSE_W] + pr.bin_units[BIN_DENSE_B] +
+                                            pr.bin_units[BIN_DENSE_BN] + pr.bin_units[BIN_DENSE_SPLIT];
         info->kind_units[MSP_KIND_HASH] += pr.bin_units[BIN_HASH_W] + pr.bin_units[BIN_HASH_B];
         info->kind_units[MSP_KIND_MASKIDX] += pr.bin_units[BIN_MASKIDX_W] + pr.bin_units[BIN_MASKIDX_B];
         info->kind_units[MSP_KIND_INNER] += pr.bin_units[BIN_INNER_W];
+        info->kind_units[MSP_KIND_HEAP] += pr.bin_units[BIN_HEAP_L];
         for (int b = 0; b < NBINS; ++b) info->bin_units[b] += pr.bin_units[b];
     }
     return MSP_OK;

@@ -62,16 +62,17 @@ __global__ __launch_bounds__(BC_T) void k_union_rows(int64_t n, const int64_t* _
                                                      const int32_t* __restrict__ cia, const int64_t* __restrict__ rpb,
                                                      const int32_t* __restrict__ cib, const int64_t* __restrict__ rpu,
                                                      int32_t* __restrict__ ciu) {
-    const int64_t r = (int64_t)blockIdx.x * (BC_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (r >= n) return;
-    const int64_t a0 = rpa[r], a1 = rpa[r + 1], b0 = rpb[r], b1 = rpb[r + 1], u0 = rpu[r];
-    for (int64_t x = lane(); x < a1 - a0; x += WAVE) {
-        const int32_t c = cia[a0 + x];
-        ciu[u0 + x + (lower_bound_g(cib, b0, b1, c) - b0)] = c;
-    }
-    for (int64_t x = lane(); x < b1 - b0; x += WAVE) {
-        const int32_t c = cib[b0 + x];
-        ciu[u0 + x + (lower_bound_g(cia, a0, a1, c) - a0)] = c;
+    const int64_t first = (int64_t)blockIdx.x * (BC_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (BC_T / WAVE)) {
+        const int64_t a0 = rpa[r], a1 = rpa[r + 1], b0 = rpb[r], b1 = rpb[r + 1], u0 = rpu[r];
+        for (int64_t x = lane(); x < a1 - a0; x += WAVE) {
+            const int32_t c = cia[a0 + x];
+            ciu[u0 + x + (lower_bound_g(cib, b0, b1, c) - b0)] = c;
+        }
+        for (int64_t x = lane(); x < b1 - b0; x += WAVE) {
+            const int32_t c = cib[b0 + x];
+            ciu[u0 + x + (lower_bound_g(cia, a0, a1, c) - a0)] = c;
+        }
     }
 }
 
@@ -88,29 +89,33 @@ __global__ __launch_bounds__(BC_T) void k_bc_gather(int64_t n, const int64_t* __
                                                     const int32_t* __restrict__ cif, const double* __restrict__ sigf,
                                                     const int64_t* __restrict__ rpc, const int32_t* __restrict__ cic,
                                                     const double* __restrict__ vc, double* __restrict__ delta) {
-    const int64_t r = (int64_t)blockIdx.x * (BC_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (r >= n) return;
-    const int64_t f0 = rpf[r], f1 = rpf[r + 1], c0 = rpc[r], c1 = rpc[r + 1];
-    for (int64_t x = f0 + lane(); x < f1; x += WAVE) {
-        const int32_t c = cif[x];
-        const int64_t p = lower_bound_g(cic, c0, c1, c);
-        delta[x] = (p < c1 && cic[p] == c) ? __dmul_rn(sigf[x], vc[p]) : 0.0;
+    const int64_t first = (int64_t)blockIdx.x * (BC_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (BC_T / WAVE)) {
+        const int64_t f0 = rpf[r], f1 = rpf[r + 1], c0 = rpc[r], c1 = rpc[r + 1];
+        for (int64_t x = f0 + lane(); x < f1; x += WAVE) {
+            const int32_t c = cif[x];
+            const int64_t p = lower_bound_g(cic, c0, c1, c);
+            delta[x] = (p < c1 && cic[p] == c) ? __dmul_rn(sigf[x], vc[p]) : 0.0;
+        }
     }
 }
 
 // bc[row] += sum of the row's delta (one wave per row, fixed order)
 __global__ __launch_bounds__(BC_T) void k_bc_rowsum(int64_t n, const int64_t* __restrict__ rp,
                                                     const double* __restrict__ delta, double* __restrict__ bc) {
-    const int64_t r = (int64_t)blockIdx.x * (BC_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (r >= n) return;
-    double s = 0.0;
-    for (int64_t x = rp[r] + lane(); x < rp[r + 1]; x += WAVE) s = __dadd_rn(s, delta[x]);
+    const int64_t first = (int64_t)blockIdx.x * (BC_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (BC_T / WAVE)) {
+        double s = 0.0;
+        for (int64_t x = rp[r] + lane(); x < rp[r + 1]; x += WAVE) s = __dadd_rn(s, delta[x]);
 #pragma unroll
-    for (int d = WAVE / 2; d >= 1; d >>= 1) s = __dadd_rn(s, __shfl_xor(s, d, WAVE));
-    if (lane() == 0 && s != 0.0) bc[r] = __dadd_rn(bc[r], s);
+        for (int d = WAVE / 2; d >= 1; d >>= 1) s = __dadd_rn(s, __shfl_xor(s, d, WAVE));
+        if (lane() == 0 && s != 0.0) bc[r] = __dadd_rn(bc[r], s);
+    }
 }
 
 unsigned blocks_for(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+// wave-per-row kernels loop over rows: the grid stays far below 2^32 work-items
+unsigned row_blocks(int64_t n) { return (unsigned)std::min<int64_t>(blocks_for(n, BC_T / WAVE), int64_t(1) << 20); }
 unsigned grid_cap(int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 65536); }
 
 // Stream-ordered device allocations released together (in stream order).
@@ -253,7 +258,7 @@ extern "C" msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int
         BC_CHECK(mem.get(&urp, n + 1));
         BC_CHECK(mem.get(&uci, vnnz + next.nnz));
         hipLaunchKernelGGL(k_add_rowptr, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, n + 1, vrp, next.rp, urp);
-        hipLaunchKernelGGL(k_union_rows, dim3(blocks_for(n, BC_T / WAVE)), dim3(BC_T), 0, s, n, vrp, vci, next.rp,
+        hipLaunchKernelGGL(k_union_rows, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, vrp, vci, next.rp,
                            next.ci, urp, uci);
         BC_HIP(hipGetLastError());
         if (vrp != f0.rp) {
@@ -290,9 +295,9 @@ extern "C" msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int
         const msp_csr Mp{n, nsrc, Fp.nnz, Fp.rp, Fp.ci, nullptr};
         Level c;
         BC_CHECK(masked_product(Aiso, Bw, Mp, 0, s, mem, c, bwd_products));
-        hipLaunchKernelGGL(k_bc_gather, dim3(blocks_for(n, BC_T / WAVE)), dim3(BC_T), 0, s, n, Fp.rp, Fp.ci,
+        hipLaunchKernelGGL(k_bc_gather, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, Fp.rp, Fp.ci,
                            Fp.val, c.rp, c.ci, c.val, delta[(size_t)d - 1]);
-        hipLaunchKernelGGL(k_bc_rowsum, dim3(blocks_for(n, BC_T / WAVE)), dim3(BC_T), 0, s, n, Fp.rp,
+        hipLaunchKernelGGL(k_bc_rowsum, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, Fp.rp,
                            delta[(size_t)d - 1], bc);
         BC_HIP(hipGetLastError());
         mem.release(w);

@@ -106,10 +106,18 @@ template <> struct SRT<MSP_PLUS_TIMES_F64> {
         return v ? static_cast<const double*>(v)[p] : 1.0;
     }
     __device__ static acc_t identity() { return -0.0; }
-    __device__ static acc_t term(in_t a, in_t b) { return __dmul_rn(a, b); }
+    // each product and each sum is rounded on its own: no fused multiply-add
+    // is formed across term() and add()
+    __device__ static acc_t term(in_t a, in_t b) {
+#pragma clang fp contract(off)
+        return a * b;
+    }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicAdd(slot, t); }
     __device__ static void merge(acc_t* slot, acc_t part) { atomicAdd(slot, part); }
-    __device__ static acc_t add(acc_t x, acc_t t) { return __dadd_rn(x, t); }
+    __device__ static acc_t add(acc_t x, acc_t t) {
+#pragma clang fp contract(off)
+        return x + t;
+    }
     __device__ static bool is_set(acc_t) { return false; }
     __device__ static out_t finish(acc_t x) { return x; }
 };

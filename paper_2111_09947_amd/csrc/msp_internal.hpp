@@ -22,7 +22,8 @@ enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_DENSE_BN = 7,   // one block, dense state over <= DENSE_W_COLS columns (product-heavy rows)
     BIN_DENSE_SPLIT = 8,  // one block per chunk of A's row, dense state over <= DENSE_B_COLS
                           // columns, merged into a per-row accumulator in global memory
-    NBINS = 9
+    BIN_HEAP_L = 9,     // one lane per row, k-way merge of <= HEAP_CAP rows of B by a heap in LDS
+    NBINS = 10
 };
 
 constexpr int DENSE_W_COLS = 512;
@@ -34,8 +35,26 @@ constexpr int MASKIDX_B_CAP = 4096;
 constexpr int INNER_CAP = 256;
 constexpr int INNER_ACAP = 1024;  // A row (column indices) staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
+constexpr int HEAP_CAP = 8;       // heap kind: iterators per row (entries of the row of A)
+constexpr int64_t HEAP_MAX_FLOPS = (int64_t(1) << 24) - 1;  // heap keys hold a B row's remaining length in 24 bits
+constexpr int64_t HEAP_LONG_MASK_RATIO = 8;  // auto HEAP also when the mask row has >= this many entries per product
+constexpr int64_t HEAP_LONG_MASK_FLOPS = 8;  // ... and the row has at most this many times heap_flops products
+// A heap bin of at most this many units, all of them rows the mask-indexed
+// wave kernel can take (normal mask, at most MASKIDX_W_CAP mask entries, the
+// same staging), runs in that kernel's launch instead of a launch of its own:
+// a small heap launch costs its latency-bound tail (a lane walks its row
+// serially) and saves less than that.
+constexpr int64_t HEAP_FOLD_MAX = 32768;
+
+// Position x of the unit list holds the units of bin bin_at(x): the bins in
+// numeric order, except that the heap bin comes right after the mask-indexed
+// wave bin, so the two form one contiguous range of units.
+__host__ __device__ inline int bin_at(int x) {
+    return x <= BIN_MASKIDX_W ? x : (x == BIN_MASKIDX_W + 1 ? (int)BIN_HEAP_L : x - 1);
+}
 constexpr int DEFAULT_MASKIDX_MAX = 8;       // auto: binary search up to this mask size, hash above
 constexpr int64_t DEFAULT_BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
+constexpr int DEFAULT_HEAP_FLOPS = 32;           // auto: HEAP for fitting rows with at most this many products
 constexpr int64_t DEFAULT_SPLIT_FLOPS = 262144;  // dense rows with more products split over several blocks
 // Units of a bin are ordered by the product count of their row, heaviest
 // first (bucket b holds rows with 4^b <= flops < 4^(b+1)), so that the
@@ -53,7 +72,8 @@ enum Stat : int {
     ST_BIN0 = 6,                 // ST_BIN0 + b * NBUCKET + bucket: units of bin b in a flops bucket
     ST_ERROR = ST_BIN0 + NBINS * NBUCKET,  // nonzero: invalid CSR found by validation
     ST_SPLITROWS = ST_ERROR + 1,           // rows split over several blocks
-    ST_COUNT = ST_SPLITROWS + 1
+    ST_HEAP_APART = ST_SPLITROWS + 1,      // heap rows the mask-indexed wave kernel cannot take
+    ST_COUNT = ST_HEAP_APART + 1
 };
 
 enum Mode : int { MODE_COUNT = 0, MODE_STAGE = 1, MODE_DIRECT = 2 };
@@ -75,6 +95,7 @@ struct AnalysisArgs {
     int maskidx_max;
     int64_t block_flops;
     int64_t split_flops;
+    int64_t heap_flops;        // auto: HEAP for fitting rows with at most this many products (0 = never)
     const int64_t* colcnt_rp;  // row pointers of B^T (column counts of B) or null
     int64_t a_nnz;             // nnz(A), nnz(M)
     int64_t m_nnz;
@@ -123,6 +144,7 @@ struct NumArgs {
     const int32_t* split_first;
     const int32_t* split_nchunk;
     int64_t nsplit;
+    int64_t split_off;         // first split row of this launch (split emission)
     unsigned int* gset;        // [nsplit][DENSE_B_COLS / 32] inserted bits
     void* gval;                // [nsplit][DENSE_B_COLS] accumulator slots
 };

@@ -19,6 +19,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "msp_device.hpp"
@@ -52,8 +53,14 @@ bool timing_disarm() {
 
 }  // namespace mspk
 
+// Every launch goes through this macro (inside a function returning
+// hipError_t). A dispatch that would hold 2^32 work-items or more is refused
+// with an error instead of being issued (the dispatch packet's grid size is a
+// 32-bit count of work-items).
 #define MSP_LAUNCH(K, G, B, SH, S, ...)                                                                    \
     do {                                                                                                 \
+        if ((uint64_t)dim3(G).x * (uint64_t)dim3(B).x >= (uint64_t(1) << 32))                           \
+            return hipErrorInvalidConfiguration;                                                         \
         if (::mspk::tl_stop) {                                                                           \
             hipExtLaunchKernelGGL(K, G, B, SH, S, ::mspk::tl_launched ? nullptr : ::mspk::tl_start,      \
                                   ::mspk::tl_stop, 0u, __VA_ARGS__);                                      \
@@ -215,9 +222,22 @@ __device__ __forceinline__ int64_t cdiv(int64_t x, int64_t y) { return (x + y - 
 
 // Accumulator kind and tiling of one row (auto or forced). alen = nnz(A(i,:)).
 __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, int comp, int force, int inner_ratio,
-                        int maskidx_max, int64_t block_flops, int64_t split_flops, int64_t icost, int& bin,
-                        int64_t& tiles) {
-    int kind = comp ? (int)MSP_KIND_DENSE : force;
+                        int maskidx_max, int64_t block_flops, int64_t split_flops, int64_t heap_flops,
+                        int64_t icost, int& bin, int64_t& tiles) {
+    // the heap holds one iterator per entry of A's row; other rows take the automatic choice
+    const bool heap_fits = alen <= HEAP_CAP && flops <= HEAP_MAX_FLOPS;
+    int kind = force == MSP_KIND_HEAP && !heap_fits ? (int)MSP_KIND_AUTO : force;
+    // Auto: very light rows are merged one row per lane (a wave-wide kind would leave most of its
+    // lanes idle on them), and so are somewhat heavier rows whose mask row is much longer than
+    // their product count (the other kinds spend time per mask entry); so is every fitting row
+    // of a complemented mask wider than one dense tile, which the dense kind would restream once
+    // per 4096-column tile.
+    if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0 &&
+        (flops <= heap_flops || (!comp && flops <= HEAP_LONG_MASK_FLOPS * heap_flops &&
+                                 mnnz >= HEAP_LONG_MASK_RATIO * flops) ||
+         (comp && n > DENSE_B_COLS)))
+        kind = MSP_KIND_HEAP;
+    if (comp && kind != MSP_KIND_HEAP) kind = MSP_KIND_DENSE;
     const bool heavy = flops > block_flops;
     if (kind == MSP_KIND_AUTO) {
         // Every mask-keyed lookup is behind the membership filter, so a light row is looked up
@@ -244,6 +264,9 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
     case MSP_KIND_MASKIDX:
         if (mnnz <= MASKIDX_W_CAP && !heavy) { bin = BIN_MASKIDX_W; tiles = 1; }
         else { bin = BIN_MASKIDX_B; tiles = cdiv(mnnz, MASKIDX_B_CAP); }
+        break;
+    case MSP_KIND_HEAP:
+        bin = BIN_HEAP_L; tiles = 1;
         break;
     default:
         bin = BIN_INNER_W; tiles = cdiv(mnnz, INNER_CAP);
@@ -272,6 +295,7 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
         adm = o.complement ? (c1 - c0) - mt : mt;
         break;
     }
+    case BIN_HEAP_L: adm = o.complement ? o.n - mnnz : mnnz; break;
     case BIN_HASH_W: case BIN_MASKIDX_W: adm = mnnz; break;
     case BIN_HASH_B: adm = min((int64_t)HASH_B_CAP, mnnz - t * HASH_B_CAP); break;
     case BIN_MASKIDX_B: adm = min((int64_t)MASKIDX_B_CAP, mnnz - t * MASKIDX_B_CAP); break;
@@ -300,8 +324,9 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
         int bin = -1;
         if (ub > 0) {
             classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
-                     a.maskidx_max, a.block_flops, a.split_flops, icost, bin, tiles);
+                     a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost, bin, tiles);
             if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
+            if (bin == BIN_HEAP_L && (o.complement || mnnz > MASKIDX_W_CAP)) atomicAdd(&sst[ST_HEAP_APART], 1ull);
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
             seg = bin * NBUCKET + flops_bucket(flops);
         }
@@ -385,11 +410,13 @@ __global__ __launch_bounds__(128) void k_segoff(const unsigned long long* __rest
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t run = 0;
-        for (int b = 0; b < NBINS; ++b)
+        for (int x = 0; x < NBINS; ++x) {
+            const int b = bin_at(x);
             for (int q = NBUCKET - 1; q >= 0; --q) {
                 seg_off[b * NBUCKET + q] = run;
                 run += segc[b * NBUCKET + q];
             }
+        }
     }
 }
 
@@ -915,7 +942,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE) void k_split_emit(NumArgs g) {
     constexpr int NW = BLOCK_NW;
     constexpr bool COUNT = MODE == MODE_COUNT;
     __shared__ int64_t tmp[NW];
-    const int sidx = blockIdx.x;
+    const int64_t sidx = g.split_off + blockIdx.x;
     const int u = g.split_first[sidx];
     const Operands& o = BATCH ? g.ops[g.unit_prob[u]] : g.op;
     const int wt = (int)o.n;
@@ -1239,6 +1266,216 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
     if (ln == 0 && MODE != MODE_DIRECT) g.cnt[u] = running;
 }
 
+// ---------------------------------------------------------------- heap kind
+//
+// Masked heap merge (Section "Masked Heap SpGEVM Algorithm"), one lane per
+// row. The lane keeps one iterator per entry A(i,k_s) over the row B(k_s,:);
+// a binary min-heap of the iterators, stored in LDS, yields the products in
+// ascending column order, so products of one column arrive one after another
+// and fold into a running value, and the row comes out sorted.
+//
+// Mask handling: before an iterator enters (or re-enters) the heap it is moved
+// past every column the mask does not admit, each column being tested against
+// the mask row. Only admitted products are merged, and a product's B value is
+// read when it leaves the heap. For a complemented mask the same test is
+// negated.
+//
+// Heap entries are 64-bit keys: column (bits 63..32), slot s of the iterator
+// (bits 31..24), remaining entries of its B row (bits 23..0; rows have fewer
+// than 2^24 products). Equal columns leave in slot order, which is the order
+// of k, so the fold order is the order of the row of A. The end position of
+// each iterator's row is kept per slot, so the current position is
+// end - remaining.
+//
+// Latency: a lane walks its row serially, so every dependent memory access
+// is paid in full. The columns of the B rows are therefore read HEAP_B at a
+// time: windows of HEAP_B positions counted back from the row's end, loaded
+// together into an LDS buffer per iterator when the iterator enters the
+// window; at the start the first (partial) window of every iterator is
+// loaded in one batch. Mask rows of up to HEAP_MREG entries sit in registers
+// and are tested by comparisons; longer ones are binary-searched.
+//
+// LDS per lane: HEAP_CAP x (key 8 B + end 8 B + HEAP_B columns 4 B) = 256 B,
+// 16 KiB per one-wave workgroup. Entry e of a lane's arrays sits at
+// [e][lane], so lanes at the same depth hit consecutive words. One wave per
+// workgroup spreads a small bin over as many CUs as possible: the bin's time
+// is bounded below by its slowest lane.
+constexpr int HEAP_T = WAVE;
+constexpr int HEAP_MREG = 8;
+constexpr int HEAP_B = 4;
+static_assert((HEAP_B & (HEAP_B - 1)) == 0, "windows are a power of two");
+
+template <int SR, int MODE, bool BATCH>
+__global__ __launch_bounds__(HEAP_T) void k_heap(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    using in_t = typename T::in_t;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    __shared__ unsigned long long hkey[HEAP_CAP][HEAP_T];
+    __shared__ int64_t hend[HEAP_CAP][HEAP_T];
+    __shared__ int32_t hcol[HEAP_CAP * HEAP_B][HEAP_T];
+    const int t = threadIdx.x;
+    const int64_t uix = (int64_t)blockIdx.x * HEAP_T + t;
+    if (uix >= g.nunits) return;  // lanes are independent: no wave-wide operation follows
+    const int u = g.units[uix];
+    const Operands& o = BATCH ? g.ops[g.unit_prob[u]] : g.op;
+    const int32_t* __restrict__ Aci = o.Aci;
+    const int64_t* __restrict__ Brp = o.Brp;
+    const int32_t* __restrict__ Bci = o.Bci;
+    const int32_t* __restrict__ Mci = o.Mci;
+    const void* Av = o.Av;
+    const void* Bv = o.Bv;
+    const bool comp = o.complement != 0;
+    const int64_t i = g.unit_row[u];
+    const int64_t pa0 = o.Arp[i];
+    const int alen = (int)(o.Arp[i + 1] - pa0);  // <= HEAP_CAP by classification
+    const int64_t m0 = o.Mrp[i], m1 = o.Mrp[i + 1];
+    const bool mreg = m1 - m0 <= HEAP_MREG;
+    int32_t mk[HEAP_MREG];
+#pragma unroll
+    for (int x = 0; x < HEAP_MREG; ++x) mk[x] = mreg && m0 + x < m1 ? Mci[m0 + x] : -1;
+    auto admitted = [&](int32_t col) -> bool {
+        bool f = false;
+        if (mreg) {
+#pragma unroll
+            for (int x = 0; x < HEAP_MREG; ++x) f |= mk[x] == col;
+        } else {
+            const int64_t q = lower_bound_g(Mci, m0, m1, col);
+            f = q < m1 && Mci[q] == col;
+        }
+        return f != comp;
+    };
+    // column at position p of slot s's row (ending at e): from the buffer, or, at the first
+    // position of a window, by loading the whole window (it lies inside the row)
+    auto col_at = [&](int s, int64_t p, int64_t e) -> int32_t {
+        const int idx = (int)((e - p - 1) & (HEAP_B - 1));
+        if (idx == HEAP_B - 1) {
+            int32_t c[HEAP_B];
+#pragma unroll
+            for (int x = 0; x < HEAP_B; ++x) c[x] = Bci[p + x];
+#pragma unroll
+            for (int x = 1; x < HEAP_B; ++x) hcol[s * HEAP_B + HEAP_B - 1 - x][t] = c[x];
+            return c[0];
+        }
+        return hcol[s * HEAP_B + idx][t];
+    };
+    // first position in [p, e) whose column the mask admits (e if none); its column in `col`
+    auto next_admitted = [&](int s, int64_t p, int64_t e, int32_t& col) -> int64_t {
+        for (; p < e; ++p) {
+            col = col_at(s, p, e);
+            if (admitted(col)) break;
+        }
+        return p;
+    };
+    auto make_key = [](int32_t col, int s, int64_t rem) -> unsigned long long {
+        return ((unsigned long long)(uint32_t)col << 32) | ((unsigned long long)s << 24) | (unsigned long long)rem;
+    };
+    // the iterators' rows and first windows, each level loaded in one batch
+    int32_t ks[HEAP_CAP];
+#pragma unroll
+    for (int s = 0; s < HEAP_CAP; ++s) ks[s] = s < alen ? Aci[pa0 + s] : 0;
+    int64_t bs[HEAP_CAP], be[HEAP_CAP];
+#pragma unroll
+    for (int s = 0; s < HEAP_CAP; ++s) {
+        bs[s] = s < alen ? Brp[ks[s]] : 0;
+        be[s] = s < alen ? Brp[ks[s] + 1] : 0;
+    }
+    int32_t cw[HEAP_CAP][HEAP_B];
+#pragma unroll
+    for (int s = 0; s < HEAP_CAP; ++s) {
+        const int n0 = bs[s] < be[s] ? (int)((be[s] - bs[s] - 1) & (HEAP_B - 1)) + 1 : 0;  // rest of the window
+#pragma unroll
+        for (int x = 0; x < HEAP_B; ++x) cw[s][x] = x < n0 ? Bci[bs[s] + x] : 0;
+#pragma unroll
+        for (int x = 1; x < HEAP_B; ++x)
+            if (x < n0) hcol[s * HEAP_B + n0 - 1 - x][t] = cw[s][x];
+    }
+    // build the heap: one iterator per entry of A's row that has an admitted product
+    int h = 0;
+#pragma unroll
+    for (int s = 0; s < HEAP_CAP; ++s) {
+        if (s < alen && bs[s] < be[s]) {
+            const int64_t e = be[s];
+            int32_t col = cw[s][0];
+            int64_t p = bs[s];
+            if (!admitted(col)) p = next_admitted(s, p + 1, e, col);
+            if (p < e) {
+                hend[s][t] = e;
+                const unsigned long long key = make_key(col, s, e - p);
+                int x = h++;
+                while (x > 0) {  // sift up
+                    const int par = (x - 1) >> 1;
+                    const unsigned long long pk = hkey[par][t];
+                    if (pk <= key) break;
+                    hkey[x][t] = pk;
+                    x = par;
+                }
+                hkey[x][t] = key;
+            }
+        }
+    }
+    const int64_t ob = COUNT ? 0 : g.out_off[u];
+    typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+    int64_t cnt = 0;
+    int32_t prev = -1;
+    acc_t acc = T::identity();
+    while (h > 0) {
+        const unsigned long long top = hkey[0][t];
+        const int32_t col = (int32_t)(top >> 32);
+        const int s = (int)((top >> 24) & 0xffu);
+        const int64_t e = hend[s][t];
+        const int64_t p = e - (int64_t)(top & 0xffffffull);
+        if (col != prev) {  // a new output column: the previous one is complete
+            if (prev >= 0) {
+                if (!COUNT) {
+                    g.out_col[ob + cnt] = prev;
+                    ov[ob + cnt] = T::finish(acc);
+                }
+                ++cnt;
+            }
+            prev = col;
+            acc = T::identity();
+        }
+        if (!COUNT) {
+            const in_t a = T::needs_values ? T::load(Av, pa0 + s) : T::one();
+            const in_t b = T::needs_values ? T::load(Bv, p) : T::one();
+            acc = T::add(acc, T::term(a, b));
+        }
+        // advance the popped iterator; a finished one is replaced by the last entry
+        int32_t nc = 0;
+        const int64_t np = next_admitted(s, p + 1, e, nc);
+        unsigned long long key;
+        if (np < e) {
+            key = make_key(nc, s, e - np);
+        } else {
+            if (--h == 0) break;
+            key = hkey[h][t];
+        }
+        int x = 0;
+        while (true) {  // sift down from the root
+            int c = 2 * x + 1;
+            if (c >= h) break;
+            unsigned long long ck = hkey[c][t];
+            if (c + 1 < h) {
+                const unsigned long long ck2 = hkey[c + 1][t];
+                if (ck2 < ck) { ck = ck2; ++c; }
+            }
+            if (key <= ck) break;
+            hkey[x][t] = ck;
+            x = c;
+        }
+        hkey[x][t] = key;
+    }
+    if (prev >= 0) {
+        if (!COUNT) {
+            g.out_col[ob + cnt] = prev;
+            ov[ob + cnt] = T::finish(acc);
+        }
+        ++cnt;
+    }
+    if (MODE != MODE_DIRECT) g.cnt[u] = cnt;
+}
+
 #ifndef MSP_HASH_LOOKUP
 #define MSP_HASH_LOOKUP 1
 #endif
@@ -1247,8 +1484,13 @@ __global__ __launch_bounds__(WPB * WAVE) void k_inner(NumArgs g) {
 #endif
 constexpr int WPB = MSP_WPB;  // independent one-wave units per block
 
+// A dispatch holds fewer than 2^32 work-items, so a bin with more units than
+// this (a workgroup of 256 per unit in the block kinds) runs as several
+// launches over consecutive slices of its unit list.
+constexpr int64_t NUM_CHUNK = int64_t(1) << 22;
+
 template <int SR, int MODE, bool BATCH>
-static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
+static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
     const dim3 gw((unsigned)((a.nunits + WPB - 1) / WPB)), gb((unsigned)a.nunits);
     const dim3 bw(WPB * WAVE), bb(BLOCK_NW * WAVE);
     switch (bin) {
@@ -1279,17 +1521,40 @@ static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
     case BIN_DENSE_SPLIT:
         MSP_LAUNCH((k_dense_split<SR, MODE, BATCH>), gb, bb, 0, s, a);
         break;
+    case BIN_HEAP_L:
+        MSP_LAUNCH((k_heap<SR, MODE, BATCH>), dim3((unsigned)((a.nunits + HEAP_T - 1) / HEAP_T)), dim3(HEAP_T), 0,
+                   s, a);
+        break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int SR, int MODE, bool BATCH>
+static hipError_t launch_numeric_t(int bin, const NumArgs& a, hipStream_t s) {
+    for (int64_t off = 0; off < a.nunits; off += NUM_CHUNK) {
+        NumArgs c = a;
+        c.units = a.units + off;
+        c.nunits = std::min(NUM_CHUNK, a.nunits - off);
+        const hipError_t e = launch_numeric_one<SR, MODE, BATCH>(bin, c, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <int SR, int MODE>
 static hipError_t launch_split_emit_t(const NumArgs& a, hipStream_t s) {
-    if (a.ops) MSP_LAUNCH((k_split_emit<SR, MODE, true>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
-    else MSP_LAUNCH((k_split_emit<SR, MODE, false>), dim3((unsigned)a.nsplit), dim3(BLOCK_NW * WAVE), 0, s, a);
-    return hipGetLastError();
+    for (int64_t off = 0; off < a.nsplit; off += NUM_CHUNK) {  // a workgroup per split row
+        NumArgs c = a;
+        c.split_off = off;
+        const dim3 g((unsigned)std::min(NUM_CHUNK, a.nsplit - off));
+        if (a.ops) MSP_LAUNCH((k_split_emit<SR, MODE, true>), g, dim3(BLOCK_NW * WAVE), 0, s, c);
+        else MSP_LAUNCH((k_split_emit<SR, MODE, false>), g, dim3(BLOCK_NW * WAVE), 0, s, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int SR>
@@ -1366,16 +1631,17 @@ hipError_t launch_numeric(int semiring, int bin, int mode, const NumArgs& a, hip
 
 template <typename V>
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
-    const int64_t u = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (u >= a.U) return;
-    const OutBind& ob = a.outs ? a.outs[a.unit_prob[u]] : a.one;
-    const int64_t src = a.stg_off[u], n = a.out_off[u + 1] - a.out_off[u];
-    const int64_t dst = a.out_off[u] - a.out_off[ob.unit_first];
-    const V* sv = static_cast<const V*>(a.stg_val);
-    V* dv = static_cast<V*>(ob.val);
-    for (int64_t x = lane(); x < n; x += WAVE) {
-        ob.col[dst + x] = a.stg_col[src + x];
-        dv[dst + x] = sv[src + x];
+    const int64_t first = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t u = first; u < a.U; u += (int64_t)gridDim.x * 4) {
+        const OutBind& ob = a.outs ? a.outs[a.unit_prob[u]] : a.one;
+        const int64_t src = a.stg_off[u], n = a.out_off[u + 1] - a.out_off[u];
+        const int64_t dst = a.out_off[u] - a.out_off[ob.unit_first];
+        const V* sv = static_cast<const V*>(a.stg_val);
+        V* dv = static_cast<V*>(ob.val);
+        for (int64_t x = lane(); x < n; x += WAVE) {
+            ob.col[dst + x] = a.stg_col[src + x];
+            dv[dst + x] = sv[src + x];
+        }
     }
 }
 
@@ -1385,6 +1651,9 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
 // among the group's (scalar) offsets and reads from that unit's staging run.
 constexpr int CG = 4;
 
+template <typename V>
+__device__ __forceinline__ void compact_group(const CompactArgs& a, int64_t grp);
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
@@ -1393,9 +1662,13 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
 
 template <typename V>
 __global__ __launch_bounds__(256) void k_compact_group(CompactArgs a) {
-    const int64_t grp = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int64_t first = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t grp = first; grp * CG < a.U; grp += (int64_t)gridDim.x * 4) compact_group<V>(a, grp);
+}
+
+template <typename V>
+__device__ __forceinline__ void compact_group(const CompactArgs& a, int64_t grp) {
     const int64_t u0 = grp * CG;
-    if (u0 >= a.U) return;
     const int nk = (int)min((int64_t)CG, a.U - u0);
     const int l = lane();
     const int64_t oo = l <= nk ? a.out_off[u0 + l] : 0;
@@ -1423,7 +1696,7 @@ __global__ __launch_bounds__(256) void k_compact_group(CompactArgs a) {
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
     if (a.U <= 0) return hipSuccess;
     if (!a.outs) {
-        const dim3 g(grid_for(a.U, 4 * CG, INT32_MAX));
+        const dim3 g(grid_for(a.U, 4 * CG, int64_t(1) << 20));
         switch (a.val_bytes) {
         case 1: MSP_LAUNCH(k_compact_group<uint8_t>, g, dim3(256), 0, s, a); break;
         case 4: MSP_LAUNCH(k_compact_group<uint32_t>, g, dim3(256), 0, s, a); break;
@@ -1432,7 +1705,7 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
         }
         return hipGetLastError();
     }
-    const dim3 grid(grid_for(a.U, 4, INT32_MAX));
+    const dim3 grid(grid_for(a.U, 4, int64_t(1) << 20));
     switch (a.val_bytes) {
     case 1: MSP_LAUNCH(k_compact<uint8_t>, grid, dim3(256), 0, s, a); break;
     case 4: MSP_LAUNCH(k_compact<uint32_t>, grid, dim3(256), 0, s, a); break;
@@ -1486,13 +1759,14 @@ __global__ __launch_bounds__(256) void k_tscatter(const int64_t* __restrict__ rp
                                                   const uint8_t* __restrict__ v, int vb, int64_t nrows,
                                                   const int64_t* __restrict__ trp, unsigned long long* cursor,
                                                   int32_t* __restrict__ tci, uint8_t* __restrict__ tv) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (r >= nrows) return;
-    for (int64_t p = rp[r] + lane(); p < rp[r + 1]; p += WAVE) {
-        const int32_t c = ci[p];
-        const int64_t pos = trp[c] + (int64_t)atomicAdd(&cursor[c], 1ull);
-        tci[pos] = (int32_t)r;
-        for (int b = 0; b < vb; ++b) tv[pos * vb + b] = v[p * vb + b];
+    const int64_t first = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t r = first; r < nrows; r += (int64_t)gridDim.x * 4) {
+        for (int64_t p = rp[r] + lane(); p < rp[r + 1]; p += WAVE) {
+            const int32_t c = ci[p];
+            const int64_t pos = trp[c] + (int64_t)atomicAdd(&cursor[c], 1ull);
+            tci[pos] = (int32_t)r;
+            for (int b = 0; b < vb; ++b) tv[pos * vb + b] = v[p * vb + b];
+        }
     }
 }
 
@@ -1500,7 +1774,7 @@ hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const 
                                     int64_t nrows, const int64_t* trp, unsigned long long* cursor, int32_t* tci,
                                     void* tv, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;
-    MSP_LAUNCH(k_tscatter, dim3(grid_for(nrows, 4, INT32_MAX)), dim3(256), 0, s, rp, ci,
+    MSP_LAUNCH(k_tscatter, dim3(grid_for(nrows, 4, int64_t(1) << 20)), dim3(256), 0, s, rp, ci,
                        static_cast<const uint8_t*>(v), v ? val_bytes : 0, nrows, trp, cursor, tci,
                        static_cast<uint8_t*>(tv));
     return hipGetLastError();

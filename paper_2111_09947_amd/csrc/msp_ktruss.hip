@@ -30,12 +30,13 @@ constexpr int KT_T = 256;
 __global__ __launch_bounds__(KT_T) void k_prune_count(int64_t n, const int64_t* __restrict__ rp,
                                                       const int64_t* __restrict__ v, int64_t thresh,
                                                       int64_t* __restrict__ cnt) {
-    const int64_t r = (int64_t)blockIdx.x * (KT_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (r >= n) return;
-    int64_t c = 0;
-    for (int64_t x = rp[r] + lane(); x < rp[r + 1]; x += WAVE) c += v[x] >= thresh ? 1 : 0;
-    c = wave_sum(c);
-    if (lane() == 0) cnt[r] = c;
+    const int64_t first = (int64_t)blockIdx.x * (KT_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (KT_T / WAVE)) {
+        int64_t c = 0;
+        for (int64_t x = rp[r] + lane(); x < rp[r + 1]; x += WAVE) c += v[x] >= thresh ? 1 : 0;
+        c = wave_sum(c);
+        if (lane() == 0) cnt[r] = c;
+    }
 }
 
 // copies the kept entries of every row, in order, to out_rp[r]
@@ -43,22 +44,26 @@ __global__ __launch_bounds__(KT_T) void k_prune_copy(int64_t n, const int64_t* _
                                                      const int32_t* __restrict__ ci, const int64_t* __restrict__ v,
                                                      int64_t thresh, const int64_t* __restrict__ out_rp,
                                                      int32_t* __restrict__ out_ci, int64_t* __restrict__ out_v) {
-    const int64_t r = (int64_t)blockIdx.x * (KT_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (r >= n) return;
-    int64_t pos = out_rp[r];
-    for (int64_t base = rp[r]; base < rp[r + 1]; base += WAVE) {
-        const int64_t x = base + lane();
-        const bool keep = x < rp[r + 1] && v[x] >= thresh;
-        const uint64_t m = __ballot(keep);
-        if (keep) {
-            out_ci[pos + rank_below(m)] = ci[x];
-            out_v[pos + rank_below(m)] = v[x];
+    const int64_t first = (int64_t)blockIdx.x * (KT_T / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (KT_T / WAVE)) {
+        int64_t pos = out_rp[r];
+        for (int64_t base = rp[r]; base < rp[r + 1]; base += WAVE) {
+            const int64_t x = base + lane();
+            const bool keep = x < rp[r + 1] && v[x] >= thresh;
+            const uint64_t m = __ballot(keep);
+            if (keep) {
+                out_ci[pos + rank_below(m)] = ci[x];
+                out_v[pos + rank_below(m)] = v[x];
+            }
+            pos += __popcll(m);
         }
-        pos += __popcll(m);
     }
 }
 
-unsigned kt_blocks(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+// rows are looped over, so the grid is capped (far below 2^32 work-items)
+unsigned kt_blocks(int64_t n, int per) {
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + per - 1) / per), int64_t(1) << 20);
+}
 
 #define KT_HIP(expr)                                                                    \
     do {                                                                                \

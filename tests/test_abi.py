@@ -43,6 +43,7 @@ def test_host_only_calls():
     o = L.MspOptions()
     lib.msp_options_default(ctypes.byref(o))
     assert (o.phase, o.force_kind, o.validate, o.inner_ratio) == (1, -1, 0, 0)
+    assert (o.maskidx_max, o.heap_flops, o.block_flops, o.split_flops) == (-1, -1, -1, -1)
 
 
 def _csr(L, nrows, ncols, nnz=0, rowptr=1):
@@ -71,6 +72,11 @@ def test_argument_errors_need_no_gpu():
         st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 1, 0,
                                  ctypes.byref(o), None)
         assert st == 4
+    # unknown kind
+    o.force_kind = 5
+    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 0, 0,
+                             ctypes.byref(o), None)
+    assert st == 1 and b"force_kind" in lib.msp_last_error()
     # bad phase
     o.force_kind = -1
     o.phase = 3

@@ -69,6 +69,23 @@ def test_complement_heavy_wide():
     run_and_check(A, B, M, True, "lor_land_bool", phase=2)
 
 
+def test_more_units_than_one_dispatch_holds():
+    """A complemented mask over 2^20 columns in the dense kind cuts every row
+    into 256 column tiles, one 256-lane workgroup each: ~22M units, more
+    than 2^32 work-items, so the bin runs as several launches over slices of
+    its unit list (a single dispatch would silently leave units out)."""
+    A = mspgen.er(120000, 120000, 2.0, 201, "i32")
+    B = mspgen.er(120000, 1 << 20, 1.0, 202, "i32")
+    M = mspgen.er(120000, 1 << 20, 4.0, 203, None)
+    R = oracle.masked_spgemm(A, B, M, True, "plus_times_i32")
+    for phase in (1, 2):
+        with msp().Plan(up(A, "plus_times_i32"), up(B, "plus_times_i32"), up(M), True, "plus_times_i32",
+                        phase=phase, force_kind="dense") as p:
+            assert p.bin_units["dense_block"] * 256 > 1 << 32
+            C = p.execute()
+        assert_same(C, R, "plus_times_i32")
+
+
 def _empty(m, n):
     return mspgen.CSR(m, n, np.zeros(m + 1, np.int64), np.zeros(0, np.int32))
 
