@@ -163,10 +163,13 @@ typedef struct msp_options {
                              row with at least 8 entries per product, or, under
                              a complemented mask with more than 4096 columns,
                              whatever their product count (-1 = default 32;
-                             0 = never). An automatic heap bin of at most 32768
-                             rows whose mask rows (normal) hold at most 256
-                             entries runs in the MASKIDX wave kernel instead:
-                             a small heap launch costs more than it saves. */
+                             0 = never). An automatic heap bin runs in the
+                             MASKIDX wave kernel instead when it has at most
+                             32768 rows, all with normal mask rows of at most
+                             256 entries, or in the MASKIDX block kernel when
+                             it has at most 4096 rows, all with normal mask
+                             rows of 257 to 4096 entries: a small heap launch
+                             costs more than it saves. */
     int64_t block_flops;  /* rows with more products than this run on a whole
                              256-thread workgroup instead of one wavefront
                              (-1 = default 8192) */
@@ -211,7 +214,8 @@ enum {
     MSP_BIN_DENSE_SPLIT = 8,         /* rows with many products: one workgroup per chunk of the
                                         row of A, merged into a per-row accumulator */
     MSP_BIN_HEAP_LANE = 9,           /* one lane per row, k-way merge (HEAP kind) */
-    MSP_NBINS = 10
+    MSP_BIN_HEAP_LANE_LONG_MASK = 10,  /* the same, normal mask rows of more than 256 entries */
+    MSP_NBINS = 11
 };
 
 /* Stage slots of msp_execute_profiled: 0..15 = numeric kernel of bin b,

@@ -127,7 +127,8 @@ struct msp_plan {
     // units (global)
     int64_t bin_count[NBINS] = {};
     int64_t bin_off[NBINS + 1] = {};
-    bool heap_fold = false;  // the heap units run in the mask-indexed wave kernel's launch
+    bool heap_fold = false;     // BIN_HEAP_L units run in the mask-indexed wave kernel's launch
+    bool heap_lm_fold = false;  // BIN_HEAP_LM units run in the mask-indexed block kernel's launch
     int64_t seg_off[NBINS * NBUCKET] = {};
     int64_t* seg_off_d = nullptr;
     int64_t* icost = nullptr;
@@ -474,7 +475,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
 
     // totals; bins in order, inside a bin the flops buckets from the heaviest down
     std::vector<int64_t> segc(NBINS * NBUCKET, 0);
-    int64_t heap_apart = 0;
+    int64_t heap_apart = 0, heap_lm_apart = 0;
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
         const unsigned long long* st = &P->stats[(size_t)(p * ST_COUNT)];
@@ -496,6 +497,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         P->ub += pr.ub;
         P->nsplit += (int64_t)st[ST_SPLITROWS];
         heap_apart += (int64_t)st[ST_HEAP_APART];
+        heap_lm_apart += (int64_t)st[ST_HEAPLM_APART];
     }
     int64_t run = 0;
     for (int x = 0; x < NBINS; ++x) {  // the layout of the unit list (the device computed the same)
@@ -511,6 +513,8 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     if (run != P->U) return fail(MSP_ERR_DEVICE, "inconsistent unit statistics");
     P->heap_fold = o.force_kind == MSP_KIND_AUTO && P->bin_count[BIN_HEAP_L] > 0 &&
                    P->bin_count[BIN_HEAP_L] <= HEAP_FOLD_MAX && heap_apart == 0;
+    P->heap_lm_fold = o.force_kind == MSP_KIND_AUTO && P->bin_count[BIN_HEAP_LM] > 0 &&
+                      P->bin_count[BIN_HEAP_LM] <= HEAP_LM_FOLD_MAX && heap_lm_apart == 0;
     if (P->U >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many work units");
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
@@ -719,16 +723,18 @@ struct StageTimer {
 };
 
 // Numeric kernels of every non-empty bin, in bin order on `s`, in `mode`,
-// with `a` giving the outputs. A folded heap bin (heap_fold) runs as part of
-// the mask-indexed wave launch: its units directly follow that bin's.
+// with `a` giving the outputs. A folded heap bin runs as part of its
+// mask-indexed neighbour's launch: BIN_HEAP_L's units directly follow the
+// wave bin's, BIN_HEAP_LM's directly precede the block bin's.
 static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream_t s, StageTimer* tm) {
     for (int b = 0; b < NBINS; ++b) {
-        const bool fold_in = P->heap_fold && b == BIN_MASKIDX_W;
-        if (P->heap_fold && b == BIN_HEAP_L) continue;
-        if (!P->bin_count[b] && !fold_in) continue;
+        if ((P->heap_fold && b == BIN_HEAP_L) || (P->heap_lm_fold && b == BIN_HEAP_LM)) continue;
+        const int64_t after = P->heap_fold && b == BIN_MASKIDX_W ? P->bin_count[BIN_HEAP_L] : 0;
+        const int64_t before = P->heap_lm_fold && b == BIN_MASKIDX_B ? P->bin_count[BIN_HEAP_LM] : 0;
+        if (!P->bin_count[b] && !after && !before) continue;
         NumArgs ab = a;
-        ab.units = P->bin_units + P->bin_off[b];  // a folded heap bin starts where this one ends
-        ab.nunits = P->bin_count[b] + (fold_in ? P->bin_count[BIN_HEAP_L] : 0);
+        ab.units = P->bin_units + P->bin_off[b] - before;
+        ab.nunits = P->bin_count[b] + after + before;
         if (tm) MSP_CHECK(tm->begin(b));
         MSP_HIP(launch_numeric(P->sr, b, mode, ab, s));
         if (tm) MSP_CHECK(tm->end());
@@ -975,7 +981,7 @@ msp_status msp_batch_info(const msp_plan* P, int64_t p, msp_plan_info_t* info) {
         info->kind_units[MSP_KIND_HASH] += pr.bin_units[BIN_HASH_W] + pr.bin_units[BIN_HASH_B];
         info->kind_units[MSP_KIND_MASKIDX] += pr.bin_units[BIN_MASKIDX_W] + pr.bin_units[BIN_MASKIDX_B];
         info->kind_units[MSP_KIND_INNER] += pr.bin_units[BIN_INNER_W];
-        info->kind_units[MSP_KIND_HEAP] += pr.bin_units[BIN_HEAP_L];
+        info->kind_units[MSP_KIND_HEAP] += pr.bin_units[BIN_HEAP_L] + pr.bin_units[BIN_HEAP_LM];
         for (int b = 0; b < NBINS; ++b) info->bin_units[b] += pr.bin_units[b];
     }
     return MSP_OK;

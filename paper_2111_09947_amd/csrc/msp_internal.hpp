@@ -23,7 +23,9 @@ enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_DENSE_SPLIT = 8,  // one block per chunk of A's row, dense state over <= DENSE_B_COLS
                           // columns, merged into a per-row accumulator in global memory
     BIN_HEAP_L = 9,     // one lane per row, k-way merge of <= HEAP_CAP rows of B by a heap in LDS
-    NBINS = 10
+                        // (normal masks of <= MASKIDX_W_CAP entries, and complemented masks)
+    BIN_HEAP_LM = 10,   // the same for normal masks of more than MASKIDX_W_CAP entries
+    NBINS = 11
 };
 
 constexpr int DENSE_W_COLS = 512;
@@ -38,19 +40,27 @@ constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 constexpr int HEAP_CAP = 8;       // heap kind: iterators per row (entries of the row of A)
 constexpr int64_t HEAP_MAX_FLOPS = (int64_t(1) << 24) - 1;  // heap keys hold a B row's remaining length in 24 bits
 constexpr int64_t HEAP_LONG_MASK_RATIO = 8;  // auto HEAP also when the mask row has >= this many entries per product
-constexpr int64_t HEAP_LONG_MASK_FLOPS = 8;  // ... and the row has at most this many times heap_flops products
-// A heap bin of at most this many units, all of them rows the mask-indexed
-// wave kernel can take (normal mask, at most MASKIDX_W_CAP mask entries, the
-// same staging), runs in that kernel's launch instead of a launch of its own:
-// a small heap launch costs its latency-bound tail (a lane walks its row
-// serially) and saves less than that.
+constexpr int64_t HEAP_LONG_MASK_FLOPS = 2;  // ... and the row has at most this many times heap_flops products
+// An automatic heap bin of at most this many units, all of them rows that the
+// neighbouring mask-indexed kernel can take with the same staging (BIN_HEAP_L:
+// the wave kernel, normal masks of at most MASKIDX_W_CAP entries; BIN_HEAP_LM:
+// the block kernel, at most MASKIDX_B_CAP entries, one tile), runs in that
+// kernel's launch instead of a launch of its own: a small heap launch costs
+// its latency-bound tail (a lane walks its row serially, a long mask row
+// costs a binary search per product) and saves less than that. The block
+// kernel spends time per mask entry, so long-mask bins fold only when small.
 constexpr int64_t HEAP_FOLD_MAX = 32768;
+constexpr int64_t HEAP_LM_FOLD_MAX = 4096;
 
 // Position x of the unit list holds the units of bin bin_at(x): the bins in
-// numeric order, except that the heap bin comes right after the mask-indexed
-// wave bin, so the two form one contiguous range of units.
+// numeric order, except that the two heap bins sit between the mask-indexed
+// wave and block bins (wave, heap, heap with long masks, block), so that each
+// heap bin and its mask-indexed neighbour form one contiguous range of units.
 __host__ __device__ inline int bin_at(int x) {
-    return x <= BIN_MASKIDX_W ? x : (x == BIN_MASKIDX_W + 1 ? (int)BIN_HEAP_L : x - 1);
+    return x <= BIN_MASKIDX_W ? x
+           : x == BIN_MASKIDX_W + 1 ? (int)BIN_HEAP_L
+           : x == BIN_MASKIDX_W + 2 ? (int)BIN_HEAP_LM
+           : x - 2;
 }
 constexpr int DEFAULT_MASKIDX_MAX = 8;       // auto: binary search up to this mask size, hash above
 constexpr int64_t DEFAULT_BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
@@ -72,8 +82,9 @@ enum Stat : int {
     ST_BIN0 = 6,                 // ST_BIN0 + b * NBUCKET + bucket: units of bin b in a flops bucket
     ST_ERROR = ST_BIN0 + NBINS * NBUCKET,  // nonzero: invalid CSR found by validation
     ST_SPLITROWS = ST_ERROR + 1,           // rows split over several blocks
-    ST_HEAP_APART = ST_SPLITROWS + 1,      // heap rows the mask-indexed wave kernel cannot take
-    ST_COUNT = ST_HEAP_APART + 1
+    ST_HEAP_APART = ST_SPLITROWS + 1,      // BIN_HEAP_L rows the mask-indexed wave kernel cannot take
+    ST_HEAPLM_APART = ST_HEAP_APART + 1,   // BIN_HEAP_LM rows the mask-indexed block kernel cannot take
+    ST_COUNT = ST_HEAPLM_APART + 1
 };
 
 enum Mode : int { MODE_COUNT = 0, MODE_STAGE = 1, MODE_DIRECT = 2 };

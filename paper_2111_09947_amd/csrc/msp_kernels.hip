@@ -266,7 +266,7 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
         else { bin = BIN_MASKIDX_B; tiles = cdiv(mnnz, MASKIDX_B_CAP); }
         break;
     case MSP_KIND_HEAP:
-        bin = BIN_HEAP_L; tiles = 1;
+        bin = !comp && mnnz > MASKIDX_W_CAP ? BIN_HEAP_LM : BIN_HEAP_L; tiles = 1;
         break;
     default:
         bin = BIN_INNER_W; tiles = cdiv(mnnz, INNER_CAP);
@@ -295,7 +295,7 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
         adm = o.complement ? (c1 - c0) - mt : mt;
         break;
     }
-    case BIN_HEAP_L: adm = o.complement ? o.n - mnnz : mnnz; break;
+    case BIN_HEAP_L: case BIN_HEAP_LM: adm = o.complement ? o.n - mnnz : mnnz; break;
     case BIN_HASH_W: case BIN_MASKIDX_W: adm = mnnz; break;
     case BIN_HASH_B: adm = min((int64_t)HASH_B_CAP, mnnz - t * HASH_B_CAP); break;
     case BIN_MASKIDX_B: adm = min((int64_t)MASKIDX_B_CAP, mnnz - t * MASKIDX_B_CAP); break;
@@ -326,7 +326,8 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
             classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
                      a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost, bin, tiles);
             if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
-            if (bin == BIN_HEAP_L && (o.complement || mnnz > MASKIDX_W_CAP)) atomicAdd(&sst[ST_HEAP_APART], 1ull);
+            if (bin == BIN_HEAP_L && o.complement) atomicAdd(&sst[ST_HEAP_APART], 1ull);
+            if (bin == BIN_HEAP_LM && mnnz > MASKIDX_B_CAP) atomicAdd(&sst[ST_HEAPLM_APART], 1ull);
             for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
             seg = bin * NBUCKET + flops_bucket(flops);
         }
@@ -1521,7 +1522,7 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
     case BIN_DENSE_SPLIT:
         MSP_LAUNCH((k_dense_split<SR, MODE, BATCH>), gb, bb, 0, s, a);
         break;
-    case BIN_HEAP_L:
+    case BIN_HEAP_L: case BIN_HEAP_LM:
         MSP_LAUNCH((k_heap<SR, MODE, BATCH>), dim3((unsigned)((a.nunits + HEAP_T - 1) / HEAP_T)), dim3(HEAP_T), 0,
                    s, a);
         break;

@@ -48,6 +48,7 @@ def run_plan(A, B, M, comp, sr, **kw):
     with m.Plan(up(A, sr), up(B, sr), up(M), comp, sr, **kw) as p:
         C = p.execute()
         bins = dict(p.bin_units)
+        bins["heap"] = bins["heap_lane"] + bins["heap_lane_long_mask"]  # both heap bins
         kinds = dict(p.kind_units)
     R = oracle.masked_spgemm(A, B, M, comp, sr)
     return C, R, bins, kinds
@@ -83,7 +84,7 @@ def test_forced_heap(shape, sr, comp, phase):
     C, R, bins, kinds = run_plan(A, B, M, comp, sr, force_kind="heap", phase=phase)
     check_exact(C, R, sr)
     units = rows_with_output_bound(A, B, M, comp)
-    assert bins["heap_lane"] == units and kinds["heap"] == units
+    assert bins["heap"] == units and kinds["heap"] == units
 
 
 def test_rows_too_long_for_the_heap_take_the_automatic_choice():
@@ -96,7 +97,7 @@ def test_rows_too_long_for_the_heap_take_the_automatic_choice():
     for comp in (False, True):
         C, R, bins, _ = run_plan(A, B, M, comp, sr, force_kind="heap")
         assert_same(C, R, sr)
-        assert 0 < bins["heap_lane"] < rows_with_output_bound(A, B, M, comp)
+        assert 0 < bins["heap"] < rows_with_output_bound(A, B, M, comp)
 
 
 def test_equal_columns_from_every_iterator():
@@ -114,7 +115,7 @@ def test_equal_columns_from_every_iterator():
         for phase in (1, 2):
             C, R, bins, _ = run_plan(A, B, M, comp, sr, force_kind="heap", phase=phase)
             check_exact(C, R, sr)
-            assert bins["heap_lane"] == rows_with_output_bound(A, B, M, comp)
+            assert bins["heap"] == rows_with_output_bound(A, B, M, comp)
 
 
 def test_explicit_zeros_and_wraparound_in_heap():
@@ -145,15 +146,15 @@ def test_auto_picks_heap_for_light_rows():
     M = mspgen.er(3000, 3000, 64.0, 93, None)
     C, R, bins, _ = run_plan(A, B, M, False, sr)
     assert_same(C, R, sr)
-    assert bins["heap_lane"] > 1000
+    assert bins["heap"] > 1000
     C0, _, bins0, _ = run_plan(A, B, M, False, sr, heap_flops=0)
     assert_same(C0, R, sr)
-    assert bins0["heap_lane"] == 0
+    assert bins0["heap"] == 0
     # light rows under a complemented mask
     Mc = mspgen.er(3000, 3000, 10.0, 94, None)
     C, R, bins, _ = run_plan(A, B, Mc, True, sr)
     assert_same(C, R, sr)
-    assert bins["heap_lane"] > 1000
+    assert bins["heap"] > 1000
     # a complemented mask wider than one 4096-column dense tile: every fitting row, however
     # many products it has
     A2 = clip_rows(mspgen.er(2000, 500, 4.0, 95, "f64"), HEAP_CAP)
@@ -161,23 +162,26 @@ def test_auto_picks_heap_for_light_rows():
     M2 = mspgen.er(2000, 10000, 50.0, 97, None)
     C, R, bins, _ = run_plan(A2, B2, M2, True, sr)
     assert_same(C, R, sr)
-    assert bins["heap_lane"] == rows_with_output_bound(A2, B2, M2, True)
+    assert bins["heap"] == rows_with_output_bound(A2, B2, M2, True)
 
 
-def test_auto_heap_small_and_large_bins():
-    """A small automatic heap bin (at most 32768 units, normal mask, mask rows
-    of at most 256 entries) runs inside the mask-indexed wave kernel's launch;
-    a large one runs in the heap kernel. Both agree with the oracle, across
-    semirings and phases."""
-    for n, sr in ((5000, "plus_times_f64"), (120000, "plus_times_f64"), (120000, "plus_times_i32"),
-                  (120000, "lor_land_bool")):
-        A = mspgen.er(n, n, 1.2, 301, VKIND[sr])
-        B = mspgen.er(n, n, 1.2, 302, VKIND[sr])
-        M = mspgen.er(n, n, 24.0, 303, None)
-        for phase in (1, 2):
-            C, R, bins, _ = run_plan(A, B, M, False, sr, phase=phase)
-            assert_same(C, R, sr)
-            assert (bins["heap_lane"] > 32768) == (n > 100000)
+@pytest.mark.parametrize("n,sr,dm", [(5000, "plus_times_f64", 24.0), (120000, "plus_times_f64", 24.0),
+                                     (120000, "plus_times_i32", 24.0), (120000, "lor_land_bool", 24.0),
+                                     (5000, "plus_times_f64", 400.0), (40000, "plus_times_i64", 400.0)])
+def test_auto_heap_small_and_large_bins(n, sr, dm):
+    """A small automatic heap bin (normal mask) runs inside the launch of its
+    mask-indexed neighbour: the wave kernel for mask rows of at most 256
+    entries (bins of at most 32768 units), the block kernel for longer ones
+    (at most 4096 units); a larger one runs in the heap kernel. Both agree
+    with the oracle in both phases."""
+    A = mspgen.er(n, n, 1.2, 301, VKIND[sr])
+    B = mspgen.er(n, n, 1.2, 302, VKIND[sr])
+    M = mspgen.er(n, n, dm, 303, None)
+    for phase in (1, 2):
+        C, R, bins, _ = run_plan(A, B, M, False, sr, phase=phase)
+        assert_same(C, R, sr)
+        key = "heap_lane_long_mask" if dm > 256 else "heap_lane"
+        assert bins[key] == bins["heap"] and (bins["heap"] > (4096 if dm > 256 else 32768)) == (n > 10000)
 
 
 def test_triangle_counting_heap():
@@ -186,7 +190,7 @@ def test_triangle_counting_heap():
     for phase in (1, 2):
         C, _, bins, _ = run_plan(L, L, L, False, "plus_pair_i64", force_kind="heap", phase=phase)
         assert_same(C, R, "plus_pair_i64")
-        assert bins["heap_lane"] > 0
+        assert bins["heap"] > 0
 
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_i32", "lor_land_bool"])
@@ -203,7 +207,7 @@ def test_heap_in_batch(sr):
     with m.Batch(dev, semiring=sr, force_kind="heap") as b:
         b.bind_new_outputs()
         b.execute()
-        assert b.bin_units["heap_lane"] > 0
+        assert b.bin_units["heap_lane"] + b.bin_units["heap_lane_long_mask"] > 0
         for (A, B, M, c), C, d in zip(probs, b.results(), dev):
             check_exact(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
             single = m.masked_spgemm(d[0], d[1], d[2], complement=c, semiring=sr, force_kind="heap")
