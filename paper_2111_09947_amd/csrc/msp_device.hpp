@@ -95,6 +95,13 @@ __device__ __forceinline__ int64_t lower_bound_g(const int32_t* __restrict__ a, 
 // IEEE addition, so an atomic add of the first product returns it exactly.
 template <int SR> struct SRT;
 
+// A value in global memory at a byte address (kept in the global address
+// space, so that the load is a global rather than a flat one).
+template <class V>
+__device__ __forceinline__ V gload(uint64_t addr) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) V*>(addr);
+}
+
 template <> struct SRT<MSP_PLUS_TIMES_F64> {
     using in_t = double;
     using acc_t = double;
@@ -105,6 +112,8 @@ template <> struct SRT<MSP_PLUS_TIMES_F64> {
     __device__ static in_t load(const void* v, int64_t p) {
         return v ? static_cast<const double*>(v)[p] : 1.0;
     }
+    static constexpr int vbytes = 8;  // width of a stored value
+    __device__ static in_t load_at(uint64_t addr) { return gload<double>(addr); }
     __device__ static acc_t identity() { return -0.0; }
     // each product and each sum is rounded on its own: no fused multiply-add
     // is formed across term() and add()
@@ -130,6 +139,8 @@ template <> struct SRT<MSP_PLUS_PAIR_I64> {
     static constexpr bool sep_flag = false;
     __device__ static in_t one() { return 1; }
     __device__ static in_t load(const void*, int64_t) { return 1; }
+    static constexpr int vbytes = 4;
+    __device__ static in_t load_at(uint64_t) { return 1; }
     __device__ static acc_t identity() { return 0ull; }
     __device__ static acc_t term(in_t, in_t) { return 1ull; }
     __device__ static void lds_add(acc_t* slot, acc_t) { atomicAdd(slot, 1ull); }
@@ -151,6 +162,8 @@ template <> struct SRT<MSP_LOR_LAND_BOOL> {
     __device__ static in_t load(const void* v, int64_t p) {
         return v ? (uint32_t)static_cast<const uint8_t*>(v)[p] : 1u;
     }
+    static constexpr int vbytes = 1;
+    __device__ static in_t load_at(uint64_t addr) { return (uint32_t)gload<uint8_t>(addr); }
     __device__ static acc_t identity() { return 0u; }
     __device__ static acc_t term(in_t a, in_t b) { return 2u | (uint32_t)((a != 0u) & (b != 0u)); }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicOr(slot, t); }
@@ -170,6 +183,8 @@ template <> struct SRT<MSP_PLUS_TIMES_I32> {
     __device__ static in_t load(const void* v, int64_t p) {
         return v ? (uint32_t)static_cast<const int32_t*>(v)[p] : 1u;
     }
+    static constexpr int vbytes = 4;
+    __device__ static in_t load_at(uint64_t addr) { return gload<uint32_t>(addr); }
     __device__ static acc_t identity() { return 0ull; }
     __device__ static acc_t term(in_t a, in_t b) { return (1ull << 32) | (unsigned long long)(a * b); }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicAdd(slot, t); }
@@ -189,6 +204,8 @@ template <> struct SRT<MSP_PLUS_TIMES_I64> {
     __device__ static in_t load(const void* v, int64_t p) {
         return v ? (unsigned long long)static_cast<const int64_t*>(v)[p] : 1ull;
     }
+    static constexpr int vbytes = 8;
+    __device__ static in_t load_at(uint64_t addr) { return gload<unsigned long long>(addr); }
     __device__ static acc_t identity() { return 0ull; }
     __device__ static acc_t term(in_t a, in_t b) { return a * b; }
     __device__ static void lds_add(acc_t* slot, acc_t t) { atomicAdd(slot, t); }

@@ -581,6 +581,22 @@ constexpr int STREAM_U = MSP_STREAM_U;
 // address space, so the loads stay global rather than flat).
 typedef __attribute__((address_space(1))) const int32_t gint32_t;
 
+// B's values are parallel to its column indices: the value of the product
+// whose column index sits at byte address cb is at Bv + (cb - Bci) / 4 * w
+// for values of w bytes. With a per-operand constant this is one shift-add.
+template <int W>
+struct ValAddr {
+    uint64_t d;
+    __device__ ValAddr(const void* Bv, const int32_t* Bci)
+        : d(W == 8 ? (uint64_t)Bv - 2ull * (uint64_t)Bci
+            : W == 4 ? (uint64_t)Bv - (uint64_t)Bci
+                     : (uint64_t)Bv - ((uint64_t)Bci >> 2)) {}
+    __device__ uint64_t at(uint64_t cb) const {
+        static_assert(W == 8 || W == 4 || W == 1, "value widths 1, 4 or 8");
+        return (W == 8 ? cb << 1 : W == 4 ? cb : cb >> 2) + d;  // Bci and cb are 4-byte aligned
+    }
+};
+
 // Per-wave LDS for one batch of up to 64 A entries: for the s-th stanza with
 // a nonzero length (in A order), its start in the flattened product
 // sequence, the shift from flattened position to B position, and A's value;
@@ -596,10 +612,10 @@ struct StanzaLds {
 
 // Streams every product (k, j) of the A entries [pa0, pa1) of one row: for each stored A(i,k) and each
 // stored B(k,j) with lo <= j <= hi (when `window`). The products reach the
-// caller one window at a time: f(j, s, q, act) gets STREAM_U products per
-// lane, where for slot u, q[u] is the position of B(k,j), j[u] its column and
-// s[u] indexes st.a for A(i,k); slots past the last product have act[u] ==
-// false and meaningless j, s, q. Handing over a whole window lets the caller
+// caller one window at a time: f(j, s, cb, act) gets STREAM_U products per
+// lane, where for slot u, cb[u] is the byte address of B(k,j)'s column index,
+// j[u] the column and s[u] indexes st.a for A(i,k); slots past the last
+// product have act[u] == false and meaningless j, s, cb. Handing over a whole window lets the caller
 // issue the LDS (and value) reads of all its slots before waiting for any.
 // Wave `wv` of `nw` waves processes the windows wv, wv + nw, ... of
 // 64 * STREAM_U products of each batch; batch_end() runs after the last
@@ -680,10 +696,9 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
             const gint32_t* bp[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) bp[u] = reinterpret_cast<const gint32_t*>(st.ptr[sidx[u]] + pos4);
-            int64_t q[STREAM_U];
+            uint64_t cb[STREAM_U];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u)
-                q[u] = (int64_t)(((uint64_t)(bp[u] + u * WAVE) - (uint64_t)o.Bci) >> 2);
+            for (int u = 0; u < STREAM_U; ++u) cb[u] = (uint64_t)(bp[u] + u * WAVE);
             // a full window (every slot holds a product) and the batch's last, partial one take
             // separate straight-line copies of the window's work
             auto run = [&](auto full) {
@@ -694,7 +709,7 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
                 int32_t j[STREAM_U];
 #pragma unroll
                 for (int u = 0; u < STREAM_U; ++u) j[u] = (FULL || act[u]) ? bp[u][u * WAVE] : 0;
-                f(j, sidx, q, act);
+                f(j, sidx, cb, act);
             };
             if (lim == WIN) run(std::integral_constant<bool, true>{});
             else run(std::integral_constant<bool, false>{});
@@ -709,15 +724,18 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
 // u goes to vals[slot[u]] when hit[u]. B values are loaded only for admitted
 // products; all loads of the window are issued before the first LDS update.
 template <class T, bool FLAGS, bool COUNT>
-__device__ __forceinline__ void window_accumulate(const bool* hit, const int* slot, const int* s, const int64_t* q,
+__device__ __forceinline__ void window_accumulate(const bool* hit, const int* slot, const int* s, const uint64_t* cb,
                                                   const Operands& o, const StanzaLds<T>& st,
                                                   typename T::acc_t* vals, uint8_t* flags) {
     typename T::in_t b[STREAM_U], a[STREAM_U];
     if (!COUNT) {
 #pragma unroll
-        for (int u = 0; u < STREAM_U; ++u) {
-            b[u] = T::one();
-            if (T::needs_values && hit[u]) b[u] = T::load(o.Bv, q[u]);
+        for (int u = 0; u < STREAM_U; ++u) b[u] = T::one();
+        if (T::needs_values && o.Bv) {  // one uniform test per window (iso-valued B: all ones)
+            const ValAddr<T::vbytes> va(o.Bv, o.Bci);
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u)
+                if (hit[u]) b[u] = T::load_at(va.at(cb[u]));
         }
 #pragma unroll
         for (int u = 0; u < STREAM_U; ++u) a[u] = T::needs_values ? st.a[s[u]] : T::one();
@@ -829,7 +847,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
     unit_sync<NW>();
     StanzaLds<T>& S = st[wave];
     stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
-                       [&](const int32_t* j, const int* s, const int64_t* q, const bool* act) {
+                       [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
                            uint32_t w[STREAM_U];
                            bool hit[STREAM_U];
@@ -840,7 +858,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
                            }
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u) hit[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u);
-                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, q, o, S, vals, flags);
+                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, cb, o, S, vals, flags);
                        },
                        [] {});
     unit_sync<NW>();
@@ -908,7 +926,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
     const int64_t a0 = ra0 + min((int64_t)t * chunk, alen), a1 = ra0 + min((int64_t)(t + 1) * chunk, alen);
     StanzaLds<T>& S = st[wv];
     stream_products<T>(o, a0, a1, false, 0, 0, wv, NW, S,
-                       [&](const int32_t* j, const int* s, const int64_t* q, const bool* act) {
+                       [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
                            uint32_t w[STREAM_U];
                            bool hit[STREAM_U];
@@ -919,7 +937,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
                            }
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u) hit[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u);
-                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, q, o, S, vals, flags);
+                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, cb, o, S, vals, flags);
                        },
                        [] {});
     __syncthreads();
@@ -1052,7 +1070,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     __shared__ uint8_t flags_[WPB][FLAGS ? CAP : 1];
     __shared__ uint32_t filt_[WPB][FW];
     __shared__ int32_t qj_[WPB * NW][QCAP + WAVE];
-    __shared__ int64_t qq_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];
+    __shared__ uint64_t qq_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];  // column byte addresses
     __shared__ uint8_t qs_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
@@ -1068,7 +1086,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     uint8_t* flags = flags_[gi];
     uint32_t* filt = filt_[gi];
     int32_t* qj = qj_[wave];
-    int64_t* qq = qq_[QVAL ? wave : 0];
+    uint64_t* qq = qq_[QVAL ? wave : 0];
     uint8_t* qs = qs_[QVAL ? wave : 0];
     // the unit is the same for every lane of the wave
     const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
@@ -1111,6 +1129,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     const int32_t lo = keys[0], hi = keys[cnt - 1];
     const int top = 1 << (31 - __clz(cnt));
     StanzaLds<T>& S = st[wave];
+    const ValAddr<T::vbytes> va(o.Bv, o.Bci);
     // candidate ring of this wave: entries [qh, qn) (mod QCAP) wait for a lookup; qh, qn are wave-uniform
     uint32_t qh = 0, qn = 0;
     // looks up `count` <= 64 candidates starting at ring entry `base`, one per lane
@@ -1124,7 +1143,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
             if (!COUNT) {
                 typename T::in_t av = T::one(), bv = T::one();
                 if (QVAL) {
-                    bv = T::load(o.Bv, qq[e]);
+                    if (o.Bv) bv = T::load_at(va.at(qq[e]));
                     av = S.a[qs[e]];
                 }
                 T::lds_add(&vals[r], T::term(av, bv));
@@ -1133,7 +1152,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     };
     stream_products<T>(
         o, o.Arp[i], o.Arp[i + 1], tiled, lo, hi, wv, NW, S,
-        [&](const int32_t* j, const int* s, const int64_t* q, const bool* act) {
+        [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
             uint32_t w[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) w[u] = filt[__builtin_amdgcn_ubfe((uint32_t)j[u], 5, (uint32_t)fwb)];
@@ -1158,7 +1177,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
                 const int e = eb + (int)pass[u] * (ea - eb);
                 qj[e] = j[u];
                 if (QVAL) {
-                    qq[e] = q[u];
+                    qq[e] = cb[u];
                     qs[e] = (uint8_t)s[u];
                 }
                 cum += (uint32_t)__popcll(m[u]);
