@@ -721,13 +721,14 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
 }
 
 // Folds the admitted products of one window into the LDS accumulator: slot
-// u goes to vals[slot[u]] when hit[u]. B values are loaded only for admitted
-// products; all loads of the window are issued before the first LDS update.
+// u goes to vals[slot[u]] when slot[u] >= 0 (-1: not admitted). B values are
+// loaded only for admitted products; all loads of the window are issued
+// before the first LDS update.
 template <class T, bool FLAGS, bool COUNT>
-__device__ __forceinline__ void window_accumulate(const bool* hit, const int* slot, const int* s, const uint64_t* cb,
+__device__ __forceinline__ void window_accumulate(const int* slot, const int* s, const uint64_t* cb,
                                                   const Operands& o, const StanzaLds<T>& st,
                                                   typename T::acc_t* vals, uint8_t* flags) {
-    typename T::in_t b[STREAM_U], a[STREAM_U];
+    typename T::in_t b[STREAM_U];
     if (!COUNT) {
 #pragma unroll
         for (int u = 0; u < STREAM_U; ++u) b[u] = T::one();
@@ -735,16 +736,14 @@ __device__ __forceinline__ void window_accumulate(const bool* hit, const int* sl
             const ValAddr<T::vbytes> va(o.Bv, o.Bci);
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u)
-                if (hit[u]) b[u] = T::load_at(va.at(cb[u]));
+                if (slot[u] >= 0) b[u] = T::load_at(va.at(cb[u]));
         }
-#pragma unroll
-        for (int u = 0; u < STREAM_U; ++u) a[u] = T::needs_values ? st.a[s[u]] : T::one();
     }
 #pragma unroll
     for (int u = 0; u < STREAM_U; ++u) {
-        if (hit[u]) {
+        if (slot[u] >= 0) {
             if (FLAGS) flags[slot[u]] = 1;
-            if (!COUNT) T::lds_add(&vals[slot[u]], T::term(a[u], b[u]));
+            if (!COUNT) T::lds_add(&vals[slot[u]], T::term(T::needs_values ? st.a[s[u]] : T::one(), b[u]));
         }
     }
 }
@@ -850,15 +849,16 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
                        [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
                            uint32_t w[STREAM_U];
-                           bool hit[STREAM_U];
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u) {
                                c[u] = act[u] ? j[u] - (int)c0 : 0;  // column 0 of the tile always exists
                                w[u] = allowed[c[u] >> 5];
                            }
+                           // the tile column of an admitted product, -1 otherwise
 #pragma unroll
-                           for (int u = 0; u < STREAM_U; ++u) hit[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u);
-                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, cb, o, S, vals, flags);
+                           for (int u = 0; u < STREAM_U; ++u)
+                               c[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u) ? c[u] : -1;
+                           window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
                        },
                        [] {});
     unit_sync<NW>();
@@ -929,15 +929,15 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
                        [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
                            uint32_t w[STREAM_U];
-                           bool hit[STREAM_U];
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u) {
                                c[u] = act[u] ? j[u] : 0;
                                w[u] = allowed[c[u] >> 5];
                            }
 #pragma unroll
-                           for (int u = 0; u < STREAM_U; ++u) hit[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u);
-                           window_accumulate<T, FLAGS, COUNT>(hit, c, s, cb, o, S, vals, flags);
+                           for (int u = 0; u < STREAM_U; ++u)
+                               c[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u) ? c[u] : -1;
+                           window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
                        },
                        [] {});
     __syncthreads();
