@@ -820,9 +820,11 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
     const int u = __builtin_amdgcn_readfirstlane(g.units[uix]);
     const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
     const int64_t i = g.unit_row[u];
-    const int64_t c0 = (int64_t)g.unit_tile[u] * W;
+    // the one-wave-tile bins hold only rows of matrices with n <= DENSE_W_COLS: one tile at column 0
+    constexpr bool ONE_TILE = W == DENSE_W_COLS;
+    const int64_t c0 = ONE_TILE ? 0 : (int64_t)g.unit_tile[u] * W;
     const int wt = (int)min((int64_t)W, o.n - c0);
-    const bool tiled = o.n > W;
+    const bool tiled = !ONE_TILE && o.n > W;
     for (int x = ut; x < NWORDS; x += UT) {
         const int lo = x * 32;
         const uint32_t valid = (lo + 32 <= wt) ? 0xFFFFFFFFu : (lo >= wt ? 0u : ((1u << (wt - lo)) - 1u));
@@ -857,7 +859,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
                            // the tile column of an admitted product, -1 otherwise
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u)
-                               c[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u) ? c[u] : -1;
+                               c[u] = act[u] && __builtin_amdgcn_ubfe(w[u], (uint32_t)c[u], 1) ? c[u] : -1;
                            window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
                        },
                        [] {});
@@ -936,7 +938,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
                            }
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u)
-                               c[u] = act[u] && ((w[u] >> (c[u] & 31)) & 1u) ? c[u] : -1;
+                               c[u] = act[u] && __builtin_amdgcn_ubfe(w[u], (uint32_t)c[u], 1) ? c[u] : -1;
                            window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
                        },
                        [] {});
