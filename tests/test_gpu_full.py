@@ -2,7 +2,8 @@
 benchmark times: triangle counting on R-MAT scale 18 compared entry by entry
 with the oracle; the 512-source BFS step on R-MAT scale 20 on sampled rows
 (the oracle computes them one by one); the 64-product batch on sampled rows of
-every product."""
+every product; light Erdos-Renyi products of the density heatmap that run in
+the heap kind, in full."""
 import numpy as np
 import pytest
 
@@ -62,3 +63,18 @@ def test_batch_full_mix_sampled():
         rows = np.unique(rng.integers(0, p["A"].nrows, 64))
         R = oracle.masked_spgemm(p["A"], p["B"], p["M"], False, "plus_times_f64", rows=rows)
         assert_same(C, R, "plus_times_f64", rows=rows)
+
+
+@pytest.mark.parametrize("d,dm,comp", [(1.0, 64.0, False), (4.0, 1024.0, False), (2.0, 8.0, True)])
+def test_light_er_heap_sizes_full(d, dm, comp):
+    """The density-heatmap regime where the heap kind carries the rows (inputs
+    much sparser than the mask; a complemented mask over 2^20 columns),
+    compared in full with the oracle at the heatmap's size."""
+    n = 1 << 20 if dm < 1000 else 1 << 18
+    A = mspgen.er(n, n, d, 11 + n, "f64")
+    B = mspgen.er(n, n, d, 12 + n, "f64")
+    M = mspgen.er(n, n, dm, 13 + n, None)
+    with msp().Plan(up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M), comp, "plus_times_f64") as p:
+        C = p.execute()
+        assert p.bin_units["heap_lane"] + p.bin_units["heap_lane_long_mask"] > 32768
+    assert_same(C, oracle.masked_spgemm(A, B, M, comp, "plus_times_f64"), "plus_times_f64")
