@@ -53,6 +53,24 @@ def tuning_kw(args):
     return kw
 
 
+def other_stages(make_plan, nrows, dtype, stage_ms, steps, dev, runs=2):
+    """Times the stages other than the kernel bins (scans, row pointers,
+    compaction, split emission) in `runs` untimed profiled executions and
+    stores them in stage_ms scaled to `steps` steps."""
+    import torch
+
+    import paper_2111_09947_amd as msp
+    extra = np.zeros_like(stage_ms)
+    for _ in range(runs):
+        with make_plan() as p:
+            cap = max(p.upper_bound, 1)
+            p.execute_profiled(torch.empty(nrows + 1, dtype=torch.int64, device=dev),
+                               torch.empty(cap, dtype=torch.int32, device=dev),
+                               torch.empty(cap, dtype=dtype, device=dev), cap, extra)
+    nb = len(msp.BIN_NAMES)
+    stage_ms[nb:] = extra[nb:] / runs * steps
+
+
 def row_quantities(L):
     """Per-row counts of the push method for A = B = M = L: A row length,
     products flops_i = sum over k in row i of nnz(L(k,:)), mask length."""
@@ -167,30 +185,38 @@ def run_tc(args):
               **tuning_kw(args))
 
     plan_ms = [0.0]
+    # kernel-bin times: HIP events attached to the bins' own launches, recorded into a timing
+    # session during the timed steps and read once after them (no synchronization per step);
+    # the other stages are timed in untimed runs afterwards
+    timing = msp.Timing(max(args.steps, args.warmup), stages=msp.BIN_NAMES)
 
     def step(record):
         c0 = time.perf_counter()
-        with msp.Plan(dL, dL, dL, **kw) as p:
-            if record is not None:
+        with msp.Plan(dL, dL, dL, **kw) as p:  # the plan's one synchronization
+            if record:
                 plan_ms[0] += (time.perf_counter() - c0) * 1e3
             cap = max(p.upper_bound, 1)
             rp = torch.empty(L.nrows + 1, dtype=torch.int64, device=dev)
             ci = torch.empty(cap, dtype=torch.int32, device=dev)
             v = torch.empty(cap, dtype=torch.int64, device=dev)
-            ms = record if record is not None else np.zeros_like(stage_ms)
-            nnz = p.execute_profiled(rp, ci, v, cap, ms)
-            msp.reduce(v[:nnz], sr, out=total_dev)
-            return p, rp, v, nnz
+            p.execute_timed(rp, ci, v, cap, timing)
+            msp.reduce_csr(rp, L.nrows, v, sr, out=total_dev)  # the count of C stays on the device
+            return rp, v
 
     for _ in range(args.warmup):
-        step(None)
+        step(False)
     torch.cuda.synchronize()
+    timing.collect(np.zeros_like(stage_ms))  # warm-up stages are not counted
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        plan, rp, v, nnz = step(stage_ms)
+        rp, v = step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed / args.steps * 1e3
+    timing.collect(stage_ms)
+    timing.close()
+    nnz = int(rp[-1].item())
+    other_stages(lambda: msp.Plan(dL, dL, dL, **kw), L.nrows, torch.int64, stage_ms, args.steps, dev)
 
     # quantities of the result (for the metric's numerator and the byte model)
     triangles = int(total_dev.item())
@@ -296,24 +322,32 @@ def run_bfs(args):
         dF = msp.DeviceCSR.from_host(F, dev, dt)
         dV = msp.DeviceCSR.from_host(V, dev)
         stage_ms = np.zeros(len(msp.STAGE_NAMES))
+        # bin events of the timed steps, read after them; other stages from untimed runs
+        timing = msp.Timing(max(args.steps, args.warmup), stages=msp.BIN_NAMES)
 
-        def step(record):
+        def step():
             with msp.Plan(dA, dF, dV, complement=True, semiring=sr, **tuning_kw(args)) as p:
                 cap = max(p.upper_bound, 1)
                 rp = torch.empty(G.nrows + 1, dtype=torch.int64, device=dev)
                 ci = torch.empty(cap, dtype=torch.int32, device=dev)
                 v = torch.empty(cap, dtype=dt, device=dev)
-                nnz = p.execute_profiled(rp, ci, v, cap, record if record is not None else np.zeros_like(stage_ms))
-                return p, rp, nnz
+                p.execute_timed(rp, ci, v, cap, timing)
+                return rp
 
         for _ in range(args.warmup):
-            step(None)
+            step()
         torch.cuda.synchronize()
+        timing.collect(np.zeros_like(stage_ms))  # warm-up stages are not counted
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            p, rp, nnz = step(stage_ms)
+            rp = step()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) / args.steps * 1e3
+        timing.collect(stage_ms)
+        timing.close()
+        nnz = int(rp[-1].item())
+        other_stages(lambda: msp.Plan(dA, dF, dV, complement=True, semiring=sr, **tuning_kw(args)), G.nrows, dt,
+                     stage_ms, args.steps, dev)
         # useful products = plus-pair count of admitted products
         with msp.Plan(dA, dF, dV, complement=True, semiring="plus_pair_i64") as pp:
             Cp = pp.execute()

@@ -284,6 +284,26 @@ msp_status msp_execute(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* 
 msp_status msp_execute_profiled(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, double* stage_ms,
                                 void* stream);
 
+/*
+ * Timing sessions: stage timing without a synchronization per execution.
+ * msp_execute_timed runs msp_execute and records the stages' HIP events into
+ * the session (it synchronizes only when nnz_host is not NULL);
+ * msp_timing_collect waits for the recorded events and ADDS each stage's
+ * milliseconds, summed over the executions since the last collect, to
+ * stage_ms[MSP_NSTAGES] (host). A session belongs to the device current at
+ * its creation and to one host thread at a time; it owns its events.
+ */
+typedef struct msp_timing msp_timing;
+/* `executions`: events for this many executions are created up front (more
+   are created on demand); 0 creates none. `stages`: bit s set times stage s
+   (MSP_STAGE_* or a bin number); 0 times every stage. Each timed stage costs
+   the events attached to its launches. */
+msp_status msp_timing_create(msp_timing** timing, int32_t executions, uint32_t stages);
+msp_status msp_execute_timed(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, msp_timing* timing,
+                             void* stream);
+msp_status msp_timing_collect(msp_timing* timing, double* stage_ms);
+void msp_timing_destroy(msp_timing* timing);
+
 /* Copies the kernel bin of every row (MSP_BIN_*, or -1 for rows with no
    possible output) into bins (host, nrows entries). SYNCHRONIZES. */
 msp_status msp_plan_row_bins(const msp_plan* plan, int8_t* bins, void* stream);
@@ -314,6 +334,15 @@ msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M,
  */
 msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result,
                       void* stream);
+
+/*
+ * msp_reduce over the entries of an output CSR without reading its size on
+ * the host: reduces values[0 .. rowptr[nrows]) (rowptr and values device;
+ * the count is read on the device, clamped to [0, capacity], the length of
+ * `values`). Does not synchronize.
+ */
+msp_status msp_reduce_csr(const int64_t* rowptr, int64_t nrows, const void* values, int64_t capacity,
+                          msp_semiring semiring, void* result, void* stream);
 
 /*
  * ---- Batches: many products in one set of launches ----

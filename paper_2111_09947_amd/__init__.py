@@ -226,6 +226,16 @@ class Plan:
                "msp_execute_profiled")
         return n.value
 
+    def execute_timed(self, rowptr, colidx, values, capacity: int, timing: "Timing", sync_nnz: bool = False) -> int:
+        """Like execute_into, recording the stage events into `timing` (read
+        later by Timing.collect); returns nnz(C) if sync_nnz, else -1."""
+        out = L.MspCsrOut(self.nrows, self.ncols, capacity, rowptr.data_ptr(), colidx.data_ptr(),
+                          values.data_ptr())
+        n = ctypes.c_int64(-1)
+        _check(L.load().msp_execute_timed(self._h, ctypes.byref(out), ctypes.byref(n) if sync_nnz else None,
+                                          timing._h, _stream()), "msp_execute_timed")
+        return n.value
+
     def row_bins(self):
         """Kernel bin of every row (numpy int8; -1 = no possible output)."""
         import numpy as np
@@ -270,6 +280,54 @@ def upper_bound(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = Fal
     _check(lib.msp_upper_bound(*(ctypes.byref(v) for v in vs), int(bool(complement)), ctypes.byref(ub), _stream()),
            "msp_upper_bound")
     return ub.value
+
+
+class Timing:
+    """A timing session: Plan.execute_timed records stage events into it
+    without synchronizing; collect() waits for them and adds each stage's
+    milliseconds into a float64 numpy array of len(STAGE_NAMES)."""
+
+    def __init__(self, executions: int = 0, stages=None):
+        """`executions`: create the events of that many executions now.
+        `stages`: names (STAGE_NAMES) of the stages to time; None: all."""
+        mask = 0
+        for name in stages or ():
+            mask |= 1 << L.STAGE_NAMES.index(name)
+        h = ctypes.c_void_p()
+        _check(L.load().msp_timing_create(ctypes.byref(h), int(executions), mask), "msp_timing_create")
+        self._h = h
+
+    def collect(self, stage_ms):
+        import numpy as np
+        assert stage_ms.dtype == np.float64 and len(stage_ms) == L.NSTAGES
+        _check(L.load().msp_timing_collect(self._h, stage_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "msp_timing_collect")
+        return stage_ms
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().msp_timing_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reduce_csr(rowptr, nrows: int, values, semiring: str, out=None):
+    """(+)-reduction of values[:rowptr[nrows]] with the count read on the
+    device (no synchronization); `values` holds at most its length."""
+    t = _torch()
+    if values.dtype != out_dtype(semiring):
+        raise TypeError("values dtype does not match the semiring's output type")
+    if out is None:
+        out = t.empty(1, dtype=values.dtype, device=values.device)
+    _check(L.load().msp_reduce_csr(ctypes.c_void_p(rowptr.data_ptr()), int(nrows),
+                                   ctypes.c_void_p(values.data_ptr() if values.numel() else 0), values.numel(),
+                                   SEMIRINGS[semiring], ctypes.c_void_p(out.data_ptr()), _stream()), "msp_reduce_csr")
+    return out
 
 
 def reduce(values, semiring: str, out=None):

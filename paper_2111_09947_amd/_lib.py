@@ -64,6 +64,10 @@ SIGNATURES = {
     "msp_execute": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp]),
     "msp_execute_profiled": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64),
                                             ctypes.POINTER(ctypes.c_double), c_vp]),
+    "msp_timing_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.c_int32, ctypes.c_uint32]),
+    "msp_execute_timed": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp, c_vp]),
+    "msp_timing_collect": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_double)]),
+    "msp_timing_destroy": (None, [c_vp]),
     "msp_plan_row_bins": (ctypes.c_int, [c_vp, c_vp, c_vp]),
     "msp_plan_destroy": (None, [c_vp]),
     "msp_masked_spgemm": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
@@ -72,6 +76,7 @@ SIGNATURES = {
     "msp_upper_bound": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
                                        ctypes.c_int, ctypes.POINTER(c_i64), c_vp]),
     "msp_reduce": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_vp]),
+    "msp_reduce_csr": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp, c_vp]),
     "msp_batch_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(MspProblem), c_i64, ctypes.c_int,
                                         ctypes.POINTER(MspOptions), c_vp]),
     "msp_batch_count": (c_i64, [c_vp]),

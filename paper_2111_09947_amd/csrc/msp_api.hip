@@ -672,16 +672,39 @@ static std::vector<hipEvent_t>& event_pool() {
     return pools[dev];
 }
 
+// A timing session (msp_timing_*): the event pairs of any number of
+// executions, read out together by msp_timing_collect. Its events are its own.
+struct msp_timing {
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    std::vector<hipEvent_t> spare;  // events free for reuse
+    std::vector<hipEvent_t> all;    // every event created, destroyed with the session
+    int device = 0;
+    uint32_t stages = 0;            // bit s set: stage s is timed
+};
+
 // Stage times from events attached to the stage's own kernel launches
 // (hipExtLaunchKernel): begin() arms a start/stop pair, end() disarms it.
+// With a session the pairs go to the session and are read later; otherwise
+// collect() reads them after synchronizing the stream.
 struct StageTimer {
     bool on = false;
     hipStream_t s = nullptr;
+    msp_timing* sess = nullptr;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
     std::vector<hipEvent_t> held;  // taken from the pool, returned at destruction
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     int open_stage = -1;
     msp_status take(hipEvent_t* e) {
+        if (sess) {
+            if (sess->spare.empty()) {
+                MSP_HIP(hipEventCreate(e));
+                sess->all.push_back(*e);
+            } else {
+                *e = sess->spare.back();
+                sess->spare.pop_back();
+            }
+            return MSP_OK;
+        }
         auto& pool = event_pool();
         if (pool.empty()) {
             MSP_HIP(hipEventCreate(e));
@@ -694,6 +717,10 @@ struct StageTimer {
     }
     msp_status begin(int stage) {
         if (!on) return MSP_OK;
+        if (sess && !((sess->stages >> stage) & 1u)) {  // not a stage of this session
+            open_stage = -1;
+            return MSP_OK;
+        }
         MSP_CHECK(take(&ev_start));
         MSP_CHECK(take(&ev_stop));
         open_stage = stage;
@@ -701,8 +728,13 @@ struct StageTimer {
         return MSP_OK;
     }
     msp_status end() {
-        if (!on) return MSP_OK;
-        if (timing_disarm()) marks.push_back({open_stage, {ev_start, ev_stop}});
+        if (!on || open_stage < 0) return MSP_OK;
+        if (timing_disarm()) {
+            (sess ? sess->marks : marks).push_back({open_stage, {ev_start, ev_stop}});
+        } else if (sess) {  // nothing was launched: the pair is free again
+            sess->spare.push_back(ev_start);
+            sess->spare.push_back(ev_stop);
+        }
         return MSP_OK;
     }
     msp_status collect(double* ms) {
@@ -894,6 +926,61 @@ msp_status msp_execute_profiled(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, 
     return tm.collect(stage_ms);
 }
 
+msp_status msp_timing_create(msp_timing** timing, int32_t executions, uint32_t stages) {
+    if (!timing) return fail(MSP_ERR_INVALID_ARGUMENT, "timing is NULL");
+    if (executions < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "executions must be >= 0");
+    msp_timing* T = new (std::nothrow) msp_timing();
+    if (!T) return fail(MSP_ERR_OUT_OF_MEMORY, "timing session");
+    (void)hipGetDevice(&T->device);
+    T->stages = stages ? stages : (uint32_t)((1ull << MSP_NSTAGES) - 1);
+    // events for `executions` executions are created now, outside any timed region
+    const int64_t n = 2 * (int64_t)MSP_NSTAGES * executions;
+    for (int64_t x = 0; x < n; ++x) {
+        hipEvent_t e = nullptr;
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) {
+            msp_timing_destroy(T);
+            return fail(MSP_ERR_DEVICE, "hipEventCreate for the timing session");
+        }
+        T->all.push_back(e);
+        T->spare.push_back(e);
+    }
+    *timing = T;
+    return MSP_OK;
+}
+
+void msp_timing_destroy(msp_timing* T) {
+    if (!T) return;
+    for (hipEvent_t e : T->all) (void)hipEventDestroy(e);
+    delete T;
+}
+
+msp_status msp_execute_timed(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, msp_timing* T, void* stream) {
+    if (!P || !T) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    int dev = 0;
+    MSP_HIP(hipGetDevice(&dev));
+    if (dev != T->device) return fail(MSP_ERR_INVALID_ARGUMENT, "the timing session belongs to another device");
+    StageTimer tm;
+    tm.on = true;
+    tm.s = (hipStream_t)stream;
+    tm.sess = T;
+    return execute_impl(P, C, nnz_host, tm.s, tm);
+}
+
+msp_status msp_timing_collect(msp_timing* T, double* stage_ms) {
+    if (!T || !stage_ms) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    for (auto& mk : T->marks) {
+        MSP_HIP(hipEventSynchronize(mk.second.second));
+        float t = 0.f;
+        MSP_HIP(hipEventElapsedTime(&t, mk.second.first, mk.second.second));
+        stage_ms[mk.first] += (double)t;
+        T->spare.push_back(mk.second.first);
+        T->spare.push_back(mk.second.second);
+    }
+    T->marks.clear();
+    return MSP_OK;
+}
+
 msp_status msp_plan_row_bins(const msp_plan* P, int8_t* bins, void* stream) {
     if (!P || (!bins && P->R > 0)) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
     if (P->R == 0) return MSP_OK;
@@ -937,7 +1024,21 @@ msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M,
     return MSP_OK;
 }
 
+static msp_status reduce_impl(const void* values, int64_t n, const int64_t* n_dev, msp_semiring semiring,
+                              void* result, void* stream);
+
 msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result, void* stream) {
+    return reduce_impl(values, n, nullptr, semiring, result, stream);
+}
+
+msp_status msp_reduce_csr(const int64_t* rowptr, int64_t nrows, const void* values, int64_t capacity,
+                          msp_semiring semiring, void* result, void* stream) {
+    if (!rowptr || nrows < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "bad row pointers");
+    return reduce_impl(values, capacity, rowptr + nrows, semiring, result, stream);
+}
+
+static msp_status reduce_impl(const void* values, int64_t n, const int64_t* n_dev, msp_semiring semiring,
+                              void* result, void* stream) {
     if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     if (n < 0 || !result || (n > 0 && !values)) return fail(MSP_ERR_INVALID_ARGUMENT, "bad reduce arguments");
     configure_pool();
@@ -948,7 +1049,7 @@ msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void
     hipError_t e = hipMallocAsync(&partial, bytes, s);
     if (e == hipErrorNotSupported) { pooled = false; e = hipMalloc(&partial, bytes); }
     MSP_HIP(e);
-    const hipError_t le = launch_reduce(semiring, values, n, partial, result, s);
+    const hipError_t le = launch_reduce(semiring, values, n, n_dev, partial, result, s);
     if (pooled) (void)hipFreeAsync(partial, s);
     else { (void)hipStreamSynchronize(s); (void)hipFree(partial); }
     MSP_HIP(le);

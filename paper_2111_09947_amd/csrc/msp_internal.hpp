@@ -215,7 +215,8 @@ hipError_t launch_transpose_scatter(const int64_t* rp, const int32_t* ci, const 
                                     int32_t* tci, void* tv, hipStream_t s);
 // Deterministic (+)-reduction into one value.
 int64_t reduce_partial_elems();
-hipError_t launch_reduce(int semiring, const void* vals, int64_t n, void* partial, void* result,
+// (+)-reduction of n values, or of min(*n_dev, n) when n_dev (device) is given.
+hipError_t launch_reduce(int semiring, const void* vals, int64_t n, const int64_t* n_dev, void* partial, void* result,
                          hipStream_t s);
 
 // Unit-list segment offsets from the per-product statistics; zeroes the

@@ -1849,10 +1849,12 @@ __device__ typename Red<SR>::A block_reduce(typename Red<SR>::A v) {
     return r;
 }
 
+// n elements, or min(*n_dev, n) when the count is given on the device
 template <int SR>
 __global__ __launch_bounds__(RED_T) void k_reduce_partial(const typename Red<SR>::V* __restrict__ v, int64_t n,
-                                                          typename Red<SR>::A* partial) {
+                                                          const int64_t* n_dev, typename Red<SR>::A* partial) {
     using R = Red<SR>;
+    if (n_dev) n = max((int64_t)0, min(n, *n_dev));
     typename R::A acc = R::from(typename R::V(0));
     for (int64_t x = (int64_t)blockIdx.x * RED_T + threadIdx.x; x < n; x += (int64_t)gridDim.x * RED_T)
         acc = R::op(acc, R::from(v[x]));
@@ -1871,23 +1873,25 @@ __global__ __launch_bounds__(RED_T) void k_reduce_final(const typename Red<SR>::
 }
 
 template <int SR>
-static hipError_t launch_reduce_t(const void* vals, int64_t n, void* partial, void* result, hipStream_t s) {
+static hipError_t launch_reduce_t(const void* vals, int64_t n, const int64_t* n_dev, void* partial, void* result,
+                                  hipStream_t s) {
     using R = Red<SR>;
     const int nb = (int)grid_for(n, RED_T * 8, RED_BLOCKS);
-    MSP_LAUNCH(k_reduce_partial<SR>, dim3(nb), dim3(RED_T), 0, s, static_cast<const typename R::V*>(vals), n,
+    MSP_LAUNCH(k_reduce_partial<SR>, dim3(nb), dim3(RED_T), 0, s, static_cast<const typename R::V*>(vals), n, n_dev,
                        static_cast<typename R::A*>(partial));
     MSP_LAUNCH(k_reduce_final<SR>, dim3(1), dim3(RED_T), 0, s, static_cast<const typename R::A*>(partial), nb,
                        static_cast<typename R::V*>(result));
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int semiring, const void* vals, int64_t n, void* partial, void* result, hipStream_t s) {
+hipError_t launch_reduce(int semiring, const void* vals, int64_t n, const int64_t* n_dev, void* partial, void* result,
+                         hipStream_t s) {
     switch (semiring) {
-    case MSP_PLUS_TIMES_F64: return launch_reduce_t<MSP_PLUS_TIMES_F64>(vals, n, partial, result, s);
-    case MSP_PLUS_PAIR_I64: return launch_reduce_t<MSP_PLUS_PAIR_I64>(vals, n, partial, result, s);
-    case MSP_LOR_LAND_BOOL: return launch_reduce_t<MSP_LOR_LAND_BOOL>(vals, n, partial, result, s);
-    case MSP_PLUS_TIMES_I32: return launch_reduce_t<MSP_PLUS_TIMES_I32>(vals, n, partial, result, s);
-    case MSP_PLUS_TIMES_I64: return launch_reduce_t<MSP_PLUS_TIMES_I64>(vals, n, partial, result, s);
+    case MSP_PLUS_TIMES_F64: return launch_reduce_t<MSP_PLUS_TIMES_F64>(vals, n, n_dev, partial, result, s);
+    case MSP_PLUS_PAIR_I64: return launch_reduce_t<MSP_PLUS_PAIR_I64>(vals, n, n_dev, partial, result, s);
+    case MSP_LOR_LAND_BOOL: return launch_reduce_t<MSP_LOR_LAND_BOOL>(vals, n, n_dev, partial, result, s);
+    case MSP_PLUS_TIMES_I32: return launch_reduce_t<MSP_PLUS_TIMES_I32>(vals, n, n_dev, partial, result, s);
+    case MSP_PLUS_TIMES_I64: return launch_reduce_t<MSP_PLUS_TIMES_I64>(vals, n, n_dev, partial, result, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -281,3 +281,55 @@ def test_split_rows_in_batch():
                 b.graph_launch()
             for (A, B, M, c), C in zip(probs, b.results()):
                 assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
+
+
+def test_reduce_csr_reads_the_count_on_the_device():
+    torch = torch_or_skip()
+    m = msp()
+    L = mspgen.triangle_input(12, 16, 7)
+    dL = up(L)
+    with m.Plan(dL, dL, dL, semiring="plus_pair_i64") as p:
+        cap = max(p.upper_bound, 1)
+        dev = dL.rowptr.device
+        rp = torch.empty(L.nrows + 1, dtype=torch.int64, device=dev)
+        ci = torch.empty(cap, dtype=torch.int32, device=dev)
+        v = torch.full((cap,), 7, dtype=torch.int64, device=dev)  # entries past nnz(C) must not count
+        assert p.execute_into(rp, ci, v, cap) == -1
+        got = m.reduce_csr(rp, L.nrows, v, "plus_pair_i64")
+        n = int(rp[-1].item())
+        assert n < cap
+        assert int(got.item()) == int(m.reduce(v[:n], "plus_pair_i64").item())
+        R = oracle.masked_spgemm(L, L, L, False, "plus_pair_i64")
+        assert int(got.item()) == int(R.values.sum())
+        # the count is clamped to the length of `values`
+        assert int(m.reduce_csr(rp, L.nrows, v[:5], "plus_pair_i64").item()) == int(v[:5].sum().item())
+
+
+def test_timing_session_without_per_execution_sync():
+    torch = torch_or_skip()
+    m = msp()
+    A, B, M = rand_problem(31, 3000, 2000, 4000, 6.0, 9.0, 40.0, "plus_times_f64")
+    R = oracle.masked_spgemm(A, B, M, False, "plus_times_f64")
+    dA, dB, dM = up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M)
+    T = m.Timing()
+    stage = np.zeros(len(m.STAGE_NAMES))
+    with m.Plan(dA, dB, dM, semiring="plus_times_f64") as p:
+        cap = max(p.upper_bound, 1)
+        outs = []
+        for _ in range(3):
+            rp = torch.empty(A.nrows + 1, dtype=torch.int64, device="cuda")
+            ci = torch.empty(cap, dtype=torch.int32, device="cuda")
+            v = torch.empty(cap, dtype=torch.float64, device="cuda")
+            p.execute_timed(rp, ci, v, cap, T)
+            outs.append((rp, ci, v))
+        T.collect(stage)
+        used = [b for b, k in enumerate(m.BIN_NAMES) if p.bin_units[k] > 0]
+    # (a small heap bin runs inside the mask-indexed launch and has no time of its own)
+    assert used and all(stage[b] > 0 for b in used if not m.BIN_NAMES[b].startswith("heap"))
+    assert stage[m.STAGE_NAMES.index("compact")] > 0 and stage[m.STAGE_NAMES.index("scan")] > 0
+    again = T.collect(np.zeros(len(m.STAGE_NAMES)))  # the session was emptied by the first collect
+    assert not again.any()
+    for rp, ci, v in outs:
+        n = int(rp[-1].item())
+        assert_same(msp().DeviceCSR(A.nrows, B.ncols, rp, ci[:n], v[:n]), R, "plus_times_f64")
+    T.close()
