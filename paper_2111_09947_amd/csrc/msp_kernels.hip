@@ -551,10 +551,49 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(const int64_t* in, int64_t
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = partial[blockIdx.x] + tot;
 }
 
+// k_scan_down for up to SCAN_FUSE_TILES tiles, taking the raw tile sums: each
+// block adds up the sums of the tiles before it (at most SCAN_FUSE_TILES
+// reads), which saves the launch of k_scan_partials.
+constexpr int64_t SCAN_FUSE_TILES = 1024;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_down_fused(const int64_t* in, int64_t* out, int64_t n,
+                                                            const int64_t* __restrict__ tile_sum) {
+    __shared__ int64_t tmp[SCAN_T / WAVE];
+    __shared__ int64_t red[SCAN_T / WAVE];
+    int64_t o = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_T) o += tile_sum[b];
+    o = wave_sum(o);
+    if (lane() == 0) red[threadIdx.x / WAVE] = o;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+    int64_t v[SCAN_I];
+    int64_t run = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; ++j) {
+        v[j] = (base + j < n) ? in[base + j] : 0;
+        run += v[j];
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan<SCAN_T / WAVE>(run, tmp, tot);  // its barriers also order `red`
+    int64_t off = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_T / WAVE; ++w) off += red[w];
+    int64_t acc = off + ex;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; ++j) {
+        if (base + j < n) out[base + j] = acc;
+        acc += v[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = off + tot;
+}
+
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s) {
     if (n <= 0) return launch_fill_i64(out, 1, 0, s);
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     MSP_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, partial);
+    if (nb <= SCAN_FUSE_TILES) {
+        MSP_LAUNCH(k_scan_down_fused, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, (const int64_t*)partial);
+        return hipGetLastError();
+    }
     MSP_LAUNCH(k_scan_partials, dim3(1), dim3(SCAN_T), 0, s, partial, nb);
     MSP_LAUNCH(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, (const int64_t*)partial);
     return hipGetLastError();
