@@ -410,7 +410,8 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         }
         MSP_CHECK(P->alloc_carve(c));
     }
-    MSP_HIP(hipMemsetAsync(P->stats_d, 0, sizeof(unsigned long long) * ST_COUNT * count, s));
+    // the statistics and every product's row counts start at zero (one launch)
+    MSP_HIP(launch_zero2(reinterpret_cast<int64_t*>(P->stats_d), ST_COUNT * count, P->flops, R, s));
     if (o.validate) {
         unsigned long long* err = P->stats_d + ST_ERROR;
         for (int64_t p = 0; p < count; ++p) {
@@ -455,6 +456,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.m_nnz = probs[p].M.nnz;
         aa.icost = (aa.inner_ratio > 0 && aa.colcnt_rp && o.force_kind == MSP_KIND_AUTO) ? P->icost : nullptr;
         aa.flops = P->flops;
+        aa.flops_zeroed = true;
         aa.tiles = P->unit_base;
         aa.bin = P->bin;
         aa.stats = P->stats_d + p * ST_COUNT;

@@ -112,6 +112,7 @@ struct AnalysisArgs {
     int64_t m_nnz;
     int64_t* icost;            // [m] pull cost per row (auto INNER choice) or null
     int64_t* flops;            // [R] global rows
+    bool flops_zeroed;         // flops of this product's rows are zero already
     int64_t* tiles;            // [R+1], number of units per row (scanned later)
     int8_t* bin;               // [R]
     unsigned long long* stats; // [ST_COUNT] of this product
@@ -186,6 +187,8 @@ struct CompactArgs {
 hipError_t launch_validate(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int64_t nnz,
                            unsigned long long* err, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+// Zeroes a[0, na) and b[0, nb) in one launch.
+hipError_t launch_zero2(int64_t* a, int64_t na, int64_t* b, int64_t nb, hipStream_t s);
 hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s);
 hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s);
 __host__ __device__ inline int flops_bucket(int64_t flops) {

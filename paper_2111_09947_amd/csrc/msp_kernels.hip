@@ -374,10 +374,23 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
 
 
 
+__global__ void k_zero2(int64_t* a, int64_t na, int64_t* b, int64_t nb) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < na + nb; x += (int64_t)gridDim.x * blockDim.x) {
+        if (x < na) a[x] = 0;
+        else b[x - na] = 0;
+    }
+}
+
+hipError_t launch_zero2(int64_t* a, int64_t na, int64_t* b, int64_t nb, hipStream_t s) {
+    if (na + nb <= 0) return hipSuccess;
+    MSP_LAUNCH(k_zero2, dim3(grid_for(na + nb, 256, 4096)), dim3(256), 0, s, a, na, b, nb);
+    return hipGetLastError();
+}
+
 hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
     if (a.op.m <= 0) return hipSuccess;
     // products per row: sum over A(i,:) of nnz(B(k,:)); pull cost: sum over M(i,:) of nnz(B(:,j))
-    hipError_t e = launch_fill_i64(a.flops + a.row_off, a.op.m, 0, s);
+    hipError_t e = a.flops_zeroed ? hipSuccess : launch_fill_i64(a.flops + a.row_off, a.op.m, 0, s);
     if (e != hipSuccess) return e;
     if (a.a_nnz > 0)
         MSP_LAUNCH(k_rowsum, dim3(grid_for(a.a_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Arp, a.op.Aci,
