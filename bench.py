@@ -184,17 +184,13 @@ def run_tc(args):
     kw = dict(semiring=sr, phase=args.phase, force_kind=args.force_kind, inner_ratio=args.inner_ratio,
               **tuning_kw(args))
 
-    plan_ms = [0.0]
     # kernel-bin times: HIP events attached to the bins' own launches, recorded into a timing
     # session during the timed steps and read once after them (no synchronization per step);
     # the other stages are timed in untimed runs afterwards
     timing = msp.Timing(max(args.steps, args.warmup), stages=msp.BIN_NAMES)
 
     def step(record):
-        c0 = time.perf_counter()
         with msp.Plan(dL, dL, dL, **kw) as p:  # the plan's one synchronization
-            if record:
-                plan_ms[0] += (time.perf_counter() - c0) * 1e3
             cap = max(p.upper_bound, 1)
             rp = torch.empty(L.nrows + 1, dtype=torch.int64, device=dev)
             ci = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -217,6 +213,13 @@ def run_tc(args):
     timing.close()
     nnz = int(rp[-1].item())
     other_stages(lambda: msp.Plan(dL, dL, dL, **kw), L.nrows, torch.int64, stage_ms, args.steps, dev)
+    # plan creation alone (in the timed steps its synchronization also waits for the previous step)
+    plan_ms = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        msp.Plan(dL, dL, dL, **kw).close()
+        plan_ms.append((time.perf_counter() - c0) * 1e3)
 
     # quantities of the result (for the metric's numerator and the byte model)
     triangles = int(total_dev.item())
@@ -293,7 +296,7 @@ def run_tc(args):
             "alg_bytes_total": bytes_total,
             "hbm_frac_whole_step": round(bytes_total / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "stage_ms": {n: round(float(t) / args.steps, 5) for n, t in zip(msp.STAGE_NAMES, stage_ms) if t > 0},
-            "plan_create_ms": round(plan_ms[0] / args.steps, 4),
+            "plan_create_ms": round(float(np.median(plan_ms)), 4),
         },
         "cpu_baseline": cpu,
     }
