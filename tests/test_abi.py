@@ -89,3 +89,17 @@ def test_argument_errors_need_no_gpu():
     assert st == 1
     # reduce with negative length
     assert lib.msp_reduce(None, -1, 0, ctypes.c_void_p(8), None) == 1
+
+
+def test_timing_and_csr_reduce_argument_errors():
+    lib, L = _lib()
+    assert lib.msp_timing_create(None, 0, 0) == 1
+    h = ctypes.c_void_p()
+    assert lib.msp_timing_create(ctypes.byref(h), -1, 0) == 1 and b"executions" in lib.msp_last_error()
+    assert lib.msp_execute_timed(None, None, None, None, None) == 1
+    assert lib.msp_timing_collect(None, None) == 1
+    lib.msp_timing_destroy(None)  # accepted, does nothing
+    assert lib.msp_reduce_csr(None, 5, None, 0, 1, None, None) == 1
+    assert lib.msp_reduce_csr(ctypes.c_void_p(8), -1, None, 0, 1, None, None) == 1
+    assert lib.msp_reduce_csr(ctypes.c_void_p(8), 5, None, 0, 9, ctypes.c_void_p(8), None) == 1  # semiring
+    assert lib.msp_reduce_csr(ctypes.c_void_p(8), 5, None, 4, 1, ctypes.c_void_p(8), None) == 1  # values NULL
