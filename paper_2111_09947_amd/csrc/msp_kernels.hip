@@ -937,11 +937,12 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
 // in global memory with atomics (inserted bits, and values with the
 // semiring's (+)); a second kernel emits every split row in column order.
 // Integer semirings stay exact; FP64 sums are reordered (within tolerance).
-template <int SR, int MODE, bool BATCH>
+template <int SR, int MODE, bool BATCH, int LW>
 __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split(NumArgs g) {
+    // LW: the LDS tile (n <= LW); the global accumulator of a split row keeps DENSE_B_COLS columns
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
-    constexpr int W = DENSE_B_COLS;
+    constexpr int W = LW;
     constexpr int NW = BLOCK_NW;
     constexpr bool COUNT = MODE == MODE_COUNT;
     constexpr bool FLAGS = COUNT || T::sep_flag;
@@ -995,8 +996,8 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
                        },
                        [] {});
     __syncthreads();
-    unsigned int* gset = g.gset + (int64_t)sidx * NWORDS;
-    acc_t* gval = static_cast<acc_t*>(g.gval) + (int64_t)sidx * W;
+    unsigned int* gset = g.gset + (int64_t)sidx * (DENSE_B_COLS / 32);
+    acc_t* gval = static_cast<acc_t*>(g.gval) + (int64_t)sidx * DENSE_B_COLS;
     for (int c = ut; c < wt; c += UT) {
         const bool set = FLAGS ? (flags[c] != 0) : T::is_set(vals[c]);
         if (set) {
@@ -1594,8 +1595,11 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
     case BIN_DENSE_BN:
         MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH>), gb, bb, 0, s, a);
         break;
-    case BIN_DENSE_SPLIT:
-        MSP_LAUNCH((k_dense_split<SR, MODE, BATCH>), gb, bb, 0, s, a);
+    case BIN_DENSE_SPLIT:  // a narrow LDS tile (more blocks per CU) when every column fits it
+        if (!BATCH && a.op.n <= DENSE_W_COLS)
+            MSP_LAUNCH((k_dense_split<SR, MODE, BATCH, DENSE_W_COLS>), gb, bb, 0, s, a);
+        else
+            MSP_LAUNCH((k_dense_split<SR, MODE, BATCH, DENSE_B_COLS>), gb, bb, 0, s, a);
         break;
     case BIN_HEAP_L: case BIN_HEAP_LM:
         MSP_LAUNCH((k_heap<SR, MODE, BATCH>), dim3((unsigned)((a.nunits + HEAP_T - 1) / HEAP_T)), dim3(HEAP_T), 0,
