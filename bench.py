@@ -53,6 +53,26 @@ def tuning_kw(args):
     return kw
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def device_info(dev):
+    """The properties of the GPU the run used (as the runtime reports them)."""
+    import torch
+    p = torch.cuda.get_device_properties(dev)
+    keys = ("name", "gcnArchName", "multi_processor_count", "total_memory", "L2_cache_size",
+            "max_threads_per_multi_processor", "regs_per_multiprocessor", "warp_size")
+    return {k: getattr(p, k) for k in keys if hasattr(p, k)}
+
+
 def other_stages(make_plan, nrows, dtype, stage_ms, steps, dev, runs=2):
     """Times the stages other than the kernel bins (scans, row pointers,
     compaction, split emission) in `runs` untimed profiled executions and
@@ -189,23 +209,26 @@ def run_tc(args):
     # the other stages are timed in untimed runs afterwards
     timing = msp.Timing(max(args.steps, args.warmup), stages=msp.BIN_NAMES)
 
-    def step(record):
+    def step(timed=True):
         with msp.Plan(dL, dL, dL, **kw) as p:  # the plan's one synchronization
             cap = max(p.upper_bound, 1)
             rp = torch.empty(L.nrows + 1, dtype=torch.int64, device=dev)
             ci = torch.empty(cap, dtype=torch.int32, device=dev)
             v = torch.empty(cap, dtype=torch.int64, device=dev)
-            p.execute_timed(rp, ci, v, cap, timing)
+            if timed:
+                p.execute_timed(rp, ci, v, cap, timing)
+            else:
+                p.execute_into(rp, ci, v, cap)
             msp.reduce_csr(rp, L.nrows, v, sr, out=total_dev)  # the count of C stays on the device
             return rp, v
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     timing.collect(np.zeros_like(stage_ms))  # warm-up stages are not counted
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        rp, v = step(True)
+        rp, v = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed / args.steps * 1e3
@@ -220,6 +243,17 @@ def run_tc(args):
         c0 = time.perf_counter()
         msp.Plan(dL, dL, dL, **kw).close()
         plan_ms.append((time.perf_counter() - c0) * 1e3)
+    # cold steps: L2 and the last-level cache flushed by writing 512 MiB before each one
+    flush = torch.empty(1 << 26, dtype=torch.int64, device=dev)
+    cold_ms = []
+    for r in range(5):
+        flush.fill_(r)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        step(False)
+        torch.cuda.synchronize()
+        cold_ms.append((time.perf_counter() - c0) * 1e3)
+    del flush
 
     # quantities of the result (for the metric's numerator and the byte model)
     triangles = int(total_dev.item())
@@ -263,8 +297,12 @@ def run_tc(args):
         if s != triangles:
             print(f"[bench] MISMATCH: oracle {s} triangles, GPU {triangles}", file=sys.stderr)
             sys.exit(1)
+        c0 = time.perf_counter()
+        oracle.masked_spgemm(L, L, L, False, sr, nthreads=1)
+        t_one = time.perf_counter() - c0
         cpu = {"value": round(2 * s / t_cpu / 1e9, 3), "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"the whole workload (masked product + sum), median of 5 runs of {t_cpu:.3f} s"}
+               "sample": f"the whole workload (masked product + sum), median of 5 runs of {t_cpu:.3f} s",
+               "one_thread_value": round(2 * s / t_one / 1e9, 3), "cpu_model": cpu_model()}
 
     out = {
         "metric": "useful_masked_gflops",
@@ -297,7 +335,11 @@ def run_tc(args):
             "hbm_frac_whole_step": round(bytes_total / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "stage_ms": {n: round(float(t) / args.steps, 5) for n, t in zip(msp.STAGE_NAMES, stage_ms) if t > 0},
             "plan_create_ms": round(float(np.median(plan_ms)), 4),
+            "cold_ms_per_step": round(float(np.median(cold_ms)), 4),
+            # each operand once (A, B, M pattern, C) whatever the accumulator: a lower bound
+            "bytes_min": int(3 * (8 * (L.nrows + 1) + 4 * L.nnz) + 8 * (L.nrows + 1) + 12 * int(nnz)),
         },
+        "device": device_info(dev),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
