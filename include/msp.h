@@ -157,14 +157,14 @@ typedef struct msp_options {
                              light rows (at most block_flops products) with at
                              most 256 mask entries use MASKIDX too, other rows
                              with at most 512 use HASH (-1 = default 8) */
-    int32_t heap_flops;   /* auto mode: rows whose row of A has at most 8
-                             entries use HEAP when they have at most this many
-                             products, or at most twice as many and a mask row
-                             with at least 8 entries per product; under a
-                             complemented mask, when they have at most this
-                             many products and the mask has more than 512
-                             columns, or whatever their product count when it
-                             has more than 4096 (-1 = default 32;
+    int32_t heap_flops;   /* auto mode, matrices of more than 512 columns:
+                             rows whose row of A has at most 8 entries use HEAP
+                             when they have at most this many products, or at
+                             most twice as many and a mask row with at least 8
+                             entries per product; under a complemented mask,
+                             when they have at most this many products, or
+                             whatever their product count with more than 4096
+                             columns (-1 = default 32;
                              0 = never). An automatic heap bin runs in the
                              MASKIDX wave kernel instead when it has at most
                              32768 rows, all with normal mask rows of at most

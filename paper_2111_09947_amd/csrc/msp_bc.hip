@@ -76,6 +76,40 @@ __global__ __launch_bounds__(BC_T) void k_union_rows(int64_t n, const int64_t* _
     }
 }
 
+// The same union for at most BC_NARROW columns (a batch of at most that many
+// sources): one wave per row marks both rows' columns in a bitmap in LDS and
+// emits the set bits in column order, with no search.
+constexpr int BC_NARROW = 512;
+
+__global__ __launch_bounds__(BC_T) void k_union_rows_narrow(int64_t n, const int64_t* __restrict__ rpa,
+                                                            const int32_t* __restrict__ cia,
+                                                            const int64_t* __restrict__ rpb,
+                                                            const int32_t* __restrict__ cib,
+                                                            const int64_t* __restrict__ rpu, int32_t* __restrict__ ciu) {
+    __shared__ uint32_t bits_[BC_T / WAVE][BC_NARROW / 32];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    uint32_t* bits = bits_[wv];
+    const int64_t first = (int64_t)blockIdx.x * (BC_T / WAVE) + wv;
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (BC_T / WAVE)) {
+        const int64_t a0 = rpa[r], a1 = rpa[r + 1], b0 = rpb[r], b1 = rpb[r + 1];
+        if (a0 == a1 && b0 == b1) continue;  // wave-uniform
+        int64_t pos = rpu[r];
+        if (lane() < BC_NARROW / 32) bits[lane()] = 0u;
+        wave_lds_sync();
+        for (int64_t x = a0 + lane(); x < a1; x += WAVE) atomicOr(&bits[cia[x] >> 5], 1u << (cia[x] & 31));
+        for (int64_t x = b0 + lane(); x < b1; x += WAVE) atomicOr(&bits[cib[x] >> 5], 1u << (cib[x] & 31));
+        wave_lds_sync();
+        for (int base = 0; base < BC_NARROW; base += WAVE) {
+            const int c = base + lane();
+            const bool set = (bits[c >> 5] >> (c & 31)) & 1u;
+            const uint64_t m = __ballot(set);
+            if (set) ciu[pos + rank_below(m)] = c;
+            pos += __popcll(m);
+        }
+        wave_lds_sync();  // the bitmap is cleared for the next row only after every lane read it
+    }
+}
+
 // w = (1 + delta) / sigma, entry by entry
 __global__ void k_bc_weight(int64_t nnz, const double* __restrict__ sigma, const double* __restrict__ delta,
                             double* __restrict__ w) {
@@ -97,6 +131,40 @@ __global__ __launch_bounds__(BC_T) void k_bc_gather(int64_t n, const int64_t* __
             const int64_t p = lower_bound_g(cic, c0, c1, c);
             delta[x] = (p < c1 && cic[p] == c) ? __dmul_rn(sigf[x], vc[p]) : 0.0;
         }
+    }
+}
+
+// The same gather for at most BC_NARROW columns: one wave per row scatters
+// C's row into a dense row of values and a bitmap in LDS, then reads them at
+// F's columns, with no search.
+__global__ __launch_bounds__(BC_T) void k_bc_gather_narrow(int64_t n, const int64_t* __restrict__ rpf,
+                                                           const int32_t* __restrict__ cif,
+                                                           const double* __restrict__ sigf,
+                                                           const int64_t* __restrict__ rpc,
+                                                           const int32_t* __restrict__ cic,
+                                                           const double* __restrict__ vc, double* __restrict__ delta) {
+    __shared__ uint32_t bits_[BC_T / WAVE][BC_NARROW / 32];
+    __shared__ double vals_[BC_T / WAVE][BC_NARROW];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    uint32_t* bits = bits_[wv];
+    double* vals = vals_[wv];
+    const int64_t first = (int64_t)blockIdx.x * (BC_T / WAVE) + wv;
+    for (int64_t r = first; r < n; r += (int64_t)gridDim.x * (BC_T / WAVE)) {
+        const int64_t f0 = rpf[r], f1 = rpf[r + 1], c0 = rpc[r], c1 = rpc[r + 1];
+        if (f0 == f1) continue;  // wave-uniform
+        if (lane() < BC_NARROW / 32) bits[lane()] = 0u;
+        wave_lds_sync();
+        for (int64_t x = c0 + lane(); x < c1; x += WAVE) {  // columns of a row are distinct: plain stores
+            const int32_t c = cic[x];
+            vals[c] = vc[x];
+            atomicOr(&bits[c >> 5], 1u << (c & 31));
+        }
+        wave_lds_sync();
+        for (int64_t x = f0 + lane(); x < f1; x += WAVE) {
+            const int32_t c = cif[x];
+            delta[x] = ((bits[c >> 5] >> (c & 31)) & 1u) ? __dmul_rn(sigf[x], vals[c]) : 0.0;
+        }
+        wave_lds_sync();  // the next row rewrites the bitmap and values only after every lane read them
     }
 }
 
@@ -258,8 +326,12 @@ extern "C" msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int
         BC_CHECK(mem.get(&urp, n + 1));
         BC_CHECK(mem.get(&uci, vnnz + next.nnz));
         hipLaunchKernelGGL(k_add_rowptr, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, n + 1, vrp, next.rp, urp);
-        hipLaunchKernelGGL(k_union_rows, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, vrp, vci, next.rp,
-                           next.ci, urp, uci);
+        if (nsrc <= BC_NARROW)
+            hipLaunchKernelGGL(k_union_rows_narrow, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, vrp, vci, next.rp,
+                               next.ci, urp, uci);
+        else
+            hipLaunchKernelGGL(k_union_rows, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, vrp, vci, next.rp,
+                               next.ci, urp, uci);
         BC_HIP(hipGetLastError());
         if (vrp != f0.rp) {
             mem.release(vrp);
@@ -295,8 +367,12 @@ extern "C" msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int
         const msp_csr Mp{n, nsrc, Fp.nnz, Fp.rp, Fp.ci, nullptr};
         Level c;
         BC_CHECK(masked_product(Aiso, Bw, Mp, 0, s, mem, c, bwd_products));
-        hipLaunchKernelGGL(k_bc_gather, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, Fp.rp, Fp.ci,
-                           Fp.val, c.rp, c.ci, c.val, delta[(size_t)d - 1]);
+        if (nsrc <= BC_NARROW)
+            hipLaunchKernelGGL(k_bc_gather_narrow, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, Fp.rp, Fp.ci,
+                               Fp.val, c.rp, c.ci, c.val, delta[(size_t)d - 1]);
+        else
+            hipLaunchKernelGGL(k_bc_gather, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, Fp.rp, Fp.ci,
+                               Fp.val, c.rp, c.ci, c.val, delta[(size_t)d - 1]);
         hipLaunchKernelGGL(k_bc_rowsum, dim3(row_blocks(n)), dim3(BC_T), 0, s, n, Fp.rp,
                            delta[(size_t)d - 1], bc);
         BC_HIP(hipGetLastError());

@@ -229,13 +229,13 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
     int kind = force == MSP_KIND_HEAP && !heap_fits ? (int)MSP_KIND_AUTO : force;
     // Auto: very light rows are merged one row per lane (a wave-wide kind would leave most of its
     // lanes idle on them), and so are somewhat heavier rows whose mask row is much longer than
-    // their product count (the other kinds spend time per mask entry). Under a complemented mask
-    // the one-wave dense tile (n <= 512) is kept; light rows of a wider one go to the heap, and
-    // every fitting row of one wider than a 4096-column tile, which the dense kind would
-    // restream once per tile.
-    if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0) {
+    // their product count (the other kinds spend time per mask entry). Matrices of at most 512
+    // columns keep the one-wave dense tile. Under a complemented mask light rows of a wider one go
+    // to the heap, and every fitting row of one wider than a 4096-column tile, which the dense
+    // kind would restream once per tile.
+    if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0 && n > DENSE_W_COLS) {
         const bool light = flops <= heap_flops;
-        if (comp ? (n > DENSE_B_COLS || (n > DENSE_W_COLS && light))
+        if (comp ? (n > DENSE_B_COLS || light)
                  : (light || (flops <= HEAP_LONG_MASK_FLOPS * heap_flops && mnnz >= HEAP_LONG_MASK_RATIO * flops)))
             kind = MSP_KIND_HEAP;
     }
