@@ -69,7 +69,7 @@ def device_info(dev):
     import torch
     p = torch.cuda.get_device_properties(dev)
     keys = ("name", "gcnArchName", "multi_processor_count", "total_memory", "L2_cache_size",
-            "max_threads_per_multi_processor", "regs_per_multiprocessor", "warp_size")
+            "shared_memory_per_block", "max_threads_per_multi_processor", "regs_per_multiprocessor", "warp_size")
     return {k: getattr(p, k) for k in keys if hasattr(p, k)}
 
 
