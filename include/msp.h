@@ -170,7 +170,7 @@ typedef struct msp_options {
                              32768 rows, all with normal mask rows of at most
                              256 entries, or in the MASKIDX block kernel when
                              it has at most 4096 rows, all with normal mask
-                             rows of 257 to 4096 entries: a small heap launch
+                             rows of 257 to 2048 entries: a small heap launch
                              costs more than it saves. */
     int64_t block_flops;  /* rows with more products than this run on a whole
                              256-thread workgroup instead of one wavefront

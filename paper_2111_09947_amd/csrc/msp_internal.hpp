@@ -33,10 +33,25 @@ constexpr int DENSE_B_COLS = 4096;
 constexpr int HASH_W_CAP = 256;
 constexpr int HASH_B_CAP = 512;
 constexpr int MASKIDX_W_CAP = 256;
-constexpr int MASKIDX_B_CAP = 4096;
+// Keys per tile of the mask-indexed block kind. Its lookups are binary
+// searches over the tile's keys in LDS, so the kernel is bound by LDS latency
+// rather than by issue: 2048 keys keep a workgroup's LDS (keys, values, flags,
+// filter, candidate rings) at 36-47 KB, three or four workgroups per CU, which hides
+// that latency better than two workgroups of 4096-key tiles. Smaller tiles
+// help hub rows a little more but leave rows of a few thousand mask entries
+// and few products in a heap launch of their own (a folded heap unit must fit
+// one tile).
+#ifndef MSP_MASKIDX_B_CAP
+#define MSP_MASKIDX_B_CAP 2048
+#endif
+constexpr int MASKIDX_B_CAP = MSP_MASKIDX_B_CAP;
 constexpr int INNER_CAP = 256;
 constexpr int INNER_ACAP = 1024;  // A row (column indices) staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
+#ifndef MSP_MASKIDX_B_NW
+#define MSP_MASKIDX_B_NW 4
+#endif
+constexpr int MASKIDX_B_NW = MSP_MASKIDX_B_NW;  // waves per block of the mask-indexed block kind
 constexpr int HEAP_CAP = 8;       // heap kind: iterators per row (entries of the row of A)
 constexpr int64_t HEAP_MAX_FLOPS = (int64_t(1) << 24) - 1;  // heap keys hold a B row's remaining length in 24 bits
 constexpr int64_t HEAP_LONG_MASK_RATIO = 8;  // auto HEAP also when the mask row has >= this many entries per product

@@ -42,8 +42,8 @@ def test_complemented_mask(shape, sr, phase):
 
 @pytest.mark.parametrize("kind", ["auto", "hash", "maskidx", "dense", "inner"])
 def test_heavy_rows_span_several_tiles(kind):
-    """Mask rows longer than every LDS capacity (4096 mask entries, 1024 hash
-    entries, 4096-column tiles), A rows longer than one 64-entry batch and
+    """Mask rows longer than every LDS capacity (2048 mask entries per search
+    tile, 512 hash entries, 4096-column tiles), A rows longer than one 64-entry batch and
     B rows longer than a wave."""
     rng = np.random.default_rng(5)
     m, k, n = 40, 300, 20000
