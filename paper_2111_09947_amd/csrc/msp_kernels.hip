@@ -669,10 +669,14 @@ struct StanzaLds {
 // j[u] the column and s[u] indexes st.a for A(i,k); slots past the last
 // product have act[u] == false and meaningless j, s, cb. Handing over a whole window lets the caller
 // issue the LDS (and value) reads of all its slots before waiting for any.
-// Wave `wv` of `nw` waves processes the windows wv, wv + nw, ... of
-// 64 * STREAM_U products of each batch; batch_end() runs after the last
-// window of every batch of 64 A entries, while st.a and st.ptr still
-// describe that batch.
+// Work split among the nw waves of a unit: without `claim`, every wave walks
+// every batch of 64 A entries and wave `wv` takes the windows wv, wv + nw,
+// ... of 64 * STREAM_U products of each batch. With `claim` (an LDS counter
+// that starts at 0), the waves take whole batches instead, the next free one
+// each time, and each walks all windows of its batches: a row with many
+// batches then does each batch's loads and window searches once, not once per
+// wave. batch_end() runs after the last window of every batch the wave
+// walks, while st.a and st.ptr still describe that batch.
 //
 // Lane-to-stanza mapping of a window: every stanza that starts inside the
 // window sets bit (start - window base) of a 64 * STREAM_U-bit map; the
@@ -683,10 +687,21 @@ struct StanzaLds {
 // consumed, so a wave keeps STREAM_U stanza reads outstanding.
 template <class T, class F, class E>
 __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, int64_t pa1, bool window, int32_t lo,
-                                                int32_t hi, int wv, int nw, StanzaLds<T>& st, F&& f, E&& batch_end) {
+                                                int32_t hi, int wv, int nw, StanzaLds<T>& st, F&& f, E&& batch_end,
+                                                int* claim = nullptr) {
     const int ln = lane();
     constexpr int64_t WIN = (int64_t)WAVE * STREAM_U;
-    for (int64_t pb = pa0; pb < pa1; pb += WAVE) {
+    const int w0 = claim ? 0 : wv, ws = claim ? 1 : nw;  // this wave's windows of a batch: w0, w0 + ws, ...
+    for (int64_t next = pa0;;) {
+        int64_t pb;
+        if (claim) {
+            const int b = ln == 0 ? atomicAdd(claim, 1) : 0;
+            pb = pa0 + (int64_t)__builtin_amdgcn_readfirstlane(b) * WAVE;
+        } else {
+            pb = next;
+            next += WAVE;
+        }
+        if (pb >= pa1) break;
         const int64_t p = pb + ln;
         int64_t b0 = 0, b1 = 0;
         typename T::in_t a = T::one();
@@ -714,7 +729,7 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
         }
         wave_lds_sync();
         const int64_t my_start = ln < nz ? st.start[ln] : INT64_MAX;
-        for (int64_t base = (int64_t)wv * WIN; base < total; base += (int64_t)nw * WIN) {
+        for (int64_t base = (int64_t)w0 * WIN; base < total; base += (int64_t)ws * WIN) {
             const int before = __popcll(__ballot(my_start < base));
             const int64_t rel = my_start - base;
             if (rel >= 0 && rel < WIN) atomicOr(&st.S[rel >> 6], 1ull << (rel & 63));
@@ -770,6 +785,19 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
         batch_end();
         wave_lds_sync();
     }
+}
+
+// A unit of NW > 1 waves claims whole batches when its A row has at least
+// this many batches of 64 entries per wave (0: never). Fewer batches than
+// that are shared window by window, which balances rows whose products sit
+// in a few long rows of B.
+#ifndef MSP_BATCH_SPLIT_MIN
+#define MSP_BATCH_SPLIT_MIN 2
+#endif
+template <int NW>
+__device__ __forceinline__ int* batch_claim(int* counter, int64_t alen) {
+    return (NW > 1 && MSP_BATCH_SPLIT_MIN > 0 && alen >= (int64_t)MSP_BATCH_SPLIT_MIN * NW * WAVE) ? counter
+                                                                                                  : nullptr;
 }
 
 // Folds the admitted products of one window into the LDS accumulator: slot
@@ -899,6 +927,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
     }
     unit_sync<NW>();
     StanzaLds<T>& S = st[wave];
+    // the waves share every batch's windows: claiming whole batches measured slower with the
+    // 512-column tile (the waves' concurrent LDS updates of the same few columns) and no faster
+    // with the 4096-column one
     stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
                        [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
@@ -952,6 +983,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
     __shared__ acc_t vals[COUNT ? 1 : W];
     __shared__ uint8_t flags[FLAGS ? W : 1];
     __shared__ StanzaLds<T> st[NW];
+    __shared__ int claim;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)), ut = threadIdx.x;
     const int u = __builtin_amdgcn_readfirstlane(g.units[blockIdx.x]);
     const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
@@ -968,6 +1000,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
     if (!COUNT) for (int x = ut; x < wt; x += UT) vals[x] = T::identity();
     if (FLAGS) for (int x = ut; x < wt; x += UT) flags[x] = 0;
     if (lane() < STREAM_U) st[wv].S[lane()] = 0ull;
+    if (ut == 0) claim = 0;
     __syncthreads();
     for (int64_t p = o.Mrp[i] + ut; p < o.Mrp[i + 1]; p += UT) {
         const int c = o.Mci[p];
@@ -994,7 +1027,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
                                c[u] = act[u] && __builtin_amdgcn_ubfe(w[u], (uint32_t)c[u], 1) ? c[u] : -1;
                            window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
                        },
-                       [] {});
+                       [] {}, batch_claim<NW>(&claim, a1 - a0));
     __syncthreads();
     unsigned int* gset = g.gset + (int64_t)sidx * (DENSE_B_COLS / 32);
     acc_t* gval = static_cast<acc_t*>(g.gval) + (int64_t)sidx * DENSE_B_COLS;
@@ -1129,6 +1162,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     __shared__ uint8_t qs_[QVAL ? WPB * NW : 1][QVAL ? QCAP + WAVE : 1];
     __shared__ StanzaLds<T> st[WPB * NW];
     __shared__ int64_t tmp[NW];
+    __shared__ int claim_[WPB];
     // the wave index is the same on every lane: keep it (and what derives from it) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int gi = wave / NW, wv = wave % NW, ut = threadIdx.x % UT;
@@ -1166,6 +1200,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     if (HASHED)
         for (int x = ut; x <= (int)bmask; x += UT) tkey[x] = make_int4(-1, -1, -1, -1);
     if (lane() < STREAM_U) st[wave].S[lane()] = 0ull;
+    if (ut == 0) claim_[gi] = 0;
     unit_sync<NW>();
     for (int x = ut; x < cnt; x += UT) {
         const int32_t key = keys[x];
@@ -1254,7 +1289,8 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
                 lookup_round(qh, (int)(qn - qh));
                 qh = qn;
             }
-        });
+        },
+        batch_claim<NW>(&claim_[gi], o.Arp[i + 1] - o.Arp[i]));
     unit_sync<NW>();
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);

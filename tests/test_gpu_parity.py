@@ -7,7 +7,7 @@ import pytest
 
 import mspgen
 import oracle
-from tests.gpu_util import (assert_same, msp, rand_problem, run_and_check, torch_or_skip, up)
+from tests.gpu_util import (VKIND, assert_same, msp, rand_problem, run_and_check, torch_or_skip, up)
 
 pytestmark = pytest.mark.gpu
 
@@ -260,6 +260,39 @@ def test_split_rows(sr, complement, phase, ncols):
                   "lor_land_bool": "u8", "plus_times_i32": "i32", "plus_times_i64": "i64"}[sr] or None)
     M = mspgen.er(120, ncols, ncols / 6.0, 63, None)
     C, R = run_and_check(A, B, M, complement, sr, phase=phase, force_kind="dense", split_flops=300)
+
+
+def long_a_rows(seed, m, k, sr):
+    """Rows of A with 3 to 2500 entries: some below and some above the length
+    at which a workgroup's waves take whole batches of 64 A entries (8
+    batches), most with a ragged last batch."""
+    rng = np.random.default_rng(seed)
+    degs = rng.choice([3, 300, 511, 513, 700, 1500, 2500], size=m)
+    rows = np.repeat(np.arange(m), degs)
+    cols = np.concatenate([rng.choice(k, size=d, replace=False) for d in degs])
+    A = mspgen.from_coo(m, k, rows, cols)
+    return A.with_values(mspgen.random_values(A.nnz, VKIND[sr], rng))
+
+
+@pytest.mark.parametrize("ncols", [400, 9000])
+@pytest.mark.parametrize("kind", ["auto", "dense", "hash", "maskidx", "split"])
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64", "lor_land_bool", "plus_times_i32"])
+@pytest.mark.parametrize("complement", [False, True])
+def test_long_a_rows_claim_whole_batches(ncols, kind, sr, complement):
+    """Long rows of A: the waves of a workgroup claim whole batches from a
+    shared counter instead of sharing the windows of every batch. Forced
+    kinds, both mask modes, and (n <= 512) rows split over workgroups whose
+    chunks are long enough to claim batches too."""
+    if kind == "split" and ncols > 512:
+        pytest.skip("split rows are dense rows of at most 512 columns")
+    if complement and kind in ("hash", "maskidx"):
+        pytest.skip("a complemented mask takes only the dense and heap kinds")
+    A = long_a_rows(31, 40, 6000, sr)
+    B = mspgen.er(6000, ncols, 3.0, 32, VKIND[sr])
+    M = mspgen.er(40, ncols, ncols / 8.0, 33, None)
+    kw = dict(force_kind="dense", split_flops=2000) if kind == "split" else dict(force_kind=kind)
+    for phase in (1, 2):
+        run_and_check(A, B, M, complement, sr, phase=phase, **kw)
 
 
 def test_split_rows_in_batch():
