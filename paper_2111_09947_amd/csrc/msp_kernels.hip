@@ -1090,7 +1090,7 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t j, int tbits) {
 }
 
 // Bucketed open addressing: buckets of 4 keys (16 bytes, -1 = empty) filled
-// in slot order, at most one key per bucket on average; the mask rank of a
+// in slot order, at most two keys per bucket on average; the mask rank of a
 // key sits in a parallel table. One 16-byte LDS read settles a lookup unless
 // the home bucket is full without holding the key, in which case the next
 // buckets are read (linear probing over buckets).
@@ -1125,6 +1125,14 @@ __device__ __forceinline__ int hash_find(const int4* tkey, const uint16_t* trank
 // full lane occupancy instead of once per product. The ring is drained at
 // the end of every batch of A entries (candidates refer to that batch's A
 // values).
+// Hash table size: buckets of four slots, at least (keys >> shift) of them.
+// Shift 1 fills at most half of the slots, in half the LDS of shift 0: one
+// more workgroup of the 512-key block kernel per CU, which outweighs the
+// longer probes.
+#ifndef MSP_HASH_BUCKET_SHIFT
+#define MSP_HASH_BUCKET_SHIFT 1
+#endif
+
 template <int CAP, bool QVAL>
 struct MaskKeyCfg {
     static constexpr int FILTER_WORDS = CAP < 1024 ? CAP : 1024;  // <= 1 key per 32 bits up to 1024 keys
@@ -1143,7 +1151,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     constexpr bool COUNT = MODE == MODE_COUNT;
     constexpr bool FLAGS = COUNT || T::sep_flag;
     constexpr bool QVAL = !COUNT && T::needs_values;  // candidates carry the positions of their values
-    constexpr int NBK = HASHED ? CAP : 1;             // buckets (4 slots each)
+    constexpr int HSHIFT = MSP_HASH_BUCKET_SHIFT;      // buckets >= keys >> HSHIFT
+    static_assert(HSHIFT >= 0 && HSHIFT <= 1, "at most two keys per bucket of four slots");
+    constexpr int NBK = HASHED ? CAP >> HSHIFT : 1;   // buckets (4 slots each)
     constexpr int UT = NW * WAVE;
     constexpr int FW = MaskKeyCfg<CAP, QVAL>::FILTER_WORDS;
     constexpr int FW_BITS = __builtin_ctz(FW);
@@ -1193,7 +1203,9 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     }
     int bbits = 1;
     while ((1 << bbits) < cnt) ++bbits;
-    const uint32_t bmask = (1u << bbits) - 1u;
+    // the hash table's buckets: 2^hbits >= cnt >> HSHIFT, so at most half of the slots fill
+    const int hbits = max(1, bbits - HSHIFT);
+    const uint32_t bmask = (1u << hbits) - 1u;
     // the filter uses about one word (32 bits) per key: at most 1 bit in 32 set
     const int fwb = min(bbits, FW_BITS);
     for (int x = ut; x < (1 << fwb); x += UT) filt[x] = 0u;
@@ -1207,7 +1219,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
         atomicOr(&filt[(key >> 5) & ((1 << fwb) - 1)], 1u << (key & 31));
         if (HASHED) {
             int32_t* slots = reinterpret_cast<int32_t*>(tkey);
-            uint32_t b = hash_slot(key, bbits);
+            uint32_t b = hash_slot(key, hbits);
             int sl = 0;
             while (atomicCAS(&slots[b * 4 + sl], -1, key) != -1) {
                 if (++sl == 4) { sl = 0; b = (b + 1) & bmask; }
@@ -1227,7 +1239,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
         const int x = lane();
         const int e = (int)((base + (uint32_t)x) & (QCAP - 1));
         const int32_t jv = x < count ? qj[e] : INT32_MIN;  // an idle lane looks up a column no mask holds
-        const int r = HASHED ? hash_find(tkey, trank, bmask, bbits, jv) : rank_search(keys, cnt, top, jv);
+        const int r = HASHED ? hash_find(tkey, trank, bmask, hbits, jv) : rank_search(keys, cnt, top, jv);
         if (r >= 0) {
             if (FLAGS) flags[r] = 1;
             if (!COUNT) {
