@@ -657,7 +657,7 @@ template <class T>
 struct StanzaLds {
     int64_t start[WAVE];
     uint64_t ptr[WAVE];  // byte address that flattened position 0 would have in B's column indices
-    typename T::in_t a[WAVE];
+    typename T::in_t a[T::needs_values ? WAVE : 1];  // semirings that ignore values keep none
     unsigned long long S[STREAM_U];
 };
 
@@ -725,7 +725,7 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
             const int sl = rank_below(nzm);
             st.start[sl] = incl - len;
             st.ptr[sl] = (uint64_t)(o.Bci + b0) - 4ull * (uint64_t)(incl - len);
-            if (T::needs_values) st.a[sl] = a;
+            if constexpr (T::needs_values) st.a[sl] = a;
         }
         wave_lds_sync();
         const int64_t my_start = ln < nz ? st.start[ln] : INT64_MAX;
@@ -823,7 +823,11 @@ __device__ __forceinline__ void window_accumulate(const int* slot, const int* s,
     for (int u = 0; u < STREAM_U; ++u) {
         if (slot[u] >= 0) {
             if (FLAGS) flags[slot[u]] = 1;
-            if (!COUNT) T::lds_add(&vals[slot[u]], T::term(T::needs_values ? st.a[s[u]] : T::one(), b[u]));
+            if constexpr (!COUNT) {
+                typename T::in_t av = T::one();
+                if constexpr (T::needs_values) av = st.a[s[u]];
+                T::lds_add(&vals[slot[u]], T::term(av, b[u]));
+            }
         }
     }
 }
@@ -1137,8 +1141,9 @@ template <int CAP, bool QVAL>
 struct MaskKeyCfg {
     static constexpr int FILTER_WORDS = CAP < 1024 ? CAP : 1024;  // <= 1 key per 32 bits up to 1024 keys
     // candidates are appended DRAIN slots at a time before full rounds are looked up, so the
-    // ring holds up to 63 waiting + 64 * DRAIN new ones (entries with value positions are larger)
-    static constexpr int DRAIN = QVAL ? 1 : 2;
+    // ring holds up to 63 waiting + 64 * DRAIN new ones (entries with value positions are larger;
+    // the one-wave kernels, CAP <= 256, keep the smaller ring for occupancy)
+    static constexpr int DRAIN = QVAL || CAP <= 256 ? 1 : 2;
     static constexpr int QCAP = DRAIN == 1 ? 2 * WAVE : (DRAIN == 2 ? 4 * WAVE : 8 * WAVE);
     static_assert(WAVE - 1 + WAVE * DRAIN <= QCAP, "candidate ring too small");
 };
@@ -1244,7 +1249,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
             if (FLAGS) flags[r] = 1;
             if (!COUNT) {
                 typename T::in_t av = T::one(), bv = T::one();
-                if (QVAL) {
+                if constexpr (QVAL) {
                     if (o.Bv) bv = T::load_at(va.at(qq[e]));
                     av = S.a[qs[e]];
                 }
