@@ -295,6 +295,44 @@ def test_long_a_rows_claim_whole_batches(ncols, kind, sr, complement):
         run_and_check(A, B, M, complement, sr, phase=phase, **kw)
 
 
+def colliding_columns(count, bits, n):
+    """The first `count` columns below n whose multiplicative hash (the odd
+    constant 0x9E3779B1, top `bits` bits) is 0: keys that all share one home
+    bucket, so the table's probe chains are as long as they can be."""
+    j = np.arange(n, dtype=np.uint64)
+    h = ((j * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - bits)
+    cols = np.nonzero(h == 0)[0][:count]
+    assert len(cols) == count
+    return cols.astype(np.int64)
+
+
+@pytest.mark.parametrize("keys", [200, 300, 512])
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64"])
+def test_hash_keys_sharing_one_bucket(keys, sr):
+    """Mask rows whose keys all hash to the same bucket (worst-case linear
+    probing, both for inserting the keys and for looking up columns that are
+    not keys), under the forced hash kind (one wave for at most 256 keys,
+    a block above) and the automatic choice."""
+    rng = np.random.default_rng(keys)
+    n, k, m = 1 << 18, 400, 12
+    hot = colliding_columns(keys, 8, n)
+    M = mspgen.from_coo(m, n, np.repeat(np.arange(m), keys), np.tile(hot, m))
+    # rows of B mix key columns (hits) with other columns that often share their home bucket
+    near = colliding_columns(keys + 400, 8, n)[keys:]
+    rows, cols = [], []
+    for r in range(k):
+        c = np.unique(np.concatenate([rng.choice(hot, 6, replace=False), rng.choice(near, 6, replace=False),
+                                      rng.integers(0, n, 4)]))
+        rows.append(np.full(len(c), r))
+        cols.append(c)
+    B = mspgen.from_coo(k, n, np.concatenate(rows), np.concatenate(cols))
+    B = B.with_values(mspgen.random_values(B.nnz, VKIND[sr], rng))
+    A = mspgen.er(m, k, 60.0, keys + 1, VKIND[sr])
+    for kind in ("hash", "auto"):
+        for phase in (1, 2):
+            run_and_check(A, B, M, False, sr, phase=phase, force_kind=kind)
+
+
 def test_split_rows_in_batch():
     torch = torch_or_skip()
     m = msp()
