@@ -295,6 +295,30 @@ def test_long_a_rows_claim_whole_batches(ncols, kind, sr, complement):
         run_and_check(A, B, M, complement, sr, phase=phase, **kw)
 
 
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64"])
+def test_long_a_rows_claim_whole_batches_in_batch(sr):
+    """The same long rows of A in a batch of products (the batched kernels
+    read each unit's operands from the descriptor table), replayed from a
+    graph twice."""
+    torch = torch_or_skip()
+    m = msp()
+    probs = []
+    for t, (n, comp) in enumerate([(400, False), (9000, False), (400, True), (9000, True)]):
+        A = long_a_rows(40 + t, 30, 5000, sr)
+        B = mspgen.er(5000, n, 3.0, 50 + t, VKIND[sr])
+        M = mspgen.er(30, n, n / 8.0, 60 + t, None)
+        probs.append((A, B, M, comp))
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr) as b:
+            b.bind_new_outputs()
+            for _ in range(2):
+                b.graph_launch()
+                for (A, B, M, c), C in zip(probs, b.results()):
+                    assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
+
+
 def colliding_columns(count, bits, n):
     """The first `count` columns below n whose multiplicative hash (the odd
     constant 0x9E3779B1, top `bits` bits) is 0: keys that all share one home
