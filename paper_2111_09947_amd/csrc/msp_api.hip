@@ -770,6 +770,24 @@ static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream
         ab.units = P->bin_units + P->bin_off[b] - before;
         ab.nunits = P->bin_count[b] + after + before;
         if (tm) MSP_CHECK(tm->begin(b));
+        // the mask-indexed block bin's heaviest units (its first buckets) in a wider launch
+        const int64_t wide = b == BIN_MASKIDX_B && MASKIDX_B_WIDE_BUCKET > 0
+                                 ? P->seg_off[b * NBUCKET + MASKIDX_B_WIDE_BUCKET - 1] - P->bin_off[b]
+                                 : 0;
+        if (wide > 0) {
+            NumArgs aw = a;
+            aw.units = P->bin_units + P->bin_off[b];
+            aw.nunits = wide;
+            MSP_HIP(launch_numeric(P->sr, LAUNCH_MASKIDX_B_WIDE, mode, aw, s));
+            if (before > 0) {  // the folded heap units that precede the bin
+                NumArgs ah = a;
+                ah.units = P->bin_units + P->bin_off[b] - before;
+                ah.nunits = before;
+                MSP_HIP(launch_numeric(P->sr, b, mode, ah, s));
+            }
+            ab.units = P->bin_units + P->bin_off[b] + wide;
+            ab.nunits = P->bin_count[b] - wide;
+        }
         MSP_HIP(launch_numeric(P->sr, b, mode, ab, s));
         if (tm) MSP_CHECK(tm->end());
     }

@@ -52,6 +52,17 @@ constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 #define MSP_MASKIDX_B_NW 4
 #endif
 constexpr int MASKIDX_B_NW = MSP_MASKIDX_B_NW;  // waves per block of the mask-indexed block kind
+// The mask-indexed block bin's heaviest units (rows of at least
+// 4^MASKIDX_B_WIDE_BUCKET products, 0: none) run in a launch of their own
+// with MASKIDX_B_WIDE_NW waves per unit: such rows have many batches of A
+// entries for the waves to claim, and the extra waves hide the latency of
+// the search lookups. Lighter units would leave the extra waves idle.
+#ifndef MSP_MASKIDX_B_WIDE_BUCKET
+#define MSP_MASKIDX_B_WIDE_BUCKET 8
+#endif
+constexpr int MASKIDX_B_WIDE_BUCKET = MSP_MASKIDX_B_WIDE_BUCKET;
+constexpr int MASKIDX_B_WIDE_NW = 8;
+constexpr int LAUNCH_MASKIDX_B_WIDE = NBINS;  // launch id (not a bin) of that kernel
 constexpr int HEAP_CAP = 8;       // heap kind: iterators per row (entries of the row of A)
 constexpr int64_t HEAP_MAX_FLOPS = (int64_t(1) << 24) - 1;  // heap keys hold a B row's remaining length in 24 bits
 constexpr int64_t HEAP_LONG_MASK_RATIO = 8;  // auto HEAP also when the mask row has >= this many entries per product

@@ -1643,6 +1643,10 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
         MSP_LAUNCH((k_maskkey<SR, MODE, MASKIDX_B_NW, MASKIDX_B_CAP, false, 1, BATCH>), gb,
                    dim3(MASKIDX_B_NW * WAVE), 0, s, a);
         break;
+    case LAUNCH_MASKIDX_B_WIDE:
+        MSP_LAUNCH((k_maskkey<SR, MODE, MASKIDX_B_WIDE_NW, MASKIDX_B_CAP, false, 1, BATCH>), gb,
+                   dim3(MASKIDX_B_WIDE_NW * WAVE), 0, s, a);
+        break;
     case BIN_INNER_W:
         MSP_LAUNCH((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB, BATCH>), gw, bw, 0, s, a);
         break;
