@@ -173,8 +173,9 @@ typedef struct msp_options {
                              rows of 257 to 2048 entries: a small heap launch
                              costs more than it saves. */
     int64_t block_flops;  /* rows with more products than this run on a whole
-                             256-thread workgroup instead of one wavefront
-                             (-1 = default 8192) */
+                             workgroup (256 threads; 512 for mask-indexed
+                             rows of at least 65536 products) instead of
+                             one wavefront (-1 = default 8192) */
     int64_t split_flops;  /* dense-kind rows (at most 4096 columns) with more
                              products than this are split over several
                              workgroups by chunks of A's row (-1 = default
@@ -202,7 +203,8 @@ typedef struct msp_plan_info_t {
 /*
  * Kernel bins: every work unit runs in the numeric kernel of its bin. The
  * "wave" bins give one wavefront per unit, the "block" bins one 256-thread
- * workgroup per unit.
+ * workgroup per unit (512 threads for the units of MSP_BIN_MASKIDX_BLOCK
+ * whose row has at least 65536 products).
  */
 enum {
     MSP_BIN_DENSE_WAVE = 0,
