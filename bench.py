@@ -661,7 +661,7 @@ def run_serve(args):
         with msp.Plan(A, B, M, complement=c, semiring="plus_pair_i64") as p:
             C = p.execute()
             it["useful"] = int(C.values.sum().item())
-        it["est"] = {sr: serve.estimate_bytes(A, B, M, c, 8) for sr in ("plus_pair_i64", "plus_times_f64")}
+        it["bytes"] = {sr: serve.product_bytes(A, B, M, c, sr) for sr in ("plus_pair_i64", "plus_times_f64")}
 
     def draw(n, seed):
         r = np.random.default_rng(seed)
@@ -674,7 +674,7 @@ def run_serve(args):
         def mk(i):
             k, sr = seq[i]
             it = pool[k]
-            return serve.Request(rid=i, semiring=sr, operands=it["ops"], est_bytes=it["est"][sr])
+            return serve.Request(rid=i, semiring=sr, operands=it["ops"], mem_bytes=it["bytes"][sr])
         return mk
 
     mem_budget = 64 << 30

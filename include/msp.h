@@ -32,6 +32,12 @@
  *  - Dimension rule: A.ncols == B.nrows, M.nrows == A.nrows,
  *    M.ncols == B.ncols; a violation returns MSP_ERR_DIMENSION_MISMATCH.
  *    Empty shapes (m, n or k = 0, nnz = 0) are valid and give an empty C.
+ *  - Device memory: the library allocates none. Every device buffer it works
+ *    in is the caller's: the operands, the outputs, and workspaces whose
+ *    sizes the *_workspace_size queries give (see "Workspaces" below). A
+ *    workspace smaller than its query's size returns
+ *    MSP_ERR_INSUFFICIENT_CAPACITY before any work is enqueued. Workspaces
+ *    need no initialisation: the library clears what it uses.
  */
 #ifndef MSP_H
 #define MSP_H
@@ -230,24 +236,60 @@ enum {
     MSP_STAGE_ROWPTR = 18,    /* row pointers of C */
     MSP_STAGE_COMPACT = 19,   /* one-phase staging -> C */
     MSP_STAGE_SPLIT_EMIT = 20,  /* emission of the split rows */
-    MSP_NSTAGES = 21
+    MSP_STAGE_PLACE = 21,       /* placement of the work units in the execution workspace */
+    MSP_NSTAGES = 22
 };
 
 typedef struct msp_plan msp_plan;
 
 /*
+ * ---- Workspaces ----
+ * A plan works in two caller-owned device buffers (any device allocation
+ * aligned to 256 bytes, e.g. a torch tensor of bytes):
+ *  - the PLAN workspace, given to msp_plan_create and held by the plan until
+ *    msp_plan_destroy (the caller keeps it alive and does not touch it):
+ *    per-row product counts, tile counts and bins, the plan statistics, the
+ *    unit-list segment offsets, and B^T when the inner kind may run. Its
+ *    size depends only on the operands' shapes and nnz, so
+ *    msp_plan_workspace_size computes it on the host without GPU work.
+ *  - the EXECUTION workspace, given to every call that runs the product
+ *    (msp_execute*, msp_symbolic, msp_numeric, msp_batch_bind): the work-unit
+ *    lists (placed at the start of each such call), per-unit counts and
+ *    prefix sums, the one-phase staging (Section "Symbolic and Numeric
+ *    Phases": the output of the one-phase method is written to storage sized
+ *    by an upper bound and then copied), and the accumulators of rows split
+ *    over several workgroups. Its size depends on the binning, known after
+ *    msp_plan_create: msp_workspace_size. Its contents matter only within a
+ *    call, except from msp_symbolic to msp_numeric, and from msp_batch_bind
+ *    to the batch's executions.
+ * Executions of one plan with DIFFERENT execution workspaces may run
+ * concurrently on different streams; two executions that share one
+ * workspace must be ordered by the caller. A plan is used by one host thread
+ * at a time.
+ */
+
+/* Plan workspace bytes for these operands and options (host only; the same
+   argument checks as msp_plan_create). */
+msp_status msp_plan_workspace_size(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                                   msp_semiring semiring, const msp_options* opt, size_t* bytes);
+
+/*
  * Analyse the operands and bind a plan to them (row analysis and row
  * binning). Computes per row the product count
  * flops_i = sum over stored A(i,k) of nnz(B(k,:)), the mask count, the
- * output bound, and the accumulator kind and tiling; then places every work
- * unit in its kind's bin. Allocates the plan's device workspace
- * (stream-ordered) and SYNCHRONIZES `stream` once to read the sizes.
- * The operands must stay alive and unchanged while the plan is used.
- * `opt` may be NULL (defaults).
+ * output bound, and the accumulator kind and tiling, and counts the work
+ * units of every bin. Works in `workspace` (device, workspace_bytes >=
+ * msp_plan_workspace_size), which the plan holds until msp_plan_destroy,
+ * and SYNCHRONIZES `stream` once to read the sizes. The operands must stay
+ * alive and unchanged while the plan is used. `opt` may be NULL (defaults).
  */
 msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
                            int complement, msp_semiring semiring, const msp_options* opt,
-                           void* stream);
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* Execution workspace bytes of a plan or batch (host; for a single-product
+   plan, those of its phase: the one-phase bytes include the staging). */
+msp_status msp_workspace_size(const msp_plan* plan, size_t* bytes);
 
 /* Copies the plan's statistics into `info` (host). */
 msp_status msp_plan_info(const msp_plan* plan, msp_plan_info_t* info);
@@ -255,15 +297,22 @@ msp_status msp_plan_info(const msp_plan* plan, msp_plan_info_t* info);
 /*
  * Two-phase, symbolic step: counts nnz(C(i,:)) from indices only and writes
  * the row pointers of C into C_rowptr (device, nrows + 1). If nnz_host is not
- * NULL, SYNCHRONIZES and stores nnz(C) there.
+ * NULL, SYNCHRONIZES and stores nnz(C) there. The execution workspace keeps
+ * the unit lists and counts for msp_numeric.
  */
-msp_status msp_symbolic(msp_plan* plan, int64_t* C_rowptr, int64_t* nnz_host, void* stream);
+msp_status msp_symbolic(msp_plan* plan, int64_t* C_rowptr, int64_t* nnz_host, void* workspace,
+                        size_t workspace_bytes, void* stream);
 
 /*
  * Two-phase, numeric step (after msp_symbolic on the same plan, with the same
- * C->rowptr): writes colidx and values of C. C->capacity must be >= nnz(C).
+ * C->rowptr and the same, untouched execution workspace): writes colidx and
+ * values of C. C->capacity must be >= nnz(C): when msp_symbolic did not
+ * return nnz(C) and the capacity is below the plan's upper bound, this call
+ * SYNCHRONIZES once to read nnz(C). A short capacity returns
+ * MSP_ERR_INSUFFICIENT_CAPACITY before any kernel runs.
  */
-msp_status msp_numeric(msp_plan* plan, msp_csr_out* C, void* stream);
+msp_status msp_numeric(msp_plan* plan, msp_csr_out* C, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 /*
  * Runs the whole product on a plan: phase 1 (numeric into staging sized by
@@ -272,10 +321,12 @@ msp_status msp_numeric(msp_plan* plan, msp_csr_out* C, void* stream);
  * Phase 1 needs C->capacity >= info.upper_bound; phase 2 needs
  * C->capacity >= nnz(C) and SYNCHRONIZES once to check it.
  * If nnz_host is not NULL, SYNCHRONIZES and stores nnz(C) there.
- * May be called repeatedly on one plan (e.g. after the values of A or B
- * changed in place).
+ * Works in the execution workspace (device, workspace_bytes >=
+ * msp_workspace_size). May be called repeatedly on one plan (e.g. after the
+ * values of A or B changed in place).
  */
-msp_status msp_execute(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* stream);
+msp_status msp_execute(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* workspace,
+                       size_t workspace_bytes, void* stream);
 
 /*
  * msp_execute with timing: records HIP events on `stream` around every
@@ -283,8 +334,8 @@ msp_status msp_execute(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* 
  * stage_ms[MSP_NSTAGES] (host; stages that did not run add 0). For
  * measurement; the results are those of msp_execute.
  */
-msp_status msp_execute_profiled(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, double* stage_ms,
-                                void* stream);
+msp_status msp_execute_profiled(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* workspace,
+                                size_t workspace_bytes, double* stage_ms, void* stream);
 
 /*
  * Timing sessions: stage timing without a synchronization per execution.
@@ -301,8 +352,8 @@ typedef struct msp_timing msp_timing;
    (MSP_STAGE_* or a bin number); 0 times every stage. Each timed stage costs
    the events attached to its launches. */
 msp_status msp_timing_create(msp_timing** timing, int32_t executions, uint32_t stages);
-msp_status msp_execute_timed(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, msp_timing* timing,
-                             void* stream);
+msp_status msp_execute_timed(msp_plan* plan, msp_csr_out* C, int64_t* nnz_host, void* workspace,
+                             size_t workspace_bytes, msp_timing* timing, void* stream);
 msp_status msp_timing_collect(msp_timing* timing, double* stage_ms);
 void msp_timing_destroy(msp_timing* timing);
 
@@ -310,32 +361,47 @@ void msp_timing_destroy(msp_timing* timing);
    possible output) into bins (host, nrows entries). SYNCHRONIZES. */
 msp_status msp_plan_row_bins(const msp_plan* plan, int8_t* bins, void* stream);
 
-/* Releases the plan's device workspace (stream-ordered on the plan's stream). */
+/* Releases the plan's host state and graph. The plan frees no device memory
+   (its workspaces are the caller's); the caller may reuse them once the work
+   it enqueued with the plan has finished. */
 void msp_plan_destroy(msp_plan* plan);
 
 /*
- * One-shot product: plan, execute, destroy. C->capacity must be at least the
- * upper bound (phase 1) or nnz(C) (phase 2); otherwise returns
- * MSP_ERR_INSUFFICIENT_CAPACITY and writes the bound into *nnz_host when it
- * is not NULL. SYNCHRONIZES.
+ * One-shot product: plan, execute, destroy, in ONE caller-owned device
+ * workspace that holds the plan workspace followed by the execution
+ * workspace. C->capacity must be at least the upper bound (phase 1) or
+ * nnz(C) (phase 2); otherwise returns MSP_ERR_INSUFFICIENT_CAPACITY and
+ * writes the bound into *nnz_host when it is not NULL. A workspace that is
+ * too small returns MSP_ERR_INSUFFICIENT_CAPACITY and, when ws_needed is not
+ * NULL, the bytes needed: the plan workspace alone if even that does not
+ * fit (a second call then learns the whole size), else the whole size.
+ * SYNCHRONIZES.
  */
 msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
                              msp_semiring semiring, const msp_options* opt, msp_csr_out* C,
-                             int64_t* nnz_host, void* stream);
+                             int64_t* nnz_host, void* workspace, size_t workspace_bytes, size_t* ws_needed,
+                             void* stream);
 
-/* Exact per-row output bound summed over rows (see msp_plan_info_t).
+/* Exact per-row output bound summed over rows (see msp_plan_info_t), by the
+   row analysis in `workspace` (device, at least msp_plan_workspace_size of
+   the same operands under MSP_PLUS_PAIR_I64 and default options).
    SYNCHRONIZES. */
 msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
-                           int64_t* upper_bound, void* stream);
+                           int64_t* upper_bound, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * (+)-reduction of n output values of the semiring's output type into one
  * value written to `result` (device, one element of the output type); the
  * post-reduction of triangle counting (sum of L .* (L L), Section "Triangle
  * Counting"). Deterministic for a given n. n = 0 writes the identity.
+ * Works in `workspace` (device, at least msp_reduce_workspace_size bytes).
  */
 msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result,
-                      void* stream);
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of msp_reduce and msp_reduce_csr (the per-block partial
+   sums; the same for every n). */
+msp_status msp_reduce_workspace_size(size_t* bytes);
 
 /*
  * msp_reduce over the entries of an output CSR without reading its size on
@@ -344,7 +410,8 @@ msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void
  * `values`). Does not synchronize.
  */
 msp_status msp_reduce_csr(const int64_t* rowptr, int64_t nrows, const void* values, int64_t capacity,
-                          msp_semiring semiring, void* result, void* stream);
+                          msp_semiring semiring, void* result, void* workspace, size_t workspace_bytes,
+                          void* stream);
 
 /*
  * ---- Batches: many products in one set of launches ----
@@ -361,9 +428,16 @@ typedef struct msp_problem {
     int32_t reserved;     /* 0 */
 } msp_problem;
 
-/* Analyses and bins all products (one synchronization). */
+/* Plan workspace bytes of a batch (host only). */
+msp_status msp_batch_workspace_size(const msp_problem* problems, int64_t count, msp_semiring semiring,
+                                    const msp_options* opt, size_t* bytes);
+
+/* Analyses and bins all products (one synchronization) in the plan
+   workspace (device, at least msp_batch_workspace_size bytes), which the
+   batch holds until msp_plan_destroy. */
 msp_status msp_batch_create(msp_plan** batch, const msp_problem* problems, int64_t count,
-                            msp_semiring semiring, const msp_options* opt, void* stream);
+                            msp_semiring semiring, const msp_options* opt, void* workspace,
+                            size_t workspace_bytes, void* stream);
 
 /* Number of products of a batch (1 for a single-product plan). */
 int64_t msp_batch_count(const msp_plan* batch);
@@ -371,9 +445,14 @@ int64_t msp_batch_count(const msp_plan* batch);
 /* Statistics of product p (0 <= p < count), or of all products (p = -1). */
 msp_status msp_batch_info(const msp_plan* batch, int64_t p, msp_plan_info_t* info);
 
-/* Binds the outputs C[0..count) (capacity of C[p] >= its upper bound).
-   SYNCHRONIZES. Invalidates a previously captured graph. */
-msp_status msp_batch_bind(msp_plan* batch, const msp_csr_out* C, void* stream);
+/* Binds the outputs C[0..count) (capacity of C[p] >= its upper bound) and
+   the execution workspace (device, at least msp_workspace_size bytes), and
+   places the work units there; the batch's executions use both until the
+   next bind or msp_plan_destroy, so the caller keeps them alive and leaves
+   the workspace untouched. SYNCHRONIZES. Invalidates a previously captured
+   graph. */
+msp_status msp_batch_bind(msp_plan* batch, const msp_csr_out* C, void* workspace, size_t workspace_bytes,
+                          void* stream);
 
 /* Enqueues the whole batch on `stream`: kernels only, no allocation, no
    memset and no synchronization, so the sequence may be captured. */
@@ -386,6 +465,24 @@ msp_status msp_batch_graph_launch(msp_plan* batch, void* stream);
 
 /* nnz of every product's output into nnz[0..count) (host). SYNCHRONIZES. */
 msp_status msp_batch_nnz(const msp_plan* batch, int64_t* nnz, void* stream);
+
+/*
+ * Device memory of the iterated products below, whose sizes depend on the
+ * data (every level or iteration sizes the next): the library asks the
+ * caller's allocator for each buffer and returns it when done.
+ *  alloc(ctx, bytes, stream)   device memory of at least `bytes` bytes,
+ *                              256-byte aligned, usable by work enqueued on
+ *                              `stream`; NULL when none is left (the call
+ *                              then returns MSP_ERR_OUT_OF_MEMORY).
+ *  release(ctx, ptr, stream)   `ptr` (from alloc) may be reused by work
+ *                              enqueued on `stream` after this point.
+ * Every buffer is released before the call returns, on success or error.
+ */
+typedef struct msp_allocator {
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*release)(void* ctx, void* ptr, void* stream);
+    void* ctx;
+} msp_allocator;
 
 /*
  * Betweenness-centrality dependencies of a batch of sources (Section
@@ -406,9 +503,11 @@ msp_status msp_batch_nnz(const msp_plan* batch, int64_t* nnz, void* stream);
  *           halved). The caller zeroes it for a fresh result.
  *  info     optional host struct filled with level and product counts and
  *           the wall time of each stage.
- * Allocates its working memory on `stream`; SYNCHRONIZES (every level sizes
- * the next). Errors: MSP_ERR_DIMENSION_MISMATCH (A not square),
- * MSP_ERR_INVALID_ARGUMENT (NULL pointers, a source out of range).
+ *  mem      the caller's allocator (required) for every working buffer.
+ * SYNCHRONIZES (every level sizes the next). Errors:
+ * MSP_ERR_DIMENSION_MISMATCH (A not square), MSP_ERR_INVALID_ARGUMENT (NULL
+ * pointers, a source out of range), MSP_ERR_OUT_OF_MEMORY (alloc returned
+ * NULL).
  */
 typedef struct msp_bc_info {
     int64_t levels;            /* D: frontiers F_1..F_D were non-empty */
@@ -420,7 +519,7 @@ typedef struct msp_bc_info {
 } msp_bc_info_t;
 
 msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int64_t nsrc, double* bc,
-                        msp_bc_info_t* info, void* stream);
+                        msp_bc_info_t* info, const msp_allocator* mem, void* stream);
 
 /*
  * k-truss (Section "Experimental Setup": the edges supported by at least
@@ -440,7 +539,8 @@ msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int64_t nsrc, 
  *  nnz_host   host: nnz of the truss.
  *  info       optional: iterations, products summed over all iterations,
  *             wall time.
- * Allocates its working memory on `stream`; SYNCHRONIZES every iteration.
+ *  mem        the caller's allocator (required) for every working buffer.
+ * SYNCHRONIZES every iteration.
  */
 typedef struct msp_ktruss_info {
     int64_t iterations;
@@ -449,7 +549,7 @@ typedef struct msp_ktruss_info {
 } msp_ktruss_info_t;
 
 msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr, int32_t* C_colidx, int64_t* C_support,
-                      int64_t* nnz_host, msp_ktruss_info_t* info, void* stream);
+                      int64_t* nnz_host, msp_ktruss_info_t* info, const msp_allocator* mem, void* stream);
 
 /* Static message for a status code. */
 const char* msp_status_string(msp_status status);

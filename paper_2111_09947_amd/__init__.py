@@ -114,6 +114,45 @@ def _check(st: int, where: str):
         raise MspError(st, where)
 
 
+def _workspace(nbytes: int, device):
+    """A caller-owned device workspace of nbytes bytes (a torch tensor; the
+    caching allocator's blocks are 512-byte aligned, the library needs 256)."""
+    t = _torch()
+    ws = t.empty(max(int(nbytes), 1), dtype=t.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+class _TorchAllocator:
+    """msp_allocator over torch device tensors: the library's iterated
+    products (betweenness centrality, k-truss) take every working buffer from
+    here, on the current stream, and release it in stream order."""
+
+    def __init__(self, device):
+        self.device = device
+        self.held = {}
+        self.peak = 0
+        self.in_use = 0
+        self._alloc = L.ALLOC_FN(self._on_alloc)
+        self._release = L.RELEASE_FN(self._on_release)
+        self.struct = L.MspAllocator(self._alloc, self._release, None)
+
+    def _on_alloc(self, ctx, nbytes, stream):
+        try:
+            t = _workspace(nbytes, self.device)
+        except Exception:  # out of memory: the library reports MSP_ERR_OUT_OF_MEMORY
+            return None
+        self.held[t.data_ptr()] = t
+        self.in_use += t.numel()
+        self.peak = max(self.peak, self.in_use)
+        return t.data_ptr()
+
+    def _on_release(self, ctx, ptr, stream):
+        t = self.held.pop(ptr, None)
+        if t is not None:
+            self.in_use -= t.numel()
+
+
 def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio: int = 0,
             b_transpose: Optional[L.MspCsr] = None, maskidx_max: int = -1,
             block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1) -> L.MspOptions:
@@ -151,11 +190,21 @@ class Plan:
                             split_flops, heap_flops)
         self.phase = phase
         self.nrows, self.ncols = A.nrows, B.ncols
+        self.device = A.rowptr.device
+        cv = int(bool(complement))
+        nb = ctypes.c_size_t(0)
+        _check(lib.msp_plan_workspace_size(*(ctypes.byref(v) for v in self._views), cv, SEMIRINGS[semiring],
+                                           ctypes.byref(self._opt), ctypes.byref(nb)), "msp_plan_workspace_size")
+        self.plan_workspace_bytes = nb.value
+        self._pws = _workspace(nb.value, self.device)
         h = ctypes.c_void_p()
-        st = lib.msp_plan_create(ctypes.byref(h), *(ctypes.byref(v) for v in self._views),
-                                 int(bool(complement)), SEMIRINGS[semiring], ctypes.byref(self._opt), _stream())
+        st = lib.msp_plan_create(ctypes.byref(h), *(ctypes.byref(v) for v in self._views), cv, SEMIRINGS[semiring],
+                                 ctypes.byref(self._opt), ctypes.c_void_p(self._pws.data_ptr()), nb.value, _stream())
         _check(st, "msp_plan_create")
         self._h = h
+        _check(lib.msp_workspace_size(self._h, ctypes.byref(nb)), "msp_workspace_size")
+        self.workspace_bytes = nb.value
+        self._xws = None
         info = L.MspPlanInfo()
         _check(lib.msp_plan_info(self._h, ctypes.byref(info)), "msp_plan_info")
         self.upper_bound = info.upper_bound
@@ -165,6 +214,16 @@ class Plan:
         self.mask_nnz = info.mask_nnz
         self.kind_units = {k: info.kind_units[i] for i, k in enumerate(["dense", "hash", "maskidx", "inner", "heap"])}
         self.bin_units = {k: info.bin_units[i] for i, k in enumerate(L.BIN_NAMES)}
+
+    def workspace(self):
+        """The execution workspace (allocated on first use, then reused)."""
+        if self._xws is None:
+            self._xws = _workspace(self.workspace_bytes, self.device)
+        return self._xws
+
+    def _ws_args(self):
+        ws = self.workspace()
+        return ctypes.c_void_p(ws.data_ptr()), ws.numel()
 
     def _out(self, capacity: int):
         t = _torch()
@@ -184,17 +243,19 @@ class Plan:
             t = _torch()
             rp = t.empty(self.nrows + 1, dtype=t.int64, device=self.A.rowptr.device)
             n = ctypes.c_int64(0)
-            _check(lib.msp_symbolic(self._h, ctypes.c_void_p(rp.data_ptr()), ctypes.byref(n), s), "msp_symbolic")
+            _check(lib.msp_symbolic(self._h, ctypes.c_void_p(rp.data_ptr()), ctypes.byref(n), *self._ws_args(), s),
+                   "msp_symbolic")
             nn = n.value
             ci = t.empty(max(nn, 1), dtype=t.int32, device=rp.device)
             v = t.empty(max(nn, 1), dtype=out_dtype(self.semiring), device=rp.device)
             out = L.MspCsrOut(self.nrows, self.ncols, nn, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
-            _check(lib.msp_numeric(self._h, ctypes.byref(out), s), "msp_numeric")
+            _check(lib.msp_numeric(self._h, ctypes.byref(out), *self._ws_args(), s), "msp_numeric")
             return DeviceCSR(self.nrows, self.ncols, rp, ci[:nn], v[:nn])
         rp, ci, v = self._out(self.upper_bound)
         out = L.MspCsrOut(self.nrows, self.ncols, self.upper_bound, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
         n = ctypes.c_int64(0)
-        _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if nnz else None, s), "msp_execute")
+        _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if nnz else None, *self._ws_args(), s),
+               "msp_execute")
         if not nnz:
             return DeviceCSR(self.nrows, self.ncols, rp, ci, v)
         nn = n.value
@@ -207,8 +268,8 @@ class Plan:
         out = L.MspCsrOut(self.nrows, self.ncols, capacity, rowptr.data_ptr(), colidx.data_ptr(),
                           values.data_ptr())
         n = ctypes.c_int64(-1)
-        _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if sync_nnz else None, _stream()),
-               "msp_execute")
+        _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if sync_nnz else None, *self._ws_args(),
+                               _stream()), "msp_execute")
         return n.value
 
     def execute_profiled(self, rowptr, colidx, values, capacity: int, stage_ms) -> int:
@@ -221,7 +282,7 @@ class Plan:
         out = L.MspCsrOut(self.nrows, self.ncols, capacity, rowptr.data_ptr(), colidx.data_ptr(),
                           values.data_ptr())
         n = ctypes.c_int64(-1)
-        _check(lib.msp_execute_profiled(self._h, ctypes.byref(out), ctypes.byref(n),
+        _check(lib.msp_execute_profiled(self._h, ctypes.byref(out), ctypes.byref(n), *self._ws_args(),
                                         stage_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
                "msp_execute_profiled")
         return n.value
@@ -233,7 +294,7 @@ class Plan:
                           values.data_ptr())
         n = ctypes.c_int64(-1)
         _check(L.load().msp_execute_timed(self._h, ctypes.byref(out), ctypes.byref(n) if sync_nnz else None,
-                                          timing._h, _stream()), "msp_execute_timed")
+                                          *self._ws_args(), timing._h, _stream()), "msp_execute_timed")
         return n.value
 
     def row_bins(self):
@@ -276,10 +337,58 @@ def masked_spgemm(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = F
 def upper_bound(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False) -> int:
     lib = L.load()
     vs = (_view(A, None, "A"), _view(B, None, "B"), _view(M, None, "M"))
+    nb = ctypes.c_size_t(0)
+    _check(lib.msp_plan_workspace_size(*(ctypes.byref(v) for v in vs), int(bool(complement)),
+                                       SEMIRINGS["plus_pair_i64"], None, ctypes.byref(nb)), "msp_plan_workspace_size")
+    ws = _workspace(nb.value, A.rowptr.device)
     ub = ctypes.c_int64(0)
-    _check(lib.msp_upper_bound(*(ctypes.byref(v) for v in vs), int(bool(complement)), ctypes.byref(ub), _stream()),
-           "msp_upper_bound")
+    _check(lib.msp_upper_bound(*(ctypes.byref(v) for v in vs), int(bool(complement)), ctypes.byref(ub),
+                               ctypes.c_void_p(ws.data_ptr()), nb.value, _stream()), "msp_upper_bound")
     return ub.value
+
+
+def one_shot(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
+             semiring: str = "plus_times_f64", workspace=None, **opts):
+    """msp_masked_spgemm: the one-shot product in one workspace (a uint8
+    device tensor; None: sized by the call itself, which reports the bytes it
+    needs). Returns (DeviceCSR, workspace bytes needed)."""
+    t = _torch()
+    lib = L.load()
+    vs = (_view(A, semiring, "A"), _view(B, semiring, "B"), _view(M, None, "M"))
+    o = options(**opts)
+    dev = A.rowptr.device
+    need = ctypes.c_size_t(0)
+    ws = workspace
+    for _ in range(3):  # at most: plan size, then whole size
+        if ws is None:
+            ws = _workspace(need.value, dev)
+        ub = ctypes.c_int64(0)
+        rp = t.empty(A.nrows + 1, dtype=t.int64, device=dev)
+        # capacity from the bound: a first call with no capacity reports it
+        out = L.MspCsrOut(A.nrows, B.ncols, 0, rp.data_ptr(), 0, 0)
+        st = lib.msp_masked_spgemm(*(ctypes.byref(v) for v in vs), int(bool(complement)), SEMIRINGS[semiring],
+                                   ctypes.byref(o), ctypes.byref(out), ctypes.byref(ub),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(need), _stream())
+        if st == 5 and need.value > ws.numel():
+            if workspace is not None:
+                _check(st, "msp_masked_spgemm")
+            ws = None
+            continue
+        if st == 5:  # the output capacity: ub holds the bound (phase 1) or nnz (phase 2)
+            cap = max(ub.value, 1)
+            ci = t.empty(cap, dtype=t.int32, device=dev)
+            v = t.empty(cap, dtype=out_dtype(semiring), device=dev)
+            out = L.MspCsrOut(A.nrows, B.ncols, cap, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
+            n = ctypes.c_int64(0)
+            _check(lib.msp_masked_spgemm(*(ctypes.byref(v_) for v_ in vs), int(bool(complement)),
+                                         SEMIRINGS[semiring], ctypes.byref(o), ctypes.byref(out), ctypes.byref(n),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(need), _stream()),
+                   "msp_masked_spgemm")
+            return DeviceCSR(A.nrows, B.ncols, rp, ci[:n.value], v[:n.value]), need.value
+        _check(st, "msp_masked_spgemm")
+        return DeviceCSR(A.nrows, B.ncols, rp, t.empty(0, dtype=t.int32, device=dev),
+                         t.empty(0, dtype=out_dtype(semiring), device=dev)), need.value
+    raise MspError(5, "msp_masked_spgemm: workspace size did not settle")
 
 
 class Timing:
@@ -324,10 +433,18 @@ def reduce_csr(rowptr, nrows: int, values, semiring: str, out=None):
         raise TypeError("values dtype does not match the semiring's output type")
     if out is None:
         out = t.empty(1, dtype=values.dtype, device=values.device)
+    ws = _reduce_workspace(values.device)
     _check(L.load().msp_reduce_csr(ctypes.c_void_p(rowptr.data_ptr()), int(nrows),
                                    ctypes.c_void_p(values.data_ptr() if values.numel() else 0), values.numel(),
-                                   SEMIRINGS[semiring], ctypes.c_void_p(out.data_ptr()), _stream()), "msp_reduce_csr")
+                                   SEMIRINGS[semiring], ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "msp_reduce_csr")
     return out
+
+
+def _reduce_workspace(device):
+    nb = ctypes.c_size_t(0)
+    _check(L.load().msp_reduce_workspace_size(ctypes.byref(nb)), "msp_reduce_workspace_size")
+    return _workspace(nb.value, device)
 
 
 def reduce(values, semiring: str, out=None):
@@ -337,8 +454,10 @@ def reduce(values, semiring: str, out=None):
         raise TypeError("values dtype does not match the semiring's output type")
     if out is None:
         out = t.empty(1, dtype=values.dtype, device=values.device)
+    ws = _reduce_workspace(values.device)
     _check(L.load().msp_reduce(ctypes.c_void_p(values.data_ptr() if values.numel() else 0), values.numel(),
-                               SEMIRINGS[semiring], ctypes.c_void_p(out.data_ptr()), _stream()), "msp_reduce")
+                               SEMIRINGS[semiring], ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), _stream()), "msp_reduce")
     return out
 
 
@@ -354,10 +473,13 @@ def bc_batch(A: DeviceCSR, sources, bc=None):
         bc = t.zeros(A.nrows, dtype=t.float64, device=A.rowptr.device)
     view = _view(A, None, "A")
     info = L.MspBcInfo()
+    mem = _TorchAllocator(A.rowptr.device)
     _check(L.load().msp_bc_batch(ctypes.byref(view), ctypes.c_void_p(src.ctypes.data if len(src) else 0),
                                  len(src), ctypes.c_void_p(bc.data_ptr() if bc.numel() else 0),
-                                 ctypes.byref(info), _stream()), "msp_bc_batch")
-    return bc, {f: getattr(info, f) for f, _ in L.MspBcInfo._fields_}
+                                 ctypes.byref(info), ctypes.byref(mem.struct), _stream()), "msp_bc_batch")
+    res = {f: getattr(info, f) for f, _ in L.MspBcInfo._fields_}
+    res["peak_device_bytes"] = mem.peak
+    return bc, res
 
 
 def ktruss(A: DeviceCSR, k: int):
@@ -373,12 +495,14 @@ def ktruss(A: DeviceCSR, k: int):
     view = _view(A, None, "A")
     n = ctypes.c_int64(0)
     info = L.MspKtrussInfo()
+    mem = _TorchAllocator(dev)
     _check(L.load().msp_ktruss(ctypes.byref(view), int(k), ctypes.c_void_p(rp.data_ptr()),
                                ctypes.c_void_p(ci.data_ptr()), ctypes.c_void_p(sup.data_ptr()), ctypes.byref(n),
-                               ctypes.byref(info), _stream()), "msp_ktruss")
+                               ctypes.byref(info), ctypes.byref(mem.struct), _stream()), "msp_ktruss")
     nn = n.value
-    return (DeviceCSR(A.nrows, A.ncols, rp, ci[:nn], sup[:nn]),
-            {f: getattr(info, f) for f, _ in L.MspKtrussInfo._fields_})
+    res = {f: getattr(info, f) for f, _ in L.MspKtrussInfo._fields_}
+    res["peak_device_bytes"] = mem.peak
+    return DeviceCSR(A.nrows, A.ncols, rp, ci[:nn], sup[:nn]), res
 
 
 def version() -> int:
@@ -407,10 +531,19 @@ class Batch:
         self._arr = arr
         self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops, split_flops,
                             heap_flops)
+        self.device = self.problems[0][0].rowptr.device if n else None
+        nb = ctypes.c_size_t(0)
+        _check(lib.msp_batch_workspace_size(arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt), ctypes.byref(nb)),
+               "msp_batch_workspace_size")
+        self.plan_workspace_bytes = nb.value
+        self._pws = _workspace(nb.value, self.device)
         h = ctypes.c_void_p()
         _check(lib.msp_batch_create(ctypes.byref(h), arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt),
-                                    _stream()), "msp_batch_create")
+                                    ctypes.c_void_p(self._pws.data_ptr()), nb.value, _stream()), "msp_batch_create")
         self._h = h
+        _check(lib.msp_workspace_size(self._h, ctypes.byref(nb)), "msp_workspace_size")
+        self.workspace_bytes = nb.value
+        self._xws = None
         self.count = n
         self.upper_bounds = []
         self.products = []
@@ -438,7 +571,10 @@ class Batch:
             v = t.empty(cap, dtype=out_dtype(self.semiring), device=dev)
             self.outputs.append((rp, ci, v))
             outs[p] = L.MspCsrOut(A.nrows, B.ncols, cap, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
-        _check(L.load().msp_batch_bind(self._h, outs, _stream()), "msp_batch_bind")
+        if self._xws is None:
+            self._xws = _workspace(self.workspace_bytes, self.device)
+        _check(L.load().msp_batch_bind(self._h, outs, ctypes.c_void_p(self._xws.data_ptr()), self._xws.numel(),
+                                       _stream()), "msp_batch_bind")
         return self.outputs
 
     def execute(self):

@@ -44,7 +44,7 @@ class MspKtrussInfo(ctypes.Structure):
 BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wave", "maskidx_block",
              "inner_wave", "dense_block_narrow", "dense_split", "heap_lane", "heap_lane_long_mask"]
 STAGE_NAMES = BIN_NAMES + [f"bin{b}" for b in range(len(BIN_NAMES), 16)] + [
-    "symbolic", "scan", "rowptr", "compact", "split_emit"]
+    "symbolic", "scan", "rowptr", "compact", "split_emit", "place"]
 NSTAGES = len(STAGE_NAMES)
 
 
@@ -52,42 +52,58 @@ class MspProblem(ctypes.Structure):
     _fields_ = [("A", MspCsr), ("B", MspCsr), ("M", MspCsr), ("complement", c_i32), ("reserved", c_i32)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, c_vp, ctypes.c_size_t, c_vp)
+RELEASE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp, c_vp)
+
+
+class MspAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("ctx", c_vp)]
+
+
+c_sz = ctypes.c_size_t
+P_sz = ctypes.POINTER(ctypes.c_size_t)
+P_csr = ctypes.POINTER(MspCsr)
+P_out = ctypes.POINTER(MspCsrOut)
+P_opt = ctypes.POINTER(MspOptions)
+
 # every symbol include/msp.h declares, with its ctypes signature
 SIGNATURES = {
-    "msp_options_default": (None, [ctypes.POINTER(MspOptions)]),
-    "msp_plan_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
-                                       ctypes.POINTER(MspCsr), ctypes.c_int, ctypes.c_int,
-                                       ctypes.POINTER(MspOptions), c_vp]),
+    "msp_options_default": (None, [P_opt]),
+    "msp_plan_workspace_size": (ctypes.c_int, [P_csr, P_csr, P_csr, ctypes.c_int, ctypes.c_int, P_opt, P_sz]),
+    "msp_plan_create": (ctypes.c_int, [ctypes.POINTER(c_vp), P_csr, P_csr, P_csr, ctypes.c_int, ctypes.c_int,
+                                       P_opt, c_vp, c_sz, c_vp]),
+    "msp_workspace_size": (ctypes.c_int, [c_vp, P_sz]),
     "msp_plan_info": (ctypes.c_int, [c_vp, ctypes.POINTER(MspPlanInfo)]),
-    "msp_symbolic": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
-    "msp_numeric": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), c_vp]),
-    "msp_execute": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp]),
-    "msp_execute_profiled": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64),
+    "msp_symbolic": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_sz, c_vp]),
+    "msp_numeric": (ctypes.c_int, [c_vp, P_out, c_vp, c_sz, c_vp]),
+    "msp_execute": (ctypes.c_int, [c_vp, P_out, ctypes.POINTER(c_i64), c_vp, c_sz, c_vp]),
+    "msp_execute_profiled": (ctypes.c_int, [c_vp, P_out, ctypes.POINTER(c_i64), c_vp, c_sz,
                                             ctypes.POINTER(ctypes.c_double), c_vp]),
     "msp_timing_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.c_int32, ctypes.c_uint32]),
-    "msp_execute_timed": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp, c_vp]),
+    "msp_execute_timed": (ctypes.c_int, [c_vp, P_out, ctypes.POINTER(c_i64), c_vp, c_sz, c_vp, c_vp]),
     "msp_timing_collect": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_double)]),
     "msp_timing_destroy": (None, [c_vp]),
     "msp_plan_row_bins": (ctypes.c_int, [c_vp, c_vp, c_vp]),
     "msp_plan_destroy": (None, [c_vp]),
-    "msp_masked_spgemm": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
-                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(MspOptions),
-                                         ctypes.POINTER(MspCsrOut), ctypes.POINTER(c_i64), c_vp]),
-    "msp_upper_bound": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr), ctypes.POINTER(MspCsr),
-                                       ctypes.c_int, ctypes.POINTER(c_i64), c_vp]),
-    "msp_reduce": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_vp]),
-    "msp_reduce_csr": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp, c_vp]),
+    "msp_masked_spgemm": (ctypes.c_int, [P_csr, P_csr, P_csr, ctypes.c_int, ctypes.c_int, P_opt, P_out,
+                                         ctypes.POINTER(c_i64), c_vp, c_sz, P_sz, c_vp]),
+    "msp_upper_bound": (ctypes.c_int, [P_csr, P_csr, P_csr, ctypes.c_int, ctypes.POINTER(c_i64), c_vp, c_sz, c_vp]),
+    "msp_reduce": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_vp, c_sz, c_vp]),
+    "msp_reduce_workspace_size": (ctypes.c_int, [P_sz]),
+    "msp_reduce_csr": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp, c_vp, c_sz, c_vp]),
+    "msp_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(MspProblem), c_i64, ctypes.c_int, P_opt, P_sz]),
     "msp_batch_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(MspProblem), c_i64, ctypes.c_int,
-                                        ctypes.POINTER(MspOptions), c_vp]),
+                                        P_opt, c_vp, c_sz, c_vp]),
     "msp_batch_count": (c_i64, [c_vp]),
     "msp_batch_info": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(MspPlanInfo)]),
-    "msp_batch_bind": (ctypes.c_int, [c_vp, ctypes.POINTER(MspCsrOut), c_vp]),
+    "msp_batch_bind": (ctypes.c_int, [c_vp, P_out, c_vp, c_sz, c_vp]),
     "msp_batch_execute": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_graph_launch": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_nnz": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i64), c_vp]),
-    "msp_ktruss": (ctypes.c_int, [ctypes.POINTER(MspCsr), ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64),
-                                  ctypes.POINTER(MspKtrussInfo), c_vp]),
-    "msp_bc_batch": (ctypes.c_int, [ctypes.POINTER(MspCsr), c_vp, c_i64, c_vp, ctypes.POINTER(MspBcInfo), c_vp]),
+    "msp_ktruss": (ctypes.c_int, [P_csr, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64),
+                                  ctypes.POINTER(MspKtrussInfo), ctypes.POINTER(MspAllocator), c_vp]),
+    "msp_bc_batch": (ctypes.c_int, [P_csr, c_vp, c_i64, c_vp, ctypes.POINTER(MspBcInfo),
+                                    ctypes.POINTER(MspAllocator), c_vp]),
     "msp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "msp_last_error": (ctypes.c_char_p, []),
     "msp_version": (ctypes.c_int, []),

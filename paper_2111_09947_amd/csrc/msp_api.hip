@@ -1,13 +1,18 @@
-// Host runtime of the C-ABI (include/msp.h): argument checks, plan
-// workspace, kernel sequencing for the one-phase and two-phase paths
-// (Section "Symbolic and Numeric Phases"), and batches of products that
-// share one set of launches.
+// Host runtime of the C-ABI (include/msp.h): argument checks, workspace
+// layout, kernel sequencing for the one-phase and two-phase paths (Section
+// "Symbolic and Numeric Phases"), and batches of products that share one set
+// of launches.
 //
 // A plan covers P >= 1 products on one semiring. Their rows are numbered
 // globally (product p owns rows row_off_p .. row_off_p + m_p - 1) and their
 // work units share one unit space, so that each kernel bin runs one launch
 // over the units of all products; a unit finds its operands through a device
 // table. A single product (msp_plan_create) is the case P = 1.
+//
+// The library allocates no device memory. A plan lays its arrays out in two
+// caller-owned buffers: the plan workspace (sized from the operand shapes,
+// held by the plan) and the execution workspace (sized from the binning,
+// given to every call that runs the product).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,23 +56,6 @@ msp_status from_hip(hipError_t e, const char* what) {
         if (_st != MSP_OK) return _st;          \
     } while (0)
 
-// Stream-ordered allocations come from the device's default memory pool with
-// an unlimited release threshold, so a plan created per call reuses memory
-// released by the previous one without returning it to the driver.
-std::once_flag g_pool_once[64];
-
-void configure_pool() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-    std::call_once(g_pool_once[dev], [dev] {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t threshold = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
-        }
-    });
-}
-
 }  // namespace
 
 msp_status mspk::set_error(msp_status st, const char* msg) { return fail(st, msg); }
@@ -96,13 +84,36 @@ msp_status check_triple(const msp_csr* A, const msp_csr* B, const msp_csr* M) {
     return MSP_OK;
 }
 
+// Lays out arrays one after another from `base`, each starting on a 256-byte
+// boundary; with a null base it only adds up their sizes (the size queries
+// and the checks use the same walk as the placement).
+struct Layout {
+    char* base = nullptr;
+    size_t off = 0;
+    void bytes(void** p, size_t n) {
+        if (n == 0) n = 1;
+        if (p) *p = base ? base + off : nullptr;
+        off += (n + 255) & ~(size_t)255;
+    }
+    template <class T>
+    void take(T** p, int64_t n) {
+        bytes(reinterpret_cast<void**>(p), (size_t)(n > 0 ? n : 1) * sizeof(T));
+    }
+};
+
 struct Product {
     Operands op{};
     int64_t row_off = 0;
     int64_t nnzB = 0;
+    int64_t nnzA = 0;
+    int64_t nnzM = 0;
+    // B^T built by the plan for the inner kind (plan workspace)
     int64_t* BTrp = nullptr;
     int32_t* BTci = nullptr;
     void* BTv = nullptr;
+    int64_t* bt_part = nullptr;
+    unsigned long long* bt_cursor = nullptr;
+    bool bt_counted = false, bt_scattered = false;
     int64_t ub = 0, flops = 0, units = 0, staging = 0, mnnz = 0;
     int64_t bin_units[NBINS] = {};
 };
@@ -110,45 +121,48 @@ struct Product {
 }  // namespace
 
 struct msp_plan {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // stream of creation
     int sr = 0;
     msp_options opt{};
     std::vector<Product> prods;
     int64_t P = 0, R = 0, U = 0, S = 0, ub = 0;
-    std::vector<void*> allocs;
-    bool pooled = true;
-    // analysis (global rows)
+    bool inner_any = false;       // the inner kind may run: pull costs and B^T
+    bool plain_readback = false;  // read host values by plain copies (no page-locked buffers)
+    // plan workspace: analysis (global rows)
     unsigned long long* stats_d = nullptr;  // [P * ST_COUNT]
     std::vector<unsigned long long> stats;
     int64_t* flops = nullptr;
     int64_t* unit_base = nullptr;
     int8_t* bin = nullptr;
     int64_t* scan_partial = nullptr;
+    int64_t* seg_off_d = nullptr;
+    int64_t* icost = nullptr;
     // units (global)
     int64_t bin_count[NBINS] = {};
     int64_t bin_off[NBINS + 1] = {};
     bool heap_fold = false;     // BIN_HEAP_L units run in the mask-indexed wave kernel's launch
     bool heap_lm_fold = false;  // BIN_HEAP_LM units run in the mask-indexed block kernel's launch
     int64_t seg_off[NBINS * NBUCKET] = {};
-    int64_t* seg_off_d = nullptr;
-    int64_t* icost = nullptr;
-    unsigned long long* seg_cursor = nullptr;
+    int64_t nsplit = 0;
+    // execution workspace: valid for the workspace the units were last placed in
+    const void* placed_ws = nullptr;
+    bool placed_staging = false;
+    unsigned long long* seg_cursor = nullptr;  // [NBINS * NBUCKET] + the split-row counter
     int32_t* unit_row = nullptr;
     int32_t* unit_tile = nullptr;
     int32_t* unit_prob = nullptr;
     int64_t* stg_off = nullptr;
     int64_t* cnt = nullptr;
     int32_t* bin_units = nullptr;
+    int64_t* xpart = nullptr;  // scan partials over the units
     int32_t* stg_col = nullptr;
     void* stg_val = nullptr;
-    // split rows
-    int64_t nsplit = 0;
     unsigned long long* split_counter = nullptr;
     int32_t* unit_aux = nullptr;
     int32_t* split_first = nullptr;
     int32_t* split_nchunk = nullptr;
     unsigned int* gacc = nullptr;  // [nsplit] x (inserted bits, slots)
-    // batch tables
+    // batch tables (plan workspace)
     Operands* ops_d = nullptr;
     OutBind* outs_d = nullptr;
     int64_t* ent_off_d = nullptr;
@@ -158,57 +172,13 @@ struct msp_plan {
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;
     bool symbolic_done = false;
+    int64_t sym_nnz = -1;  // nnz(C) when msp_symbolic read it back
 
-    msp_status alloc(void** p, size_t bytes) {
-        if (bytes < 256) bytes = 256;
-        hipError_t e = hipErrorNotSupported;
-        if (pooled) {
-            e = hipMallocAsync(p, bytes, stream);
-            if (e == hipErrorNotSupported) pooled = false;
-        }
-        if (!pooled) e = hipMalloc(p, bytes);
-        if (e != hipSuccess) {
-            *p = nullptr;
-            return from_hip(e, "device allocation");
-        }
-        allocs.push_back(*p);
-        return MSP_OK;
-    }
-    template <class T>
-    msp_status alloc_n(T** p, int64_t n) {
-        return alloc(reinterpret_cast<void**>(p), (size_t)(n > 0 ? n : 1) * sizeof(T));
-    }
-    // Carves several arrays out of one allocation (256-byte aligned pieces).
-    struct Carve {
-        std::vector<std::pair<void**, size_t>> parts;
-        template <class T>
-        void add(T** p, int64_t n) {
-            parts.push_back({reinterpret_cast<void**>(p), (size_t)(n > 0 ? n : 1) * sizeof(T)});
-        }
-        void add_bytes(void** p, size_t bytes) { parts.push_back({p, bytes > 0 ? bytes : 1}); }
-    };
-    msp_status alloc_carve(Carve& c) {
-        size_t total = 0;
-        for (auto& pt : c.parts) total += (pt.second + 255) & ~(size_t)255;
-        char* base = nullptr;
-        MSP_CHECK(alloc(reinterpret_cast<void**>(&base), total));
-        size_t off = 0;
-        for (auto& pt : c.parts) {
-            *pt.first = base + off;
-            off += (pt.second + 255) & ~(size_t)255;
-        }
-        return MSP_OK;
-    }
     void release() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
-        for (void* p : allocs) {
-            if (pooled) (void)hipFreeAsync(p, stream);
-            else (void)hipFree(p);
-        }
-        allocs.clear();
     }
 };
 
@@ -243,39 +213,159 @@ const char* msp_status_string(msp_status s) {
 
 const char* msp_last_error(void) { return g_last_error.c_str(); }
 
-int msp_version(void) { return 200; }
+int msp_version(void) { return 300; }
 
 }  // extern "C"
+
+// Checks the arguments of a plan over `probs` and fills the plan's options
+// and products (host only: no GPU work).
+static msp_status plan_setup(msp_plan* P, const msp_problem* probs, int64_t count, msp_semiring semiring,
+                             const msp_options* opt) {
+    if (count < 1) return fail(MSP_ERR_INVALID_ARGUMENT, "a plan needs at least one product");
+    if (!probs) return fail(MSP_ERR_INVALID_ARGUMENT, "problems is NULL");
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
+    msp_options o;
+    msp_options_default(&o);
+    if (opt) o = *opt;
+    if (o.phase == 0) o.phase = 1;
+    if (o.phase != 1 && o.phase != 2) return fail(MSP_ERR_INVALID_ARGUMENT, "phase must be 1 or 2");
+    if (count > 1 && o.phase != 1) return fail(MSP_ERR_UNSUPPORTED, "a batch runs one-phase only");
+    if (o.force_kind < MSP_KIND_AUTO || o.force_kind > MSP_KIND_HEAP)
+        return fail(MSP_ERR_INVALID_ARGUMENT, "unknown force_kind");
+    if (o.inner_ratio < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "inner_ratio must be >= 0");
+    if (o.maskidx_max < 0) o.maskidx_max = DEFAULT_MASKIDX_MAX;
+    if (o.block_flops < 0) o.block_flops = DEFAULT_BLOCK_FLOPS;
+    if (o.split_flops < 0) o.split_flops = DEFAULT_SPLIT_FLOPS;
+    if (o.heap_flops < 0) o.heap_flops = DEFAULT_HEAP_FLOPS;
+    if (count > 1 && o.b_transpose) return fail(MSP_ERR_UNSUPPORTED, "b_transpose applies to a single product");
+    int64_t R = 0;
+    P->prods.assign((size_t)count, Product{});
+    for (int64_t p = 0; p < count; ++p) {
+        const msp_problem& q = probs[p];
+        MSP_CHECK(check_triple(&q.A, &q.B, &q.M));
+        if (q.complement != 0 && q.complement != 1)
+            return fail(MSP_ERR_INVALID_ARGUMENT, "complement must be 0 or 1");
+        if (q.complement && o.force_kind != MSP_KIND_AUTO && o.force_kind != MSP_KIND_DENSE &&
+            o.force_kind != MSP_KIND_HEAP)
+            return fail(MSP_ERR_UNSUPPORTED, "a complemented mask supports only the dense and heap kinds");
+        Product& pr = P->prods[(size_t)p];
+        Operands& op = pr.op;
+        op.m = q.A.nrows; op.k = q.A.ncols; op.n = q.B.ncols;
+        op.Arp = q.A.rowptr; op.Aci = q.A.colidx; op.Av = q.A.values;
+        op.Brp = q.B.rowptr; op.Bci = q.B.colidx; op.Bv = q.B.values;
+        op.Mrp = q.M.rowptr; op.Mci = q.M.colidx;
+        op.complement = q.complement;
+        pr.nnzA = q.A.nnz;
+        pr.nnzB = q.B.nnz;
+        pr.nnzM = q.M.nnz;
+        pr.row_off = R;
+        R += op.m;
+    }
+    if (R >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many rows in one plan");
+    if (o.b_transpose) {
+        MSP_CHECK(check_csr(o.b_transpose, "B^T"));
+        const msp_csr& B = probs[0].B;
+        if (o.b_transpose->nrows != B.ncols || o.b_transpose->ncols != B.nrows || o.b_transpose->nnz != B.nnz)
+            return fail(MSP_ERR_DIMENSION_MISMATCH, "B^T must be B.ncols x B.nrows with nnz(B) entries");
+    }
+    P->sr = semiring;
+    P->opt = o;
+    P->P = count;
+    P->R = R;
+    P->inner_any = o.force_kind == MSP_KIND_INNER || (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0);
+    return MSP_OK;
+}
+
+// The plan workspace: the analysis arrays over the global rows, the batch
+// tables, and B^T of every product with a normal mask when the inner kind may
+// run and the caller gave no B^T. Returns its size.
+static size_t plan_layout(msp_plan* P, char* base) {
+    Layout L{base};
+    const int64_t count = P->P, R = P->R;
+    L.take(&P->stats_d, count * ST_COUNT);
+    L.take(&P->flops, R);
+    L.take(&P->unit_base, R + 1);
+    L.take(&P->bin, R);
+    L.take(&P->scan_partial, scan_partial_elems(R + 1));
+    L.take(&P->seg_off_d, NBINS * NBUCKET);
+    if (P->inner_any) {  // pull cost per row, one product at a time (stream order)
+        int64_t mmax = 0;
+        for (const Product& pr : P->prods) mmax = std::max(mmax, pr.op.m);
+        L.take(&P->icost, mmax);
+    }
+    if (count > 1) {
+        L.take(&P->ops_d, count);
+        L.take(&P->outs_d, count);
+        L.take(&P->ent_off_d, count + 1);
+    }
+    if (P->inner_any && !P->opt.b_transpose) {
+        const int vb = in_bytes(P->sr);
+        for (Product& pr : P->prods) {
+            if (pr.op.complement) continue;
+            L.take(&pr.BTrp, pr.op.n + 1);
+            L.take(&pr.bt_part, scan_partial_elems(pr.op.n));
+            L.take(&pr.BTci, pr.nnzB);
+            if (vb && pr.op.Bv) L.bytes(&pr.BTv, (size_t)(pr.nnzB > 0 ? pr.nnzB : 1) * vb);
+            L.take(&pr.bt_cursor, pr.op.n);
+        }
+    }
+    return L.off;
+}
+
+// The execution workspace: placement cursors, the unit lists, per-unit
+// counts and staging offsets, their scan partials, the split rows'
+// accumulators, and the one-phase staging when `staging`. Returns its size.
+static size_t exec_layout(msp_plan* P, char* base, bool staging) {
+    Layout L{base};
+    const int64_t U = P->U;
+    L.take(&P->seg_cursor, NBINS * NBUCKET + 1);
+    L.take(&P->unit_row, U);
+    L.take(&P->unit_tile, U);
+    L.take(&P->unit_prob, U);
+    L.take(&P->stg_off, U + 1);
+    L.take(&P->cnt, U + 1);
+    L.take(&P->bin_units, U);
+    L.take(&P->unit_aux, U);
+    L.take(&P->xpart, scan_partial_elems(U + 1));
+    L.take(&P->split_first, P->nsplit);
+    L.take(&P->split_nchunk, P->nsplit);
+    L.bytes(reinterpret_cast<void**>(&P->gacc), (size_t)(P->nsplit > 0 ? P->nsplit : 1) * split_acc_bytes(P->sr));
+    if (staging) {
+        L.take(&P->stg_col, P->S);
+        L.bytes(&P->stg_val, (size_t)(P->S > 0 ? P->S : 1) * out_bytes(P->sr));
+    } else {
+        P->stg_col = nullptr;
+        P->stg_val = nullptr;
+    }
+    P->split_counter = P->seg_cursor ? P->seg_cursor + NBINS * NBUCKET : nullptr;
+    return L.off;
+}
+
+static bool exec_staging(const msp_plan* P) { return P->opt.phase == 1; }
 
 // B^T of product `pr`: column counts and their prefix sum (always), rows
 // scattered (when `scatter`). Rows of B^T come out in no particular order.
 static msp_status build_transpose(msp_plan* P, Product& pr, bool scatter) {
     const Operands& o = pr.op;
     hipStream_t s = P->stream;
-    if (!pr.BTrp) {
-        MSP_CHECK(P->alloc_n(&pr.BTrp, o.n + 1));
+    if (!pr.bt_counted) {
         MSP_HIP(launch_fill_i64(pr.BTrp, o.n + 1, 0, s));
         MSP_HIP(launch_colcount(o.Bci, pr.nnzB, pr.BTrp, s));
-        int64_t* part = nullptr;
-        MSP_CHECK(P->alloc_n(&part, scan_partial_elems(o.n)));
-        MSP_HIP(launch_scan(pr.BTrp, pr.BTrp, o.n, part, s));
+        MSP_HIP(launch_scan(pr.BTrp, pr.BTrp, o.n, pr.bt_part, s));
         pr.op.BTrp = pr.BTrp;
+        pr.bt_counted = true;
     }
-    if (scatter && !pr.BTci) {
+    if (scatter && !pr.bt_scattered) {
         const int vb = in_bytes(P->sr);
-        MSP_CHECK(P->alloc_n(&pr.BTci, pr.nnzB));
-        if (vb && o.Bv) MSP_CHECK(P->alloc(&pr.BTv, (size_t)(pr.nnzB > 0 ? pr.nnzB : 1) * vb));
-        unsigned long long* cursor = nullptr;
-        MSP_CHECK(P->alloc_n(&cursor, o.n));
-        MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(cursor), o.n, 0, s));
-        MSP_HIP(launch_transpose_scatter(o.Brp, o.Bci, o.Bv, vb, o.k, pr.BTrp, cursor, pr.BTci, pr.BTv, s));
+        MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(pr.bt_cursor), o.n, 0, s));
+        MSP_HIP(launch_transpose_scatter(o.Brp, o.Bci, o.Bv, vb, o.k, pr.BTrp, pr.bt_cursor, pr.BTci, pr.BTv, s));
         pr.op.BTci = pr.BTci;
         pr.op.BTv = pr.BTv;
+        pr.bt_scattered = true;
     }
     return MSP_OK;
 }
 
-// Plans the products `probs` (count P). want_staging: allocate one-phase staging.
 // Page-locked, device-mapped host words for the small device-to-host reads
 // (statistics and output counts), reused through a process-wide pool. A
 // kernel writes them directly, so a read costs no copy-engine pass.
@@ -328,7 +418,14 @@ struct PinnedBuf {
 };
 
 // Reads one int64 from device memory after the stream's work (synchronizes).
-static msp_status read_back_i64(int64_t* dst, const int64_t* src, hipStream_t s) {
+static msp_status read_back_i64(const msp_plan* P, int64_t* dst, const int64_t* src, hipStream_t s) {
+    if (P && P->plain_readback) {
+        int64_t v = 0;
+        MSP_HIP(hipMemcpyAsync(&v, src, sizeof(v), hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+        *dst = v;
+        return MSP_OK;
+    }
     PinnedBuf pin;
     MSP_CHECK(pin.get(sizeof(int64_t)));
     MSP_HIP(launch_peek(src, static_cast<int64_t*>(pin.dev), s));
@@ -338,78 +435,19 @@ static msp_status read_back_i64(int64_t* dst, const int64_t* src, hipStream_t s)
 }
 
 static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_t count, msp_semiring semiring,
-                                   const msp_options* opt, hipStream_t stream, bool want_staging) {
-    if (count < 1) return fail(MSP_ERR_INVALID_ARGUMENT, "a plan needs at least one product");
-    if (!probs) return fail(MSP_ERR_INVALID_ARGUMENT, "problems is NULL");
-    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
-    msp_options o;
-    msp_options_default(&o);
-    if (opt) o = *opt;
-    if (o.phase == 0) o.phase = 1;
-    if (o.phase != 1 && o.phase != 2) return fail(MSP_ERR_INVALID_ARGUMENT, "phase must be 1 or 2");
-    if (count > 1 && o.phase != 1) return fail(MSP_ERR_UNSUPPORTED, "a batch runs one-phase only");
-    if (o.force_kind < MSP_KIND_AUTO || o.force_kind > MSP_KIND_HEAP)
-        return fail(MSP_ERR_INVALID_ARGUMENT, "unknown force_kind");
-    if (o.inner_ratio < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "inner_ratio must be >= 0");
-    if (o.maskidx_max < 0) o.maskidx_max = DEFAULT_MASKIDX_MAX;
-    if (o.block_flops < 0) o.block_flops = DEFAULT_BLOCK_FLOPS;
-    if (o.split_flops < 0) o.split_flops = DEFAULT_SPLIT_FLOPS;
-    if (o.heap_flops < 0) o.heap_flops = DEFAULT_HEAP_FLOPS;
-    if (count > 1 && o.b_transpose) return fail(MSP_ERR_UNSUPPORTED, "b_transpose applies to a single product");
-    int64_t R = 0;
-    P->prods.resize((size_t)count);
-    for (int64_t p = 0; p < count; ++p) {
-        const msp_problem& q = probs[p];
-        MSP_CHECK(check_triple(&q.A, &q.B, &q.M));
-        if (q.complement != 0 && q.complement != 1)
-            return fail(MSP_ERR_INVALID_ARGUMENT, "complement must be 0 or 1");
-        if (q.complement && o.force_kind != MSP_KIND_AUTO && o.force_kind != MSP_KIND_DENSE &&
-            o.force_kind != MSP_KIND_HEAP)
-            return fail(MSP_ERR_UNSUPPORTED, "a complemented mask supports only the dense and heap kinds");
-        Product& pr = P->prods[(size_t)p];
-        Operands& op = pr.op;
-        op.m = q.A.nrows; op.k = q.A.ncols; op.n = q.B.ncols;
-        op.Arp = q.A.rowptr; op.Aci = q.A.colidx; op.Av = q.A.values;
-        op.Brp = q.B.rowptr; op.Bci = q.B.colidx; op.Bv = q.B.values;
-        op.Mrp = q.M.rowptr; op.Mci = q.M.colidx;
-        op.complement = q.complement;
-        pr.nnzB = q.B.nnz;
-        pr.row_off = R;
-        R += op.m;
-    }
-    if (R >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many rows in one plan");
-    if (o.b_transpose) {
-        MSP_CHECK(check_csr(o.b_transpose, "B^T"));
-        const msp_csr& B = probs[0].B;
-        if (o.b_transpose->nrows != B.ncols || o.b_transpose->ncols != B.nrows || o.b_transpose->nnz != B.nnz)
-            return fail(MSP_ERR_DIMENSION_MISMATCH, "B^T must be B.ncols x B.nrows with nnz(B) entries");
-    }
-    configure_pool();
+                                   const msp_options* opt, void* ws, size_t ws_bytes, hipStream_t stream) {
+    MSP_CHECK(plan_setup(P, probs, count, semiring, opt));
+    const size_t need = plan_layout(P, nullptr);
+    if (ws_bytes < need)
+        return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "plan workspace of " + std::to_string(ws_bytes) +
+                                                       " bytes is below the " + std::to_string(need) + " needed");
+    if (!ws) return fail(MSP_ERR_INVALID_ARGUMENT, "plan workspace is NULL");
+    plan_layout(P, static_cast<char*>(ws));
+    const msp_options& o = P->opt;
+    const int64_t R = P->R;
     P->stream = stream;
-    P->sr = semiring;
-    P->opt = o;
-    P->P = count;
-    P->R = R;
     hipStream_t s = stream;
 
-    const bool inner_any = o.force_kind == MSP_KIND_INNER || (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0);
-    // workspace sized by the operand shapes
-    {
-        msp_plan::Carve c;
-        c.add(&P->stats_d, count * ST_COUNT);
-        c.add(&P->flops, R);
-        c.add(&P->unit_base, R + 1);
-        c.add(&P->bin, R);
-        c.add(&P->scan_partial, scan_partial_elems(R + 1));
-        c.add(&P->seg_off_d, NBINS * NBUCKET);
-        c.add(&P->seg_cursor, NBINS * NBUCKET + 1);  // + the split-row counter
-        if (inner_any) {  // pull cost per row, one product at a time (stream order)
-            int64_t mmax = 0;
-            for (const Product& pr : P->prods) mmax = std::max(mmax, pr.op.m);
-            c.add(&P->icost, mmax);
-        }
-        MSP_CHECK(P->alloc_carve(c));
-    }
     // the statistics and every product's row counts start at zero (one launch)
     MSP_HIP(launch_zero2(reinterpret_cast<int64_t*>(P->stats_d), ST_COUNT * count, P->flops, R, s));
     if (o.validate) {
@@ -431,7 +469,7 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     }
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
-        if (pr.op.complement || !inner_any) continue;
+        if (pr.op.complement || !P->inner_any) continue;
         if (o.b_transpose) {
             pr.op.BTrp = o.b_transpose->rowptr;
             pr.op.BTci = o.b_transpose->colidx;
@@ -446,14 +484,14 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.op = pr.op;
         aa.row_off = pr.row_off;
         aa.force_kind = o.force_kind;
-        aa.inner_ratio = (!pr.op.complement && inner_any) ? o.inner_ratio : 0;
+        aa.inner_ratio = (!pr.op.complement && P->inner_any) ? o.inner_ratio : 0;
         aa.maskidx_max = o.maskidx_max;
         aa.block_flops = o.block_flops;
         aa.split_flops = o.split_flops;
         aa.heap_flops = o.heap_flops;
         aa.colcnt_rp = pr.op.BTrp;
-        aa.a_nnz = probs[p].A.nnz;
-        aa.m_nnz = probs[p].M.nnz;
+        aa.a_nnz = pr.nnzA;
+        aa.m_nnz = pr.nnzM;
         aa.icost = (aa.inner_ratio > 0 && aa.colcnt_rp && o.force_kind == MSP_KIND_AUTO) ? P->icost : nullptr;
         aa.flops = P->flops;
         aa.flops_zeroed = true;
@@ -466,13 +504,19 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     {
         // the one synchronization of plan creation: the statistics size the unit arrays
         const size_t sb = sizeof(unsigned long long) * ST_COUNT * (size_t)count;
-        PinnedBuf pin;
-        MSP_CHECK(pin.get(sb));
-        MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, P->seg_cursor,
-                              static_cast<unsigned long long*>(pin.dev), s));
-        MSP_HIP(hipStreamSynchronize(s));
         P->stats.assign((size_t)(count * ST_COUNT), 0ull);
-        std::memcpy(P->stats.data(), pin.p, sb);
+        if (P->plain_readback) {
+            MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, nullptr, nullptr, s));
+            MSP_HIP(hipMemcpyAsync(P->stats.data(), P->stats_d, sb, hipMemcpyDeviceToHost, s));
+            MSP_HIP(hipStreamSynchronize(s));
+        } else {
+            PinnedBuf pin;
+            MSP_CHECK(pin.get(sb));
+            MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, nullptr,
+                                  static_cast<unsigned long long*>(pin.dev), s));
+            MSP_HIP(hipStreamSynchronize(s));
+            std::memcpy(P->stats.data(), pin.p, sb);
+        }
     }
 
     // totals; bins in order, inside a bin the flops buckets from the heaviest down
@@ -522,36 +566,6 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         Product& pr = P->prods[(size_t)p];
         if (pr.bin_units[BIN_INNER_W] > 0 && !o.b_transpose) MSP_CHECK(build_transpose(P, pr, true));
     }
-
-    const int64_t U = P->U;
-    // workspace sized by the units (and the one-phase staging)
-    {
-        msp_plan::Carve c;
-        c.add(&P->unit_row, U);
-        c.add(&P->unit_tile, U);
-        c.add(&P->unit_prob, U);
-        c.add(&P->stg_off, U + 1);
-        c.add(&P->cnt, U + 1);
-        c.add(&P->bin_units, U);
-        c.add(&P->unit_aux, U);
-        c.add(&P->split_first, P->nsplit);
-        c.add(&P->split_nchunk, P->nsplit);
-        c.add_bytes(reinterpret_cast<void**>(&P->gacc), (size_t)(P->nsplit > 0 ? P->nsplit : 1) * split_acc_bytes(semiring));
-        int64_t* part = nullptr;
-        if (U + 1 > R + 1) c.add(&part, scan_partial_elems(U + 1));
-        if (want_staging && o.phase == 1) {
-            c.add(&P->stg_col, P->S);
-            c.add_bytes(&P->stg_val, (size_t)(P->S > 0 ? P->S : 1) * out_bytes(semiring));
-        }
-        if (count > 1) {
-            c.add(&P->ops_d, count);
-            c.add(&P->outs_d, count);
-            c.add(&P->ent_off_d, count + 1);
-        }
-        MSP_CHECK(P->alloc_carve(c));
-        if (part) P->scan_partial = part;
-    }
-    P->split_counter = P->seg_cursor + NBINS * NBUCKET;
     if (count > 1) {
         std::vector<Operands> ops((size_t)count);
         std::vector<int64_t> ent((size_t)count + 1, 0);
@@ -563,7 +577,23 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         MSP_HIP(hipMemcpyAsync(P->ent_off_d, ent.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s));
         MSP_HIP(hipStreamSynchronize(s));  // the host staging vectors go out of scope
     }
-    for (int64_t p = 0; p < count; ++p) {
+    return MSP_OK;
+}
+
+// Places the work units in the execution workspace `ws`: every row's units
+// into its (bin, flops bucket) segment, their staging sizes and, when
+// `staging`, the staging offsets (a prefix sum). Kernels only.
+static msp_status place_units(msp_plan* P, void* ws, size_t ws_bytes, bool staging, hipStream_t s) {
+    const size_t need = exec_layout(P, nullptr, staging);
+    if (ws_bytes < need)
+        return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "execution workspace of " + std::to_string(ws_bytes) +
+                                                       " bytes is below the " + std::to_string(need) + " needed");
+    if (!ws) return fail(MSP_ERR_INVALID_ARGUMENT, "execution workspace is NULL");
+    exec_layout(P, static_cast<char*>(ws), staging);
+    P->placed_ws = nullptr;
+    // placement cursors and the split-row counter start at zero
+    MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(P->seg_cursor), NBINS * NBUCKET + 1, 0, s));
+    for (int64_t p = 0; p < P->P; ++p) {
         Product& pr = P->prods[(size_t)p];
         if (pr.op.m == 0) continue;
         UnitArgs ua{};
@@ -586,24 +616,38 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         ua.split_nchunk = P->split_nchunk;
         MSP_HIP(launch_units(ua, pr.op.m, s));
     }
-    if (want_staging && o.phase == 1) MSP_HIP(launch_scan(P->stg_off, P->stg_off, U, P->scan_partial, s));
+    if (staging) MSP_HIP(launch_scan(P->stg_off, P->stg_off, P->U, P->xpart, s));
+    P->placed_ws = ws;
+    P->placed_staging = staging;
     return MSP_OK;
 }
 
 static msp_status create_common(msp_plan** plan, const msp_problem* probs, int64_t count, msp_semiring semiring,
-                                const msp_options* opt, void* stream, bool want_staging) {
+                                const msp_options* opt, void* ws, size_t ws_bytes, void* stream,
+                                bool plain_readback = false) {
     if (!plan) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
     *plan = nullptr;
     msp_plan* P = new (std::nothrow) msp_plan();
     if (!P) return fail(MSP_ERR_OUT_OF_MEMORY, "host allocation");
-    const msp_status st = plan_create_impl(P, probs, count, semiring, opt, (hipStream_t)stream, want_staging);
+    P->plain_readback = plain_readback;
+    const msp_status st = plan_create_impl(P, probs, count, semiring, opt, ws, ws_bytes, (hipStream_t)stream);
     if (st != MSP_OK) {
+        // kernels enqueued before the error may still use the caller's workspace
         (void)hipStreamSynchronize((hipStream_t)stream);
         P->release();
         delete P;
         return st;
     }
     *plan = P;
+    return MSP_OK;
+}
+
+static msp_status workspace_size_common(const msp_problem* probs, int64_t count, msp_semiring semiring,
+                                        const msp_options* opt, size_t* bytes) {
+    if (!bytes) return fail(MSP_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    msp_plan tmp;
+    MSP_CHECK(plan_setup(&tmp, probs, count, semiring, opt));
+    *bytes = plan_layout(&tmp, nullptr);
     return MSP_OK;
 }
 
@@ -796,9 +840,10 @@ static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream
 
 // The one-phase sequence over all products: numeric into staging, prefix sum
 // of the unit counts, row pointers, compaction. Kernels only (no allocation,
-// no memset, no synchronization), so it can be captured in a HIP graph.
+// no memset, no synchronization), so it can be captured in a HIP graph. The
+// units must be placed (with staging) in the execution workspace.
 static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, StageTimer& tm) {
-    if (!P->stg_col) return fail(MSP_ERR_INVALID_ARGUMENT, "plan has no one-phase staging");
+    if (!P->placed_ws || !P->placed_staging) return fail(MSP_ERR_INVALID_ARGUMENT, "no one-phase workspace placed");
     MSP_CHECK(split_clear(P, s));
     NumArgs a = num_args(P, 0);
     a.out_off = P->stg_off;
@@ -810,7 +855,7 @@ static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, 
     MSP_CHECK(split_emit(P, MODE_STAGE, a, s));
     MSP_CHECK(tm.end());
     MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
-    MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
+    MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->xpart, s));
     MSP_CHECK(tm.end());
     const OutBind* outs = P->P > 1 ? P->outs_d : nullptr;
     const int64_t entries = P->P > 1 ? P->R + P->P : P->prods[0].op.m + 1;
@@ -833,8 +878,14 @@ static msp_status run_one_phase(msp_plan* P, const OutBind& one, hipStream_t s, 
     return MSP_OK;
 }
 
-static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
+static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, void* ws, size_t ws_bytes,
+                                hipStream_t s, StageTimer& tm) {
     const Product& pr = P->prods[0];
+    P->symbolic_done = false;
+    P->sym_nnz = -1;
+    MSP_CHECK(tm.begin(MSP_STAGE_PLACE));
+    MSP_CHECK(place_units(P, ws, ws_bytes, false, s));
+    MSP_CHECK(tm.end());
     MSP_CHECK(tm.begin(MSP_STAGE_SYMBOLIC));
     MSP_CHECK(split_clear(P, s));
     {
@@ -849,7 +900,7 @@ static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_hos
     }
     MSP_CHECK(tm.end());
     MSP_CHECK(tm.begin(MSP_STAGE_SCAN));
-    MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->scan_partial, s));
+    MSP_HIP(launch_scan(P->cnt, P->cnt, P->U, P->xpart, s));
     MSP_CHECK(tm.end());
     OutBind one{};
     one.rowptr = C_rowptr;
@@ -858,11 +909,27 @@ static msp_status symbolic_impl(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_hos
     MSP_HIP(launch_rowptr(1, pr.op.m + 1, nullptr, nullptr, one, P->unit_base, P->cnt, s));
     MSP_CHECK(tm.end());
     P->symbolic_done = true;
-    if (nnz_host) MSP_CHECK(read_back_i64(nnz_host, C_rowptr + pr.op.m, s));
+    if (nnz_host) {
+        MSP_CHECK(read_back_i64(P, nnz_host, C_rowptr + pr.op.m, s));
+        P->sym_nnz = *nnz_host;
+    }
     return MSP_OK;
 }
 
-static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, hipStream_t s, StageTimer& tm) {
+// Two-phase numeric step; the workspace must be the one msp_symbolic placed
+// the units in, and C must hold nnz(C).
+static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, const void* ws, hipStream_t s, StageTimer& tm) {
+    if (!P->symbolic_done) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric needs msp_symbolic first");
+    if (!ws || ws != P->placed_ws || P->placed_staging)
+        return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric needs the execution workspace of msp_symbolic");
+    if (C->capacity < P->ub) {
+        int64_t nnz = P->sym_nnz;
+        if (nnz < 0) {  // the count after the scan of the unit counts
+            MSP_CHECK(read_back_i64(P, &nnz, P->cnt + P->U, s));
+            P->sym_nnz = nnz;
+        }
+        if (C->capacity < nnz) return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "capacity below nnz(C)");
+    }
     MSP_CHECK(split_clear(P, s));
     NumArgs a = num_args(P, 0);
     a.out_off = P->cnt;
@@ -875,18 +942,19 @@ static msp_status numeric_impl(msp_plan* P, msp_csr_out* C, hipStream_t s, Stage
     return MSP_OK;
 }
 
-static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, hipStream_t s, StageTimer& tm) {
+static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* ws, size_t ws_bytes,
+                               hipStream_t s, StageTimer& tm) {
     if (P->P != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_execute takes a single-product plan; use msp_batch_*");
     const Product& pr = P->prods[0];
     MSP_CHECK(check_out(pr, C));
     if (P->opt.phase == 2) {
         int64_t nnz = 0;
-        MSP_CHECK(symbolic_impl(P, C->rowptr, &nnz, s, tm));
+        MSP_CHECK(symbolic_impl(P, C->rowptr, &nnz, ws, ws_bytes, s, tm));
         if (C->capacity < nnz) {
             if (nnz_host) *nnz_host = nnz;
             return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "capacity below nnz(C)");
         }
-        MSP_CHECK(numeric_impl(P, C, s, tm));
+        MSP_CHECK(numeric_impl(P, C, ws, s, tm));
         if (nnz_host) *nnz_host = nnz;
         return MSP_OK;
     }
@@ -894,55 +962,135 @@ static msp_status execute_impl(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, h
         if (nnz_host) *nnz_host = P->ub;
         return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "one-phase output capacity below the upper bound");
     }
+    MSP_CHECK(tm.begin(MSP_STAGE_PLACE));
+    MSP_CHECK(place_units(P, ws, ws_bytes, true, s));
+    MSP_CHECK(tm.end());
     const OutBind one = bind_of(P, C, 0);
     MSP_CHECK(run_one_phase(P, one, s, tm));
-    if (nnz_host) MSP_CHECK(read_back_i64(nnz_host, C->rowptr + pr.op.m, s));
+    if (nnz_host) MSP_CHECK(read_back_i64(P, nnz_host, C->rowptr + pr.op.m, s));
     return MSP_OK;
 }
 
-extern "C" {
-
-msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
-                           int complement, msp_semiring semiring, const msp_options* opt, void* stream) {
-    if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
+static msp_problem single_problem(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement) {
     msp_problem pb{};
     pb.A = *A;
     pb.B = *B;
     pb.M = *M;
     pb.complement = complement;
-    return create_common(plan, &pb, 1, semiring, opt, stream, true);
+    return pb;
+}
+
+// The one-shot product in one workspace: the plan workspace, then the
+// execution workspace.
+static msp_status one_shot(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                           msp_semiring semiring, const msp_options* opt, msp_csr_out* C, int64_t* nnz_host,
+                           void* ws, size_t ws_bytes, size_t* ws_needed, hipStream_t s, bool plain_readback) {
+    if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
+    const msp_problem pb = single_problem(A, B, M, complement);
+    size_t pneed = 0;
+    MSP_CHECK(workspace_size_common(&pb, 1, semiring, opt, &pneed));
+    if (ws_bytes < pneed) {
+        if (ws_needed) *ws_needed = pneed;
+        return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "workspace of " + std::to_string(ws_bytes) +
+                                                       " bytes is below the plan's " + std::to_string(pneed));
+    }
+    msp_plan* P = nullptr;
+    MSP_CHECK(create_common(&P, &pb, 1, semiring, opt, ws, pneed, s, plain_readback));
+    const size_t xneed = exec_layout(P, nullptr, exec_staging(P));
+    msp_status st = MSP_OK;
+    if (ws_bytes - pneed < xneed) {
+        if (ws_needed) *ws_needed = pneed + xneed;
+        st = fail(MSP_ERR_INSUFFICIENT_CAPACITY, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
+                                                     std::to_string(pneed + xneed) + " needed");
+    } else {
+        if (ws_needed) *ws_needed = pneed + xneed;
+        StageTimer none;
+        st = execute_impl(P, C, nnz_host, static_cast<char*>(ws) + pneed, ws_bytes - pneed, s, none);
+    }
+    // the caller may reuse the workspace when this returns
+    const hipError_t e = hipStreamSynchronize(s);
+    msp_plan_destroy(P);
+    if (st == MSP_OK) MSP_HIP(e);
+    return st;
+}
+
+extern "C" {
+
+msp_status msp_plan_workspace_size(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                                   msp_semiring semiring, const msp_options* opt, size_t* bytes) {
+    if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
+    const msp_problem pb = single_problem(A, B, M, complement);
+    return workspace_size_common(&pb, 1, semiring, opt, bytes);
+}
+
+msp_status msp_batch_workspace_size(const msp_problem* problems, int64_t count, msp_semiring semiring,
+                                    const msp_options* opt, size_t* bytes) {
+    return workspace_size_common(problems, count, semiring, opt, bytes);
+}
+
+msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
+                           int complement, msp_semiring semiring, const msp_options* opt, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+    if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
+    const msp_problem pb = single_problem(A, B, M, complement);
+    return create_common(plan, &pb, 1, semiring, opt, workspace, workspace_bytes, stream);
+}
+
+msp_status msp_workspace_size(const msp_plan* P, size_t* bytes) {
+    if (!P || !bytes) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    msp_plan* Q = const_cast<msp_plan*>(P);
+    // a size-only walk: the layout with no base leaves the placed pointers alone
+    msp_plan tmp;
+    tmp.U = Q->U;
+    tmp.S = Q->S;
+    tmp.nsplit = Q->nsplit;
+    tmp.sr = Q->sr;
+    *bytes = exec_layout(&tmp, nullptr, exec_staging(Q));
+    return MSP_OK;
 }
 
 msp_status msp_plan_info(const msp_plan* P, msp_plan_info_t* info) { return msp_batch_info(P, -1, info); }
 
-msp_status msp_symbolic(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, void* stream) {
+msp_status msp_symbolic(msp_plan* P, int64_t* C_rowptr, int64_t* nnz_host, void* workspace, size_t workspace_bytes,
+                        void* stream) {
     if (!P || !C_rowptr) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
     if (P->P != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_symbolic takes a single-product plan");
     StageTimer none;
-    return symbolic_impl(P, C_rowptr, nnz_host, (hipStream_t)stream, none);
+    return symbolic_impl(P, C_rowptr, nnz_host, workspace, workspace_bytes, (hipStream_t)stream, none);
 }
 
-msp_status msp_numeric(msp_plan* P, msp_csr_out* C, void* stream) {
+msp_status msp_numeric(msp_plan* P, msp_csr_out* C, void* workspace, size_t workspace_bytes, void* stream) {
     if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
     if (P->P != 1) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric takes a single-product plan");
     MSP_CHECK(check_out(P->prods[0], C));
-    if (!P->symbolic_done) return fail(MSP_ERR_INVALID_ARGUMENT, "msp_numeric needs msp_symbolic first");
+    size_t need = 0;
+    MSP_CHECK(msp_workspace_size(P, &need));
+    if (P->opt.phase == 1) {  // a one-phase plan's size includes staging that the two-phase steps leave unused
+        msp_plan tmp;
+        tmp.U = P->U;
+        tmp.nsplit = P->nsplit;
+        tmp.sr = P->sr;
+        need = exec_layout(&tmp, nullptr, false);
+    }
+    if (workspace_bytes < need) return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "execution workspace too small");
     StageTimer none;
-    return numeric_impl(P, C, (hipStream_t)stream, none);
+    return numeric_impl(P, C, workspace, (hipStream_t)stream, none);
 }
 
-msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* stream) {
+msp_status msp_execute(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* workspace, size_t workspace_bytes,
+                       void* stream) {
     if (!P) return fail(MSP_ERR_INVALID_ARGUMENT, "plan is NULL");
     StageTimer none;
-    return execute_impl(P, C, nnz_host, (hipStream_t)stream, none);
+    return execute_impl(P, C, nnz_host, workspace, workspace_bytes, (hipStream_t)stream, none);
 }
 
-msp_status msp_execute_profiled(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, double* stage_ms, void* stream) {
+msp_status msp_execute_profiled(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* workspace,
+                                size_t workspace_bytes, double* stage_ms, void* stream) {
     if (!P || !stage_ms) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
     StageTimer tm;
     tm.on = true;
     tm.s = (hipStream_t)stream;
-    MSP_CHECK(execute_impl(P, C, nnz_host, tm.s, tm));
+    MSP_CHECK(execute_impl(P, C, nnz_host, workspace, workspace_bytes, tm.s, tm));
     return tm.collect(stage_ms);
 }
 
@@ -975,7 +1123,8 @@ void msp_timing_destroy(msp_timing* T) {
     delete T;
 }
 
-msp_status msp_execute_timed(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, msp_timing* T, void* stream) {
+msp_status msp_execute_timed(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, void* workspace, size_t workspace_bytes,
+                             msp_timing* T, void* stream) {
     if (!P || !T) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
     int dev = 0;
     MSP_HIP(hipGetDevice(&dev));
@@ -984,7 +1133,7 @@ msp_status msp_execute_timed(msp_plan* P, msp_csr_out* C, int64_t* nnz_host, msp
     tm.on = true;
     tm.s = (hipStream_t)stream;
     tm.sess = T;
-    return execute_impl(P, C, nnz_host, tm.s, tm);
+    return execute_impl(P, C, nnz_host, workspace, workspace_bytes, tm.s, tm);
 }
 
 msp_status msp_timing_collect(msp_timing* T, double* stage_ms) {
@@ -1018,69 +1167,61 @@ void msp_plan_destroy(msp_plan* P) {
 
 msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
                              msp_semiring semiring, const msp_options* opt, msp_csr_out* C, int64_t* nnz_host,
-                             void* stream) {
-    msp_plan* P = nullptr;
-    MSP_CHECK(msp_plan_create(&P, A, B, M, complement, semiring, opt, stream));
-    const msp_status st = msp_execute(P, C, nnz_host, stream);
-    if (st == MSP_OK && !nnz_host) (void)hipStreamSynchronize((hipStream_t)stream);
-    msp_plan_destroy(P);
-    return st;
+                             void* workspace, size_t workspace_bytes, size_t* ws_needed, void* stream) {
+    return one_shot(A, B, M, complement, semiring, opt, C, nnz_host, workspace, workspace_bytes, ws_needed,
+                    (hipStream_t)stream, false);
 }
 
 msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
-                           int64_t* upper_bound, void* stream) {
+                           int64_t* upper_bound, void* workspace, size_t workspace_bytes, void* stream) {
     if (!upper_bound) return fail(MSP_ERR_INVALID_ARGUMENT, "upper_bound is NULL");
     if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
-    msp_problem pb{};
-    pb.A = *A;
-    pb.B = *B;
-    pb.M = *M;
-    pb.complement = complement;
+    const msp_problem pb = single_problem(A, B, M, complement);
     msp_plan* P = nullptr;
-    MSP_CHECK(create_common(&P, &pb, 1, MSP_PLUS_PAIR_I64, nullptr, stream, false));
+    MSP_CHECK(create_common(&P, &pb, 1, MSP_PLUS_PAIR_I64, nullptr, workspace, workspace_bytes, stream));
     *upper_bound = P->ub;
-    (void)hipStreamSynchronize((hipStream_t)stream);
     msp_plan_destroy(P);
     return MSP_OK;
 }
 
 static msp_status reduce_impl(const void* values, int64_t n, const int64_t* n_dev, msp_semiring semiring,
-                              void* result, void* stream);
+                              void* result, void* ws, size_t ws_bytes, void* stream);
 
-msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result, void* stream) {
-    return reduce_impl(values, n, nullptr, semiring, result, stream);
+msp_status msp_reduce_workspace_size(size_t* bytes) {
+    if (!bytes) return fail(MSP_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    *bytes = sizeof(unsigned long long) * (size_t)reduce_partial_elems();
+    return MSP_OK;
+}
+
+msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    return reduce_impl(values, n, nullptr, semiring, result, workspace, workspace_bytes, stream);
 }
 
 msp_status msp_reduce_csr(const int64_t* rowptr, int64_t nrows, const void* values, int64_t capacity,
-                          msp_semiring semiring, void* result, void* stream) {
+                          msp_semiring semiring, void* result, void* workspace, size_t workspace_bytes,
+                          void* stream) {
     if (!rowptr || nrows < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "bad row pointers");
-    return reduce_impl(values, capacity, rowptr + nrows, semiring, result, stream);
+    return reduce_impl(values, capacity, rowptr + nrows, semiring, result, workspace, workspace_bytes, stream);
 }
 
 static msp_status reduce_impl(const void* values, int64_t n, const int64_t* n_dev, msp_semiring semiring,
-                              void* result, void* stream) {
+                              void* result, void* ws, size_t ws_bytes, void* stream) {
     if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     if (n < 0 || !result || (n > 0 && !values)) return fail(MSP_ERR_INVALID_ARGUMENT, "bad reduce arguments");
-    configure_pool();
-    hipStream_t s = (hipStream_t)stream;
-    void* partial = nullptr;
-    const size_t bytes = sizeof(unsigned long long) * (size_t)reduce_partial_elems();
-    bool pooled = true;
-    hipError_t e = hipMallocAsync(&partial, bytes, s);
-    if (e == hipErrorNotSupported) { pooled = false; e = hipMalloc(&partial, bytes); }
-    MSP_HIP(e);
-    const hipError_t le = launch_reduce(semiring, values, n, n_dev, partial, result, s);
-    if (pooled) (void)hipFreeAsync(partial, s);
-    else { (void)hipStreamSynchronize(s); (void)hipFree(partial); }
-    MSP_HIP(le);
+    size_t need = 0;
+    MSP_CHECK(msp_reduce_workspace_size(&need));
+    if (ws_bytes < need) return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "reduce workspace too small");
+    if (!ws) return fail(MSP_ERR_INVALID_ARGUMENT, "reduce workspace is NULL");
+    MSP_HIP(launch_reduce(semiring, values, n, n_dev, ws, result, (hipStream_t)stream));
     return MSP_OK;
 }
 
 // ------------------------------------------------------------------- batches
 
 msp_status msp_batch_create(msp_plan** batch, const msp_problem* problems, int64_t count, msp_semiring semiring,
-                            const msp_options* opt, void* stream) {
-    return create_common(batch, problems, count, semiring, opt, stream, true);
+                            const msp_options* opt, void* workspace, size_t workspace_bytes, void* stream) {
+    return create_common(batch, problems, count, semiring, opt, workspace, workspace_bytes, stream);
 }
 
 int64_t msp_batch_count(const msp_plan* P) { return P ? P->P : 0; }
@@ -1108,8 +1249,9 @@ msp_status msp_batch_info(const msp_plan* P, int64_t p, msp_plan_info_t* info) {
     return MSP_OK;
 }
 
-msp_status msp_batch_bind(msp_plan* P, const msp_csr_out* C, void* stream) {
+msp_status msp_batch_bind(msp_plan* P, const msp_csr_out* C, void* workspace, size_t workspace_bytes, void* stream) {
     if (!P || !C) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (P->opt.phase != 1) return fail(MSP_ERR_UNSUPPORTED, "a batch runs one-phase only");
     std::vector<OutBind> outs((size_t)P->P);
     for (int64_t p = 0; p < P->P; ++p) {
         const Product& pr = P->prods[(size_t)p];
@@ -1117,15 +1259,16 @@ msp_status msp_batch_bind(msp_plan* P, const msp_csr_out* C, void* stream) {
         if (C[p].capacity < pr.ub) return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "output capacity below its upper bound");
         outs[(size_t)p] = bind_of(P, &C[p], p);
     }
-    if (P->P > 1) {
-        hipStream_t s = (hipStream_t)stream;
-        MSP_HIP(hipMemcpyAsync(P->outs_d, outs.data(), sizeof(OutBind) * P->P, hipMemcpyHostToDevice, s));
-        MSP_HIP(hipStreamSynchronize(s));
-    }
-    P->outs = std::move(outs);
-    // a captured graph refers to the previous outputs
+    // a captured graph refers to the previous outputs and workspace
     if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
     if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+    P->bound = false;
+    hipStream_t s = (hipStream_t)stream;
+    MSP_CHECK(place_units(P, workspace, workspace_bytes, true, s));
+    if (P->P > 1)
+        MSP_HIP(hipMemcpyAsync(P->outs_d, outs.data(), sizeof(OutBind) * P->P, hipMemcpyHostToDevice, s));
+    MSP_HIP(hipStreamSynchronize(s));
+    P->outs = std::move(outs);
     P->bound = true;
     return MSP_OK;
 }

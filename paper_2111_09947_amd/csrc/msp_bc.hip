@@ -186,33 +186,6 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, 
 unsigned row_blocks(int64_t n) { return (unsigned)std::min<int64_t>(blocks_for(n, BC_T / WAVE), int64_t(1) << 20); }
 unsigned grid_cap(int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 65536); }
 
-// Stream-ordered device allocations released together (in stream order).
-struct DevArena {
-    hipStream_t s;
-    std::vector<void*> ptrs;
-    explicit DevArena(hipStream_t st) : s(st) {}
-    template <class T>
-    msp_status get(T** p, int64_t count) {
-        void* q = nullptr;
-        const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
-        const hipError_t e = hipMallocAsync(&q, bytes, s);
-        if (e != hipSuccess) return set_error(MSP_ERR_OUT_OF_MEMORY, "device allocation for the BC levels");
-        ptrs.push_back(q);
-        *p = static_cast<T*>(q);
-        return MSP_OK;
-    }
-    void release(void* p) {
-        auto it = std::find(ptrs.begin(), ptrs.end(), p);
-        if (it != ptrs.end()) {
-            (void)hipFreeAsync(p, s);
-            ptrs.erase(it);
-        }
-    }
-    ~DevArena() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, s);
-    }
-};
-
 struct Level {
     int64_t* rp = nullptr;
     int32_t* ci = nullptr;
@@ -231,15 +204,23 @@ struct Level {
         if (_st != MSP_OK) return _st;      \
     } while (0)
 
-// One masked FP64 product into freshly allocated arrays (rows = n).
+// One masked FP64 product into freshly allocated arrays (rows = n); the
+// plan's workspaces come from `mem` and go back to it before returning.
 msp_status masked_product(const msp_csr& A, const msp_csr& B, const msp_csr& M, int complement, hipStream_t s,
-                          DevArena& mem, Level& out, int64_t& products) {
-    msp_plan* P = nullptr;
+                          DevMem& mem, Level& out, int64_t& products) {
     msp_options opt;
     msp_options_default(&opt);
-    BC_CHECK(msp_plan_create(&P, &A, &B, &M, complement, MSP_PLUS_TIMES_F64, &opt, s));
+    size_t pws_bytes = 0, xws_bytes = 0;
+    BC_CHECK(msp_plan_workspace_size(&A, &B, &M, complement, MSP_PLUS_TIMES_F64, &opt, &pws_bytes));
+    void* pws = nullptr;
+    BC_CHECK(mem.bytes(&pws, pws_bytes));
+    msp_plan* P = nullptr;
+    BC_CHECK(msp_plan_create(&P, &A, &B, &M, complement, MSP_PLUS_TIMES_F64, &opt, pws, pws_bytes, s));
     msp_plan_info_t pi;
     msp_status st = msp_plan_info(P, &pi);
+    void* xws = nullptr;
+    if (st == MSP_OK) st = msp_workspace_size(P, &xws_bytes);
+    if (st == MSP_OK) st = mem.bytes(&xws, xws_bytes);
     if (st == MSP_OK) {
         products += pi.products;
         const int64_t cap = std::max<int64_t>(pi.upper_bound, 1);
@@ -248,10 +229,12 @@ msp_status masked_product(const msp_csr& A, const msp_csr& B, const msp_csr& M, 
         if (st == MSP_OK) st = mem.get(&out.val, cap);
         if (st == MSP_OK) {
             msp_csr_out C{A.nrows, B.ncols, cap, out.rp, out.ci, out.val};
-            st = msp_execute(P, &C, &out.nnz, s);
+            st = msp_execute(P, &C, &out.nnz, xws, xws_bytes, s);  // synchronizes: nnz is read back
         }
     }
     msp_plan_destroy(P);
+    if (xws) mem.release(xws);
+    mem.release(pws);
     return st;
 }
 
@@ -261,12 +244,13 @@ msp_status masked_product(const msp_csr& A, const msp_csr& B, const msp_csr& M, 
 using namespace mspk;
 
 extern "C" msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int64_t nsrc, double* bc,
-                                   msp_bc_info_t* info, void* stream) {
+                                   msp_bc_info_t* info, const msp_allocator* alloc, void* stream) {
     if (info) std::memset(info, 0, sizeof(*info));
     if (!A) return set_error(MSP_ERR_INVALID_ARGUMENT, "A is NULL");
     if (A->nrows != A->ncols) return set_error(MSP_ERR_DIMENSION_MISMATCH, "A must be square");
     if (nsrc < 0 || (nsrc > 0 && !sources)) return set_error(MSP_ERR_INVALID_ARGUMENT, "bad source list");
     if (nsrc > INT32_MAX) return set_error(MSP_ERR_UNSUPPORTED, "too many sources");
+    if (!alloc || !alloc->alloc || !alloc->release) return set_error(MSP_ERR_INVALID_ARGUMENT, "no allocator");
     const int64_t n = A->nrows;
     if (n > 0 && !bc) return set_error(MSP_ERR_INVALID_ARGUMENT, "bc is NULL");
     for (int64_t j = 0; j < nsrc; ++j)
@@ -275,7 +259,7 @@ extern "C" msp_status msp_bc_batch(const msp_csr* A, const int32_t* sources, int
     if (n == 0 || nsrc == 0) return MSP_OK;
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
-    DevArena mem(s);
+    DevMem mem(alloc, s);
     const msp_csr Aiso{A->nrows, A->ncols, A->nnz, A->rowptr, A->colidx, nullptr};
 
     // level 0: row src_j holds column j with sigma = 1 (entries sorted by row, then column)

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include <vector>
 
 #include "msp.h"
 
@@ -249,8 +252,9 @@ hipError_t launch_reduce(int semiring, const void* vals, int64_t n, const int64_
                          hipStream_t s);
 
 // Unit-list segment offsets from the per-product statistics; zeroes the
-// placement cursors (NBINS * NBUCKET + 1 entries); copies the statistics to
-// `host_stats` (device-visible page-locked host memory) unless it is null.
+// placement cursors (NBINS * NBUCKET + 1 entries) unless `cursor` is null;
+// copies the statistics to `host_stats` (device-visible page-locked host
+// memory) unless it is null.
 hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
                          unsigned long long* cursor, unsigned long long* host_stats, hipStream_t s);
 // *host_dst = *src, with host_dst device-visible page-locked host memory.
@@ -258,6 +262,40 @@ hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s);
 
 // Records `msg` as the thread's last error (msp_last_error) and returns `st`.
 msp_status set_error(msp_status st, const char* msg);
+
+// Device buffers of the iterated applications (betweenness centrality,
+// k-truss), taken from the caller's allocator; every buffer still held is
+// released, in stream order, when the holder goes out of scope.
+struct DevMem {
+    const msp_allocator* a;
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    DevMem(const msp_allocator* alloc, hipStream_t st) : a(alloc), s(st) {}
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    msp_status bytes(void** p, size_t n) {
+        void* q = a->alloc(a->ctx, n > 0 ? n : 1, (void*)s);
+        if (!q) return set_error(MSP_ERR_OUT_OF_MEMORY, "the caller's allocator returned no memory");
+        ptrs.push_back(q);
+        *p = q;
+        return MSP_OK;
+    }
+    template <class T>
+    msp_status get(T** p, int64_t count) {
+        return bytes(reinterpret_cast<void**>(p), sizeof(T) * (size_t)(count > 0 ? count : 1));
+    }
+    void release(const void* p) {
+        for (size_t x = 0; x < ptrs.size(); ++x)
+            if (ptrs[x] == p) {
+                a->release(a->ctx, ptrs[x], (void*)s);
+                ptrs.erase(ptrs.begin() + (std::ptrdiff_t)x);
+                return;
+            }
+    }
+    ~DevMem() {
+        for (size_t x = ptrs.size(); x-- > 0;) a->release(a->ctx, ptrs[x], (void*)s);
+    }
+};
 
 // Stage timing: between timing_arm(start, stop) and timing_disarm(), the
 // launches of this thread record `start` at the beginning of the first kernel

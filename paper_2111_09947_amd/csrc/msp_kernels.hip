@@ -422,7 +422,8 @@ __global__ __launch_bounds__(128) void k_segoff(const unsigned long long* __rest
         for (int64_t p = 0; p < count; ++p) c += (int64_t)stats[p * ST_COUNT + ST_BIN0 + x];
         segc[x] = c;
     }
-    for (int x = threadIdx.x; x < NBINS * NBUCKET + 1; x += blockDim.x) cursor[x] = 0ull;
+    if (cursor)
+        for (int x = threadIdx.x; x < NBINS * NBUCKET + 1; x += blockDim.x) cursor[x] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t run = 0;

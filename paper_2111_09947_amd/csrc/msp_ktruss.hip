@@ -76,31 +76,14 @@ unsigned kt_blocks(int64_t n, int per) {
         if (_st != MSP_OK) return _st;      \
     } while (0)
 
-struct Arena {
-    hipStream_t s;
-    std::vector<void*> ptrs;
-    explicit Arena(hipStream_t st) : s(st) {}
-    template <class T>
-    msp_status get(T** p, int64_t count) {
-        void* q = nullptr;
-        if (hipMallocAsync(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1), s) != hipSuccess)
-            return set_error(MSP_ERR_OUT_OF_MEMORY, "device allocation for the k-truss iterations");
-        ptrs.push_back(q);
-        *p = static_cast<T*>(q);
-        return MSP_OK;
-    }
-    ~Arena() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, s);
-    }
-};
-
 }  // namespace
 }  // namespace mspk
 
 using namespace mspk;
 
 extern "C" msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr, int32_t* C_colidx,
-                                 int64_t* C_support, int64_t* nnz_host, msp_ktruss_info_t* info, void* stream) {
+                                 int64_t* C_support, int64_t* nnz_host, msp_ktruss_info_t* info,
+                                 const msp_allocator* alloc, void* stream) {
     if (info) std::memset(info, 0, sizeof(*info));
     if (!A || !nnz_host) return set_error(MSP_ERR_INVALID_ARGUMENT, "A and nnz_host must not be NULL");
     if (A->nrows != A->ncols) return set_error(MSP_ERR_DIMENSION_MISMATCH, "A must be square");
@@ -108,10 +91,11 @@ extern "C" msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr,
     const int64_t n = A->nrows;
     if (!C_rowptr || (A->nnz > 0 && (!C_colidx || !C_support)))
         return set_error(MSP_ERR_INVALID_ARGUMENT, "output arrays must not be NULL");
+    if (!alloc || !alloc->alloc || !alloc->release) return set_error(MSP_ERR_INVALID_ARGUMENT, "no allocator");
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t thresh = (int64_t)k - 2;
-    Arena mem(s);
+    DevMem mem(alloc, s);
     // current graph (pattern): starts as A
     const int64_t* rp = A->rowptr;
     const int32_t* ci = A->colidx;
@@ -139,12 +123,18 @@ extern "C" msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr,
         msp_plan* P = nullptr;
         msp_options opt;
         msp_options_default(&opt);
-        KT_CHECK(msp_plan_create(&P, &Cv, &Cv, &Cv, 0, MSP_PLUS_PAIR_I64, &opt, s));
+        size_t pws_bytes = 0, xws_bytes = 0;
+        KT_CHECK(msp_plan_workspace_size(&Cv, &Cv, &Cv, 0, MSP_PLUS_PAIR_I64, &opt, &pws_bytes));
+        void *pws = nullptr, *xws = nullptr;
+        KT_CHECK(mem.bytes(&pws, pws_bytes));
+        KT_CHECK(msp_plan_create(&P, &Cv, &Cv, &Cv, 0, MSP_PLUS_PAIR_I64, &opt, pws, pws_bytes, s));
         msp_plan_info_t pi;
         msp_status st = msp_plan_info(P, &pi);
         int64_t *srp = nullptr, *sv = nullptr;
         int32_t* sci = nullptr;
         int64_t snnz = 0;
+        if (st == MSP_OK) st = msp_workspace_size(P, &xws_bytes);
+        if (st == MSP_OK) st = mem.bytes(&xws, xws_bytes);
         if (st == MSP_OK) {
             products += pi.products;
             const int64_t cap = std::max<int64_t>(pi.upper_bound, 1);
@@ -153,10 +143,12 @@ extern "C" msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr,
             if (st == MSP_OK) st = mem.get(&sv, cap);
             if (st == MSP_OK) {
                 msp_csr_out So{n, n, cap, srp, sci, sv};
-                st = msp_execute(P, &So, &snnz, s);
+                st = msp_execute(P, &So, &snnz, xws, xws_bytes, s);  // synchronizes: nnz is read back
             }
         }
         msp_plan_destroy(P);
+        if (xws) mem.release(xws);
+        mem.release(pws);
         if (st != MSP_OK) return st;
         ++iters;
         // keep the entries with support >= k - 2
@@ -177,6 +169,15 @@ extern "C" msp_status msp_ktruss(const msp_csr* A, int32_t k, int64_t* C_rowptr,
                            nrp, nci, nv);
         KT_HIP(hipGetLastError());
         const bool done = nn == nnz;
+        // the previous graph and the support product are no longer needed (stream order)
+        if (rp != A->rowptr) {
+            mem.release(rp);
+            mem.release(ci);
+            mem.release(sup);
+        }
+        mem.release(srp);
+        mem.release(sci);
+        mem.release(sv);
         rp = nrp;
         ci = nci;
         sup = nv;

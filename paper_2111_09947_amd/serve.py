@@ -13,10 +13,15 @@ Design
     A group of one runs as a single-product plan, a larger group as one batch
     (one launch per kernel bin for all its products). Slots overlap on the
     device.
-  - Admission is by memory: a request's output/staging estimate must fit the
-    budget minus what running groups hold; otherwise it waits. A request that
-    alone exceeds the budget, or whose execution raises, completes with an
-    error and the loop keeps serving.
+  - Admission is by memory: a request's device bytes must fit the budget
+    minus what running groups hold; otherwise it waits. The bytes are the
+    library's own sizes for the product (plan workspace, execution workspace
+    and the output at its upper bound: product_bytes), taken once per
+    resident operand set. A batch's device tables add a little to the sum of
+    its products; the executor reports the group's real bytes and the
+    accounting follows them while the group runs. A request that alone
+    exceeds the budget, or whose execution raises, completes with an error
+    and the loop keeps serving.
   - Latency is measured from the request's arrival time to the moment its
     group's stream has finished (the worker synchronizes its own stream).
 
@@ -36,7 +41,7 @@ class Request:
     rid: int
     semiring: str
     operands: Any               # (A, B, M, complement) for the GPU executor
-    est_bytes: int = 0          # admission estimate
+    mem_bytes: int = 0          # device bytes the product needs (admission)
     t_arrival: float = 0.0      # perf_counter() time of arrival
     t_start: float = 0.0
     t_done: float = 0.0
@@ -50,12 +55,16 @@ class Request:
         return self.t_done - self.t_arrival
 
 
-def estimate_bytes(A, B, M, complement: bool, out_width: int) -> int:
-    """Upper estimate of a product's output + staging bytes before planning:
-    every admitted position can produce at most one entry (the mask count for
-    a normal mask, the complement's size otherwise)."""
-    adm = (A.nrows * B.ncols - M.nnz) if complement else M.nnz
-    return 2 * adm * (4 + out_width) + 16 * (A.nrows + 1)
+def product_bytes(A, B, M, complement: bool, semiring: str) -> int:
+    """Device bytes one product takes in the library: its plan workspace,
+    its execution workspace and its output (row pointers, and column indices
+    and values at the upper bound), as the library's size queries give them.
+    Runs the row analysis once (one plan creation)."""
+    from . import Plan, out_dtype
+    with Plan(A, B, M, complement=complement, semiring=semiring) as p:
+        width = out_dtype(semiring).itemsize
+        return (p.plan_workspace_bytes + p.workspace_bytes + 8 * (p.nrows + 1)
+                + max(p.upper_bound, 1) * (4 + width))
 
 
 class Server:
@@ -107,24 +116,24 @@ class Server:
         that fit the remaining memory budget."""
         head = self._queue[0]
         room = self.mem_budget - self._mem_in_use
-        if head.est_bytes > self.mem_budget:
+        if head.mem_bytes > self.mem_budget:
             self._queue.popleft()
             head.error = "request exceeds the memory budget"
             head.t_done = time.perf_counter()
             head.done.set()
             self.completed.append(head)
             return []
-        if head.est_bytes > room:
+        if head.mem_bytes > room:
             return []  # wait for memory
         group = [self._queue.popleft()]
-        room -= head.est_bytes
+        room -= head.mem_bytes
         if self.continuous:
             keep: Deque[Request] = collections.deque()
             while self._queue and len(group) < self.max_batch:
                 r = self._queue.popleft()
-                if r.semiring == head.semiring and r.est_bytes <= room:
+                if r.semiring == head.semiring and r.mem_bytes <= room:
                     group.append(r)
-                    room -= r.est_bytes
+                    room -= r.mem_bytes
                 else:
                     keep.append(r)
             keep.extend(self._queue)
@@ -140,11 +149,11 @@ class Server:
                     return
                 group = self._pick_group()
                 if not group:
-                    if self._queue and self._queue[0].est_bytes <= self.mem_budget:
+                    if self._queue and self._queue[0].mem_bytes <= self.mem_budget:
                         self._cv.wait(timeout=0.01)  # memory is held by running groups
                     continue
                 slot = self._free_slots.pop(0)
-                self._mem_in_use += sum(r.est_bytes for r in group)
+                self._mem_in_use += sum(r.mem_bytes for r in group)
                 self._work[slot].append(group)
                 self._cv.notify_all()
 
@@ -159,8 +168,17 @@ class Server:
             t0 = time.perf_counter()
             for r in group:
                 r.t_start = t0
+            admitted = sum(r.mem_bytes for r in group)
+            held = admitted
+
+            def report(actual: int):
+                """The executor's real bytes for the group (a batch's tables)."""
+                nonlocal held
+                with self._cv:
+                    self._mem_in_use += int(actual) - held
+                    held = int(actual)
             try:
-                self.executor(slot, group)
+                self.executor(slot, group, report)
             except Exception as e:  # the loop keeps serving; the group fails
                 for r in group:
                     r.error = f"{type(e).__name__}: {e}"
@@ -170,23 +188,33 @@ class Server:
                     r.t_done = t1
                     self.completed.append(r)
                     r.done.set()
-                self._mem_in_use -= sum(r.est_bytes for r in group)
+                self._mem_in_use -= held
                 self._free_slots.append(slot)
                 self._cv.notify_all()
 
 
 class GpuExecutor:
     """Runs a group on the slot's own stream: one product as a plan, several
-    as one batch. Stores each request's DeviceCSR result."""
+    as one batch. Stores each request's DeviceCSR result and reports the
+    group's device bytes (workspaces and outputs) to the server."""
 
     def __init__(self, slots: int):
         import torch
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self._sizes: Dict[Any, int] = {}
 
-    def __call__(self, slot: int, group: List[Request]):
+    def bytes_of(self, operands, semiring: str) -> int:
+        """product_bytes of a resident operand set, computed once."""
+        key = (id(operands), semiring)
+        if key not in self._sizes:
+            A, B, M, comp = operands
+            self._sizes[key] = product_bytes(A, B, M, comp, semiring)
+        return self._sizes[key]
+
+    def __call__(self, slot: int, group: List[Request], report: Optional[Callable[[int], None]] = None):
         import torch
 
-        from . import Batch, Plan
+        from . import Batch, Plan, out_dtype
         s = self.streams[slot]
         with torch.cuda.stream(s):
             if len(group) == 1:
@@ -197,7 +225,11 @@ class GpuExecutor:
                     r.result = C if r.keep else int(C.colidx.numel())
             else:
                 with Batch([r.operands for r in group], semiring=group[0].semiring) as b:
-                    b.bind_new_outputs()
+                    outs = b.bind_new_outputs()
+                    if report is not None:
+                        width = out_dtype(group[0].semiring).itemsize
+                        report(b.plan_workspace_bytes + b.workspace_bytes +
+                               sum(rp.numel() * 8 + ci.numel() * (4 + width) for rp, ci, _ in outs))
                     b.execute()
                     for r, C in zip(group, b.results()):
                         r.result = C if r.keep else int(C.colidx.numel())

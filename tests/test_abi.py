@@ -55,14 +55,16 @@ def test_argument_errors_need_no_gpu():
     h = ctypes.c_void_p()
     A, B, M = _csr(L, 4, 5), _csr(L, 5, 6), _csr(L, 4, 6)
     # NULL operand
-    st = lib.msp_plan_create(ctypes.byref(h), None, ctypes.byref(B), ctypes.byref(M), 0, 0, None, None)
+    st = lib.msp_plan_create(ctypes.byref(h), None, ctypes.byref(B), ctypes.byref(M), 0, 0, None, None, 0, None)
     assert st == 1
     # dimension mismatch
     Bbad = _csr(L, 7, 6)
-    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(Bbad), ctypes.byref(M), 0, 0, None, None)
+    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(Bbad), ctypes.byref(M), 0, 0, None, None, 0,
+                             None)
     assert st == 2 and b"A.ncols" in lib.msp_last_error()
     # unknown semiring
-    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 0, 9, None, None)
+    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 0, 9, None, None, 0,
+                             None)
     assert st == 1
     # complemented mask with a mask-keyed kind
     o = L.MspOptions()
@@ -70,25 +72,26 @@ def test_argument_errors_need_no_gpu():
     for kind in (1, 2, 3):
         o.force_kind = kind
         st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 1, 0,
-                                 ctypes.byref(o), None)
+                                 ctypes.byref(o), None, 0, None)
         assert st == 4
     # unknown kind
     o.force_kind = 5
     st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 0, 0,
-                             ctypes.byref(o), None)
+                             ctypes.byref(o), None, 0, None)
     assert st == 1 and b"force_kind" in lib.msp_last_error()
     # bad phase
     o.force_kind = -1
     o.phase = 3
     st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(A), ctypes.byref(B), ctypes.byref(M), 0, 0,
-                             ctypes.byref(o), None)
+                             ctypes.byref(o), None, 0, None)
     assert st == 1
     # nnz > 0 with NULL colidx
     Anull = L.MspCsr(4, 5, 3, 1, 0, 0)
-    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(Anull), ctypes.byref(B), ctypes.byref(M), 0, 0, None, None)
+    st = lib.msp_plan_create(ctypes.byref(h), ctypes.byref(Anull), ctypes.byref(B), ctypes.byref(M), 0, 0, None, None,
+                             0, None)
     assert st == 1
     # reduce with negative length
-    assert lib.msp_reduce(None, -1, 0, ctypes.c_void_p(8), None) == 1
+    assert lib.msp_reduce(None, -1, 0, ctypes.c_void_p(8), None, 0, None) == 1
 
 
 def test_timing_and_csr_reduce_argument_errors():
@@ -96,10 +99,67 @@ def test_timing_and_csr_reduce_argument_errors():
     assert lib.msp_timing_create(None, 0, 0) == 1
     h = ctypes.c_void_p()
     assert lib.msp_timing_create(ctypes.byref(h), -1, 0) == 1 and b"executions" in lib.msp_last_error()
-    assert lib.msp_execute_timed(None, None, None, None, None) == 1
+    assert lib.msp_execute_timed(None, None, None, None, 0, None, None) == 1
     assert lib.msp_timing_collect(None, None) == 1
     lib.msp_timing_destroy(None)  # accepted, does nothing
-    assert lib.msp_reduce_csr(None, 5, None, 0, 1, None, None) == 1
-    assert lib.msp_reduce_csr(ctypes.c_void_p(8), -1, None, 0, 1, None, None) == 1
-    assert lib.msp_reduce_csr(ctypes.c_void_p(8), 5, None, 0, 9, ctypes.c_void_p(8), None) == 1  # semiring
-    assert lib.msp_reduce_csr(ctypes.c_void_p(8), 5, None, 4, 1, ctypes.c_void_p(8), None) == 1  # values NULL
+    assert lib.msp_reduce_csr(None, 5, None, 0, 1, None, None, 0, None) == 1
+    assert lib.msp_reduce_csr(ctypes.c_void_p(8), -1, None, 0, 1, None, None, 0, None) == 1
+    assert lib.msp_reduce_csr(ctypes.c_void_p(8), 5, None, 0, 9, ctypes.c_void_p(8), None, 0, None) == 1  # semiring
+    assert lib.msp_reduce_csr(ctypes.c_void_p(8), 5, None, 4, 1, ctypes.c_void_p(8), None, 0, None) == 1  # values
+
+
+def test_workspace_sizes_on_the_host():
+    """The plan workspace is sized from shapes alone (no GPU): it grows with
+    the rows and with B^T when the inner kind may run, and a workspace one
+    byte short is refused before any device work."""
+    lib, L = _lib()
+    sz = ctypes.c_size_t(0)
+    small = [_csr(L, 100, 50, 10), _csr(L, 50, 60, 10), _csr(L, 100, 60, 10)]
+    big = [_csr(L, 100000, 50, 10), _csr(L, 50, 60, 10), _csr(L, 100000, 60, 10)]
+    assert lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in small), 0, 0, None, ctypes.byref(sz)) == 0
+    s_small = sz.value
+    assert lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in big), 0, 0, None, ctypes.byref(sz)) == 0
+    s_big = sz.value
+    # flops + unit_base (int64) and bin (int8) per row at least
+    assert s_big - s_small >= (100000 - 100) * 17
+    o = L.MspOptions()
+    lib.msp_options_default(ctypes.byref(o))
+    o.force_kind = 3  # inner: B^T is laid out in the plan workspace
+    assert lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in small), 0, 0, ctypes.byref(o),
+                                       ctypes.byref(sz)) == 0
+    assert sz.value > s_small
+    # argument errors of the size query match plan creation's
+    bad = _csr(L, 7, 60)
+    assert lib.msp_plan_workspace_size(ctypes.byref(small[0]), ctypes.byref(bad), ctypes.byref(small[2]), 0, 0, None,
+                                       ctypes.byref(sz)) == 2
+    assert lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in small), 0, 0, None, None) == 1
+    # a workspace one byte short of the query: MSP_ERR_INSUFFICIENT_CAPACITY, nothing enqueued
+    h = ctypes.c_void_p()
+    st = lib.msp_plan_create(ctypes.byref(h), *(ctypes.byref(x) for x in small), 0, 0, None, ctypes.c_void_p(256),
+                             s_small - 1, None)
+    assert st == 5 and b"plan workspace" in lib.msp_last_error() and not h.value
+    # the one-shot call reports the bytes it needs
+    need = ctypes.c_size_t(0)
+    out = L.MspCsrOut(100, 60, 0, 8, 0, 0)
+    st = lib.msp_masked_spgemm(*(ctypes.byref(x) for x in small), 0, 0, None, ctypes.byref(out), None, None, 0,
+                               ctypes.byref(need), None)
+    assert st == 5 and need.value == s_small
+    # batches: the size of two products exceeds that of one
+    pr = (L.MspProblem * 2)()
+    for q in range(2):
+        pr[q].A, pr[q].B, pr[q].M = small
+    assert lib.msp_batch_workspace_size(pr, 2, 0, None, ctypes.byref(sz)) == 0
+    assert sz.value > s_small
+    # reduce
+    assert lib.msp_reduce_workspace_size(ctypes.byref(sz)) == 0 and sz.value > 0
+    assert lib.msp_reduce(ctypes.c_void_p(8), 4, 0, ctypes.c_void_p(8), ctypes.c_void_p(256), sz.value - 1, None) == 5
+
+
+def test_iterated_products_need_an_allocator():
+    lib, L = _lib()
+    A = _csr(L, 4, 4, 0)
+    n = ctypes.c_int64(0)
+    src = (ctypes.c_int32 * 1)(0)
+    assert lib.msp_ktruss(ctypes.byref(A), 3, ctypes.c_void_p(8), None, None, ctypes.byref(n), None, None, None) == 1
+    assert lib.msp_bc_batch(ctypes.byref(A), src, 1, ctypes.c_void_p(8), None, None, None) == 1
+    assert b"allocator" in lib.msp_last_error()

@@ -17,16 +17,16 @@ class FakeExec:
         self.active = 0
         self.max_active = 0
 
-    def __call__(self, slot, group):
+    def __call__(self, slot, group, report=None):
         with self.lock:
             self.groups.append([r.rid for r in group])
-            self.mem += sum(r.est_bytes for r in group)
+            self.mem += sum(r.mem_bytes for r in group)
             self.max_mem = max(self.max_mem, self.mem)
             self.active += 1
             self.max_active = max(self.max_active, self.active)
         time.sleep(self.delay)
         with self.lock:
-            self.mem -= sum(r.est_bytes for r in group)
+            self.mem -= sum(r.mem_bytes for r in group)
             self.active -= 1
         if any(r.rid in self.fail_on for r in group):
             raise RuntimeError("injected failure")
@@ -35,7 +35,7 @@ class FakeExec:
 
 
 def _mk(i, sr=None, est=100):
-    return Request(rid=i, semiring=sr or ("a" if i % 2 else "b"), operands=None, est_bytes=est)
+    return Request(rid=i, semiring=sr or ("a" if i % 2 else "b"), operands=None, mem_bytes=est)
 
 
 def test_all_complete_and_latency_positive():
