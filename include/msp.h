@@ -382,6 +382,30 @@ msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* 
                              int64_t* nnz_host, void* workspace, size_t workspace_bytes, size_t* ws_needed,
                              void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * one-shot product of msp_masked_spgemm with the same arguments and results,
+ * but working in a fixed scratch array of MSP_NOALLOC_SCRATCH_BYTES bytes
+ * that the library holds in device memory instead of a caller workspace.
+ * Allocates no device memory and no page-locked host memory. Each GPU the
+ * library runs on holds its own copy of the array until the process ends;
+ * its device address is looked up once per device on the first call there,
+ * with that device current, and `stream` must belong to the current device.
+ * The caller still passes the operands and the output C (capacity rules as
+ * msp_masked_spgemm). A product whose workspace would exceed the array
+ * returns MSP_ERR_INSUFFICIENT_CAPACITY with *ws_needed (when not NULL) set
+ * to the bytes msp_masked_spgemm reports. Every call on one GPU shares that
+ * GPU's array and leaves its contents behind (the next call clears what it
+ * needs): calls that overlap on one GPU, from several host threads or
+ * streams, race and must be serialized by the caller. SYNCHRONIZES.
+ */
+#define MSP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+msp_status msp_masked_spgemm_noalloc(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                                     msp_semiring semiring, const msp_options* opt, msp_csr_out* C,
+                                     int64_t* nnz_host, size_t* ws_needed, void* stream);
+
 /* Exact per-row output bound summed over rows (see msp_plan_info_t), by the
    row analysis in `workspace` (device, at least msp_plan_workspace_size of
    the same operands under MSP_PLUS_PAIR_I64 and default options).

@@ -391,6 +391,29 @@ def one_shot(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
     raise MspError(5, "msp_masked_spgemm: workspace size did not settle")
 
 
+def masked_spgemm_noalloc(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, rowptr, colidx, values,
+                          complement: bool = False, semiring: str = "plus_times_f64", **opts) -> int:
+    """msp_masked_spgemm_noalloc: the one-shot product in the library's fixed
+    device scratch, into caller-allocated outputs (rowptr: nrows+1 int64;
+    colidx and values of equal length, the capacity). Allocates nothing;
+    returns nnz(C). Raises MspError (MSP_ERR_INSUFFICIENT_CAPACITY) when the
+    capacity is below the bound or the product needs more than the scratch."""
+    lib = L.load()
+    vs = (_view(A, semiring, "A"), _view(B, semiring, "B"), _view(M, None, "M"))
+    o = options(**opts)
+    cap = int(colidx.numel())
+    if int(values.numel()) != cap or values.dtype != out_dtype(semiring):
+        raise ValueError("values must match colidx in length and have the semiring's output type")
+    out = L.MspCsrOut(A.nrows, B.ncols, cap, rowptr.data_ptr(), colidx.data_ptr() if cap else 0,
+                      values.data_ptr() if cap else 0)
+    n = ctypes.c_int64(0)
+    need = ctypes.c_size_t(0)
+    _check(lib.msp_masked_spgemm_noalloc(*(ctypes.byref(v) for v in vs), int(bool(complement)), SEMIRINGS[semiring],
+                                         ctypes.byref(o), ctypes.byref(out), ctypes.byref(n), ctypes.byref(need),
+                                         _stream()), "msp_masked_spgemm_noalloc")
+    return n.value
+
+
 class Timing:
     """A timing session: Plan.execute_timed records stage events into it
     without synchronizing; collect() waits for them and adds each stage's

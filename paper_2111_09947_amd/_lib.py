@@ -87,6 +87,8 @@ SIGNATURES = {
     "msp_plan_destroy": (None, [c_vp]),
     "msp_masked_spgemm": (ctypes.c_int, [P_csr, P_csr, P_csr, ctypes.c_int, ctypes.c_int, P_opt, P_out,
                                          ctypes.POINTER(c_i64), c_vp, c_sz, P_sz, c_vp]),
+    "msp_masked_spgemm_noalloc": (ctypes.c_int, [P_csr, P_csr, P_csr, ctypes.c_int, ctypes.c_int, P_opt, P_out,
+                                                 ctypes.POINTER(c_i64), P_sz, c_vp]),
     "msp_upper_bound": (ctypes.c_int, [P_csr, P_csr, P_csr, ctypes.c_int, ctypes.POINTER(c_i64), c_vp, c_sz, c_vp]),
     "msp_reduce": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_vp, c_sz, c_vp]),
     "msp_reduce_workspace_size": (ctypes.c_int, [P_sz]),

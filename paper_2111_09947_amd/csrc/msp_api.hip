@@ -980,6 +980,34 @@ static msp_problem single_problem(const msp_csr* A, const msp_csr* B, const msp_
     return pb;
 }
 
+// The workspace of msp_masked_spgemm_noalloc: a fixed array in device memory
+// that each GPU the library runs on holds until the process ends. In host
+// code its name is only a host-side stand-in; the array's device address on
+// a GPU comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[MSP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+// The scratch array's device address on the current device.
+static msp_status scratch_address(void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    MSP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MSP_ERR_UNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return from_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                   "hipGetSymbolAddress(scratch)");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return MSP_OK;
+}
+
 // The one-shot product in one workspace: the plan workspace, then the
 // execution workspace.
 static msp_status one_shot(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
@@ -1170,6 +1198,23 @@ msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* 
                              void* workspace, size_t workspace_bytes, size_t* ws_needed, void* stream) {
     return one_shot(A, B, M, complement, semiring, opt, C, nnz_host, workspace, workspace_bytes, ws_needed,
                     (hipStream_t)stream, false);
+}
+
+msp_status msp_masked_spgemm_noalloc(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
+                                     msp_semiring semiring, const msp_options* opt, msp_csr_out* C,
+                                     int64_t* nnz_host, size_t* ws_needed, void* stream) {
+    void* ws = nullptr;
+    MSP_CHECK(scratch_address(&ws));
+    size_t need = 0;
+    // plain copies for the host reads: no page-locked host memory either
+    const msp_status st = one_shot(A, B, M, complement, semiring, opt, C, nnz_host, ws, MSP_NOALLOC_SCRATCH_BYTES,
+                                   &need, (hipStream_t)stream, true);
+    if (ws_needed) *ws_needed = need;
+    if (st == MSP_ERR_INSUFFICIENT_CAPACITY && need > MSP_NOALLOC_SCRATCH_BYTES)
+        return fail(st, "the product needs " + std::to_string(need) + " bytes of workspace (or more), above the " +
+                            std::to_string((size_t)MSP_NOALLOC_SCRATCH_BYTES) +
+                            " bytes of the fixed scratch; use msp_masked_spgemm with a workspace");
+    return st;
 }
 
 msp_status msp_upper_bound(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
