@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the masked SpGEMM hot path on one MI355X.
 
-Workload (the headline configuration): triangle counting on an R-MAT graph,
-scale 18, edge factor 16, Graph500 quadrant probabilities (a, b, c) =
-(.57, .19, .19), symmetrized and deduplicated, vertices relabelled by
-non-increasing degree, L = strict lower triangle; C = L .* (L L) under the
-plus-pair semiring (int64), then the sum of C (Section "Triangle Counting").
-Inputs are synthetic and seeded; they stand in for the paper's R-MAT inputs.
+Default run (one JSON line), three workloads, each timed as whole steps on
+device-resident operands (row analysis and binning, i.e. plan creation, the
+one-phase numeric kernels into staging, prefix sum of the counts, row
+pointers, compaction into C, and any post-reduction):
 
-One step = the whole path on device-resident operands: row analysis and
-binning (plan creation), one-phase numeric kernels into staging, prefix sum
-of the counts, row pointers, compaction into C, and the (+)-reduction of C.
+  - headline: one multi-source BFS step, C = !V .* (A F), on an R-MAT graph
+    of scale 20, edge factor 16 (Graph500 quadrant probabilities .57, .19,
+    .19, symmetrized), 512 sources at depths 1..3, complemented visited mask,
+    int32 path counts (the boolean semiring as a second record);
+  - triangle counting on R-MAT scale 18, edge factor 16, degree-relabelled:
+    C = L .* (L L) under plus-pair (int64), then the sum of C (Section
+    "Triangle Counting");
+  - Erdos-Renyi A, B, M with n = 4096 and average degree 8, FP64 plus-times,
+    normal mask.
 
-Printed: one JSON line with the useful masked GFLOP/s (2 x admitted
+Inputs are synthetic and seeded; they stand in for the paper's inputs. For
+each workload the line holds the useful masked GFLOP/s (2 x admitted
 products / step time), the HBM roofline of the dominant numeric kernel
-(algorithmic bytes of the push method per launch / its HIP-event time), and
-the CPU oracle's rate on the same workload.
+(algorithmic bytes of the push method per launch / its HIP-event time), the
+whole step's fraction of the HBM peak under the same byte model, an oracle
+check of the result, and the CPU oracle's rate on a stated sample.
 """
 import argparse
 import hashlib
@@ -143,9 +149,11 @@ def main():
     ap.add_argument("--heap-flops", type=int, default=None, help="binner: rows with at most this many products "
                     "(and at most 8 entries in A's row) use the heap kind (0: never; default: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tc", choices=("tc", "batch", "bfs", "serve", "bc", "ktruss", "heatmap", "copy"),
-                    help="tc: triangle counting (the headline line); batch: 64 mixed FP64 products, "
-                         "batched and graph-replayed vs one launch per product")
+    ap.add_argument("--workload", default="all",
+                    choices=("all", "tc", "er", "batch", "bfs", "serve", "bc", "ktruss", "heatmap", "copy"),
+                    help="all (default): the multi-source BFS step (headline), triangle counting and the "
+                         "Erdos-Renyi n=4096 product in one line; tc, er, bfs: one of them; batch: 64 mixed FP64 "
+                         "products, batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mask-cap", type=int, default=20_000_000,
                     help="batch: cap on one product's mask entries (host memory of the generator)")
@@ -154,7 +162,9 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent execution slots")
     ap.add_argument("--summarize-traffic", metavar="DIR", default=None,
                     help="turn the FETCH_SIZE / WRITE_SIZE counter runs under DIR (copy_FETCH_SIZE, copy_WRITE_SIZE, "
-                         "tc_FETCH_SIZE, tc_WRITE_SIZE) into profiles/traffic_tc_rmat18.json for --bin/--kernel")
+                         "KEY_FETCH_SIZE, KEY_WRITE_SIZE) into profiles/traffic_KEY.json for --bin/--kernel")
+    ap.add_argument("--traffic-key", default="tc_rmat18", help="with --summarize-traffic: the workload key "
+                    "(tc_rmat18, bfs_rmat20_i32, bfs_rmat20_bool, er4096)")
     ap.add_argument("--bin", default="hash_block", help="with --summarize-traffic: the kernel bin")
     ap.add_argument("--kernel", default="k_maskkey<1, 1, 4, 512, true, 1, false>",
                     help="with --summarize-traffic: the kernel name (substring) of that bin")
@@ -181,67 +191,166 @@ def main():
         return run_serve(args)
     if args.workload == "copy":
         return run_copy(args)
-    run_tc(args)
+    if args.workload == "tc":
+        return run_tc(args)
+    if args.workload == "er":
+        return run_er(args)
+    run_all(args)
 
 
-def run_tc(args):
+# ----------------------------------------------------------------------------------------------
+# measurement core: one product timed as whole steps (plan creation included), its stages, the
+# byte model per row, the dominant kernel's roofline, and the oracle's CPU leg
+
+
+def sig(x, digits=5):
+    """x rounded to `digits` significant digits."""
+    return float(f"{x:.{digits}g}")
+
+
+def cpu_threads():
+    """(host cores this process may run on, the cgroup's CPU quota in cores
+    or None when unlimited)."""
+    aff = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, per = fh.read().split()[:2]
+        if q != "max":
+            quota = max(1, int(-(-int(q) // int(per))))
+    except (OSError, ValueError):
+        pass
+    return aff, quota
+
+
+def cpu_leg(A, B, M, complement, sr, rows=None, rows_one=None, reps=5, sample=False):
+    """Runs the oracle in a child process (oracle/bench_leg.py) on these host
+    operands with every host core the process may use (and the cgroup quota,
+    when it is lower), threads bound close (OMP_PROC_BIND=close). Returns
+    the child's report plus, with `sample`, the oracle's result rows."""
+    import shutil
+    import subprocess
+    import tempfile
+    d = tempfile.mkdtemp(prefix="msp_cpu_leg_", dir="/tmp")
+    try:
+        np.save(os.path.join(d, "shape.npy"), np.array([A.nrows, A.ncols, B.ncols], np.int64))
+        for name, X in (("A", A), ("B", B), ("M", M)):
+            np.save(os.path.join(d, f"{name}_rowptr.npy"), X.rowptr)
+            np.save(os.path.join(d, f"{name}_colidx.npy"), X.colidx)
+            if X.values is not None and name != "M":
+                np.save(os.path.join(d, f"{name}_values.npy"), X.values)
+        if rows is not None:
+            np.save(os.path.join(d, "rows.npy"), np.asarray(rows, np.int64))
+        if rows_one is not None:
+            np.save(os.path.join(d, "rows_one.npy"), np.asarray(rows_one, np.int64))
+        aff, quota = cpu_threads()
+        threads = [aff] + ([quota] if quota is not None and quota < aff else [])
+        with open(os.path.join(d, "spec.json"), "w") as fh:
+            json.dump({"complement": bool(complement), "semiring": sr, "reps": int(reps), "threads": threads,
+                       "one_thread_rows": True, "sample": bool(sample)}, fh)
+        env = dict(os.environ, OMP_PROC_BIND="close")
+        res = subprocess.run([sys.executable, "-m", "oracle.bench_leg", d], env=env, cwd=ROOT, capture_output=True,
+                             text=True, timeout=900)
+        if res.returncode != 0:
+            raise RuntimeError(f"oracle CPU leg failed: {res.stderr[-2000:]}")
+        rep = json.loads(res.stdout.strip().splitlines()[-1])
+        rep["affinity_cores"], rep["cgroup_cpu_quota"] = aff, quota
+        if sample:
+            rep["C"] = tuple(np.load(os.path.join(d, f"C_{x}.npy")) for x in ("rowptr", "colidx", "values"))
+        return rep
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+
+
+def baseline_record(rep, sample_desc):
+    """cpu_baseline entry from a CPU-leg report: useful GFLOP/s of the sample
+    at the best thread count (median of the runs), and on one thread."""
+    med = {int(nt): float(np.median(ts)) for nt, ts in rep["runs"].items()}
+    nt = min(med, key=med.get)
+    t = med[nt]
+    one = rep.get("one_thread")
+    reps = len(next(iter(rep["runs"].values())))
+    return {"value": sig(2 * rep["useful"] / t / 1e9), "unit": "GFLOP/s", "cores": nt, "kind": "oracle",
+            "sample": f"{sample_desc}; median of {reps} runs of {t:.3f} s on {nt} threads (OMP_PROC_BIND=close)",
+            "one_thread_value": sig(2 * one["useful"] / one["seconds"] / 1e9) if one else None,
+            "one_thread_sample_rows": one["rows"] if one else None,
+            "seconds_by_threads": {str(k): round(v, 4) for k, v in med.items()},
+            "affinity_cores": rep["affinity_cores"], "cgroup_cpu_quota": rep["cgroup_cpu_quota"],
+            "cpu_model": cpu_model()}
+
+
+def gather_rows(rp, ci, v, rows):
+    """Rows `rows` of a host CSR as (rowptr, colidx, values)."""
+    rows = np.asarray(rows, np.int64)
+    lens = rp[rows + 1] - rp[rows]
+    out_rp = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum(lens, out=out_rp[1:])
+    idx = np.repeat(rp[rows] - out_rp[:-1], lens) + np.arange(int(out_rp[-1]), dtype=np.int64)
+    return out_rp, ci[idx], v[idx]
+
+
+def same_rows(got, exp, fp64):
+    """Patterns exactly; values exactly, or within 1e-12 relative for FP64."""
+    if not (np.array_equal(got[0], exp[0]) and np.array_equal(got[1], exp[1])):
+        return False
+    if fp64:
+        return bool(np.all(np.abs(got[2] - exp[2]) <= 1e-12 * np.abs(exp[2])))
+    return np.array_equal(got[2], exp[2])
+
+
+def row_flops(A, Bdeg):
+    """flops_i = sum over k in A(i,:) of nnz(B(k,:)) for every row i."""
+    rows = np.repeat(np.arange(A.nrows), np.diff(A.rowptr))
+    return np.bincount(rows, weights=Bdeg[A.colidx], minlength=A.nrows).astype(np.int64)
+
+
+def time_steps(dA, dB, dM, comp, sr, steps, warmup, kw, post=None):
+    """Times `steps` whole steps (plan creation, execution, and `post`) after
+    `warmup` untimed ones. The kernel bins' HIP events are recorded into a
+    timing session during the timed steps and read after them; the other
+    stages come from untimed profiled executions. Returns a dict with the
+    step time, stage times per step, plan-creation and cold-step times and
+    the last step's output (device tensors)."""
     import torch
 
-    import mspgen
     import paper_2111_09947_amd as msp
-
-    dev = torch.device("cuda:0")
-    t0 = time.time()
-    L = mspgen.triangle_input(args.scale, args.edge_factor, args.seed)
-    print(f"[bench] input: R-MAT scale {args.scale} ef {args.edge_factor}: n={L.nrows} nnz(L)={L.nnz} "
-          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
-    dL = msp.DeviceCSR.from_host(L, dev)
-    nnzA, flops, mnnz = row_quantities(L)
-
+    dev = dA.rowptr.device
+    odt = msp.out_dtype(sr)
     stage_ms = np.zeros(len(msp.STAGE_NAMES), dtype=np.float64)
-    sr = "plus_pair_i64"
-    total_dev = torch.empty(1, dtype=torch.int64, device=dev)
-    kw = dict(semiring=sr, phase=args.phase, force_kind=args.force_kind, inner_ratio=args.inner_ratio,
-              **tuning_kw(args))
-
-    # kernel-bin times: HIP events attached to the bins' own launches, recorded into a timing
-    # session during the timed steps and read once after them (no synchronization per step);
-    # the other stages are timed in untimed runs afterwards
-    timing = msp.Timing(max(args.steps, args.warmup), stages=msp.BIN_NAMES)
+    timing = msp.Timing(max(steps, warmup), stages=msp.BIN_NAMES)
 
     def step(timed=True):
-        with msp.Plan(dL, dL, dL, **kw) as p:  # the plan's one synchronization
+        with msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw) as p:  # the plan's one synchronization
             cap = max(p.upper_bound, 1)
-            rp = torch.empty(L.nrows + 1, dtype=torch.int64, device=dev)
+            rp = torch.empty(dA.nrows + 1, dtype=torch.int64, device=dev)
             ci = torch.empty(cap, dtype=torch.int32, device=dev)
-            v = torch.empty(cap, dtype=torch.int64, device=dev)
+            v = torch.empty(cap, dtype=odt, device=dev)
             if timed:
                 p.execute_timed(rp, ci, v, cap, timing)
             else:
                 p.execute_into(rp, ci, v, cap)
-            msp.reduce_csr(rp, L.nrows, v, sr, out=total_dev)  # the count of C stays on the device
-            return rp, v
+            if post is not None:
+                post(rp, v)
+            return rp, ci, v
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     timing.collect(np.zeros_like(stage_ms))  # warm-up stages are not counted
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        rp, v = step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = elapsed / args.steps * 1e3
+    ms = (time.perf_counter() - t0) / steps * 1e3
     timing.collect(stage_ms)
     timing.close()
-    nnz = int(rp[-1].item())
-    other_stages(lambda: msp.Plan(dL, dL, dL, **kw), L.nrows, torch.int64, stage_ms, args.steps, dev)
-    # plan creation alone (in the timed steps its synchronization also waits for the previous step)
+    other_stages(lambda: msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw), dA.nrows, odt, stage_ms, steps,
+                 dev)
     plan_ms = []
-    for _ in range(3):
+    for _ in range(3):  # plan creation alone (in a step it also waits for the previous step)
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        msp.Plan(dL, dL, dL, **kw).close()
+        msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw).close()
         plan_ms.append((time.perf_counter() - c0) * 1e3)
     # cold steps: L2 and the last-level cache flushed by writing 512 MiB before each one
     flush = torch.empty(1 << 26, dtype=torch.int64, device=dev)
@@ -254,102 +363,160 @@ def run_tc(args):
         torch.cuda.synchronize()
         cold_ms.append((time.perf_counter() - c0) * 1e3)
     del flush
+    with msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw) as p:
+        bins, bin_units, products = p.row_bins(), p.bin_units, p.products
+    return {"ms": ms, "stage_ms": stage_ms / steps, "plan_ms": float(np.median(plan_ms)),
+            "cold_ms": float(np.median(cold_ms)), "out": out, "bins": bins, "bin_units": bin_units,
+            "products": int(products)}
 
-    # quantities of the result (for the metric's numerator and the byte model)
-    triangles = int(total_dev.item())
-    rp_h = rp.cpu().numpy()
-    v_h = v[:nnz].cpu().numpy()
-    nnzC_row = np.diff(rp_h)
-    owner = np.repeat(np.arange(L.nrows), nnzC_row)
-    useful_row = np.bincount(owner, weights=v_h, minlength=L.nrows).astype(np.int64)
-    assert int(useful_row.sum()) == triangles
-    with msp.Plan(dL, dL, dL, **kw) as p:
-        bins = p.row_bins()
-        bin_units = p.bin_units
-        products = p.products
 
-    per_row = alg_bytes(nnzA, flops, mnnz, useful_row, nnzC_row)
-    bytes_total = int(per_row.sum())
-    bin_ms = stage_ms[:len(msp.BIN_NAMES)] / args.steps
+def useful_rows(dA, dB, dM, comp):
+    """Admitted products per row: the plus-pair product's row sums."""
+    import paper_2111_09947_amd as msp
+    with msp.Plan(dA, dB, dM, complement=comp, semiring="plus_pair_i64") as p:
+        C = p.execute()
+    rp = C.rowptr.cpu().numpy()
+    owner = np.repeat(np.arange(dA.nrows), np.diff(rp))
+    return np.bincount(owner, weights=C.values.cpu().numpy(), minlength=dA.nrows).astype(np.int64)
+
+
+def roofline_record(t, per_row, traffic_key):
+    """The dominant kernel bin (largest time per step): its rows' algorithmic
+    bytes per launch over its HIP-event time, against the HBM peak; the
+    counter-measured HBM bytes per launch (calibrated, same kernel source)
+    when a traffic summary exists for it."""
+    import paper_2111_09947_amd as msp
+    bin_ms = t["stage_ms"][:len(msp.BIN_NAMES)]
     dom = int(np.argmax(bin_ms))
-    dom_name = msp.BIN_NAMES[dom]
-    dom_bytes = int(per_row[bins == dom].sum())
+    name = msp.BIN_NAMES[dom]
+    dom_bytes = int(per_row[t["bins"] == dom].sum())
     dom_ms = float(bin_ms[dom])
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
-    khash = kernel_source_hash()
-    traffic = load_traffic(os.path.join(ROOT, "profiles", "traffic_tc_rmat18.json"), khash, dom_name)
+    traffic = load_traffic(os.path.join(ROOT, "profiles", f"traffic_{traffic_key}.json"), kernel_source_hash(), name)
+    rec = {"bound": "hbm", "achieved": sig(achieved), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": sig(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": f"numeric bin {name}",
+           "kernel_ms": round(dom_ms, 5), "alg_bytes": dom_bytes}
+    if traffic:
+        # the rate the HBM counters saw (the kernel is limited by issue and cache, not by HBM, when it is low)
+        rec["traffic_gbs"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+        rec["traffic_frac"] = round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return rec
 
-    useful_flops = 2 * triangles
-    value = useful_flops / (ms_per_step * 1e-3) / 1e9
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        nthreads = min(16, len(os.sched_getaffinity(0)))
-        times = []
-        ref = None
-        for _ in range(5):
-            c0 = time.perf_counter()
-            ref = oracle.masked_spgemm(L, L, L, False, sr, nthreads=nthreads)
-            s = int(ref.values.sum())
-            times.append(time.perf_counter() - c0)
-        t_cpu = float(np.median(times))
-        if s != triangles:
-            print(f"[bench] MISMATCH: oracle {s} triangles, GPU {triangles}", file=sys.stderr)
-            sys.exit(1)
-        c0 = time.perf_counter()
-        oracle.masked_spgemm(L, L, L, False, sr, nthreads=1)
-        t_one = time.perf_counter() - c0
-        cpu = {"value": round(2 * s / t_cpu / 1e9, 3), "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"the whole workload (masked product + sum), median of 5 runs of {t_cpu:.3f} s",
-               "one_thread_value": round(2 * s / t_one / 1e9, 3), "cpu_model": cpu_model()}
-
-    out = {
-        "metric": "useful_masked_gflops",
-        "value": round(value, 3),
-        "unit": "GFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"triangle counting C = L .* (L L), plus-pair int64, then sum; R-MAT scale {args.scale} "
-                        f"edge factor {args.edge_factor} (a,b,c = .57,.19,.19), symmetrized, degree-relabelled, "
-                        "L = strict lower triangle",
-            "n": L.nrows, "nnz_L": L.nnz, "products": int(products), "useful_products": triangles,
-            "nnz_C": int(nnz), "phase": args.phase, "kind": args.force_kind or "auto",
-            "bin_units": bin_units,
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"numeric bin {dom_name}", "kernel_ms": round(dom_ms, 5), "alg_bytes": dom_bytes,
-        },
+def product_record(t, per_row, useful, traffic_key, bytes_min):
+    import paper_2111_09947_amd as msp
+    ms = t["ms"]
+    total = int(per_row.sum())
+    return {
+        "ms_per_step": round(ms, 4),
+        "value": sig(2 * useful / (ms * 1e-3) / 1e9), "unit": "GFLOP/s",
+        "products": t["products"], "useful_products": int(useful),
+        "bin_units": t["bin_units"],
+        "roofline": roofline_record(t, per_row, traffic_key),
         "path": {
-            "alg_bytes_total": bytes_total,
-            "hbm_frac_whole_step": round(bytes_total / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "stage_ms": {n: round(float(t) / args.steps, 5) for n, t in zip(msp.STAGE_NAMES, stage_ms) if t > 0},
-            "plan_create_ms": round(float(np.median(plan_ms)), 4),
-            "cold_ms_per_step": round(float(np.median(cold_ms)), 4),
-            # each operand once (A, B, M pattern, C) whatever the accumulator: a lower bound
-            "bytes_min": int(3 * (8 * (L.nrows + 1) + 4 * L.nnz) + 8 * (L.nrows + 1) + 12 * int(nnz)),
+            "alg_bytes_total": total,
+            "hbm_frac_whole_step": sig(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "stage_ms": {n: round(float(x), 5) for n, x in zip(msp.STAGE_NAMES, t["stage_ms"]) if x > 0},
+            "plan_create_ms": round(t["plan_ms"], 4),
+            "cold_ms_per_step": round(t["cold_ms"], 4),
+            "bytes_min": int(bytes_min),
         },
-        "device": device_info(dev),
-        "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
 
 
-def run_bfs(args):
+def measure_er(args):
+    """Erdos-Renyi A, B, M, n = 4096, average degree 8, uniform columns, FP64
+    U(0,1) values, plus-times, normal mask (seeds 101, 102, 103). Whole output
+    checked against the oracle."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+    dev = torch.device("cuda:0")
+    n, d = 4096, 8.0
+    A = mspgen.er(n, n, d, 101, "f64")
+    B = mspgen.er(n, n, d, 102, "f64")
+    M = mspgen.er(n, n, d, 103, None)
+    sr = "plus_times_f64"
+    dA = msp.DeviceCSR.from_host(A, dev, torch.float64)
+    dB = msp.DeviceCSR.from_host(B, dev, torch.float64)
+    dM = msp.DeviceCSR.from_host(M, dev)
+    t = time_steps(dA, dB, dM, False, sr, args.steps, args.warmup, tuning_kw(args))
+    rp, ci, v = t["out"]
+    nnz = int(rp[-1].item())
+    got = (rp.cpu().numpy(), ci[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+    useful_row = useful_rows(dA, dB, dM, False)
+    per_row = alg_bytes(np.diff(A.rowptr), row_flops(A, np.diff(B.rowptr)), np.diff(M.rowptr), useful_row,
+                        np.diff(got[0]), wA=8, wB=8, wC=8)
+    rec = {"workload": "Erdos-Renyi A, B, M: n = 4096, average degree 8 (uniform columns), FP64 U(0,1), "
+                       "plus-times, normal mask; seeds 101, 102, 103",
+           "dtype": "f64", "n": n, "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_M": M.nnz, "nnz_C": nnz,
+           **product_record(t, per_row, int(useful_row.sum()), "er4096",
+                            3 * (8 * (n + 1)) + 12 * (A.nnz + B.nnz) + 4 * M.nnz + 12 * nnz)}
+    if not args.no_cpu_baseline:
+        rep = cpu_leg(A, B, M, False, sr, reps=5, sample=True)
+        ok = same_rows(got, rep["C"], True)
+        rec["parity"] = {"checked": "every row against the oracle", "identical_within_tolerance": ok}
+        if not ok:
+            print("[bench] MISMATCH: Erdos-Renyi n=4096 differs from the oracle", file=sys.stderr)
+            sys.exit(1)
+        rec["cpu_baseline"] = baseline_record(rep, "the whole product")
+    return rec
+
+
+def measure_tc(args):
+    """Triangle counting: R-MAT scale 18, edge factor 16, symmetrized,
+    degree-relabelled, L = strict lower triangle; C = L .* (L L) under
+    plus-pair (int64), then the sum of C."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    L = mspgen.triangle_input(args.scale, args.edge_factor, args.seed)
+    print(f"[bench] tc input: R-MAT scale {args.scale} ef {args.edge_factor}: n={L.nrows} nnz(L)={L.nnz} "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    dL = msp.DeviceCSR.from_host(L, dev)
+    sr = "plus_pair_i64"
+    total_dev = torch.empty(1, dtype=torch.int64, device=dev)
+    kw = dict(phase=args.phase, force_kind=args.force_kind, inner_ratio=args.inner_ratio, **tuning_kw(args))
+    t = time_steps(dL, dL, dL, False, sr, args.steps, args.warmup, kw,
+                   post=lambda rp, v: msp.reduce_csr(rp, L.nrows, v, sr, out=total_dev))
+    rp, ci, v = t["out"]
+    nnz = int(rp[-1].item())
+    triangles = int(total_dev.item())
+    got = (rp.cpu().numpy(), ci[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+    owner = np.repeat(np.arange(L.nrows), np.diff(got[0]))
+    useful_row = np.bincount(owner, weights=got[2], minlength=L.nrows).astype(np.int64)
+    assert int(useful_row.sum()) == triangles
+    deg = np.diff(L.rowptr)
+    per_row = alg_bytes(deg, row_flops(L, deg), deg, useful_row, np.diff(got[0]))
+    rec = {"workload": f"triangle counting C = L .* (L L), plus-pair int64, then sum; R-MAT scale {args.scale} "
+                       f"edge factor {args.edge_factor} (a,b,c = .57,.19,.19), symmetrized, degree-relabelled, "
+                       "L = strict lower triangle",
+           "dtype": "int64", "n": L.nrows, "nnz_L": L.nnz, "nnz_C": nnz, "triangles": triangles,
+           "phase": args.phase, "kind": args.force_kind or "auto",
+           **product_record(t, per_row, triangles, "tc_rmat18",
+                            3 * (8 * (L.nrows + 1) + 4 * L.nnz) + 8 * (L.nrows + 1) + 12 * nnz)}
+    if not args.no_cpu_baseline:
+        rep = cpu_leg(L, L, L, False, sr, reps=5, sample=True)
+        ok = rep["sum"] == triangles and same_rows(got, rep["C"], False)
+        rec["parity"] = {"checked": "every row and the triangle count against the oracle", "identical": ok}
+        if not ok:
+            print(f"[bench] MISMATCH: oracle {rep['sum']} triangles, GPU {triangles}", file=sys.stderr)
+            sys.exit(1)
+        rec["cpu_baseline"] = baseline_record(rep, "the whole workload (masked product + sum)")
+    return rec
+
+
+def measure_bfs(args):
     """One multi-source BFS step: R-MAT scale 20, edge factor 16, 512 sources
-    with depths 1..3; C = !V .* (A F) with A the symmetric graph, F the
-    frontiers (n x 512) and V the visited sets, under the boolean semiring
-    and the int32 path-count semiring."""
+    at depths 1..3; C = !V .* (A F) with A the symmetric graph, F the frontiers
+    (n x 512) and V the visited sets, under the int32 path-count semiring
+    (plus-times, wrapping) and the boolean semiring. Returns one record per
+    semiring."""
     import torch
 
     import mspgen
@@ -358,81 +525,99 @@ def run_bfs(args):
     dev = torch.device("cuda:0")
     t0 = time.time()
     G = mspgen.rmat_graph(20, 16, 20)
-    results = {}
-    for sr, vk, dt in (("lor_land_bool", "u8", torch.uint8), ("plus_times_i32", "i32", torch.int32)):
-        F, V, srcs, lv = mspgen.bfs_step_input(G, 512, 21, vk)
-        print(f"[bench] bfs inputs {sr} ({time.time() - t0:.1f}s): nnz(A)={G.nnz} nnz(F)={F.nnz} nnz(V)={V.nnz}",
-              file=sys.stderr, flush=True)
-        dA = msp.DeviceCSR.from_host(G, dev)
-        dF = msp.DeviceCSR.from_host(F, dev, dt)
-        dV = msp.DeviceCSR.from_host(V, dev)
-        stage_ms = np.zeros(len(msp.STAGE_NAMES))
-        # bin events of the timed steps, read after them; other stages from untimed runs
-        timing = msp.Timing(max(args.steps, args.warmup), stages=msp.BIN_NAMES)
-
-        def step():
-            with msp.Plan(dA, dF, dV, complement=True, semiring=sr, **tuning_kw(args)) as p:
-                cap = max(p.upper_bound, 1)
-                rp = torch.empty(G.nrows + 1, dtype=torch.int64, device=dev)
-                ci = torch.empty(cap, dtype=torch.int32, device=dev)
-                v = torch.empty(cap, dtype=dt, device=dev)
-                p.execute_timed(rp, ci, v, cap, timing)
-                return rp
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        timing.collect(np.zeros_like(stage_ms))  # warm-up stages are not counted
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            rp = step()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t1) / args.steps * 1e3
-        timing.collect(stage_ms)
-        timing.close()
+    print(f"[bench] bfs graph: R-MAT scale 20 ef 16: n={G.nrows} nnz={G.nnz} ({time.time() - t0:.1f}s)",
+          file=sys.stderr, flush=True)
+    F64, V, srcs, lv = mspgen.bfs_step_input(G, 512, 21, "i64")
+    print(f"[bench] bfs frontiers ({time.time() - t0:.1f}s): nnz(F)={F64.nnz} nnz(V)={V.nnz}", file=sys.stderr,
+          flush=True)
+    n = G.nrows
+    dA = msp.DeviceCSR.from_host(G, dev)
+    dV = msp.DeviceCSR.from_host(V, dev)
+    nnzA = np.diff(G.rowptr)
+    flops = row_flops(G, np.diff(F64.rowptr))
+    mnnz = np.diff(V.rowptr)
+    out = {}
+    useful_row = None
+    for sr, F, w in (("plus_times_i32", F64.with_values(F64.values.astype(np.int32)), 4),
+                     ("lor_land_bool", F64.with_values(np.ones(F64.nnz, np.uint8)), 1)):
+        dF = msp.DeviceCSR.from_host(F, dev, msp.in_dtype(sr))
+        t = time_steps(dA, dF, dV, True, sr, args.steps, args.warmup, tuning_kw(args))
+        rp, ci, v = t["out"]
         nnz = int(rp[-1].item())
-        other_stages(lambda: msp.Plan(dA, dF, dV, complement=True, semiring=sr, **tuning_kw(args)), G.nrows, dt,
-                     stage_ms, args.steps, dev)
-        # useful products = plus-pair count of admitted products
-        with msp.Plan(dA, dF, dV, complement=True, semiring="plus_pair_i64") as pp:
-            Cp = pp.execute()
-            useful = int(Cp.values.sum().item())
-            products = pp.products
-            bins = pp.row_bins()
-        nnzA = np.diff(G.rowptr)
-        Fdeg = np.diff(F.rowptr)
-        rows = np.repeat(np.arange(G.nrows), nnzA)
-        flops = np.bincount(rows, weights=Fdeg[G.colidx], minlength=G.nrows).astype(np.int64)
-        rp_h = Cp.rowptr.cpu().numpy()
-        owner = np.repeat(np.arange(G.nrows), np.diff(rp_h))
-        useful_row = np.bincount(owner, weights=Cp.values.cpu().numpy(), minlength=G.nrows).astype(np.int64)
-        wv = 1 if sr == "lor_land_bool" else 4
-        per_row = alg_bytes(nnzA, flops, np.diff(V.rowptr), useful_row, np.diff(rp_h), wA=0, wB=wv, wC=wv)
-        bin_ms = stage_ms[:len(msp.BIN_NAMES)] / args.steps
-        dom = int(np.argmax(bin_ms))
-        dom_bytes = int(per_row[bins == dom].sum())
-        achieved = dom_bytes / (bin_ms[dom] * 1e-3) / 1e9 if bin_ms[dom] > 0 else 0.0
-        results[sr] = {
-            "ms_per_step": round(ms, 4), "useful_gflops": round(2 * useful / (ms * 1e-3) / 1e9, 3),
-            "products": int(products), "useful_products": useful, "nnz_C": int(nnz),
-            "alg_bytes_total": int(per_row.sum()),
-            "hbm_frac_whole_step": round(int(per_row.sum()) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": f"numeric bin {msp.BIN_NAMES[dom]}",
-                         "kernel_ms": round(float(bin_ms[dom]), 5), "alg_bytes": dom_bytes},
-            "stage_ms": {n: round(float(t) / args.steps, 5) for n, t in zip(msp.STAGE_NAMES, stage_ms) if t > 0},
-        }
-        del dF, dV, F, V
+        got = (rp.cpu().numpy(), ci[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+        del t["out"], rp, ci, v
+        if useful_row is None:
+            useful_row = useful_rows(dA, dF, dV, True)
+        per_row = alg_bytes(nnzA, flops, mnnz, useful_row, np.diff(got[0]), wA=0, wB=w, wC=w)
+        rec = {"workload": "multi-source BFS step C = !V .* (A F): R-MAT scale 20 edge factor 16 "
+                           "(a,b,c = .57,.19,.19, symmetrized), 512 sources at depth 1..3, complemented visited "
+                           f"mask; {'int32 path counts' if w == 4 else 'boolean'}",
+               "dtype": "int32" if w == 4 else "u8", "n": n, "nnz_A": G.nnz, "nnz_F": F.nnz, "nnz_V": V.nnz,
+               "nnz_C": nnz,
+               **product_record(t, per_row, int(useful_row.sum()), f"bfs_rmat20_{'i32' if w == 4 else 'bool'}",
+                                8 * (n + 1) * 4 + 4 * G.nnz + (4 + w) * F.nnz + 4 * V.nnz + (4 + w) * nnz)}
+        if not args.no_cpu_baseline:
+            stride = 4 if w == 4 else 16
+            rows = np.arange(0, n, stride, dtype=np.int64)
+            rep = cpu_leg(G, F, V, True, sr, rows=rows, rows_one=np.arange(0, n, 64, dtype=np.int64),
+                          reps=3 if w == 4 else 1, sample=True)
+            ok = same_rows(gather_rows(*got, rows), rep["C"], False)
+            rec["parity"] = {"checked": f"every {stride}th row ({len(rows)} rows) against the oracle",
+                             "identical": ok}
+            if not ok:
+                print(f"[bench] MISMATCH: BFS step ({sr}) differs from the oracle", file=sys.stderr)
+                sys.exit(1)
+            rec["cpu_baseline"] = baseline_record(rep, f"every {stride}th row of the step ({len(rows)} rows)")
+        out[sr] = rec
+        del dF
         torch.cuda.empty_cache()
-    head = results["plus_times_i32"]
-    out = {"metric": "useful_masked_gflops", "value": head["useful_gflops"], "unit": "GFLOP/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-           "config": {"workload": "multi-source BFS step C = !V .* (A F), R-MAT scale 20 edge factor 16, "
-                                  "512 sources at depth 1..3, complemented visited mask; int32 path counts "
-                                  "(headline) and boolean"},
-           "roofline": head["roofline"], "semirings": results}
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def headline(rec, args, extra=None):
+    """The JSON line around one workload record."""
+    line = {"metric": "useful_masked_gflops", "value": rec["value"], "unit": "GFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": rec["dtype"],
+            "data": "synthetic",
+            "config": {k: v for k, v in rec.items() if k not in ("value", "unit", "ms_per_step", "roofline",
+                                                                 "path", "cpu_baseline", "dtype")},
+            "roofline": rec["roofline"], "path": rec["path"], "cpu_baseline": rec.get("cpu_baseline")}
+    if extra:
+        line.update(extra)
+    return line
+
+
+def run_tc(args):
+    print(json.dumps(headline(measure_tc(args), args)), flush=True)
+
+
+def run_er(args):
+    print(json.dumps(headline(measure_er(args), args)), flush=True)
+
+
+def run_bfs(args):
+    recs = measure_bfs(args)
+    print(json.dumps(headline(recs["plus_times_i32"], args, {"semirings": recs})), flush=True)
+
+
+def run_all(args):
+    """The default run: the multi-source BFS step (the largest single-GPU
+    workload, int32 path counts: the headline value), with the triangle
+    count and the Erdos-Renyi n = 4096 product as further records, each with
+    its own roofline, whole-step fraction, oracle check and CPU baseline."""
+    import torch
+    dev = torch.device("cuda:0")
+    bfs = measure_bfs(args)
+    torch.cuda.empty_cache()
+    tc = measure_tc(args)
+    torch.cuda.empty_cache()
+    er = measure_er(args)
+    line = headline(bfs["plus_times_i32"], args, {
+        "device": device_info(dev),
+        "workloads": {"bfs_rmat20_i32": bfs["plus_times_i32"], "bfs_rmat20_bool": bfs["lor_land_bool"],
+                      "tc_rmat18": tc, "er4096_f64": er}})
+    print(json.dumps(line), flush=True)
 
 
 def run_bc(args):
@@ -770,8 +955,9 @@ def summarize_traffic(args):
     gib_kib = float(1 << 20)
     cf, _ = _counter_kib(os.path.join(d, "copy_FETCH_SIZE"), "FETCH_SIZE", "copyBuffer")
     cw, _ = _counter_kib(os.path.join(d, "copy_WRITE_SIZE"), "WRITE_SIZE", "copyBuffer")
-    kf, nf = _counter_kib(os.path.join(d, "tc_FETCH_SIZE"), "FETCH_SIZE", args.kernel)
-    kw, nw = _counter_kib(os.path.join(d, "tc_WRITE_SIZE"), "WRITE_SIZE", args.kernel)
+    key = args.traffic_key
+    kf, nf = _counter_kib(os.path.join(d, f"{key}_FETCH_SIZE"), "FETCH_SIZE", args.kernel)
+    kw, nw = _counter_kib(os.path.join(d, f"{key}_WRITE_SIZE"), "WRITE_SIZE", args.kernel)
     f_scale, w_scale = gib_kib / cf, gib_kib / cw
     read_b = kf * 1024 * f_scale
     write_b = kw * 1024 * w_scale
@@ -781,7 +967,7 @@ def summarize_traffic(args):
            "fetch_kib_raw": round(kf, 3), "write_kib_raw": round(kw, 3), "dispatches": [nf, nw],
            "copy_fetch_kib_per_gib": round(cf, 3), "copy_write_kib_per_gib": round(cw, 3),
            "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)}
-    path = os.path.join(ROOT, "profiles", "traffic_tc_rmat18.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{key}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
