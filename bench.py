@@ -155,8 +155,8 @@ def main():
                          "Erdos-Renyi n=4096 product in one line; tc, er, bfs: one of them; batch: 64 mixed FP64 "
                          "products, batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
-    ap.add_argument("--mask-cap", type=int, default=20_000_000,
-                    help="batch: cap on one product's mask entries (host memory of the generator)")
+    ap.add_argument("--mask-cap", type=int, default=0,
+                    help="batch: cap on one product's mask entries (0: none, the full-size masks)")
     ap.add_argument("--tune", action="store_true", help="batch: autotune the binner thresholds first")
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent execution slots")
@@ -1001,9 +1001,11 @@ def _timed(fn, steps, warmup, stream=None):
 def run_batch(args):
     """64 independent FP64 masked products of uneven sizes (Erdos-Renyi and
     R-MAT, n = 2^U(12,17), degree 2^U(2,6), mask density 10^U(-1,1) times the
-    output density): one batch (one launch per kernel bin for all products,
-    replayed from a captured HIP graph) against one launch sequence per
-    product on the same GPU, with identical outputs."""
+    output density; masks at full size unless --mask-cap is given): one batch
+    (one launch per kernel bin for all products, replayed from a captured HIP
+    graph) against one launch sequence per product on the same GPU, with
+    identical outputs, and sampled rows of every product (each product's
+    heaviest rows among them) checked against the oracle."""
     import torch
 
     import mspgen
@@ -1012,17 +1014,24 @@ def run_batch(args):
 
     dev = torch.device("cuda:0")
     sr = "plus_times_f64"
+    cap = args.mask_cap if args.mask_cap and args.mask_cap > 0 else None
     t0 = time.time()
-    probs = mspgen.batch_mix(args.batch_count, seed=4, max_mask_nnz=args.mask_cap)
-    print(f"[bench] batch inputs generated ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
-    up = lambda X, v: msp.DeviceCSR.from_host(X, dev, torch.float64 if v else None)
-    devp = [(up(p["A"], True), up(p["B"], True), up(p["M"], False), False) for p in probs]
-    del probs
+    prms = mspgen.batch_params(args.batch_count, seed=4)
+    devp, host = [], []
+    for prm in prms:  # one product at a time: its mask is uploaded and its host copy dropped
+        A, B = mspgen.batch_operands(prm)
+        M = mspgen.batch_mask(prm, cap)
+        devp.append((msp.DeviceCSR.from_host(A, dev, torch.float64), msp.DeviceCSR.from_host(B, dev, torch.float64),
+                     msp.DeviceCSR.from_host(M, dev), False))
+        host.append(dict(prm=prm, A=A, B=B, mrow=np.diff(M.rowptr)))
+        del M
+    mask_nnz = int(sum(int(h["mrow"].sum()) for h in host))
+    print(f"[bench] batch inputs generated and uploaded ({time.time() - t0:.1f}s): {len(devp)} products, "
+          f"{mask_nnz} mask entries", file=sys.stderr, flush=True)
     tune = None
     cfg = {}
     if args.tune:
-        tune = autotune(devp, sr, space={"maskidx_max": [8], "block_flops": [8192, 32768],
-                                         "inner_ratio": [0, 1, 4, 16]}, repeats=2)
+        tune = autotune(devp, sr, repeats=2)
         cfg = tune["best"]
         print(f"[bench] tuned: {cfg}", file=sys.stderr, flush=True)
 
@@ -1030,27 +1039,37 @@ def run_batch(args):
     plans = [msp.Plan(A, B, M, complement=c, semiring=sr, **cfg) for (A, B, M, c) in devp]
     outs = []
     for p, (A, B, M, c) in zip(plans, devp):
-        cap = max(p.upper_bound, 1)
+        cp = max(p.upper_bound, 1)
         outs.append((torch.empty(A.nrows + 1, dtype=torch.int64, device=dev),
-                     torch.empty(cap, dtype=torch.int32, device=dev),
-                     torch.empty(cap, dtype=torch.float64, device=dev), cap))
+                     torch.empty(cp, dtype=torch.int32, device=dev),
+                     torch.empty(cp, dtype=torch.float64, device=dev), cp))
 
     def per_launch():
-        for p, (rp, ci, v, cap) in zip(plans, outs):
-            p.execute_into(rp, ci, v, cap)
+        for p, (rp, ci, v, cp) in zip(plans, outs):
+            p.execute_into(rp, ci, v, cp)
 
     ms_single = _timed(per_launch, args.steps, args.warmup)
+    print(f"[bench] per-product launches {ms_single:.3f} ms", file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
+    stage_ms = np.zeros(len(msp.STAGE_NAMES))
     with torch.cuda.stream(stream):
         b = msp.Batch(devp, semiring=sr, **cfg)
         b.bind_new_outputs()
         ms_eager = _timed(b.execute, args.steps, args.warmup)
         ms_graph = _timed(b.graph_launch, args.steps, args.warmup)
+        timing = msp.Timing(args.steps)
+        for _ in range(args.steps):
+            b.execute_timed(timing)
+        timing.collect(stage_ms)
+        timing.close()
+        stage_ms /= args.steps
         res = b.results()
+        bins = b.row_bins()
+    print(f"[bench] batched eager {ms_eager:.3f} ms, graph {ms_graph:.3f} ms", file=sys.stderr, flush=True)
 
     # identical outputs: batch vs one product at a time
     nnz_single = []
-    for p, (rp, ci, v, cap), C in zip(plans, outs, res):
+    for p, (rp, ci, v, cp), C in zip(plans, outs, res):
         n = int(rp[-1].item())
         nnz_single.append(n)
         if not same_output(rp, ci[:n], v[:n], C.rowptr, C.colidx, C.values, True):
@@ -1072,28 +1091,69 @@ def run_batch(args):
     e2e_single = _timed(single_e2e, max(1, args.steps // 5), 1)
     e2e_batch = _timed(batch_e2e, max(1, args.steps // 5), 1)
 
-    # useful products: the plus-pair count of admitted products
+    # admitted products per row (the plus-pair count), the byte model per row, the sampled oracle check
+    import oracle
     with torch.cuda.stream(stream):
         with msp.Batch(devp, semiring="plus_pair_i64") as bp:
             bp.bind_new_outputs()
             bp.execute()
-            useful = sum(int(C.values.sum().item()) for C in bp.results())
+            pair = bp.results()
+    per_row, useful = [], 0
+    rng = np.random.default_rng(9)
+    checked_rows = 0
+    t_cpu = 0.0
+    cpu_useful = 0
+    for h, Cp, C in zip(host, pair, res):
+        A, B = h["A"], h["B"]
+        prp = Cp.rowptr.cpu().numpy()
+        owner = np.repeat(np.arange(A.nrows), np.diff(prp))
+        u_row = np.bincount(owner, weights=Cp.values.cpu().numpy(), minlength=A.nrows).astype(np.int64)
+        useful += int(u_row.sum())
+        fl = row_flops(A, np.diff(B.rowptr))
+        rp_h = C.rowptr.cpu().numpy()
+        per_row.append(alg_bytes(np.diff(A.rowptr), fl, h["mrow"], u_row, np.diff(rp_h), wA=8, wB=8, wC=8))
+        # rows checked against the oracle: a uniform sample plus the heaviest rows by products and by mask length
+        rows = np.unique(np.concatenate([rng.integers(0, A.nrows, 16), np.argsort(fl)[-4:],
+                                         np.argsort(h["mrow"])[-4:]]))
+        Ms = mspgen.batch_mask_rows(h["prm"], rows, cap)
+        c0 = time.perf_counter()
+        R = oracle.masked_spgemm(A, B, Ms, False, sr, rows=rows)
+        t_cpu += time.perf_counter() - c0
+        cpu_useful += int(R.useful.sum())
+        got = gather_rows(rp_h, C.colidx.cpu().numpy(), C.values.cpu().numpy(), rows)
+        if not same_rows(got, (R.rowptr, R.colidx, R.values), True):
+            print(f"[bench] MISMATCH against the oracle in product {h['prm']['t']}", file=sys.stderr)
+            sys.exit(1)
+        checked_rows += len(rows)
+    per_row = np.concatenate(per_row)
+    bin_ms = stage_ms[:len(msp.BIN_NAMES)]
+    dom = int(np.argmax(bin_ms))
+    dom_bytes = int(per_row[bins == dom].sum())
+    achieved = dom_bytes / (bin_ms[dom] * 1e-3) / 1e9 if bin_ms[dom] > 0 else 0.0
+    total = int(per_row.sum())
     products = int(sum(b.products))
     value = 2 * useful / (ms_graph * 1e-3) / 1e9
     out = {
         "metric": "useful_masked_gflops",
-        "value": round(value, 3),
+        "value": sig(value),
         "unit": "GFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_graph, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(devp)} FP64 plus-times masked products, Erdos-Renyi / R-MAT mix, "
-                               f"n 2^12..2^17, degree 4..64, mask 0.1x..10x output density "
-                               f"(mask capped at {args.mask_cap} entries per product)",
+                               "n 2^12..2^17, degree 4..64, mask 0.1x..10x output density, normal mask",
+                   "mask_cap": cap, "mask_nnz": mask_nnz,
                    "rows": int(sum(A.nrows for (A, _, _, _) in devp)), "products": products,
                    "useful_products": useful, "nnz_C": int(sum(nnz_single)), "units": b.units,
                    "bin_units": b.bin_units, "tuned": cfg or None},
+        "roofline": {"bound": "hbm", "achieved": sig(achieved), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sig(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"numeric bin {msp.BIN_NAMES[dom]}", "kernel_ms": round(float(bin_ms[dom]), 5),
+                     "alg_bytes": dom_bytes},
+        "path": {"alg_bytes_total": total,
+                 "hbm_frac_whole_step": sig(total / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "stage_ms": {n: round(float(x), 5) for n, x in zip(msp.STAGE_NAMES, stage_ms) if x > 0}},
         "batching": {
             "per_product_launches_ms": round(ms_single, 4),
             "batched_eager_ms": round(ms_eager, 4),
@@ -1103,6 +1163,12 @@ def run_batch(args):
             "end_to_end_batched_ms": round(e2e_batch, 3),
             "identical_outputs": True,
         },
+        "parity": {"checked": f"{checked_rows} rows over all {len(devp)} products (per product 16 uniform rows and "
+                              "its 4 heaviest rows by products and by mask length) against the oracle",
+                   "identical_within_tolerance": True},
+        "cpu_baseline": {"value": sig(2 * cpu_useful / t_cpu / 1e9), "unit": "GFLOP/s",
+                         "cores": oracle.max_threads(), "kind": "oracle",
+                         "sample": f"the {checked_rows} checked rows, {t_cpu:.3f} s", "cpu_model": cpu_model()},
         "autotune": tune,
     }
     b.close()

@@ -482,6 +482,11 @@ msp_status msp_batch_bind(msp_plan* batch, const msp_csr_out* C, void* workspace
    memset and no synchronization, so the sequence may be captured. */
 msp_status msp_batch_execute(msp_plan* batch, void* stream);
 
+/* msp_batch_execute with the stage events recorded into a timing session
+   (see msp_timing_create): per kernel bin and stage, the time of all
+   products' units together. Not for graph capture. */
+msp_status msp_batch_execute_timed(msp_plan* batch, msp_timing* timing, void* stream);
+
 /* First call on a stream: captures msp_batch_execute into a HIP graph on
    `stream` (which must not be the default stream) and instantiates it; every
    call then launches the graph once. */

@@ -26,7 +26,8 @@ import numpy as np
 
 __all__ = [
     "CSR", "from_coo", "er", "rmat_edges", "rmat_graph", "degree_relabel",
-    "tril_strict", "triangle_input", "bfs_step_input", "batch_mix",
+    "tril_strict", "triangle_input", "bfs_step_input", "batch_mix", "batch_params", "batch_operands",
+    "batch_mask", "batch_mask_rows", "er_rows",
     "complete_graph", "complete_bipartite", "identity", "transpose",
     "random_values",
 ]
@@ -108,25 +109,56 @@ def random_values(nnz: int, kind: Optional[str], rng: np.random.Generator) -> Op
     raise ValueError(kind)
 
 
+def _er_stream(seed: int, nrows: int, ncols: int, d: float):
+    """(numpy generator for the values, 64-bit row-stream seed, p) of er()."""
+    rng = np.random.default_rng(seed)
+    p = min(1.0, d / ncols) if ncols else 0.0
+    if nrows == 0 or ncols == 0:
+        return rng, None, p
+    return rng, int(rng.integers(0, 2**63 - 1)), p
+
+
 def er(nrows: int, ncols: int, d: float, seed: int, values: Optional[str] = "f64") -> CSR:
     """Erdos-Renyi G(nrows, ncols, p) with p = d / ncols: every cell is
     present independently, so each row has Binomial(ncols, p) entries at
     distinct uniform columns. Rows are drawn in C by geometric skipping with a
     counter-based random stream per row (mspgen/gen.c); values with numpy."""
     from . import _native
-    rng = np.random.default_rng(seed)
+    rng, s64, p = _er_stream(seed, nrows, ncols, d)
     rowptr = np.zeros(nrows + 1, dtype=np.int64)
-    if nrows == 0 or ncols == 0:
+    if s64 is None:
         return CSR(nrows, ncols, rowptr, np.zeros(0, np.int32), random_values(0, values, rng))
-    p = min(1.0, d / ncols)
     L = _native.lib()
     cnt = np.zeros(nrows, dtype=np.int64)
-    s64 = int(rng.integers(0, 2**63 - 1))
     L.gen_er_counts(nrows, ncols, p, s64, _native.ptr(cnt))
     np.cumsum(cnt, out=rowptr[1:])
     colidx = np.empty(int(rowptr[-1]), dtype=np.int32)
     L.gen_er_fill(nrows, ncols, p, s64, _native.ptr(rowptr), _native.ptr(colidx))
     return CSR(nrows, ncols, rowptr, colidx, random_values(len(colidx), values, rng))
+
+
+def er_rows(nrows: int, ncols: int, d: float, seed: int, rows) -> CSR:
+    """The rows `rows` of the pattern er(nrows, ncols, d, seed, None) (the same
+    per-row random streams), as an nrows x ncols CSR in which every other row
+    is empty: enough for an oracle that computes only those rows, without
+    drawing the whole matrix."""
+    from . import _native
+    _, s64, p = _er_stream(seed, nrows, ncols, d)
+    rows = np.unique(np.asarray(rows, dtype=np.int64))
+    rowptr = np.zeros(nrows + 1, dtype=np.int64)
+    if s64 is None or len(rows) == 0:
+        return CSR(nrows, ncols, rowptr, np.zeros(0, np.int32), None)
+    L = _native.lib()
+    cnt = np.zeros(len(rows), dtype=np.int64)
+    L.gen_er_rows_counts(len(rows), _native.ptr(rows), ncols, p, s64, _native.ptr(cnt))
+    off = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(cnt, out=off[1:])
+    colidx = np.empty(int(off[-1]), dtype=np.int32)
+    L.gen_er_rows_fill(len(rows), _native.ptr(rows), ncols, p, s64, _native.ptr(off), _native.ptr(colidx))
+    full = np.zeros(nrows, dtype=np.int64)
+    full[rows] = cnt
+    np.cumsum(full, out=rowptr[1:])
+    return CSR(nrows, ncols, rowptr, colidx, None)
 
 
 def rmat_edges(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
@@ -275,41 +307,69 @@ def bfs_step_input(G: CSR, nsrc: int, seed: int, values: str = "u8",
     return CSR(n, nsrc, F_rp, F_ci, fvals), CSR(n, nsrc, V_rp, V_ci), sources, lv.astype(np.int64)
 
 
-def batch_mix(count: int, seed: int, n_lo: int = 12, n_hi: int = 17,
-              max_mask_nnz: Optional[int] = None):
-    """The mixed batch: ``count`` independent masked products with
+def batch_params(count: int, seed: int, n_lo: int = 12, n_hi: int = 17):
+    """The drawn parameters of the mixed batch (no matrices): per product
     n = round(2^U(n_lo, n_hi)), input degree d = 2^U(2, 6), mask density
-    factor f = 10^U(-1, 1) times the expected Erdos-Renyi density of A B.
-    Even-index products use Erdos-Renyi A and B, odd-index ones R-MAT graphs
-    (scale round(log2 n), edge factor d) truncated to n; all masks are
-    Erdos-Renyi; FP64 U(0,1) values; normal mask.
-
-    ``max_mask_nnz`` caps the mask degree so that reduced-size variants fit a
-    CPU check. Returns a list of dicts with A, B, M and the drawn parameters."""
+    factor f = 10^U(-1, 1), a sub-seed, and the mask degree
+    md = min(n, f * n * (1 - exp(-d^2 / n))), i.e. f times the expected
+    Erdos-Renyi density of A B."""
     rng = np.random.default_rng(seed)
-    probs = []
+    out = []
     for t in range(count):
         n = int(round(2 ** rng.uniform(n_lo, n_hi)))
         d = float(2 ** rng.uniform(2, 6))
         f = float(10 ** rng.uniform(-1, 1))
         sub = int(rng.integers(0, 2**31 - 1))
-        if t % 2 == 0:
-            A = er(n, n, d, sub + 1, "f64")
-            B = er(n, n, d, sub + 2, "f64")
-        else:
-            sc = max(1, int(round(math.log2(n))))
-            ef = max(1, int(round(d / 2)))  # each undirected edge appears twice
-            G = rmat_graph(sc, ef, sub + 3)
-            G = _truncate(G, n)
-            vr = np.random.default_rng(sub + 4)
-            A = G.with_values(vr.random(G.nnz))
-            B = G.with_values(vr.random(G.nnz))
         dens = 1.0 - math.exp(-d * d / n)
-        md = min(float(n), f * n * dens)
-        if max_mask_nnz is not None:
-            md = min(md, max_mask_nnz / max(n, 1))
-        M = er(n, n, md, sub + 5, None)
-        probs.append(dict(A=A, B=B, M=M, n=n, d=d, f=f))
+        out.append(dict(t=t, n=n, d=d, f=f, sub=sub, md=min(float(n), f * n * dens)))
+    return out
+
+
+def _mask_degree(prm, max_mask_nnz: Optional[int]) -> float:
+    md = prm["md"]
+    if max_mask_nnz is not None:
+        md = min(md, max_mask_nnz / max(prm["n"], 1))
+    return md
+
+
+def batch_operands(prm):
+    """A and B of one product of the mixed batch: Erdos-Renyi for even
+    indices, R-MAT (scale round(log2 n), edge factor d / 2, symmetrized)
+    truncated to n x n for odd ones; FP64 U(0,1) values."""
+    n, d, sub = prm["n"], prm["d"], prm["sub"]
+    if prm["t"] % 2 == 0:
+        return er(n, n, d, sub + 1, "f64"), er(n, n, d, sub + 2, "f64")
+    sc = max(1, int(round(math.log2(n))))
+    ef = max(1, int(round(d / 2)))  # each undirected edge appears twice
+    G = _truncate(rmat_graph(sc, ef, sub + 3), n)
+    vr = np.random.default_rng(sub + 4)
+    return G.with_values(vr.random(G.nnz)), G.with_values(vr.random(G.nnz))
+
+
+def batch_mask(prm, max_mask_nnz: Optional[int] = None) -> CSR:
+    """The Erdos-Renyi mask of one product of the mixed batch."""
+    n = prm["n"]
+    return er(n, n, _mask_degree(prm, max_mask_nnz), prm["sub"] + 5, None)
+
+
+def batch_mask_rows(prm, rows, max_mask_nnz: Optional[int] = None) -> CSR:
+    """Only the rows `rows` of batch_mask(prm) (other rows empty)."""
+    n = prm["n"]
+    return er_rows(n, n, _mask_degree(prm, max_mask_nnz), prm["sub"] + 5, rows)
+
+
+def batch_mix(count: int, seed: int, n_lo: int = 12, n_hi: int = 17,
+              max_mask_nnz: Optional[int] = None):
+    """The mixed batch: ``count`` independent masked products drawn by
+    batch_params (Erdos-Renyi or R-MAT A and B, Erdos-Renyi masks, FP64
+    U(0,1) values, normal mask).
+
+    ``max_mask_nnz`` caps the mask degree so that reduced-size variants fit a
+    CPU check. Returns a list of dicts with A, B, M and the drawn parameters."""
+    probs = []
+    for prm in batch_params(count, seed, n_lo, n_hi):
+        A, B = batch_operands(prm)
+        probs.append(dict(A=A, B=B, M=batch_mask(prm, max_mask_nnz), n=prm["n"], d=prm["d"], f=prm["f"]))
     return probs
 
 

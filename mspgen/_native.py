@@ -25,6 +25,8 @@ def lib():
         vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
         L.gen_er_counts.argtypes = [i64, i64, ctypes.c_double, u64, vp]
         L.gen_er_fill.argtypes = [i64, i64, ctypes.c_double, u64, vp, vp]
+        L.gen_er_rows_counts.argtypes = [i64, vp, i64, ctypes.c_double, u64, vp]
+        L.gen_er_rows_fill.argtypes = [i64, vp, i64, ctypes.c_double, u64, vp, vp]
         L.gen_bfs_counts.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp]
         L.gen_bfs_counts.restype = ctypes.c_int
         L.gen_bfs_lists.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]

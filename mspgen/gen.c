@@ -70,6 +70,19 @@ void gen_er_fill(int64_t m, int64_t n, double p, uint64_t seed, const int64_t* r
     for (int64_t i = 0; i < m; ++i) (void)er_row(i, n, p, seed, colidx + rowptr[i]);
 }
 
+/* Rows rows[0..nsel) only (the same random streams as the whole matrix):
+   pass 1 counts, pass 2 fills colidx at the offsets off[0..nsel]. */
+void gen_er_rows_counts(int64_t nsel, const int64_t* rows, int64_t n, double p, uint64_t seed, int64_t* cnt) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t x = 0; x < nsel; ++x) cnt[x] = er_row(rows[x], n, p, seed, NULL);
+}
+
+void gen_er_rows_fill(int64_t nsel, const int64_t* rows, int64_t n, double p, uint64_t seed, const int64_t* off,
+                      int32_t* colidx) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t x = 0; x < nsel; ++x) (void)er_row(rows[x], n, p, seed, colidx + off[x]);
+}
+
 /* BFS from src up to depth L; fills dist (-1 = unseen) and sigma for the
    reached vertices, records them (in discovery order) in order[], and returns
    how many were reached. level_start[l] = first index in order[] of level l

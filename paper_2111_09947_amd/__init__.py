@@ -603,6 +603,19 @@ class Batch:
     def execute(self):
         _check(L.load().msp_batch_execute(self._h, _stream()), "msp_batch_execute")
 
+    def execute_timed(self, timing: "Timing"):
+        """execute() with the stage events recorded into `timing`."""
+        _check(L.load().msp_batch_execute_timed(self._h, timing._h, _stream()), "msp_batch_execute_timed")
+
+    def row_bins(self):
+        """Kernel bin of every row of every product, products one after
+        another (numpy int8; -1 = no possible output)."""
+        import numpy as np
+        out = np.empty(sum(A.nrows for (A, _, _, _) in self.problems), dtype=np.int8)
+        _check(L.load().msp_plan_row_bins(self._h, out.ctypes.data_as(ctypes.c_void_p), _stream()),
+               "msp_plan_row_bins")
+        return out
+
     def graph_launch(self):
         """Replays the captured graph (captures it on first use); the current
         stream must not be the default stream."""

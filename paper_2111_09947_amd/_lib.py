@@ -100,6 +100,7 @@ SIGNATURES = {
     "msp_batch_info": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(MspPlanInfo)]),
     "msp_batch_bind": (ctypes.c_int, [c_vp, P_out, c_vp, c_sz, c_vp]),
     "msp_batch_execute": (ctypes.c_int, [c_vp, c_vp]),
+    "msp_batch_execute_timed": (ctypes.c_int, [c_vp, c_vp, c_vp]),
     "msp_batch_graph_launch": (ctypes.c_int, [c_vp, c_vp]),
     "msp_batch_nnz": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i64), c_vp]),
     "msp_ktruss": (ctypes.c_int, [P_csr, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64),

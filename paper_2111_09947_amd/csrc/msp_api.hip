@@ -1324,6 +1324,19 @@ msp_status msp_batch_execute(msp_plan* P, void* stream) {
     return run_one_phase(P, P->outs[0], (hipStream_t)stream, none);
 }
 
+msp_status msp_batch_execute_timed(msp_plan* P, msp_timing* T, void* stream) {
+    if (!P || !P->bound) return fail(MSP_ERR_INVALID_ARGUMENT, "batch outputs are not bound");
+    if (!T) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL timing session");
+    int dev = 0;
+    MSP_HIP(hipGetDevice(&dev));
+    if (dev != T->device) return fail(MSP_ERR_INVALID_ARGUMENT, "the timing session belongs to another device");
+    StageTimer tm;
+    tm.on = true;
+    tm.s = (hipStream_t)stream;
+    tm.sess = T;
+    return run_one_phase(P, P->outs[0], tm.s, tm);
+}
+
 msp_status msp_batch_graph_launch(msp_plan* P, void* stream) {
     if (!P || !P->bound) return fail(MSP_ERR_INVALID_ARGUMENT, "batch outputs are not bound");
     hipStream_t s = (hipStream_t)stream;

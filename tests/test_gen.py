@@ -63,3 +63,24 @@ def test_batch_mix_small():
             X.validate()
         assert p["A"].ncols == p["B"].nrows and p["M"].ncols == p["B"].ncols
         assert 2 ** 8 - 1 <= p["n"] <= 2 ** 10 + 1
+
+
+def test_er_rows_are_the_rows_of_er():
+    """er_rows draws exactly the selected rows of er() (same per-row streams),
+    leaving every other row empty."""
+    A = mspgen.er(5000, 3000, 40.0, 77, None)
+    rows = np.array([0, 17, 4999, 17, 2500])
+    S = mspgen.er_rows(5000, 3000, 40.0, 77, rows)
+    assert S.nrows == 5000 and S.ncols == 3000
+    for i in range(5000):
+        exp = A.row(i) if i in (0, 17, 2500, 4999) else np.zeros(0, np.int32)
+        assert np.array_equal(S.row(i), exp)
+
+
+def test_batch_mask_rows_match_the_batch_mask():
+    prm = mspgen.batch_params(3, seed=4)[2]
+    M = mspgen.batch_mask(prm, max_mask_nnz=300_000)
+    rows = np.array([1, 5, prm["n"] - 1])
+    S = mspgen.batch_mask_rows(prm, rows, max_mask_nnz=300_000)
+    for i in rows:
+        assert np.array_equal(S.row(i), M.row(i))

@@ -1,8 +1,8 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
 benchmark times: triangle counting on R-MAT scale 18 compared entry by entry
 with the oracle; the 512-source BFS step on R-MAT scale 20 on sampled rows
-(the oracle computes them one by one); the 64-product batch on sampled rows of
-every product; light Erdos-Renyi products of the density heatmap that run in
+(the oracle computes them one by one); the 64-product batch at full size on
+sampled rows of every product; light Erdos-Renyi products of the density heatmap that run in
 the heap kind, in full."""
 import numpy as np
 import pytest
@@ -46,11 +46,23 @@ def test_bfs_step_full_size_sampled(bfs_graph, sr, vk):
     assert np.all(np.diff(rp) >= 0) and rp[-1] == C.colidx.numel()
 
 
-def test_batch_full_mix_sampled():
+def test_batch_full_size_uncapped_sampled():
+    """The 64-product FP64 batch at full size (masks uncapped: about 5.5e9
+    mask entries in all), run as one batch replayed from a captured graph;
+    sampled rows of every product (a uniform sample plus the product's
+    heaviest rows by products and by mask length) against the oracle, whose
+    mask rows are drawn one by one from the same per-row streams."""
     torch = torch_or_skip()
     m = msp()
-    probs = mspgen.batch_mix(64, seed=4, max_mask_nnz=2_000_000)
-    dev = [(up(p["A"], "plus_times_f64"), up(p["B"], "plus_times_f64"), up(p["M"]), False) for p in probs]
+    prms = mspgen.batch_params(64, seed=4)
+    dev, host = [], []
+    for prm in prms:
+        A, B = mspgen.batch_operands(prm)
+        M = mspgen.batch_mask(prm)
+        dev.append((up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M), False))
+        host.append((prm, A, B, np.diff(M.rowptr)))
+        del M
+    assert sum(int(h[3].sum()) for h in host) > 5_000_000_000
     rng = np.random.default_rng(9)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -59,10 +71,15 @@ def test_batch_full_mix_sampled():
             b.graph_launch()
             b.graph_launch()
             res = b.results()
-    for p, C in zip(probs, res):
-        rows = np.unique(rng.integers(0, p["A"].nrows, 64))
-        R = oracle.masked_spgemm(p["A"], p["B"], p["M"], False, "plus_times_f64", rows=rows)
+    for (prm, A, B, mrow), C in zip(host, res):
+        fl = np.bincount(np.repeat(np.arange(A.nrows), np.diff(A.rowptr)),
+                         weights=np.diff(B.rowptr)[A.colidx], minlength=A.nrows)
+        rows = np.unique(np.concatenate([rng.integers(0, A.nrows, 32), np.argsort(fl)[-4:], np.argsort(mrow)[-4:]]))
+        Ms = mspgen.batch_mask_rows(prm, rows)
+        R = oracle.masked_spgemm(A, B, Ms, False, "plus_times_f64", rows=rows)
         assert_same(C, R, "plus_times_f64", rows=rows)
+        rp = C.rowptr.cpu().numpy()
+        assert np.all(np.diff(rp) >= 0) and rp[-1] == C.colidx.numel()
 
 
 @pytest.mark.parametrize("d,dm,comp", [(1.0, 64.0, False), (4.0, 1024.0, False), (2.0, 8.0, True)])
