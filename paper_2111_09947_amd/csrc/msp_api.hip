@@ -114,6 +114,8 @@ struct Product {
     int64_t* bt_part = nullptr;
     unsigned long long* bt_cursor = nullptr;
     bool bt_counted = false, bt_scattered = false;
+    uint16_t* bdeg = nullptr;  // B's row lengths, 2 bytes each (plan workspace), when B has many rows
+    int64_t gblk0 = 0;         // first analysis block of this product
     int64_t ub = 0, flops = 0, units = 0, staging = 0, mnnz = 0;
     int64_t bin_units[NBINS] = {};
 };
@@ -130,12 +132,17 @@ struct msp_plan {
     bool plain_readback = false;  // read host values by plain copies (no page-locked buffers)
     // plan workspace: analysis (global rows)
     unsigned long long* stats_d = nullptr;  // [P * ST_COUNT]
+    unsigned long long* part = nullptr;     // [ST_COUNT][gtot] statistics per analysis block
+    unsigned long long* segtot = nullptr;   // [NSEG] units per segment over all products
+    unsigned long long* err_d = nullptr;    // validation: nonzero when an operand is not a valid CSR
+    int64_t* blk_off_d = nullptr;           // [P + 1] first analysis block of every product (batches)
+    std::vector<int64_t> blk_off_h;         // the same on the host (kept while the plan lives)
+    int64_t gtot = 0;                       // analysis blocks of all products
     std::vector<unsigned long long> stats;
     int64_t* flops = nullptr;
     int64_t* unit_base = nullptr;
     int8_t* bin = nullptr;
     int64_t* scan_partial = nullptr;
-    int64_t* seg_off_d = nullptr;
     int64_t* icost = nullptr;
     // units (global)
     int64_t bin_count[NBINS] = {};
@@ -147,7 +154,7 @@ struct msp_plan {
     // execution workspace: valid for the workspace the units were last placed in
     const void* placed_ws = nullptr;
     bool placed_staging = false;
-    unsigned long long* seg_cursor = nullptr;  // [NBINS * NBUCKET] + the split-row counter
+    unsigned long long* split_counter = nullptr;  // split rows placed so far
     int32_t* unit_row = nullptr;
     int32_t* unit_tile = nullptr;
     int32_t* unit_prob = nullptr;
@@ -157,7 +164,6 @@ struct msp_plan {
     int64_t* xpart = nullptr;  // scan partials over the units
     int32_t* stg_col = nullptr;
     void* stg_val = nullptr;
-    unsigned long long* split_counter = nullptr;
     int32_t* unit_aux = nullptr;
     int32_t* split_first = nullptr;
     int32_t* split_nchunk = nullptr;
@@ -282,12 +288,24 @@ static msp_status plan_setup(msp_plan* P, const msp_problem* probs, int64_t coun
 static size_t plan_layout(msp_plan* P, char* base) {
     Layout L{base};
     const int64_t count = P->P, R = P->R;
+    P->blk_off_h.assign((size_t)count + 1, 0);
+    for (int64_t p = 0; p < count; ++p) {
+        Product& pr = P->prods[(size_t)p];
+        pr.gblk0 = P->blk_off_h[(size_t)p];
+        P->blk_off_h[(size_t)p + 1] = pr.gblk0 + analysis_blocks(pr.op.m);
+    }
+    P->gtot = P->blk_off_h[(size_t)count];
     L.take(&P->stats_d, count * ST_COUNT);
+    L.take(&P->part, (int64_t)ST_COUNT * P->gtot);
+    L.take(&P->segtot, NSEG);
+    L.take(&P->err_d, 1);
+    if (count > 1) L.take(&P->blk_off_d, count + 1);
     L.take(&P->flops, R);
     L.take(&P->unit_base, R + 1);
     L.take(&P->bin, R);
     L.take(&P->scan_partial, scan_partial_elems(R + 1));
-    L.take(&P->seg_off_d, NBINS * NBUCKET);
+    for (Product& pr : P->prods)  // B row pointers beyond 2 MB: gather 2-byte lengths instead
+        if (pr.op.k > BDEG_MIN_ROWS && pr.nnzA > 0) L.take(&pr.bdeg, pr.op.k);
     if (P->inner_any) {  // pull cost per row, one product at a time (stream order)
         int64_t mmax = 0;
         for (const Product& pr : P->prods) mmax = std::max(mmax, pr.op.m);
@@ -318,7 +336,7 @@ static size_t plan_layout(msp_plan* P, char* base) {
 static size_t exec_layout(msp_plan* P, char* base, bool staging) {
     Layout L{base};
     const int64_t U = P->U;
-    L.take(&P->seg_cursor, NBINS * NBUCKET + 1);
+    L.take(&P->split_counter, 1);
     L.take(&P->unit_row, U);
     L.take(&P->unit_tile, U);
     L.take(&P->unit_prob, U);
@@ -337,7 +355,6 @@ static size_t exec_layout(msp_plan* P, char* base, bool staging) {
         P->stg_col = nullptr;
         P->stg_val = nullptr;
     }
-    P->split_counter = P->seg_cursor ? P->seg_cursor + NBINS * NBUCKET : nullptr;
     return L.off;
 }
 
@@ -449,9 +466,9 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     hipStream_t s = stream;
 
     // the statistics and every product's row counts start at zero (one launch)
-    MSP_HIP(launch_zero2(reinterpret_cast<int64_t*>(P->stats_d), ST_COUNT * count, P->flops, R, s));
+    MSP_HIP(launch_zero2(reinterpret_cast<int64_t*>(P->err_d), 1, P->flops, R, s));
     if (o.validate) {
-        unsigned long long* err = P->stats_d + ST_ERROR;
+        unsigned long long* err = P->err_d;
         for (int64_t p = 0; p < count; ++p) {
             const msp_problem& q = probs[p];
             MSP_HIP(launch_validate(q.A.rowptr, q.A.colidx, q.A.nrows, q.A.ncols, q.A.nnz, err, s));
@@ -497,7 +514,11 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.flops_zeroed = true;
         aa.tiles = P->unit_base;
         aa.bin = P->bin;
-        aa.stats = P->stats_d + p * ST_COUNT;
+        aa.bdeg = pr.bdeg;
+        aa.part = P->part;
+        aa.gtot = P->gtot;
+        aa.gblk0 = pr.gblk0;
+        if (pr.bdeg) MSP_HIP(launch_deg16(pr.op.Brp, pr.op.k, pr.bdeg, s));
         MSP_HIP(launch_analysis(aa, s));
     }
     MSP_HIP(launch_scan(P->unit_base, P->unit_base, R, P->scan_partial, s));
@@ -505,15 +526,18 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         // the one synchronization of plan creation: the statistics size the unit arrays
         const size_t sb = sizeof(unsigned long long) * ST_COUNT * (size_t)count;
         P->stats.assign((size_t)(count * ST_COUNT), 0ull);
+        if (count > 1)  // the host copy lives as long as the plan
+            MSP_HIP(hipMemcpyAsync(P->blk_off_d, P->blk_off_h.data(), sizeof(int64_t) * (count + 1),
+                                   hipMemcpyHostToDevice, s));
         if (P->plain_readback) {
-            MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, nullptr, nullptr, s));
+            MSP_HIP(launch_segoff(P->part, P->gtot, P->blk_off_d, count, P->stats_d, nullptr, P->segtot, s));
             MSP_HIP(hipMemcpyAsync(P->stats.data(), P->stats_d, sb, hipMemcpyDeviceToHost, s));
             MSP_HIP(hipStreamSynchronize(s));
         } else {
             PinnedBuf pin;
             MSP_CHECK(pin.get(sb));
-            MSP_HIP(launch_segoff(P->stats_d, count, P->seg_off_d, nullptr,
-                                  static_cast<unsigned long long*>(pin.dev), s));
+            MSP_HIP(launch_segoff(P->part, P->gtot, P->blk_off_d, count, P->stats_d,
+                                  static_cast<unsigned long long*>(pin.dev), P->segtot, s));
             MSP_HIP(hipStreamSynchronize(s));
             std::memcpy(P->stats.data(), pin.p, sb);
         }
@@ -591,8 +615,8 @@ static msp_status place_units(msp_plan* P, void* ws, size_t ws_bytes, bool stagi
     if (!ws) return fail(MSP_ERR_INVALID_ARGUMENT, "execution workspace is NULL");
     exec_layout(P, static_cast<char*>(ws), staging);
     P->placed_ws = nullptr;
-    // placement cursors and the split-row counter start at zero
-    MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(P->seg_cursor), NBINS * NBUCKET + 1, 0, s));
+    // the split-row counter starts at zero
+    MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(P->split_counter), 1, 0, s));
     for (int64_t p = 0; p < P->P; ++p) {
         Product& pr = P->prods[(size_t)p];
         if (pr.op.m == 0) continue;
@@ -603,8 +627,10 @@ static msp_status place_units(msp_plan* P, void* ws, size_t ws_bytes, bool stagi
         ua.flops = P->flops;
         ua.unit_base = P->unit_base;
         ua.bin = P->bin;
-        ua.seg_off = P->seg_off_d;
-        ua.seg_cursor = P->seg_cursor;
+        ua.part = P->part;
+        ua.gtot = P->gtot;
+        ua.gblk0 = pr.gblk0;
+        ua.segtot = P->segtot;
         ua.unit_row = P->unit_row;
         ua.unit_tile = P->unit_tile;
         ua.unit_prob = P->unit_prob;

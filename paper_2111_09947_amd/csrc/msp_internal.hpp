@@ -109,8 +109,7 @@ enum Stat : int {
     ST_MNNZ = 4,
     ST_MAXFLOPS = 5,
     ST_BIN0 = 6,                 // ST_BIN0 + b * NBUCKET + bucket: units of bin b in a flops bucket
-    ST_ERROR = ST_BIN0 + NBINS * NBUCKET,  // nonzero: invalid CSR found by validation
-    ST_SPLITROWS = ST_ERROR + 1,           // rows split over several blocks
+    ST_SPLITROWS = ST_BIN0 + NBINS * NBUCKET,  // rows split over several blocks
     ST_HEAP_APART = ST_SPLITROWS + 1,      // BIN_HEAP_L rows the mask-indexed wave kernel cannot take
     ST_HEAPLM_APART = ST_HEAP_APART + 1,   // BIN_HEAP_LM rows the mask-indexed block kernel cannot take
     ST_COUNT = ST_HEAPLM_APART + 1
@@ -144,8 +143,28 @@ struct AnalysisArgs {
     bool flops_zeroed;         // flops of this product's rows are zero already
     int64_t* tiles;            // [R+1], number of units per row (scanned later)
     int8_t* bin;               // [R]
-    unsigned long long* stats; // [ST_COUNT] of this product
+    const uint16_t* bdeg;      // [k] row lengths of B saturated at 0xFFFF (or null: read B's row pointers)
+    // every analysis block writes its statistics to part[x * gtot + gblk0 + block] (no atomics)
+    unsigned long long* part;  // [ST_COUNT][gtot]
+    int64_t gtot;              // analysis blocks of all products of the plan
+    int64_t gblk0;             // first analysis block of this product
 };
+
+// Blocks of one product's analysis (and unit placement): one per chunk of
+// 256 rows up to ANA_MAXB (8 per CU), each walking every ANA_MAXB-th chunk;
+// the two kernels split the rows identically, so that the placement can use
+// the analysis's per-block counts.
+constexpr int ANA_ROWS = 256;
+constexpr int64_t ANA_MAXB = 2048;
+__host__ __device__ inline int64_t analysis_blocks(int64_t m) {
+    const int64_t b = (m + ANA_ROWS - 1) / ANA_ROWS;
+    return b < ANA_MAXB ? b : ANA_MAXB;
+}
+constexpr int NSEG = NBINS * NBUCKET;  // (bin, flops bucket) segments of the unit list
+// When B has more rows than this, its row pointers (8 bytes a row) exceed
+// 2 MB, half of one XCD's L2: the product count per row then gathers B's row
+// lengths from a 2-byte copy instead.
+constexpr int64_t BDEG_MIN_ROWS = 262144;
 
 struct UnitArgs {
     Operands op;
@@ -154,8 +173,12 @@ struct UnitArgs {
     const int64_t* flops;
     const int64_t* unit_base;  // [R+1] exclusive scan of tiles over global rows
     const int8_t* bin;
-    const int64_t* seg_off;    // [NBINS * NBUCKET] start of each (bin, bucket) segment in bin_units
-    unsigned long long* seg_cursor;  // [NBINS * NBUCKET], zeroed
+    // per analysis block and segment, the block's first position inside the segment (exclusive
+    // prefix over the blocks of all products, in place of the analysis's counts) ...
+    const unsigned long long* part;  // [ST_COUNT][gtot]
+    int64_t gtot;
+    int64_t gblk0;             // first analysis block of this product
+    const unsigned long long* segtot;  // [NSEG] ... and every segment's total over all products
     int32_t* unit_row;         // local row within the product
     int32_t* unit_tile;
     int32_t* unit_prob;        // product of the unit
@@ -251,12 +274,17 @@ int64_t reduce_partial_elems();
 hipError_t launch_reduce(int semiring, const void* vals, int64_t n, const int64_t* n_dev, void* partial, void* result,
                          hipStream_t s);
 
-// Unit-list segment offsets from the per-product statistics; zeroes the
-// placement cursors (NBINS * NBUCKET + 1 entries) unless `cursor` is null;
-// copies the statistics to `host_stats` (device-visible page-locked host
-// memory) unless it is null.
-hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
-                         unsigned long long* cursor, unsigned long long* host_stats, hipStream_t s);
+// Reduces the analysis blocks' statistics (part, [ST_COUNT][gtot]): per
+// product p (blocks blk_off[p] .. blk_off[p+1], or all gtot blocks when
+// count == 1 and blk_off is null) into stats[p * ST_COUNT + x] and, unless it
+// is null, host_stats (device-visible page-locked host memory); every
+// segment's total over all blocks into segtot; and, in place, every
+// segment's counts into exclusive prefix sums over the blocks.
+hipError_t launch_segoff(unsigned long long* part, int64_t gtot, const int64_t* blk_off, int64_t count,
+                         unsigned long long* stats, unsigned long long* host_stats, unsigned long long* segtot,
+                         hipStream_t s);
+// deg[r] = min(rp[r + 1] - rp[r], 0xFFFF) for r < nrows.
+hipError_t launch_deg16(const int64_t* rp, int64_t nrows, uint16_t* deg, hipStream_t s);
 // *host_dst = *src, with host_dst device-visible page-locked host memory.
 hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s);
 

@@ -171,7 +171,7 @@ __device__ int64_t row_of(const int64_t* __restrict__ rp, int64_t nrows, int64_t
 // when it spans blocks).
 __global__ __launch_bounds__(ANA_T) void k_rowsum(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                   int64_t nrows, int64_t nnz, const int64_t* __restrict__ grp,
-                                                  int64_t* __restrict__ out) {
+                                                  const uint16_t* __restrict__ gdeg, int64_t* __restrict__ out) {
     __shared__ int64_t lds[RS_CHUNK + RS_CHUNK / 8];
     __shared__ int64_t tmp[ANA_T / WAVE];
     __shared__ int64_t rows[2];
@@ -190,8 +190,16 @@ __global__ __launch_bounds__(ANA_T) void k_rowsum(const int64_t* __restrict__ rp
         col[x] = p < c1 ? ci[p] : -1;
     }
     int64_t gv[RS_PER];
+    if (gdeg) {  // 2-byte lengths (a quarter of the row pointers' footprint in cache); 0xFFFF: look it up
 #pragma unroll
-    for (int x = 0; x < RS_PER; ++x) gv[x] = col[x] >= 0 ? grp[col[x] + 1] - grp[col[x]] : 0;
+        for (int x = 0; x < RS_PER; ++x) gv[x] = col[x] >= 0 ? (int64_t)gdeg[col[x]] : 0;
+#pragma unroll
+        for (int x = 0; x < RS_PER; ++x)
+            if (gv[x] == 0xFFFF) gv[x] = grp[col[x] + 1] - grp[col[x]];
+    } else {
+#pragma unroll
+        for (int x = 0; x < RS_PER; ++x) gv[x] = col[x] >= 0 ? grp[col[x] + 1] - grp[col[x]] : 0;
+    }
 #pragma unroll
     for (int x = 0; x < RS_PER; ++x) lds[rs_idx(tid + x * ANA_T)] = gv[x];
     __syncthreads();
@@ -306,70 +314,85 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
     return min(adm, flops);
 }
 
+// Each block walks the chunks of 256 rows blockIdx.x, blockIdx.x + gridDim.x,
+// ... (gridDim.x = analysis_blocks(m)) and writes its own statistics, so no
+// two blocks update one address: k_segoff adds them up.
 __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
+    static_assert(ANA_T == ANA_ROWS, "one row per thread and chunk");
     __shared__ unsigned long long sst[ST_COUNT];
     const Operands& o = a.op;
-    const int64_t r0 = (int64_t)blockIdx.x * ANA_T;
-    const int64_t r1 = min(r0 + ANA_T, o.m);
     for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) sst[x] = 0;
     __syncthreads();
-    const int64_t i = r0 + threadIdx.x;
-    // products per row (and the pull cost), summed beforehand by k_rowsum
-    const int64_t flops = i < r1 ? a.flops[a.row_off + i] : 0;
-    const int64_t icost = (i < r1 && a.icost) ? a.icost[i] : 0;
-    int64_t ub = 0, tiles = 0, stg = 0, mnnz = 0;
-    int seg = -1;
-    if (i < r1) {
-        mnnz = o.Mrp[i + 1] - o.Mrp[i];
-        const int64_t adm = o.complement ? o.n - mnnz : mnnz;
-        ub = min(adm, flops);
-        int bin = -1;
-        if (ub > 0) {
-            classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
-                     a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost, bin, tiles);
-            if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
-            if (bin == BIN_HEAP_L && o.complement) atomicAdd(&sst[ST_HEAP_APART], 1ull);
-            if (bin == BIN_HEAP_LM && mnnz > MASKIDX_B_CAP) atomicAdd(&sst[ST_HEAPLM_APART], 1ull);
-            for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
-            seg = bin * NBUCKET + flops_bucket(flops);
+    for (int64_t r0 = (int64_t)blockIdx.x * ANA_T; r0 < o.m; r0 += (int64_t)gridDim.x * ANA_T) {
+        const int64_t r1 = min(r0 + ANA_T, o.m);
+        const int64_t i = r0 + threadIdx.x;
+        // products per row (and the pull cost), summed beforehand by k_rowsum
+        const int64_t flops = i < r1 ? a.flops[a.row_off + i] : 0;
+        const int64_t icost = (i < r1 && a.icost) ? a.icost[i] : 0;
+        int64_t ub = 0, tiles = 0, stg = 0, mnnz = 0;
+        int seg = -1;
+        if (i < r1) {
+            mnnz = o.Mrp[i + 1] - o.Mrp[i];
+            const int64_t adm = o.complement ? o.n - mnnz : mnnz;
+            ub = min(adm, flops);
+            int bin = -1;
+            if (ub > 0) {
+                classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
+                         a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost, bin, tiles);
+                if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
+                if (bin == BIN_HEAP_L && o.complement) atomicAdd(&sst[ST_HEAP_APART], 1ull);
+                if (bin == BIN_HEAP_LM && mnnz > MASKIDX_B_CAP) atomicAdd(&sst[ST_HEAPLM_APART], 1ull);
+                for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
+                seg = bin * NBUCKET + flops_bucket(flops);
+            }
+            a.tiles[a.row_off + i] = tiles;
+            a.bin[a.row_off + i] = (int8_t)bin;
         }
-        a.tiles[a.row_off + i] = tiles;
-        a.bin[a.row_off + i] = (int8_t)bin;
-    }
-    // per-segment unit counts: one LDS atomic per distinct segment per wave
-    bool pending = seg >= 0;
-    while (true) {
-        const uint64_t pm = __ballot(pending);
-        if (pm == 0) break;
-        const int leader = __builtin_ctzll(pm);
-        const int sg = __shfl(seg, leader, WAVE);
-        const bool mine = pending && seg == sg;
-        const int64_t cnt = wave_sum(mine ? tiles : 0);
-        if (lane() == leader) atomicAdd(&sst[ST_BIN0 + sg], (unsigned long long)cnt);
-        pending = pending && !mine;
-    }
-    // sums: wave reductions, then one LDS atomic per wave
-    const int64_t v_flops = wave_sum(i < r1 ? flops : 0);
-    const int64_t v_ub = wave_sum(ub), v_tiles = wave_sum(tiles), v_stg = wave_sum(stg), v_mnnz = wave_sum(mnnz);
-    int64_t v_max = i < r1 ? flops : 0;
+        // per-segment unit counts: one LDS atomic per distinct segment per wave
+        bool pending = seg >= 0;
+        while (true) {
+            const uint64_t pm = __ballot(pending);
+            if (pm == 0) break;
+            const int leader = __builtin_ctzll(pm);
+            const int sg = __shfl(seg, leader, WAVE);
+            const bool mine = pending && seg == sg;
+            const int64_t cnt = wave_sum(mine ? tiles : 0);
+            if (lane() == leader) atomicAdd(&sst[ST_BIN0 + sg], (unsigned long long)cnt);
+            pending = pending && !mine;
+        }
+        // sums: wave reductions, then one LDS atomic per wave
+        const int64_t v_flops = wave_sum(flops);
+        const int64_t v_ub = wave_sum(ub), v_tiles = wave_sum(tiles), v_stg = wave_sum(stg);
+        const int64_t v_mnnz = wave_sum(mnnz);
+        int64_t v_max = flops;
 #pragma unroll
-    for (int d = WAVE / 2; d >= 1; d >>= 1) v_max = max(v_max, (int64_t)__shfl_xor(v_max, d, WAVE));
-    if (lane() == 0) {
-        atomicAdd(&sst[ST_FLOPS], (unsigned long long)v_flops);
-        atomicAdd(&sst[ST_UB], (unsigned long long)v_ub);
-        atomicAdd(&sst[ST_UNITS], (unsigned long long)v_tiles);
-        atomicAdd(&sst[ST_STAGING], (unsigned long long)v_stg);
-        atomicAdd(&sst[ST_MNNZ], (unsigned long long)v_mnnz);
-        atomicMax(&sst[ST_MAXFLOPS], (unsigned long long)v_max);
+        for (int d = WAVE / 2; d >= 1; d >>= 1) v_max = max(v_max, (int64_t)__shfl_xor(v_max, d, WAVE));
+        if (lane() == 0) {
+            atomicAdd(&sst[ST_FLOPS], (unsigned long long)v_flops);
+            atomicAdd(&sst[ST_UB], (unsigned long long)v_ub);
+            atomicAdd(&sst[ST_UNITS], (unsigned long long)v_tiles);
+            atomicAdd(&sst[ST_STAGING], (unsigned long long)v_stg);
+            atomicAdd(&sst[ST_MNNZ], (unsigned long long)v_mnnz);
+            atomicMax(&sst[ST_MAXFLOPS], (unsigned long long)v_max);
+        }
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) {
-        const unsigned long long v = sst[x];
-        if (v) {
-            if (x == ST_MAXFLOPS) atomicMax(&a.stats[x], v);
-            else atomicAdd(&a.stats[x], v);
-        }
-    }
+    // this block's statistics, every one of them (the buffer is not cleared beforehand)
+    const int64_t g = a.gblk0 + blockIdx.x;
+    for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) a.part[(int64_t)x * a.gtot + g] = sst[x];
+}
+
+// deg[r] = min(rp[r + 1] - rp[r], 0xFFFF)
+__global__ void k_deg16(const int64_t* __restrict__ rp, int64_t nrows, uint16_t* __restrict__ deg) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x)
+        deg[r] = (uint16_t)min(rp[r + 1] - rp[r], (int64_t)0xFFFF);
+}
+
+hipError_t launch_deg16(const int64_t* rp, int64_t nrows, uint16_t* deg, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    MSP_LAUNCH(k_deg16, dim3(grid_for(nrows, 256, 4096)), dim3(256), 0, s, rp, nrows, deg);
+    return hipGetLastError();
 }
 
 
@@ -394,52 +417,82 @@ hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     if (a.a_nnz > 0)
         MSP_LAUNCH(k_rowsum, dim3(grid_for(a.a_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Arp, a.op.Aci,
-                   a.op.m, a.a_nnz, a.op.Brp, a.flops + a.row_off);
+                   a.op.m, a.a_nnz, a.op.Brp, a.bdeg, a.flops + a.row_off);
     if (a.icost) {
         e = launch_fill_i64(a.icost, a.op.m, 0, s);
         if (e != hipSuccess) return e;
         if (a.m_nnz > 0)
             MSP_LAUNCH(k_rowsum, dim3(grid_for(a.m_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Mrp,
-                       a.op.Mci, a.op.m, a.m_nnz, a.colcnt_rp, a.icost);
+                       a.op.Mci, a.op.m, a.m_nnz, a.colcnt_rp, (const uint16_t*)nullptr, a.icost);
     }
-    MSP_LAUNCH(k_analysis, dim3(grid_for(a.op.m, ANA_T, INT32_MAX)), dim3(ANA_T), 0, s, a);
+    MSP_LAUNCH(k_analysis, dim3(analysis_blocks(a.op.m)), dim3(ANA_T), 0, s, a);
     return hipGetLastError();
 }
 
-// Segment offsets of the unit list (bins in order, inside a bin the flops
-// buckets from the heaviest down), summed over the products of a plan, and
-// the zeroed placement cursors (+ the split-row counter). The host derives
-// the same offsets from the statistics it reads back.
-__global__ __launch_bounds__(128) void k_segoff(const unsigned long long* __restrict__ stats, int64_t count,
-                                                int64_t* __restrict__ seg_off, unsigned long long* cursor,
-                                                unsigned long long* host_stats) {
-    __shared__ int64_t segc[NBINS * NBUCKET];
-    // the statistics also go straight to the caller's page-locked host buffer (no copy engine pass)
-    if (host_stats)
-        for (int64_t x = threadIdx.x; x < count * ST_COUNT; x += blockDim.x) host_stats[x] = stats[x];
-    for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x) {
-        int64_t c = 0;
-        for (int64_t p = 0; p < count; ++p) c += (int64_t)stats[p * ST_COUNT + ST_BIN0 + x];
-        segc[x] = c;
-    }
-    if (cursor)
-        for (int x = threadIdx.x; x < NBINS * NBUCKET + 1; x += blockDim.x) cursor[x] = 0ull;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int x = 0; x < NBINS; ++x) {
-            const int b = bin_at(x);
-            for (int q = NBUCKET - 1; q >= 0; --q) {
-                seg_off[b * NBUCKET + q] = run;
-                run += segc[b * NBUCKET + q];
-            }
+// One block per statistic x over the analysis blocks' values part[x][0, gtot):
+// the total (the maximum for ST_MAXFLOPS) of every product's blocks, and for
+// a segment count also the total over all blocks and, in place, the
+// exclusive prefix sums over the blocks in order (products one after
+// another): the first position of each block's units inside the segment.
+constexpr int SEG_T = 256;
+__global__ __launch_bounds__(SEG_T) void k_segoff(unsigned long long* __restrict__ part, int64_t gtot,
+                                                  const int64_t* __restrict__ blk_off, int64_t count,
+                                                  unsigned long long* __restrict__ stats,
+                                                  unsigned long long* host_stats, unsigned long long* segtot) {
+    __shared__ unsigned long long red[SEG_T / WAVE];
+    const int x = blockIdx.x;
+    unsigned long long* row = part + (int64_t)x * gtot;
+    const bool is_max = x == ST_MAXFLOPS;
+    const int w = threadIdx.x / WAVE;
+    for (int64_t p = 0; p < count; ++p) {
+        const int64_t g0 = blk_off ? blk_off[p] : 0, g1 = blk_off ? blk_off[p + 1] : gtot;
+        unsigned long long v = 0;
+        for (int64_t g = g0 + threadIdx.x; g < g1; g += SEG_T) v = is_max ? max(v, row[g]) : v + row[g];
+#pragma unroll
+        for (int d = WAVE / 2; d >= 1; d >>= 1) {
+            const unsigned long long o = __shfl_xor(v, d, WAVE);
+            v = is_max ? max(v, o) : v + o;
         }
+        if (lane() == 0) red[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int k = 0; k < SEG_T / WAVE; ++k) t = is_max ? max(t, red[k]) : t + red[k];
+            stats[p * ST_COUNT + x] = t;
+            if (host_stats) host_stats[p * ST_COUNT + x] = t;
+        }
+        __syncthreads();
     }
+    if (x < ST_BIN0 || x >= ST_BIN0 + NSEG) return;
+    // segment counts -> exclusive prefix over all blocks, chunk by chunk
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < gtot; base += SEG_T) {
+        const int64_t g = base + threadIdx.x;
+        const unsigned long long v = g < gtot ? row[g] : 0ull;
+        unsigned long long incl = v;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const unsigned long long o = __shfl_up(incl, d, WAVE);
+            if (lane() >= d) incl += o;
+        }
+        if (lane() == WAVE - 1) red[w] = incl;
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+        for (int k = 0; k < SEG_T / WAVE; ++k) {
+            before += k < w ? red[k] : 0ull;
+            total += red[k];
+        }
+        if (g < gtot) row[g] = carry + before + incl - v;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) segtot[x - ST_BIN0] = carry;
 }
 
-hipError_t launch_segoff(const unsigned long long* stats, int64_t count, int64_t* seg_off,
-                         unsigned long long* cursor, unsigned long long* host_stats, hipStream_t s) {
-    MSP_LAUNCH(k_segoff, dim3(1), dim3(128), 0, s, stats, count, seg_off, cursor, host_stats);
+hipError_t launch_segoff(unsigned long long* part, int64_t gtot, const int64_t* blk_off, int64_t count,
+                         unsigned long long* stats, unsigned long long* host_stats, unsigned long long* segtot,
+                         hipStream_t s) {
+    MSP_LAUNCH(k_segoff, dim3(ST_COUNT), dim3(SEG_T), 0, s, part, gtot, blk_off, count, stats, host_stats, segtot);
     return hipGetLastError();
 }
 
@@ -453,54 +506,69 @@ hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s) {
 
 // --------------------------------------------------------------------- units
 
-__global__ __launch_bounds__(256) void k_units(UnitArgs a, int64_t m) {
-    __shared__ unsigned int hist[NBINS * NBUCKET];
-    __shared__ unsigned long long seg_base[NBINS * NBUCKET];
+// Same blocks and row chunks as k_analysis. A block's units of segment s go
+// to positions segment start + the block's prefix (from k_segoff) + a rank
+// taken with an LDS atomic; the counts match the analysis's, so the ranges
+// of the blocks tile every segment exactly.
+__global__ __launch_bounds__(ANA_ROWS) void k_units(UnitArgs a, int64_t m) {
+    __shared__ unsigned int hist[NSEG];
+    __shared__ int64_t sbase[NSEG];
     const Operands& o = a.op;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool has = i < m;
-    for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x) hist[x] = 0;
-    __syncthreads();
-    int64_t base = 0, tiles = 0;
-    int seg = -1;
-    unsigned int rank = 0;
-    if (has) {
-        const int64_t gr = a.row_off + i;
-        base = a.unit_base[gr];
-        tiles = a.unit_base[gr + 1] - base;
-        if (tiles > 0) {
-            const int bin = a.bin[gr];
-            const int64_t mnnz = o.Mrp[i + 1] - o.Mrp[i];
-            const int64_t flops = a.flops[gr];
-            for (int64_t t = 0; t < tiles; ++t) {
-                a.unit_row[base + t] = (int32_t)i;
-                a.unit_tile[base + t] = (int32_t)t;
-                a.unit_prob[base + t] = a.prob;
-                a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
-            }
-            seg = bin * NBUCKET + flops_bucket(flops);
-            rank = atomicAdd(&hist[seg], (unsigned int)tiles);
-            if (bin == BIN_DENSE_SPLIT) {
-                const int32_t sidx = (int32_t)atomicAdd(a.split_counter, 1ull);
-                a.split_first[sidx] = (int32_t)base;
-                a.split_nchunk[sidx] = (int32_t)tiles;
-                for (int64_t t = 0; t < tiles; ++t) a.unit_aux[base + t] = sidx;
-            }
+    const int64_t g = a.gblk0 + blockIdx.x;
+    for (int x = threadIdx.x; x < NSEG; x += blockDim.x) hist[x] = 0;
+    if (threadIdx.x < WAVE) {  // segment starts: bins in order, inside a bin the buckets from the heaviest down
+        constexpr int PER = (NSEG + WAVE - 1) / WAVE;  // consecutive list positions per lane
+        int64_t v[PER];
+        int sg[PER];
+        int64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int x = (int)threadIdx.x * PER + k;  // position in the unit list's segment order
+            sg[k] = x < NSEG ? bin_at(x / NBUCKET) * NBUCKET + (NBUCKET - 1 - x % NBUCKET) : -1;
+            v[k] = sg[k] >= 0 ? (int64_t)a.segtot[sg[k]] : 0;
+            sum += v[k];
+        }
+        int64_t run = wave_incl_scan(sum) - sum;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (sg[k] >= 0) sbase[sg[k]] = run;
+            run += v[k];
         }
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < NBINS * NBUCKET; x += blockDim.x)
-        if (hist[x]) seg_base[x] = atomicAdd(&a.seg_cursor[x], (unsigned long long)hist[x]);
+    for (int x = threadIdx.x; x < NSEG; x += blockDim.x) sbase[x] += (int64_t)a.part[(int64_t)(ST_BIN0 + x) * a.gtot + g];
     __syncthreads();
-    if (seg >= 0) {
-        const int64_t pos = a.seg_off[seg] + (int64_t)seg_base[seg] + rank;
+    for (int64_t r0 = (int64_t)blockIdx.x * ANA_ROWS; r0 < m; r0 += (int64_t)gridDim.x * ANA_ROWS) {
+        const int64_t i = r0 + threadIdx.x;
+        if (i >= m) continue;
+        const int64_t gr = a.row_off + i;
+        const int64_t base = a.unit_base[gr];
+        const int64_t tiles = a.unit_base[gr + 1] - base;
+        if (tiles <= 0) continue;
+        const int bin = a.bin[gr];
+        const int64_t mnnz = o.Mrp[i + 1] - o.Mrp[i];
+        const int64_t flops = a.flops[gr];
+        for (int64_t t = 0; t < tiles; ++t) {
+            a.unit_row[base + t] = (int32_t)i;
+            a.unit_tile[base + t] = (int32_t)t;
+            a.unit_prob[base + t] = a.prob;
+            a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
+        }
+        const int seg = bin * NBUCKET + flops_bucket(flops);
+        const int64_t pos = sbase[seg] + (int64_t)atomicAdd(&hist[seg], (unsigned int)tiles);
         for (int64_t t = 0; t < tiles; ++t) a.bin_units[pos + t] = (int32_t)(base + t);
+        if (bin == BIN_DENSE_SPLIT) {
+            const int32_t sidx = (int32_t)atomicAdd(a.split_counter, 1ull);
+            a.split_first[sidx] = (int32_t)base;
+            a.split_nchunk[sidx] = (int32_t)tiles;
+            for (int64_t t = 0; t < tiles; ++t) a.unit_aux[base + t] = sidx;
+        }
     }
 }
 
 hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    MSP_LAUNCH(k_units, dim3(grid_for(m, 256, INT32_MAX)), dim3(256), 0, s, a, m);
+    MSP_LAUNCH(k_units, dim3(analysis_blocks(m)), dim3(ANA_ROWS), 0, s, a, m);
     return hipGetLastError();
 }
 
