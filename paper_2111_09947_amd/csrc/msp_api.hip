@@ -62,7 +62,21 @@ msp_status mspk::set_error(msp_status st, const char* msg) { return fail(st, msg
 
 namespace {
 
-bool valid_sr(int s) { return s >= MSP_PLUS_TIMES_F64 && s <= MSP_PLUS_TIMES_I64; }
+// The integer a caller passed for an enumeration parameter. C callers may pass
+// any int, and reading an out-of-range value through the C++ enumeration type
+// is undefined, so the bits are copied out instead.
+template <class E>
+int enum_value(const E& e) {
+    static_assert(sizeof(E) == sizeof(int), "C enumerations have the size of int");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
+bool valid_sr(const msp_semiring& s) {
+    const int v = enum_value(s);
+    return v >= MSP_PLUS_TIMES_F64 && v <= MSP_PLUS_TIMES_I64;
+}
 
 msp_status check_csr(const msp_csr* X, const char* name) {
     if (!X) return fail(MSP_ERR_INVALID_ARGUMENT, std::string(name) + " is NULL");
@@ -204,7 +218,7 @@ void msp_options_default(msp_options* opt) {
 }
 
 const char* msp_status_string(msp_status s) {
-    switch (s) {
+    switch (enum_value(s)) {
     case MSP_OK: return "ok";
     case MSP_ERR_INVALID_ARGUMENT: return "invalid argument";
     case MSP_ERR_DIMENSION_MISMATCH: return "dimension mismatch";
@@ -1072,6 +1086,7 @@ extern "C" {
 
 msp_status msp_plan_workspace_size(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
                                    msp_semiring semiring, const msp_options* opt, size_t* bytes) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
     const msp_problem pb = single_problem(A, B, M, complement);
     return workspace_size_common(&pb, 1, semiring, opt, bytes);
@@ -1079,12 +1094,14 @@ msp_status msp_plan_workspace_size(const msp_csr* A, const msp_csr* B, const msp
 
 msp_status msp_batch_workspace_size(const msp_problem* problems, int64_t count, msp_semiring semiring,
                                     const msp_options* opt, size_t* bytes) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     return workspace_size_common(problems, count, semiring, opt, bytes);
 }
 
 msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, const msp_csr* M,
                            int complement, msp_semiring semiring, const msp_options* opt, void* workspace,
                            size_t workspace_bytes, void* stream) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     if (!A || !B || !M) return fail(MSP_ERR_INVALID_ARGUMENT, "A, B and M must not be NULL");
     const msp_problem pb = single_problem(A, B, M, complement);
     return create_common(plan, &pb, 1, semiring, opt, workspace, workspace_bytes, stream);
@@ -1222,6 +1239,7 @@ void msp_plan_destroy(msp_plan* P) {
 msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
                              msp_semiring semiring, const msp_options* opt, msp_csr_out* C, int64_t* nnz_host,
                              void* workspace, size_t workspace_bytes, size_t* ws_needed, void* stream) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     return one_shot(A, B, M, complement, semiring, opt, C, nnz_host, workspace, workspace_bytes, ws_needed,
                     (hipStream_t)stream, false);
 }
@@ -1229,6 +1247,7 @@ msp_status msp_masked_spgemm(const msp_csr* A, const msp_csr* B, const msp_csr* 
 msp_status msp_masked_spgemm_noalloc(const msp_csr* A, const msp_csr* B, const msp_csr* M, int complement,
                                      msp_semiring semiring, const msp_options* opt, msp_csr_out* C,
                                      int64_t* nnz_host, size_t* ws_needed, void* stream) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     void* ws = nullptr;
     MSP_CHECK(scratch_address(&ws));
     size_t need = 0;
@@ -1266,12 +1285,14 @@ msp_status msp_reduce_workspace_size(size_t* bytes) {
 
 msp_status msp_reduce(const void* values, int64_t n, msp_semiring semiring, void* result, void* workspace,
                       size_t workspace_bytes, void* stream) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     return reduce_impl(values, n, nullptr, semiring, result, workspace, workspace_bytes, stream);
 }
 
 msp_status msp_reduce_csr(const int64_t* rowptr, int64_t nrows, const void* values, int64_t capacity,
                           msp_semiring semiring, void* result, void* workspace, size_t workspace_bytes,
                           void* stream) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     if (!rowptr || nrows < 0) return fail(MSP_ERR_INVALID_ARGUMENT, "bad row pointers");
     return reduce_impl(values, capacity, rowptr + nrows, semiring, result, workspace, workspace_bytes, stream);
 }
@@ -1292,6 +1313,7 @@ static msp_status reduce_impl(const void* values, int64_t n, const int64_t* n_de
 
 msp_status msp_batch_create(msp_plan** batch, const msp_problem* problems, int64_t count, msp_semiring semiring,
                             const msp_options* opt, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!valid_sr(semiring)) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown semiring");
     return create_common(batch, problems, count, semiring, opt, workspace, workspace_bytes, stream);
 }
 

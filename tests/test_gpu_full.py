@@ -1,8 +1,8 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
 benchmark times: triangle counting on R-MAT scale 18 compared entry by entry
-with the oracle; the 512-source BFS step on R-MAT scale 20 on sampled rows
-(the oracle computes them one by one); the 64-product batch at full size on
-sampled rows of every product; light Erdos-Renyi products of the density heatmap that run in
+with the oracle; the 512-source BFS step on R-MAT scale 20, int32 on every
+row and boolean on the whole row-pointer array plus sampled rows; the
+64-product batch at full size on sampled rows of every product; light Erdos-Renyi products of the density heatmap that run in
 the heap kind, in full."""
 import numpy as np
 import pytest
@@ -24,26 +24,43 @@ def test_triangle_counting_full_size():
 
 
 @pytest.fixture(scope="module")
-def bfs_graph():
-    return mspgen.rmat_graph(20, 16, 20)
+def bfs_case():
+    """R-MAT scale 20 graph, the 512-source frontiers with path counts, and
+    the oracle's whole int32 result (every row)."""
+    G = mspgen.rmat_graph(20, 16, 20)
+    F, V, srcs, lv = mspgen.bfs_step_input(G, 512, 21, "i64")
+    Fi = F.with_values(F.values.astype(np.int32))
+    R = oracle.masked_spgemm(G, Fi, V, True, "plus_times_i32")
+    return G, F, V, R
 
 
-@pytest.mark.parametrize("sr,vk", [("plus_times_i32", "i32"), ("lor_land_bool", "u8")])
-def test_bfs_step_full_size_sampled(bfs_graph, sr, vk):
-    G = bfs_graph
-    F, V, srcs, lv = mspgen.bfs_step_input(G, 512, 21, vk)
-    C = msp().masked_spgemm(up(G), up(F, sr), up(V), complement=True, semiring=sr)
+def test_bfs_step_full_size_int32_every_row(bfs_case):
+    """The int32 path-count step compared with the oracle on every row:
+    row pointers, column indices and values."""
+    G, F, V, R = bfs_case
+    sr = "plus_times_i32"
+    C = msp().masked_spgemm(up(G), up(F.with_values(F.values.astype(np.int32)), sr), up(V), complement=True,
+                            semiring=sr)
+    assert_same(C, R, sr)
+
+
+def test_bfs_step_full_size_bool(bfs_case):
+    """The boolean step: the whole row-pointer array against the oracle's
+    (an entry exists under either semiring exactly when some product is
+    stored, so both patterns agree), and sampled rows (a uniform sample plus
+    the 20 hubs) in full against the boolean oracle."""
+    G, F, V, R = bfs_case
+    sr = "lor_land_bool"
+    Fb = F.with_values(np.ones(F.nnz, np.uint8))
+    C = msp().masked_spgemm(up(G), up(Fb, sr), up(V), complement=True, semiring=sr)
+    rp = C.rowptr.cpu().numpy()
+    assert np.array_equal(rp, R.rowptr)
     rng = np.random.default_rng(5)
     deg = np.diff(G.rowptr)
-    hubs = np.argsort(deg)[-20:]  # the heaviest rows plus a uniform sample
+    hubs = np.argsort(deg)[-20:]
     rows = np.unique(np.concatenate([rng.integers(0, G.nrows, 3000), hubs]))
-    R = oracle.masked_spgemm(G, F, V, True, sr, rows=rows)
-    assert_same(C, R, sr, rows=rows)
-    # totals that hold at any size: nnz(C) is the number of (vertex, source)
-    # pairs at distance l_s + 1, counted by the oracle on the sample only; the
-    # row pointers are non-decreasing and end at the output size
-    rp = C.rowptr.cpu().numpy()
-    assert np.all(np.diff(rp) >= 0) and rp[-1] == C.colidx.numel()
+    Rb = oracle.masked_spgemm(G, Fb, V, True, sr, rows=rows)
+    assert_same(C, Rb, sr, rows=rows)
 
 
 def test_batch_full_size_uncapped_sampled():
