@@ -37,6 +37,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# serving: requests with more products than this run alone (never grouped)
+GROUP_WORK_MAX = 20_000_000
 
 
 def kernel_source_hash() -> str:
@@ -803,8 +805,8 @@ def run_heatmap(args):
 def run_serve(args):
     """Poisson stream of masked products drawn uniformly from a pool of the
     benchmark shapes (Erdos-Renyi n = 4096 with fresh seeds, triangle counting
-    on R-MAT scale 18, a 512-source BFS step on R-MAT scale 18, and the 64
-    mixed products with masks capped at 2e6 entries), plus-pair int64 for
+    on R-MAT scale 18, the 512-source BFS step on R-MAT scale 20, and the 64
+    mixed products at full size), plus-pair int64 for
     triangle counting and 50/50 plus-pair int64 or FP64 plus-times otherwise;
     operands resident on the GPU. Arrival rate = 0.8 x the capacity measured
     in a closed loop. Continuous batching (slots on their own streams, same-
@@ -833,13 +835,17 @@ def run_serve(args):
     L = mspgen.triangle_input(18, 16, 18)
     dL = up(L, False)
     pool.append(dict(name="tc_rmat18", ops=(dL, dL, dL, False), f64=False))
-    G = mspgen.rmat_graph(18, 16, 20)
+    G = mspgen.rmat_graph(20, 16, 20)
     F, V, _, _ = mspgen.bfs_step_input(G, 512, 21, "i64")
     F = F.with_values(F.values.astype(np.float64))
     G = G.with_values(np.ones(G.nnz))
-    pool.append(dict(name="bfs_rmat18", ops=(up(G, True), up(F, True), up(V, False), True), f64=True))
-    for q in mspgen.batch_mix(64, seed=4, max_mask_nnz=2_000_000):
-        pool.append(dict(name="mix", ops=(up(q["A"], True), up(q["B"], True), up(q["M"], False), False), f64=True))
+    pool.append(dict(name="bfs_rmat20", ops=(up(G, True), up(F, True), up(V, False), True), f64=True))
+    del G, F, V
+    for prm in mspgen.batch_params(64, seed=4):  # full-size masks, uploaded product by product
+        A, B = mspgen.batch_operands(prm)
+        M = mspgen.batch_mask(prm)
+        pool.append(dict(name=f"mix{prm['t']}", ops=(up(A, True), up(B, True), up(M, False), False), f64=True))
+        del A, B, M
     print(f"[bench] serving pool of {len(pool)} items ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     for it in pool:  # admitted-product count per item (semiring independent)
         A, B, M, c = it["ops"]
@@ -847,6 +853,7 @@ def run_serve(args):
             C = p.execute()
             it["useful"] = int(C.values.sum().item())
         it["bytes"] = {sr: serve.product_bytes(A, B, M, c, sr) for sr in ("plus_pair_i64", "plus_times_f64")}
+        it["work"] = serve.product_info(A, B, M, c, "plus_pair_i64")[1]
 
     def draw(n, seed):
         r = np.random.default_rng(seed)
@@ -859,13 +866,14 @@ def run_serve(args):
         def mk(i):
             k, sr = seq[i]
             it = pool[k]
-            return serve.Request(rid=i, semiring=sr, operands=it["ops"], mem_bytes=it["bytes"][sr])
+            return serve.Request(rid=i, semiring=sr, operands=it["ops"], mem_bytes=it["bytes"][sr], work=it["work"])
         return mk
 
     mem_budget = 64 << 30
     # capacity: closed loop, everything queued at once
     cap_seq = draw(400, 7)
-    srv = serve.Server(serve.GpuExecutor(args.slots), slots=args.slots, max_batch=8, mem_budget=mem_budget)
+    srv = serve.Server(serve.GpuExecutor(args.slots), slots=args.slots, max_batch=8, mem_budget=mem_budget,
+                       group_work_max=GROUP_WORK_MAX)
     tc0 = time.perf_counter()
     reqs = serve.run_trace(srv, make(cap_seq), [0.0] * len(cap_seq))
     capacity = len(reqs) / (max(r.t_done for r in reqs) - tc0)
@@ -880,7 +888,7 @@ def run_serve(args):
 
     def run(continuous):
         srv = serve.Server(serve.GpuExecutor(args.slots), slots=args.slots, max_batch=8, mem_budget=mem_budget,
-                           continuous=continuous)
+                           continuous=continuous, group_work_max=GROUP_WORK_MAX)
         mk = make(seq)
 
         def mk2(i):
@@ -920,8 +928,10 @@ def run_serve(args):
            "data": "synthetic",
            "config": {"workload": "serving: Poisson arrivals at 0.8 x measured capacity over a pool of "
                                   f"{len(pool)} products (Erdos-Renyi n=4096, triangle counting R-MAT 18, BFS "
-                                  "step R-MAT 18 x 512 sources, 64 mixed products), plus-pair int64 / FP64",
-                      "slots": args.slots, "max_batch": 8, "mem_budget_bytes": mem_budget,
+                                  "step R-MAT 20 x 512 sources, the 64 mixed products at full size), "
+                                  "plus-pair int64 / FP64",
+                      "slots": args.slots, "max_batch": 8, "group_work_max": GROUP_WORK_MAX,
+                      "mem_budget_bytes": mem_budget,
                       "capacity_req_s": round(capacity, 2), "lambda_req_s": round(lam, 2)},
            "serving": {"continuous": cont, "fifo_one_at_a_time": fifo,
                        "speedup_throughput": round(cont["throughput_req_s"] / max(fifo["throughput_req_s"], 1e-9), 3),

@@ -123,6 +123,14 @@ def _workspace(nbytes: int, device):
     return ws
 
 
+def _carve(alloc, n: int, dtype):
+    """n elements of dtype from a byte allocator (alloc(nbytes) -> uint8
+    device tensor starting on a 256-byte boundary)."""
+    t = _torch()
+    width = t.empty(0, dtype=dtype).element_size()
+    return alloc(max(int(n), 1) * width)[:max(int(n), 1) * width].view(dtype)
+
+
 class _TorchAllocator:
     """msp_allocator over torch device tensors: the library's iterated
     products (betweenness centrality, k-truss) take every working buffer from
@@ -179,7 +187,11 @@ class Plan:
     def __init__(self, A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, complement: bool = False,
                  semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
                  validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None,
-                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1):
+                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1,
+                 alloc=None):
+        """`alloc(nbytes)`: optional source of the workspaces (a uint8 device
+        tensor on a 256-byte boundary, kept alive by the caller while the plan
+        is used); default: torch's caching allocator."""
         lib = L.load()
         self.semiring = semiring
         self.A, self.B, self.M = A, B, M
@@ -191,12 +203,13 @@ class Plan:
         self.phase = phase
         self.nrows, self.ncols = A.nrows, B.ncols
         self.device = A.rowptr.device
+        self._alloc = alloc if alloc is not None else (lambda n: _workspace(n, self.device))
         cv = int(bool(complement))
         nb = ctypes.c_size_t(0)
         _check(lib.msp_plan_workspace_size(*(ctypes.byref(v) for v in self._views), cv, SEMIRINGS[semiring],
                                            ctypes.byref(self._opt), ctypes.byref(nb)), "msp_plan_workspace_size")
         self.plan_workspace_bytes = nb.value
-        self._pws = _workspace(nb.value, self.device)
+        self._pws = self._alloc(nb.value)
         h = ctypes.c_void_p()
         st = lib.msp_plan_create(ctypes.byref(h), *(ctypes.byref(v) for v in self._views), cv, SEMIRINGS[semiring],
                                  ctypes.byref(self._opt), ctypes.c_void_p(self._pws.data_ptr()), nb.value, _stream())
@@ -218,40 +231,48 @@ class Plan:
     def workspace(self):
         """The execution workspace (allocated on first use, then reused)."""
         if self._xws is None:
-            self._xws = _workspace(self.workspace_bytes, self.device)
+            self._xws = self._alloc(self.workspace_bytes)
         return self._xws
 
     def _ws_args(self):
         ws = self.workspace()
         return ctypes.c_void_p(ws.data_ptr()), ws.numel()
 
-    def _out(self, capacity: int):
+    def _out(self, capacity: int, out_alloc=None):
         t = _torch()
         dev = self.A.rowptr.device
+        if out_alloc is not None:
+            return (_carve(out_alloc, self.nrows + 1, t.int64), _carve(out_alloc, capacity, t.int32),
+                    _carve(out_alloc, capacity, out_dtype(self.semiring)))
         rp = t.empty(self.nrows + 1, dtype=t.int64, device=dev)
         ci = t.empty(max(capacity, 1), dtype=t.int32, device=dev)
         v = t.empty(max(capacity, 1), dtype=out_dtype(self.semiring), device=dev)
         return rp, ci, v
 
-    def execute(self, nnz: bool = True) -> DeviceCSR:
+    def execute(self, nnz: bool = True, out_alloc=None) -> DeviceCSR:
         """Runs the product. Phase 1 allocates C with the upper-bound capacity
         and returns views trimmed to nnz(C) (one synchronization); phase 2
-        runs symbolic, allocates exactly, then numeric."""
+        runs symbolic, allocates exactly, then numeric. `out_alloc(nbytes)`:
+        optional source of the output buffers (as `alloc` of the plan)."""
         lib = L.load()
         s = _stream()
         if self.phase == 2:
             t = _torch()
-            rp = t.empty(self.nrows + 1, dtype=t.int64, device=self.A.rowptr.device)
+            rp = (_carve(out_alloc, self.nrows + 1, t.int64) if out_alloc is not None
+                  else t.empty(self.nrows + 1, dtype=t.int64, device=self.A.rowptr.device))
             n = ctypes.c_int64(0)
             _check(lib.msp_symbolic(self._h, ctypes.c_void_p(rp.data_ptr()), ctypes.byref(n), *self._ws_args(), s),
                    "msp_symbolic")
             nn = n.value
-            ci = t.empty(max(nn, 1), dtype=t.int32, device=rp.device)
-            v = t.empty(max(nn, 1), dtype=out_dtype(self.semiring), device=rp.device)
+            if out_alloc is not None:
+                ci, v = _carve(out_alloc, nn, t.int32), _carve(out_alloc, nn, out_dtype(self.semiring))
+            else:
+                ci = t.empty(max(nn, 1), dtype=t.int32, device=rp.device)
+                v = t.empty(max(nn, 1), dtype=out_dtype(self.semiring), device=rp.device)
             out = L.MspCsrOut(self.nrows, self.ncols, nn, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
             _check(lib.msp_numeric(self._h, ctypes.byref(out), *self._ws_args(), s), "msp_numeric")
             return DeviceCSR(self.nrows, self.ncols, rp, ci[:nn], v[:nn])
-        rp, ci, v = self._out(self.upper_bound)
+        rp, ci, v = self._out(self.upper_bound, out_alloc)
         out = L.MspCsrOut(self.nrows, self.ncols, self.upper_bound, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
         n = ctypes.c_int64(0)
         _check(lib.msp_execute(self._h, ctypes.byref(out), ctypes.byref(n) if nnz else None, *self._ws_args(), s),
@@ -540,7 +561,9 @@ class Batch:
     problems: list of (A, B, M, complement) DeviceCSR triples."""
 
     def __init__(self, problems, semiring: str = "plus_times_f64", force_kind=None, inner_ratio: int = 0,
-                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1):
+                 maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1,
+                 alloc=None):
+        """`alloc(nbytes)`: optional source of the workspaces (as for Plan)."""
         lib = L.load()
         self.semiring = semiring
         self.problems = list(problems)
@@ -559,7 +582,8 @@ class Batch:
         _check(lib.msp_batch_workspace_size(arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt), ctypes.byref(nb)),
                "msp_batch_workspace_size")
         self.plan_workspace_bytes = nb.value
-        self._pws = _workspace(nb.value, self.device)
+        self._alloc = alloc if alloc is not None else (lambda n: _workspace(n, self.device))
+        self._pws = self._alloc(nb.value)
         h = ctypes.c_void_p()
         _check(lib.msp_batch_create(ctypes.byref(h), arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt),
                                     ctypes.c_void_p(self._pws.data_ptr()), nb.value, _stream()), "msp_batch_create")
@@ -581,21 +605,27 @@ class Batch:
         self.bin_units = {k: info.bin_units[i] for i, k in enumerate(L.BIN_NAMES)}
         self.outputs = None
 
-    def bind_new_outputs(self):
-        """Allocates every output with its upper-bound capacity and binds it."""
+    def bind_new_outputs(self, out_alloc=None, keep=None):
+        """Allocates every output with its upper-bound capacity and binds it.
+        `out_alloc(nbytes)`: optional source of the output buffers, except
+        for the products p with keep[p] true, which get their own."""
         t = _torch()
         outs = (L.MspCsrOut * self.count)()
         self.outputs = []
         for p, (A, B, M, _) in enumerate(self.problems):
             dev = A.rowptr.device
             cap = max(self.upper_bounds[p], 1)
-            rp = t.empty(A.nrows + 1, dtype=t.int64, device=dev)
-            ci = t.empty(cap, dtype=t.int32, device=dev)
-            v = t.empty(cap, dtype=out_dtype(self.semiring), device=dev)
+            if out_alloc is not None and not (keep is not None and keep[p]):
+                rp, ci, v = (_carve(out_alloc, A.nrows + 1, t.int64), _carve(out_alloc, cap, t.int32),
+                             _carve(out_alloc, cap, out_dtype(self.semiring)))
+            else:
+                rp = t.empty(A.nrows + 1, dtype=t.int64, device=dev)
+                ci = t.empty(cap, dtype=t.int32, device=dev)
+                v = t.empty(cap, dtype=out_dtype(self.semiring), device=dev)
             self.outputs.append((rp, ci, v))
             outs[p] = L.MspCsrOut(A.nrows, B.ncols, cap, rp.data_ptr(), ci.data_ptr(), v.data_ptr())
         if self._xws is None:
-            self._xws = _workspace(self.workspace_bytes, self.device)
+            self._xws = self._alloc(self.workspace_bytes)
         _check(L.load().msp_batch_bind(self._h, outs, ctypes.c_void_p(self._xws.data_ptr()), self._xws.numel(),
                                        _stream()), "msp_batch_bind")
         return self.outputs

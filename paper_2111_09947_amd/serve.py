@@ -13,15 +13,19 @@ Design
     A group of one runs as a single-product plan, a larger group as one batch
     (one launch per kernel bin for all its products). Slots overlap on the
     device.
-  - Admission is by memory: a request's device bytes must fit the budget
-    minus what running groups hold; otherwise it waits. The bytes are the
-    library's own sizes for the product (plan workspace, execution workspace
-    and the output at its upper bound: product_bytes), taken once per
-    resident operand set. A batch's device tables add a little to the sum of
-    its products; the executor reports the group's real bytes and the
-    accounting follows them while the group runs. A request that alone
-    exceeds the budget, or whose execution raises, completes with an error
-    and the loop keeps serving.
+  - Admission is by memory: a group runs only when its device bytes can be
+    reserved from the budget; otherwise it waits. The bytes are the
+    library's own sizes for each product (plan workspace, execution
+    workspace and the output at its upper bound: product_bytes), taken once
+    per resident operand set, plus a margin per group for a batch's tables.
+    With the GPU executor the budget is one device buffer shared by all
+    slots (DevicePool): a group reserves a contiguous region of it, every
+    workspace and every output that is not kept is carved from that region,
+    and the region returns to the pool when the group's stream has finished.
+    The accounting is then the memory itself, and serving allocates no
+    device memory per request. A request that alone exceeds the budget, or
+    whose execution raises, completes with an error and the loop keeps
+    serving.
   - Latency is measured from the request's arrival time to the moment its
     group's stream has finished (the worker synchronizes its own stream).
 
@@ -42,12 +46,14 @@ class Request:
     semiring: str
     operands: Any               # (A, B, M, complement) for the GPU executor
     mem_bytes: int = 0          # device bytes the product needs (admission)
+    work: int = 0               # products of the request (grouping: heavy requests run alone)
     t_arrival: float = 0.0      # perf_counter() time of arrival
     t_start: float = 0.0
     t_done: float = 0.0
     result: Any = None
     keep: bool = False          # keep the result (otherwise dropped after completion)
     error: Optional[str] = None
+    region: Any = None          # the group's memory reservation while it runs
     done: threading.Event = dataclasses.field(default_factory=threading.Event)
 
     @property
@@ -55,34 +61,85 @@ class Request:
         return self.t_done - self.t_arrival
 
 
-def product_bytes(A, B, M, complement: bool, semiring: str) -> int:
-    """Device bytes one product takes in the library: its plan workspace,
-    its execution workspace and its output (row pointers, and column indices
-    and values at the upper bound), as the library's size queries give them.
-    Runs the row analysis once (one plan creation)."""
+def product_info(A, B, M, complement: bool, semiring: str):
+    """(device bytes, products) of one product in the library. The bytes are
+    its plan workspace, its execution workspace and its output (row
+    pointers, and column indices and values at the upper bound), as the
+    library's size queries give them. Runs the row analysis once (one plan
+    creation)."""
     from . import Plan, out_dtype
     with Plan(A, B, M, complement=complement, semiring=semiring) as p:
         width = out_dtype(semiring).itemsize
         return (p.plan_workspace_bytes + p.workspace_bytes + 8 * (p.nrows + 1)
-                + max(p.upper_bound, 1) * (4 + width))
+                + max(p.upper_bound, 1) * (4 + width)), int(p.products)
+
+
+def product_bytes(A, B, M, complement: bool, semiring: str) -> int:
+    """The device bytes of product_info."""
+    return product_info(A, B, M, complement, semiring)[0]
+
+
+class Budget:
+    """Memory accounting by a counter, with no memory behind it: a
+    reservation is its byte count, held until release."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.in_use = 0
+
+    def margin(self, count: int) -> int:
+        return 0
+
+    def largest_free(self) -> int:
+        return self.capacity - self.in_use
+
+    def reserve(self, nbytes: int):
+        if nbytes > self.largest_free():
+            return None
+        self.in_use += nbytes
+        return [nbytes]
+
+    def adjust(self, handle, actual: int):
+        """The group's real bytes (a batch's tables): the accounting follows."""
+        self.in_use += int(actual) - handle[0]
+        handle[0] = int(actual)
+
+    def release(self, handle):
+        self.in_use -= handle[0]
 
 
 class Server:
     def __init__(self, executor: Callable[[int, List[Request]], None], slots: int = 4, max_batch: int = 8,
-                 mem_budget: int = 64 << 30, continuous: bool = True):
+                 mem_budget: int = 64 << 30, continuous: bool = True, memory=None,
+                 group_work_max: Optional[int] = None):
+        """`memory`: the budget's accounting (reserve / release); default:
+        the executor's own pool when it has one (make_memory), else a
+        counter. `group_work_max`: requests with more work (products) than
+        this run alone and are never grouped (None: no limit); a group then
+        gathers only the light requests, for which one batch saves launches
+        and synchronizations, while a heavy one fills the GPU by itself."""
         self.executor = executor
         self.slots = slots if continuous else 1
         self.max_batch = max_batch if continuous else 1
         self.mem_budget = mem_budget
         self.continuous = continuous
+        self.group_work_max = group_work_max
+        if memory is None:
+            make = getattr(executor, "make_memory", None)
+            memory = make(mem_budget) if make is not None else Budget(mem_budget)
+        self.memory = memory
         self._queue: Deque[Request] = collections.deque()
         self._cv = threading.Condition()
         self._free_slots = list(range(self.slots))
-        self._mem_in_use = 0
         self._running = False
         self._threads: List[threading.Thread] = []
         self._work: Dict[int, Deque[List[Request]]] = {s: collections.deque() for s in range(self.slots)}
         self.completed: List[Request] = []
+
+    def group_bytes(self, reqs) -> int:
+        """The reservation of a group: its products' bytes plus the memory's
+        margin (a batch's tables, alignment)."""
+        return sum(r.mem_bytes for r in reqs) + self.memory.margin(len(reqs))
 
     # ---- public API
     def start(self):
@@ -113,31 +170,38 @@ class Server:
     # ---- scheduler
     def _pick_group(self) -> List[Request]:
         """Oldest request first; then same-semiring requests in arrival order
-        that fit the remaining memory budget."""
+        while the group's bytes can still be reserved; the reservation is
+        taken here (under the lock) and attached to the group's requests."""
         head = self._queue[0]
-        room = self.mem_budget - self._mem_in_use
-        if head.mem_bytes > self.mem_budget:
+        if self.group_bytes([head]) > self.mem_budget:
             self._queue.popleft()
             head.error = "request exceeds the memory budget"
             head.t_done = time.perf_counter()
             head.done.set()
             self.completed.append(head)
             return []
-        if head.mem_bytes > room:
+        room = self.memory.largest_free()
+        if self.group_bytes([head]) > room:
             return []  # wait for memory
         group = [self._queue.popleft()]
-        room -= head.mem_bytes
-        if self.continuous:
+        light = self.group_work_max is None or head.work <= self.group_work_max
+        if self.continuous and light:
             keep: Deque[Request] = collections.deque()
             while self._queue and len(group) < self.max_batch:
                 r = self._queue.popleft()
-                if r.semiring == head.semiring and r.mem_bytes <= room:
+                if (r.semiring == head.semiring and (self.group_work_max is None or r.work <= self.group_work_max)
+                        and self.group_bytes(group + [r]) <= room):
                     group.append(r)
-                    room -= r.mem_bytes
                 else:
                     keep.append(r)
             keep.extend(self._queue)
             self._queue = keep
+        handle = self.memory.reserve(self.group_bytes(group))
+        if handle is None:  # cannot happen below the largest free block; wait rather than fail
+            self._queue.extendleft(reversed(group))
+            return []
+        for r in group:
+            r.region = handle
         return group
 
     def _schedule(self):
@@ -149,11 +213,10 @@ class Server:
                     return
                 group = self._pick_group()
                 if not group:
-                    if self._queue and self._queue[0].mem_bytes <= self.mem_budget:
+                    if self._queue and self.group_bytes([self._queue[0]]) <= self.mem_budget:
                         self._cv.wait(timeout=0.01)  # memory is held by running groups
                     continue
                 slot = self._free_slots.pop(0)
-                self._mem_in_use += sum(r.mem_bytes for r in group)
                 self._work[slot].append(group)
                 self._cv.notify_all()
 
@@ -168,15 +231,14 @@ class Server:
             t0 = time.perf_counter()
             for r in group:
                 r.t_start = t0
-            admitted = sum(r.mem_bytes for r in group)
-            held = admitted
+            handle = group[0].region
 
             def report(actual: int):
                 """The executor's real bytes for the group (a batch's tables)."""
-                nonlocal held
-                with self._cv:
-                    self._mem_in_use += int(actual) - held
-                    held = int(actual)
+                adjust = getattr(self.memory, "adjust", None)
+                if adjust is not None:
+                    with self._cv:
+                        adjust(handle, actual)
             try:
                 self.executor(slot, group, report)
             except Exception as e:  # the loop keeps serving; the group fails
@@ -186,29 +248,113 @@ class Server:
             with self._cv:
                 for r in group:
                     r.t_done = t1
+                    r.region = None
                     self.completed.append(r)
                     r.done.set()
-                self._mem_in_use -= held
+                self.memory.release(handle)  # the executor has finished with the group's memory
                 self._free_slots.append(slot)
                 self._cv.notify_all()
 
 
+class DevicePool:
+    """The serving memory budget as one device buffer shared by every slot.
+    A group reserves one contiguous region (first fit over the free list,
+    offsets in 256-byte granules); release() returns it and merges it with
+    free neighbours. Serving then allocates no device memory per request:
+    allocating per request would go through the caching allocator, whose
+    cached blocks belong to one stream each, and with several slots and very
+    different sizes that churns device allocations and frees, which
+    synchronize the device."""
+
+    ALIGN = 256
+    GROUP_MARGIN = 1 << 20       # reserved beyond a group's product bytes (batch tables, alignment)
+    REQUEST_MARGIN = 64 << 10
+
+    def margin(self, count: int) -> int:
+        return self.GROUP_MARGIN + self.REQUEST_MARGIN * count
+
+    def __init__(self, capacity: int, device):
+        import torch
+        self.capacity = (int(capacity) // self.ALIGN) * self.ALIGN
+        self.buf = torch.empty(max(self.capacity, self.ALIGN), dtype=torch.uint8, device=device)
+        self.free = [[0, self.capacity]]  # [offset, size], sorted by offset, never adjacent
+
+    def largest_free(self) -> int:
+        return max((n for _, n in self.free), default=0)
+
+    def reserve(self, nbytes: int):
+        n = (max(int(nbytes), 1) + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+        for k, (off, size) in enumerate(self.free):
+            if size >= n:
+                if size == n:
+                    del self.free[k]
+                else:
+                    self.free[k] = [off + n, size - n]
+                return Region(self, off, n)
+        return None
+
+    def release(self, region: "Region"):
+        off, n = region.off, region.size
+        k = 0
+        while k < len(self.free) and self.free[k][0] < off:
+            k += 1
+        self.free.insert(k, [off, n])
+        if k + 1 < len(self.free) and off + n == self.free[k + 1][0]:  # merge with the next block
+            self.free[k][1] += self.free[k + 1][1]
+            del self.free[k + 1]
+        if k > 0 and self.free[k - 1][0] + self.free[k - 1][1] == off:  # and with the previous one
+            self.free[k - 1][1] += self.free[k][1]
+            del self.free[k]
+
+
+class Region:
+    """A group's reservation in a DevicePool: a bump allocator of 256-byte
+    aligned pieces (uint8 device tensors). A request beyond the region (a
+    batch's tables larger than the margin) gets its own block instead."""
+
+    def __init__(self, pool: DevicePool, off: int, size: int):
+        self.pool, self.off, self.size = pool, off, size
+        self.used = 0
+        self.overflow = 0
+
+    def alloc(self, nbytes: int):
+        import torch
+        n = (max(int(nbytes), 1) + DevicePool.ALIGN - 1) // DevicePool.ALIGN * DevicePool.ALIGN
+        if self.used + n > self.size:
+            self.overflow += n
+            return torch.empty(n, dtype=torch.uint8, device=self.pool.buf.device)
+        t = self.pool.buf[self.off + self.used:self.off + self.used + n]
+        self.used += n
+        return t
+
+
 class GpuExecutor:
     """Runs a group on the slot's own stream: one product as a plan, several
-    as one batch. Stores each request's DeviceCSR result and reports the
-    group's device bytes (workspaces and outputs) to the server."""
+    as one batch, with workspaces (and the outputs of results that are not
+    kept) carved from the slot's arena. Stores each request's DeviceCSR
+    result (or its nnz when not kept) and reports the group's device bytes
+    (workspaces and outputs) to the server."""
 
     def __init__(self, slots: int):
         import torch
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.device = torch.device("cuda", torch.cuda.current_device())
         self._sizes: Dict[Any, int] = {}
+
+    def make_memory(self, capacity: int) -> DevicePool:
+        """The server's budget as one device buffer (see DevicePool)."""
+        return DevicePool(capacity, self.device)
 
     def bytes_of(self, operands, semiring: str) -> int:
         """product_bytes of a resident operand set, computed once."""
+        return self.info_of(operands, semiring)[0]
+
+    def info_of(self, operands, semiring: str):
+        """(product_bytes, products) of a resident operand set, computed once."""
         key = (id(operands), semiring)
         if key not in self._sizes:
             A, B, M, comp = operands
-            self._sizes[key] = product_bytes(A, B, M, comp, semiring)
+            self._sizes[key] = product_info(A, B, M, comp, semiring)
         return self._sizes[key]
 
     def __call__(self, slot: int, group: List[Request], report: Optional[Callable[[int], None]] = None):
@@ -216,16 +362,18 @@ class GpuExecutor:
 
         from . import Batch, Plan, out_dtype
         s = self.streams[slot]
+        region = group[0].region
+        alloc = region.alloc if isinstance(region, Region) else None
         with torch.cuda.stream(s):
             if len(group) == 1:
                 r = group[0]
                 A, B, M, comp = r.operands
-                with Plan(A, B, M, complement=comp, semiring=r.semiring) as p:
-                    C = p.execute()
+                with Plan(A, B, M, complement=comp, semiring=r.semiring, alloc=alloc) as p:
+                    C = p.execute(out_alloc=None if r.keep else alloc)
                     r.result = C if r.keep else int(C.colidx.numel())
             else:
-                with Batch([r.operands for r in group], semiring=group[0].semiring) as b:
-                    outs = b.bind_new_outputs()
+                with Batch([r.operands for r in group], semiring=group[0].semiring, alloc=alloc) as b:
+                    outs = b.bind_new_outputs(out_alloc=alloc, keep=[r.keep for r in group])
                     if report is not None:
                         width = out_dtype(group[0].semiring).itemsize
                         report(b.plan_workspace_bytes + b.workspace_bytes +
