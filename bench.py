@@ -159,7 +159,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mask-cap", type=int, default=0,
                     help="batch: cap on one product's mask entries (0: none, the full-size masks)")
-    ap.add_argument("--tune", action="store_true", help="batch: autotune the binner thresholds first")
+    ap.add_argument("--no-tune", action="store_true", help="batch: skip tuning the accumulator kind per row class")
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent execution slots")
     ap.add_argument("--summarize-traffic", metavar="DIR", default=None,
@@ -741,64 +741,107 @@ def run_ktruss(args):
 def run_heatmap(args):
     """Best accumulator kind against input and mask density (the GPU analogue
     of Section "Effect of Input Matrix and Mask Density"): Erdos-Renyi A, B
-    (degree d) and M (degree dm), n = 2^12 .. 2^20, FP64 plus-times, normal
+    (degree d) and M (degree dm), n = 2^12 .. 2^22, FP64 plus-times, normal
     mask. Every kind (and the automatic binner) runs the whole product (plan
     creation included; the inner kind builds B^T inside it), best of 3; all
-    kinds must give the same result (pattern exact, values within 1e-12).
-    Cells with more than 2^31 products are skipped, the dense kind is run
-    only up to n = 2^14 (its 4096-column tiles restream a row once per
+    kinds must give the same result (pattern exact, values within 1e-12),
+    and 64 sampled rows of every cell are checked against the oracle. Cells
+    with more than 2^31 products or mask entries are skipped, the dense kind
+    is run only up to n = 2^14 (its 4096-column tiles restream a row once per
     tile), the heap kind only for d <= 4 (rows of A with more than 8 entries
-    leave it), and mask degree 1024 only up to n = 2^18."""
+    leave it), and mask degree 1024 only up to n = 2^18.
+
+    Then the binner thresholds are tuned on the heatmap: every cell runs the
+    automatic binner under each setting of a grid of maskidx_max (the
+    search/hash split for mask rows), heap_flops and block_flops, and the
+    setting with the smallest geometric mean of (automatic time / best forced
+    time) over the cells is reported beside the library's defaults."""
+    import itertools
+
     import torch
 
     import mspgen
+    import oracle
     import paper_2111_09947_amd as msp
 
     dev = torch.device("cuda:0")
     kinds = [None, "dense", "hash", "maskidx", "inner", "heap"]
+    space = {"maskidx_max": [0, 8, 64], "heap_flops": [0, 32, 128], "block_flops": [2048, 8192, 32768]}
+    settings = [dict(zip(space, v)) for v in itertools.product(*space.values())]
     grid = []
-    for lg in (12, 14, 16, 18, 20):
+    rng = np.random.default_rng(12)
+
+    def best_of(fn, reps):
+        best = float("inf")
+        out = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t) * 1e3)
+        return best, out
+
+    for lg in (12, 14, 16, 18, 20, 22):
         n = 1 << lg
         for d in (1, 4, 16, 64):
             if n * d * d > (1 << 31):
                 continue
-            A = msp.DeviceCSR.from_host(mspgen.er(n, n, d, 1000 + lg, "f64"), dev, torch.float64)
-            B = msp.DeviceCSR.from_host(mspgen.er(n, n, d, 2000 + lg, "f64"), dev, torch.float64)
+            hA = mspgen.er(n, n, d, 1000 + lg, "f64")
+            hB = mspgen.er(n, n, d, 2000 + lg, "f64")
+            A = msp.DeviceCSR.from_host(hA, dev, torch.float64)
+            B = msp.DeviceCSR.from_host(hB, dev, torch.float64)
             for dm in (1, 4, 16, 64, 256, 1024):
-                if dm == 1024 and lg > 18:
+                if (dm == 1024 and lg > 18) or n * dm > (1 << 31):
                     continue
-                M = msp.DeviceCSR.from_host(mspgen.er(n, n, dm, 3000 + lg, None), dev)
+                hM = mspgen.er(n, n, dm, 3000 + lg, None)
+                M = msp.DeviceCSR.from_host(hM, dev)
                 cell = {"n": n, "d": d, "dm": dm, "ms": {}}
                 ref = None
                 for kind in kinds:
                     if (kind == "dense" and lg > 14) or (kind == "heap" and d > 4):
                         continue
-                    best = float("inf")
-                    for _ in range(3):
-                        torch.cuda.synchronize()
-                        t = time.perf_counter()
-                        C = msp.masked_spgemm(A, B, M, semiring="plus_times_f64", force_kind=kind)
-                        torch.cuda.synchronize()
-                        best = min(best, (time.perf_counter() - t) * 1e3)
+                    t, C = best_of(lambda: msp.masked_spgemm(A, B, M, semiring="plus_times_f64", force_kind=kind), 3)
                     h = C.to_host()
                     if ref is None:
                         ref = h
-                    elif not (np.array_equal(h[0], ref[0]) and np.array_equal(h[1], ref[1])
-                              and np.allclose(h[2], ref[2], rtol=1e-12, atol=0)):
+                        rows = np.unique(rng.integers(0, n, 64))
+                        R = oracle.masked_spgemm(hA, hB, hM, False, "plus_times_f64", rows=rows)
+                        if not same_rows(gather_rows(*h, rows), (R.rowptr, R.colidx, R.values), True):
+                            print(f"[bench] MISMATCH against the oracle n={n} d={d} dm={dm}", file=sys.stderr)
+                            sys.exit(1)
+                    elif not same_rows(h, ref, True):
                         print(f"[bench] MISMATCH kind={kind} n={n} d={d} dm={dm}", file=sys.stderr)
                         sys.exit(1)
-                    cell["ms"][kind or "auto"] = round(best, 4)
+                    cell["ms"][kind or "auto"] = round(t, 4)
                 forced = {k: v for k, v in cell["ms"].items() if k != "auto"}
                 cell["best"] = min(forced, key=forced.get)
                 cell["auto_over_best"] = round(cell["ms"]["auto"] / forced[cell["best"]], 3)
+                # the automatic binner under every threshold setting of the grid
+                cell["tuning_ms"] = [round(best_of(lambda: msp.masked_spgemm(A, B, M, semiring="plus_times_f64",
+                                                                             **st), 2)[0], 4) for st in settings]
                 grid.append(cell)
                 print(f"[bench] n=2^{lg} d={d} dm={dm}: best {cell['best']} {cell['ms']}", file=sys.stderr,
                       flush=True)
+                del M, hM
+            del A, B, hA, hB
+            torch.cuda.empty_cache()
+    best_forced = np.array([min(v for k, v in c["ms"].items() if k != "auto") for c in grid])
+    tun = np.array([c["tuning_ms"] for c in grid])  # cells x settings
+    geo = np.exp(np.mean(np.log(tun / best_forced[:, None]), axis=0))
+    k_best = int(np.argmin(geo))
+    defaults = {"maskidx_max": 8, "heap_flops": 32, "block_flops": 8192}
+    k_def = settings.index(defaults)
     ratios = [c["auto_over_best"] for c in grid]
     out = {"metric": "heatmap_auto_over_best_median", "value": round(float(np.median(ratios)), 3),
            "unit": "ratio", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f64",
-           "config": {"workload": "ER n=2^12..2^20, input degree 1..64, mask degree 1..1024, FP64 plus-times"},
-           "worst_auto_over_best": round(float(np.max(ratios)), 3), "cells": grid}
+           "config": {"workload": "ER n=2^12..2^22, input degree 1..64, mask degree 1..1024, FP64 plus-times"},
+           "worst_auto_over_best": round(float(np.max(ratios)), 3),
+           "thresholds": {"space": space, "settings": settings,
+                          "geomean_auto_over_best": [round(float(g), 4) for g in geo],
+                          "best": settings[k_best], "best_geomean": round(float(geo[k_best]), 4),
+                          "defaults": defaults, "defaults_geomean": round(float(geo[k_def]), 4)},
+           "cells": [{k: v for k, v in c.items() if k != "tuning_ms"} for c in grid]}
     print(json.dumps(out), flush=True)
 
 
@@ -1020,7 +1063,7 @@ def run_batch(args):
 
     import mspgen
     import paper_2111_09947_amd as msp
-    from paper_2111_09947_amd.autotune import autotune, same_output
+    from paper_2111_09947_amd.autotune import autotune_classes, same_output, table_from_result
 
     dev = torch.device("cuda:0")
     sr = "plus_times_f64"
@@ -1040,10 +1083,12 @@ def run_batch(args):
           f"{mask_nnz} mask entries", file=sys.stderr, flush=True)
     tune = None
     cfg = {}
-    if args.tune:
-        tune = autotune(devp, sr, repeats=2)
-        cfg = tune["best"]
-        print(f"[bench] tuned: {cfg}", file=sys.stderr, flush=True)
+    if not args.no_tune:  # the accumulator kind per row class, tuned on this batch
+        t1 = time.time()
+        tune = autotune_classes(devp, sr, repeats=3)
+        cfg = {"kind_table": table_from_result(tune)} if tune["table"] else {}
+        print(f"[bench] tuned in {time.time() - t1:.1f}s: {tune['table']} ({tune['default_ms']} -> "
+              f"{tune['best_ms']} ms)", file=sys.stderr, flush=True)
 
     # one launch sequence per product, plans built beforehand
     plans = [msp.Plan(A, B, M, complement=c, semiring=sr, **cfg) for (A, B, M, c) in devp]
@@ -1085,21 +1130,10 @@ def run_batch(args):
         if not same_output(rp, ci[:n], v[:n], C.rowptr, C.colidx, C.values, True):
             print("[bench] MISMATCH between batched and per-product outputs", file=sys.stderr)
             sys.exit(1)
-
-    # end to end, planning included
-    def single_e2e():
-        for (A, B, M, c) in devp:
-            with msp.Plan(A, B, M, complement=c, semiring=sr, **cfg) as p:
-                p.execute()
-
-    def batch_e2e():
-        with torch.cuda.stream(stream):
-            with msp.Batch(devp, semiring=sr, **cfg) as bb:
-                bb.bind_new_outputs()
-                bb.execute()
-
-    e2e_single = _timed(single_e2e, max(1, args.steps // 5), 1)
-    e2e_batch = _timed(batch_e2e, max(1, args.steps // 5), 1)
+    for p in plans:
+        p.close()
+    del plans, outs
+    torch.cuda.empty_cache()
 
     # admitted products per row (the plus-pair count), the byte model per row, the sampled oracle check
     import oracle
@@ -1136,12 +1170,31 @@ def run_batch(args):
             sys.exit(1)
         checked_rows += len(rows)
     per_row = np.concatenate(per_row)
+    products, units, bin_units = int(sum(b.products)), b.units, b.bin_units
+    b.close()
+    del b, res, pair
+    torch.cuda.empty_cache()
+
+    # end to end, planning included
+    def single_e2e():
+        for (A, B, M, c) in devp:
+            with msp.Plan(A, B, M, complement=c, semiring=sr, **cfg) as p:
+                p.execute()
+
+    def batch_e2e():
+        with torch.cuda.stream(stream):
+            with msp.Batch(devp, semiring=sr, **cfg) as bb:
+                bb.bind_new_outputs()
+                bb.execute()
+
+    e2e_single = _timed(single_e2e, max(1, args.steps // 5), 1)
+    e2e_batch = _timed(batch_e2e, max(1, args.steps // 5), 1)
+
     bin_ms = stage_ms[:len(msp.BIN_NAMES)]
     dom = int(np.argmax(bin_ms))
     dom_bytes = int(per_row[bins == dom].sum())
     achieved = dom_bytes / (bin_ms[dom] * 1e-3) / 1e9 if bin_ms[dom] > 0 else 0.0
     total = int(per_row.sum())
-    products = int(sum(b.products))
     value = 2 * useful / (ms_graph * 1e-3) / 1e9
     out = {
         "metric": "useful_masked_gflops",
@@ -1155,8 +1208,8 @@ def run_batch(args):
                                "n 2^12..2^17, degree 4..64, mask 0.1x..10x output density, normal mask",
                    "mask_cap": cap, "mask_nnz": mask_nnz,
                    "rows": int(sum(A.nrows for (A, _, _, _) in devp)), "products": products,
-                   "useful_products": useful, "nnz_C": int(sum(nnz_single)), "units": b.units,
-                   "bin_units": b.bin_units, "tuned": cfg or None},
+                   "useful_products": useful, "nnz_C": int(sum(nnz_single)), "units": units,
+                   "bin_units": bin_units, "kind_table": tune["table"] if tune else None},
         "roofline": {"bound": "hbm", "achieved": sig(achieved), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sig(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": f"numeric bin {msp.BIN_NAMES[dom]}", "kernel_ms": round(float(bin_ms[dom]), 5),
@@ -1181,9 +1234,6 @@ def run_batch(args):
                          "sample": f"the {checked_rows} checked rows, {t_cpu:.3f} s", "cpu_model": cpu_model()},
         "autotune": tune,
     }
-    b.close()
-    for p in plans:
-        p.close()
     print(json.dumps(out), flush=True)
 
 

@@ -186,11 +186,26 @@ typedef struct msp_options {
                              products than this are split over several
                              workgroups by chunks of A's row (-1 = default
                              262144; 0 = never split) */
+    const int8_t* kind_table; /* auto mode: optional accumulator kind per row
+                             class (host, MSP_KIND_CLASSES bytes, read at plan
+                             creation): entry [fb * MSP_ROW_BUCKETS + mb] is the
+                             msp_kind of the rows whose product count falls in
+                             bucket fb and whose mask row length falls in bucket
+                             mb (bucket b: 4^b <= x < 4^(b+1), bucket 0 also
+                             holds 0, the last one everything above), or -1 to
+                             keep the rules above. An entry that does not fit
+                             the row (a complemented mask with other than
+                             DENSE or HEAP, HEAP for a row of A with more than
+                             8 entries or more than 2^24 - 1 products) is
+                             ignored for that row. NULL = no table. */
 } msp_options;
+
+#define MSP_ROW_BUCKETS 12
+#define MSP_KIND_CLASSES (MSP_ROW_BUCKETS * MSP_ROW_BUCKETS)
 
 /* Fills `opt` with the defaults: phase 1, auto kind, no validation,
    inner_ratio 0, no B^T, maskidx_max 8, heap_flops 32, block_flops 8192,
-   split_flops 262144. */
+   split_flops 262144, no kind table. */
 void msp_options_default(msp_options* opt);
 
 /* Plan statistics, filled by msp_plan_info. */

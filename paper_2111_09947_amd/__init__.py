@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import functools
 from typing import Optional
 
 from . import _lib as L
@@ -161,9 +162,23 @@ class _TorchAllocator:
             self.in_use -= t.numel()
 
 
+def kind_table_array(table):
+    """A kind table (a sequence of KIND_CLASSES kind names or ids, or a
+    {(flops_bucket, mask_bucket): kind} dict; None entries and missing classes
+    keep the automatic rules) as the C array msp_options.kind_table reads."""
+    arr = (ctypes.c_int8 * L.KIND_CLASSES)(*([-1] * L.KIND_CLASSES))
+    items = table.items() if isinstance(table, dict) else enumerate(table)
+    for key, kind in items:
+        c = key[0] * L.ROW_BUCKETS + key[1] if isinstance(key, tuple) else int(key)
+        arr[c] = KINDS[kind] if (kind is None or isinstance(kind, str)) else int(kind)
+    return arr
+
+
 def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio: int = 0,
             b_transpose: Optional[L.MspCsr] = None, maskidx_max: int = -1,
-            block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1) -> L.MspOptions:
+            block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1, kind_table=None) -> L.MspOptions:
+    """msp_options; `kind_table`: see kind_table_array (the array is kept on
+    the returned structure while it lives)."""
     o = L.MspOptions()
     L.load().msp_options_default(ctypes.byref(o))
     o.phase = int(phase)
@@ -176,6 +191,9 @@ def options(phase: int = 1, force_kind=None, validate: bool = False, inner_ratio
     o.heap_flops = int(heap_flops)
     if b_transpose is not None:
         o.b_transpose = ctypes.pointer(b_transpose)
+    if kind_table is not None:
+        o._table = kind_table_array(kind_table)
+        o.kind_table = ctypes.cast(o._table, ctypes.POINTER(ctypes.c_int8))
     return o
 
 
@@ -188,10 +206,11 @@ class Plan:
                  semiring: str = "plus_times_f64", phase: int = 1, force_kind=None,
                  validate: bool = False, inner_ratio: int = 0, b_transpose: Optional[DeviceCSR] = None,
                  maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1,
-                 alloc=None):
+                 alloc=None, kind_table=None):
         """`alloc(nbytes)`: optional source of the workspaces (a uint8 device
         tensor on a 256-byte boundary, kept alive by the caller while the plan
-        is used); default: torch's caching allocator."""
+        is used); default: torch's caching allocator. `kind_table`: a kind
+        per row class (see kind_table_array)."""
         lib = L.load()
         self.semiring = semiring
         self.A, self.B, self.M = A, B, M
@@ -199,11 +218,11 @@ class Plan:
         self._bt = None if b_transpose is None else _view(b_transpose, semiring, "B^T")
         self._bt_keep = b_transpose
         self._opt = options(phase, force_kind, validate, inner_ratio, self._bt, maskidx_max, block_flops,
-                            split_flops, heap_flops)
+                            split_flops, heap_flops, kind_table)
         self.phase = phase
         self.nrows, self.ncols = A.nrows, B.ncols
         self.device = A.rowptr.device
-        self._alloc = alloc if alloc is not None else (lambda n: _workspace(n, self.device))
+        self._alloc = alloc if alloc is not None else functools.partial(_workspace, device=self.device)
         cv = int(bool(complement))
         nb = ctypes.c_size_t(0)
         _check(lib.msp_plan_workspace_size(*(ctypes.byref(v) for v in self._views), cv, SEMIRINGS[semiring],
@@ -562,8 +581,9 @@ class Batch:
 
     def __init__(self, problems, semiring: str = "plus_times_f64", force_kind=None, inner_ratio: int = 0,
                  maskidx_max: int = -1, block_flops: int = -1, split_flops: int = -1, heap_flops: int = -1,
-                 alloc=None):
-        """`alloc(nbytes)`: optional source of the workspaces (as for Plan)."""
+                 alloc=None, kind_table=None):
+        """`alloc(nbytes)`: optional source of the workspaces (as for Plan);
+        `kind_table`: a kind per row class (see kind_table_array)."""
         lib = L.load()
         self.semiring = semiring
         self.problems = list(problems)
@@ -576,13 +596,13 @@ class Batch:
             arr[p].complement = int(bool(comp))
         self._arr = arr
         self._opt = options(1, force_kind, False, inner_ratio, None, maskidx_max, block_flops, split_flops,
-                            heap_flops)
+                            heap_flops, kind_table)
         self.device = self.problems[0][0].rowptr.device if n else None
         nb = ctypes.c_size_t(0)
         _check(lib.msp_batch_workspace_size(arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt), ctypes.byref(nb)),
                "msp_batch_workspace_size")
         self.plan_workspace_bytes = nb.value
-        self._alloc = alloc if alloc is not None else (lambda n: _workspace(n, self.device))
+        self._alloc = alloc if alloc is not None else functools.partial(_workspace, device=self.device)
         self._pws = self._alloc(nb.value)
         h = ctypes.c_void_p()
         _check(lib.msp_batch_create(ctypes.byref(h), arr, n, SEMIRINGS[semiring], ctypes.byref(self._opt),

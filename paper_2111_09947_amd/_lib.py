@@ -23,7 +23,12 @@ class MspCsrOut(ctypes.Structure):
 class MspOptions(ctypes.Structure):
     _fields_ = [("phase", c_i32), ("force_kind", c_i32), ("validate", c_i32),
                 ("inner_ratio", c_i32), ("b_transpose", ctypes.POINTER(MspCsr)),
-                ("maskidx_max", c_i32), ("heap_flops", c_i32), ("block_flops", c_i64), ("split_flops", c_i64)]
+                ("maskidx_max", c_i32), ("heap_flops", c_i32), ("block_flops", c_i64), ("split_flops", c_i64),
+                ("kind_table", ctypes.POINTER(ctypes.c_int8))]
+
+
+ROW_BUCKETS = 12
+KIND_CLASSES = ROW_BUCKETS * ROW_BUCKETS
 
 
 class MspPlanInfo(ctypes.Structure):

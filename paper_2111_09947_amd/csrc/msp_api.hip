@@ -193,6 +193,8 @@ struct msp_plan {
     hipStream_t graph_stream = nullptr;
     bool symbolic_done = false;
     int64_t sym_nnz = -1;  // nnz(C) when msp_symbolic read it back
+    bool has_table = false;  // the caller's kind per row class (copied at creation)
+    int8_t kind_table[MSP_KIND_CLASSES] = {};
 
     void release() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -215,6 +217,7 @@ void msp_options_default(msp_options* opt) {
     opt->heap_flops = -1;
     opt->block_flops = -1;
     opt->split_flops = -1;
+    opt->kind_table = nullptr;
 }
 
 const char* msp_status_string(msp_status s) {
@@ -258,6 +261,17 @@ static msp_status plan_setup(msp_plan* P, const msp_problem* probs, int64_t coun
     if (o.split_flops < 0) o.split_flops = DEFAULT_SPLIT_FLOPS;
     if (o.heap_flops < 0) o.heap_flops = DEFAULT_HEAP_FLOPS;
     if (count > 1 && o.b_transpose) return fail(MSP_ERR_UNSUPPORTED, "b_transpose applies to a single product");
+    P->has_table = o.kind_table != nullptr;
+    bool table_inner = false;
+    if (o.kind_table) {
+        for (int c = 0; c < MSP_KIND_CLASSES; ++c) {
+            const int8_t t = o.kind_table[c];
+            if (t < MSP_KIND_AUTO || t > MSP_KIND_HEAP) return fail(MSP_ERR_INVALID_ARGUMENT, "unknown kind in kind_table");
+            P->kind_table[c] = t;
+            table_inner = table_inner || t == MSP_KIND_INNER;
+        }
+        o.kind_table = nullptr;  // the plan keeps its own copy
+    }
     int64_t R = 0;
     P->prods.assign((size_t)count, Product{});
     for (int64_t p = 0; p < count; ++p) {
@@ -292,7 +306,8 @@ static msp_status plan_setup(msp_plan* P, const msp_problem* probs, int64_t coun
     P->opt = o;
     P->P = count;
     P->R = R;
-    P->inner_any = o.force_kind == MSP_KIND_INNER || (o.force_kind == MSP_KIND_AUTO && o.inner_ratio > 0);
+    P->inner_any = o.force_kind == MSP_KIND_INNER ||
+                   (o.force_kind == MSP_KIND_AUTO && (o.inner_ratio > 0 || table_inner));
     return MSP_OK;
 }
 
@@ -520,6 +535,8 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         aa.block_flops = o.block_flops;
         aa.split_flops = o.split_flops;
         aa.heap_flops = o.heap_flops;
+        aa.has_table = P->has_table && o.force_kind == MSP_KIND_AUTO;
+        std::memcpy(aa.kind_table, P->kind_table, sizeof(aa.kind_table));
         aa.colcnt_rp = pr.op.BTrp;
         aa.a_nnz = pr.nnzA;
         aa.m_nnz = pr.nnzM;

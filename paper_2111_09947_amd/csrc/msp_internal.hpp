@@ -99,6 +99,7 @@ constexpr int64_t DEFAULT_SPLIT_FLOPS = 262144;  // dense rows with more product
 // first (bucket b holds rows with 4^b <= flops < 4^(b+1)), so that the
 // longest units start first and do not form the tail of the launch.
 constexpr int NBUCKET = 12;
+static_assert(NBUCKET == MSP_ROW_BUCKETS, "row classes use the flops buckets");
 
 // Device statistics written by the analysis kernel (one sync reads them).
 enum Stat : int {
@@ -135,6 +136,8 @@ struct AnalysisArgs {
     int64_t block_flops;
     int64_t split_flops;
     int64_t heap_flops;        // auto: HEAP for fitting rows with at most this many products (0 = never)
+    int has_table;             // auto: kind_table holds a kind per row class
+    int8_t kind_table[MSP_KIND_CLASSES];
     const int64_t* colcnt_rp;  // row pointers of B^T (column counts of B) or null
     int64_t a_nnz;             // nnz(A), nnz(M)
     int64_t m_nnz;

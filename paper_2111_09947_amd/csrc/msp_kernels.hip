@@ -231,10 +231,17 @@ __device__ __forceinline__ int64_t cdiv(int64_t x, int64_t y) { return (x + y - 
 // Accumulator kind and tiling of one row (auto or forced). alen = nnz(A(i,:)).
 __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, int comp, int force, int inner_ratio,
                         int maskidx_max, int64_t block_flops, int64_t split_flops, int64_t heap_flops,
-                        int64_t icost, int& bin, int64_t& tiles) {
+                        int64_t icost, const int8_t* table, int& bin, int64_t& tiles) {
     // the heap holds one iterator per entry of A's row; other rows take the automatic choice
     const bool heap_fits = alen <= HEAP_CAP && flops <= HEAP_MAX_FLOPS;
     int kind = force == MSP_KIND_HEAP && !heap_fits ? (int)MSP_KIND_AUTO : force;
+    // a tuned kind for the row's class (products bucket x mask-length bucket), where it fits the row
+    if (kind == MSP_KIND_AUTO && table) {
+        const int t = table[flops_bucket(flops) * NBUCKET + flops_bucket(mnnz)];
+        const bool fits = t >= 0 && t <= MSP_KIND_HEAP && (!comp || t == MSP_KIND_DENSE || t == MSP_KIND_HEAP) &&
+                          (t != MSP_KIND_HEAP || heap_fits);
+        if (fits) kind = t;
+    }
     // Auto: very light rows are merged one row per lane (a wave-wide kind would leave most of its
     // lanes idle on them), and so are somewhat heavier rows whose mask row is much longer than
     // their product count (the other kinds spend time per mask entry). Matrices of at most 512
@@ -338,7 +345,8 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
             int bin = -1;
             if (ub > 0) {
                 classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
-                         a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost, bin, tiles);
+                         a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost,
+                         a.has_table ? a.kind_table : nullptr, bin, tiles);
                 if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
                 if (bin == BIN_HEAP_L && o.complement) atomicAdd(&sst[ST_HEAP_APART], 1ull);
                 if (bin == BIN_HEAP_LM && mnnz > MASKIDX_B_CAP) atomicAdd(&sst[ST_HEAPLM_APART], 1ull);

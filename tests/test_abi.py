@@ -163,3 +163,27 @@ def test_iterated_products_need_an_allocator():
     assert lib.msp_ktruss(ctypes.byref(A), 3, ctypes.c_void_p(8), None, None, ctypes.byref(n), None, None, None) == 1
     assert lib.msp_bc_batch(ctypes.byref(A), src, 1, ctypes.c_void_p(8), None, None, None) == 1
     assert b"allocator" in lib.msp_last_error()
+
+
+def test_kind_table_is_checked_on_the_host():
+    """A kind table entry outside the kinds is refused at plan creation (no
+    GPU work): the table is copied and validated on the host."""
+    lib, L = _lib()
+    small = [_csr(L, 100, 50, 10), _csr(L, 50, 60, 10), _csr(L, 100, 60, 10)]
+    o = L.MspOptions()
+    lib.msp_options_default(ctypes.byref(o))
+    assert not o.kind_table
+    arr = (ctypes.c_int8 * L.KIND_CLASSES)(*([-1] * L.KIND_CLASSES))
+    arr[17] = 9
+    o.kind_table = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int8))
+    sz = ctypes.c_size_t(0)
+    st = lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in small), 0, 0, ctypes.byref(o), ctypes.byref(sz))
+    assert st == 1 and b"kind_table" in lib.msp_last_error()
+    arr[17] = 3  # INNER in the table: the plan workspace then holds B^T
+    assert lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in small), 0, 0, ctypes.byref(o),
+                                       ctypes.byref(sz)) == 0
+    with_bt = sz.value
+    arr[17] = 1
+    assert lib.msp_plan_workspace_size(*(ctypes.byref(x) for x in small), 0, 0, ctypes.byref(o),
+                                       ctypes.byref(sz)) == 0
+    assert with_bt > sz.value

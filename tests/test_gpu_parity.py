@@ -429,3 +429,18 @@ def test_timing_session_without_per_execution_sync():
         n = int(rp[-1].item())
         assert_same(msp().DeviceCSR(A.nrows, B.ncols, rp, ci[:n], v[:n]), R, "plus_times_f64")
     T.close()
+
+
+@pytest.mark.parametrize("comp", [False, True])
+@pytest.mark.parametrize("rot", [0, 1, 2, 3, 4])
+def test_kind_table_per_row_class(comp, rot):
+    """Every row class forced to a kind by the table (kinds rotating over
+    the classes); entries that do not fit a row (complemented masks,
+    oversized heap rows) fall back to the rules. Same result as the oracle."""
+    m = msp()
+    sr = "plus_times_f64"
+    A, B, M = rand_problem(90 + rot, 700, 500, 6000, 6.0, 7.0, 60.0, sr)
+    kinds = ["dense", "hash", "maskidx", "inner", "heap"]
+    table = {c: kinds[(c + rot) % 5] for c in range(144)}
+    C = m.masked_spgemm(up(A, sr), up(B, sr), up(M), complement=comp, semiring=sr, kind_table=table)
+    assert_same(C, oracle.masked_spgemm(A, B, M, comp, sr), sr)

@@ -144,3 +144,30 @@ def test_iterated_products_take_memory_from_the_caller():
     assert info["peak_device_bytes"] > 0
     bc, binfo = m.bc_batch(up(G), np.arange(16))
     assert binfo["peak_device_bytes"] > 0
+
+
+def test_plans_and_batches_free_their_memory_without_the_cycle_collector():
+    """A Plan or Batch dropped by the caller releases its workspaces (and a
+    batch its outputs) at once: no reference cycle keeps them until the
+    cyclic garbage collector runs."""
+    import gc
+    import weakref
+    m = msp()
+    sr = "plus_times_f64"
+    A, B, M = rand_problem(44, 300, 200, 400, 5.0, 6.0, 30.0, sr)
+    d = (up(A, sr), up(B, sr), up(M))
+    gc.disable()
+    try:
+        p = m.Plan(*d, semiring=sr)
+        p.execute()
+        ref = weakref.ref(p)
+        del p
+        assert ref() is None
+        b = m.Batch([d + (False,), d + (False,)], semiring=sr)
+        b.bind_new_outputs()
+        b.execute()
+        ref = weakref.ref(b)
+        del b
+        assert ref() is None
+    finally:
+        gc.enable()
