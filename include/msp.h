@@ -181,7 +181,9 @@ typedef struct msp_options {
     int64_t block_flops;  /* rows with more products than this run on a whole
                              workgroup (256 threads; 512 for mask-indexed
                              rows of at least 65536 products) instead of
-                             one wavefront (-1 = default 8192) */
+                             one wavefront, except dense-kind rows of
+                             matrices of at most 512 columns, which do so
+                             only above 32 times this (-1 = default 8192) */
     int64_t split_flops;  /* dense-kind rows (at most 4096 columns) with more
                              products than this are split over several
                              workgroups by chunks of A's row (-1 = default

@@ -93,6 +93,13 @@ __host__ __device__ inline int bin_at(int x) {
 }
 constexpr int DEFAULT_MASKIDX_MAX = 8;       // auto: binary search up to this mask size, hash above
 constexpr int64_t DEFAULT_BLOCK_FLOPS = 8192;  // rows with more products run on a whole block
+// ... except dense-kind rows of matrices with at most DENSE_W_COLS columns,
+// which take a block only above this many times block_flops products: the
+// one-wave tile of 512 columns needs no block barriers and its per-row setup
+// is small, and on the 512-source BFS step one wave per row measured faster
+// up to the split threshold (6.20 against 6.39 ms a step with int32 path
+// counts, 5.57 against 5.96 ms boolean).
+constexpr int64_t DENSE_NARROW_BLOCK_MULT = 32;
 constexpr int DEFAULT_HEAP_FLOPS = 32;           // auto: HEAP for fitting rows with at most this many products
 constexpr int64_t DEFAULT_SPLIT_FLOPS = 262144;  // dense rows with more products split over several blocks
 // Units of a bin are ordered by the product count of their row, heaviest

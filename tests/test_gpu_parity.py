@@ -444,3 +444,18 @@ def test_kind_table_per_row_class(comp, rot):
     table = {c: kinds[(c + rot) % 5] for c in range(144)}
     C = m.masked_spgemm(up(A, sr), up(B, sr), up(M), complement=comp, semiring=sr, kind_table=table)
     assert_same(C, oracle.masked_spgemm(A, B, M, comp, sr), sr)
+
+
+@pytest.mark.parametrize("sr", ["plus_times_i32", "lor_land_bool", "plus_times_f64"])
+def test_narrow_dense_rows_on_a_block(sr):
+    """Dense rows of a matrix of at most 512 columns run on a block only
+    above 32 x block_flops products: a small block_flops (and no split)
+    sends the heavy rows there, under both mask modes."""
+    m = msp()
+    A, B, M = rand_problem(97, 900, 700, 480, 30.0, 40.0, 120.0, sr)
+    for comp in (False, True):
+        with m.Plan(up(A, sr), up(B, sr), up(M), complement=comp, semiring=sr, force_kind="dense",
+                    block_flops=36, split_flops=0) as p:
+            assert p.bin_units["dense_block_narrow"] > 0 and p.bin_units["dense_wave"] > 0
+            C = p.execute()
+        assert_same(C, oracle.masked_spgemm(A, B, M, comp, sr), sr)
