@@ -81,10 +81,11 @@ def device_info(dev):
     return {k: getattr(p, k) for k in keys if hasattr(p, k)}
 
 
-def other_stages(make_plan, nrows, dtype, stage_ms, steps, dev, runs=2):
+def other_stages(make_plan, nrows, dtype, stage_ms, steps, dev, runs=2, keep=None):
     """Times the stages other than the kernel bins (scans, row pointers,
-    compaction, split emission) in `runs` untimed profiled executions and
-    stores them in stage_ms scaled to `steps` steps."""
+    compaction, split emission), and the bins other than `keep` (the stage
+    timed live), in `runs` untimed profiled executions and stores them in
+    stage_ms scaled to `steps` steps."""
     import torch
 
     import paper_2111_09947_amd as msp
@@ -95,8 +96,13 @@ def other_stages(make_plan, nrows, dtype, stage_ms, steps, dev, runs=2):
             p.execute_profiled(torch.empty(nrows + 1, dtype=torch.int64, device=dev),
                                torch.empty(cap, dtype=torch.int32, device=dev),
                                torch.empty(cap, dtype=dtype, device=dev), cap, extra)
-    nb = len(msp.BIN_NAMES)
-    stage_ms[nb:] = extra[nb:] / runs * steps
+    if keep is None:
+        nb = len(msp.BIN_NAMES)
+        stage_ms[nb:] = extra[nb:] / runs * steps
+    else:
+        for x in range(len(stage_ms)):
+            if x != keep:
+                stage_ms[x] = extra[x] / runs * steps
 
 
 def row_quantities(L):
@@ -308,18 +314,20 @@ def row_flops(A, Bdeg):
 
 def time_steps(dA, dB, dM, comp, sr, steps, warmup, kw, post=None):
     """Times `steps` whole steps (plan creation, execution, and `post`) after
-    `warmup` untimed ones. The kernel bins' HIP events are recorded into a
-    timing session during the timed steps and read after them; the other
-    stages come from untimed profiled executions. Returns a dict with the
-    step time, stage times per step, plan-creation and cold-step times and
-    the last step's output (device tensors)."""
+    `warmup` untimed ones. The warm-up steps time every kernel bin to find
+    the dominant one; the timed steps record HIP events on the dominant
+    bin's launches only (an event pair costs the step several microseconds)
+    into a timing session read after them. The other stages come from
+    untimed profiled executions. Returns a dict with the step time, stage
+    times per step, plan-creation and cold-step times and the last step's
+    output (device tensors)."""
     import torch
 
     import paper_2111_09947_amd as msp
     dev = dA.rowptr.device
     odt = msp.out_dtype(sr)
     stage_ms = np.zeros(len(msp.STAGE_NAMES), dtype=np.float64)
-    timing = msp.Timing(max(steps, warmup), stages=msp.BIN_NAMES)
+    timing = msp.Timing(max(warmup, 1), stages=msp.BIN_NAMES)
 
     def step(timed=True):
         with msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw) as p:  # the plan's one synchronization
@@ -335,10 +343,13 @@ def time_steps(dA, dB, dM, comp, sr, steps, warmup, kw, post=None):
                 post(rp, v)
             return rp, ci, v
 
-    for _ in range(warmup):
+    for _ in range(max(warmup, 1)):
         step()
     torch.cuda.synchronize()
-    timing.collect(np.zeros_like(stage_ms))  # warm-up stages are not counted
+    warm_ms = timing.collect(np.zeros_like(stage_ms))
+    timing.close()
+    dom = int(np.argmax(warm_ms[:len(msp.BIN_NAMES)]))
+    timing = msp.Timing(steps, stages=[msp.BIN_NAMES[dom]])
     t0 = time.perf_counter()
     for _ in range(steps):
         out = step()
@@ -347,7 +358,7 @@ def time_steps(dA, dB, dM, comp, sr, steps, warmup, kw, post=None):
     timing.collect(stage_ms)
     timing.close()
     other_stages(lambda: msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw), dA.nrows, odt, stage_ms, steps,
-                 dev)
+                 dev, keep=dom)
     plan_ms = []
     for _ in range(3):  # plan creation alone (in a step it also waits for the previous step)
         torch.cuda.synchronize()
@@ -367,7 +378,7 @@ def time_steps(dA, dB, dM, comp, sr, steps, warmup, kw, post=None):
     del flush
     with msp.Plan(dA, dB, dM, complement=comp, semiring=sr, **kw) as p:
         bins, bin_units, products = p.row_bins(), p.bin_units, p.products
-    return {"ms": ms, "stage_ms": stage_ms / steps, "plan_ms": float(np.median(plan_ms)),
+    return {"ms": ms, "stage_ms": stage_ms / steps, "dom": dom, "plan_ms": float(np.median(plan_ms)),
             "cold_ms": float(np.median(cold_ms)), "out": out, "bins": bins, "bin_units": bin_units,
             "products": int(products)}
 
@@ -383,13 +394,13 @@ def useful_rows(dA, dB, dM, comp):
 
 
 def roofline_record(t, per_row, traffic_key):
-    """The dominant kernel bin (largest time per step): its rows' algorithmic
-    bytes per launch over its HIP-event time, against the HBM peak; the
-    counter-measured HBM bytes per launch (calibrated, same kernel source)
-    when a traffic summary exists for it."""
+    """The dominant kernel bin (largest time per step, timed live in the
+    timed steps): its rows' algorithmic bytes per launch over its HIP-event
+    time, against the HBM peak; the counter-measured HBM bytes per launch
+    (calibrated, same kernel source) when a traffic summary exists for it."""
     import paper_2111_09947_amd as msp
     bin_ms = t["stage_ms"][:len(msp.BIN_NAMES)]
-    dom = int(np.argmax(bin_ms))
+    dom = t["dom"]
     name = msp.BIN_NAMES[dom]
     dom_bytes = int(per_row[t["bins"] == dom].sum())
     dom_ms = float(bin_ms[dom])
