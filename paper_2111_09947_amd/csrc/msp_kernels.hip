@@ -1206,6 +1206,16 @@ __device__ __forceinline__ int hash_find(const int4* tkey, const uint16_t* trank
 // full lane occupancy instead of once per product. The ring is drained at
 // the end of every batch of A entries (candidates refer to that batch's A
 // values).
+// Search kind, exact-bitmap mode: when the tile's keys span at most
+// 32 * FILTER_WORDS columns, the filter words instead hold an exact bitmap of
+// the keys over [first key, last key], and a per-word prefix count of the
+// set bits (2-byte counts, in the otherwise unused candidate rings) gives a
+// key's rank in O(1): rank(j) = prefix[w] + popcount(word w below bit b).
+// A product is then tested and, on a hit, folded straight away, with no
+// candidate ring and no binary search. Masks that are dense within their
+// column range (the batch's masks of 10% to 80% density, the hub rows of
+// k-truss) take this mode; sparse, widely spread mask rows keep the filter
+// and the searches.
 // Hash table size: buckets of four slots, at least (keys >> shift) of them.
 // Shift 1 fills at most half of the slots, in half the LDS of shift 0: one
 // more workgroup of the 512-key block kernel per CU, which outweighs the
@@ -1278,6 +1288,13 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     const int64_t mnnz = o.Mrp[i + 1] - mrow;
     const int cnt = (int)min((int64_t)CAP, mnnz - r0);
     const bool tiled = mnnz > CAP;
+    // the tile's column range; an exact bitmap of it fits the filter words (search kind only)
+    const int32_t lo = __builtin_amdgcn_readfirstlane(o.Mci[mrow + r0]);
+    const int32_t hi = __builtin_amdgcn_readfirstlane(o.Mci[mrow + r0 + cnt - 1]);
+    const uint32_t span = (uint32_t)(hi - lo) + 1u;
+    const bool bmp = !HASHED && span <= 32u * (uint32_t)FW;
+    static_assert(2 * FW <= 4 * NW * (QCAP + WAVE), "the prefix counts fit the unit's candidate rings");
+    uint16_t* pre = reinterpret_cast<uint16_t*>(qj_[gi * NW]);  // the unit's rings, contiguous
     for (int x = ut; x < cnt; x += UT) {
         keys[x] = o.Mci[mrow + r0 + x];
         if (!COUNT) vals[x] = T::identity();
@@ -1290,7 +1307,8 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     const uint32_t bmask = (1u << hbits) - 1u;
     // the filter uses about one word (32 bits) per key: at most 1 bit in 32 set
     const int fwb = min(bbits, FW_BITS);
-    for (int x = ut; x < (1 << fwb); x += UT) filt[x] = 0u;
+    const int nbw = (int)((span + 31u) >> 5);  // bitmap words (exact-bitmap mode)
+    for (int x = ut; x < (bmp ? nbw : (1 << fwb)); x += UT) filt[x] = 0u;
     if (HASHED)
         for (int x = ut; x <= (int)bmask; x += UT) tkey[x] = make_int4(-1, -1, -1, -1);
     if (lane() < STREAM_U) st[wave].S[lane()] = 0ull;
@@ -1298,6 +1316,11 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     unit_sync<NW>();
     for (int x = ut; x < cnt; x += UT) {
         const int32_t key = keys[x];
+        if (bmp) {
+            const uint32_t d = (uint32_t)(key - lo);
+            atomicOr(&filt[d >> 5], 1u << (d & 31));
+            continue;
+        }
         atomicOr(&filt[(key >> 5) & ((1 << fwb) - 1)], 1u << (key & 31));
         if (HASHED) {
             int32_t* slots = reinterpret_cast<int32_t*>(tkey);
@@ -1310,7 +1333,19 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
         }
     }
     unit_sync<NW>();
-    const int32_t lo = keys[0], hi = keys[cnt - 1];
+    if (bmp) {  // prefix counts of the bitmap words: each thread takes a run of consecutive words
+        const int per = (nbw + UT - 1) / UT;
+        const int w0 = min(ut * per, nbw), w1 = min(w0 + per, nbw);
+        int64_t c = 0;
+        for (int w = w0; w < w1; ++w) c += __popc(filt[w]);
+        int64_t total;
+        int64_t run = block_excl_scan<NW>(c, tmp, total);
+        for (int w = w0; w < w1; ++w) {
+            pre[w] = (uint16_t)run;
+            run += __popc(filt[w]);
+        }
+        unit_sync<NW>();
+    }
     const int top = 1 << (31 - __clz(cnt));
     StanzaLds<T>& S = st[wave];
     const ValAddr<T::vbytes> va(o.Bv, o.Bci);
@@ -1337,6 +1372,25 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     stream_products<T>(
         o, o.Arp[i], o.Arp[i + 1], tiled, lo, hi, wv, NW, S,
         [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
+            if (!HASHED && bmp) {  // exact bitmap: rank by prefix count, fold at once
+                int r[STREAM_U];
+                uint32_t bw[STREAM_U];
+#pragma unroll
+                for (int u = 0; u < STREAM_U; ++u) {
+                    const uint32_t d = (uint32_t)(j[u] - lo);
+                    const bool in = act[u] && d < span;
+                    bw[u] = in ? filt[d >> 5] : 0u;
+                    r[u] = in && ((bw[u] >> (d & 31)) & 1u) ? (int)(d >> 5) : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < STREAM_U; ++u)
+                    if (r[u] >= 0) {
+                        const uint32_t d = (uint32_t)(j[u] - lo);
+                        r[u] = (int)pre[r[u]] + __popc(bw[u] & ((1u << (d & 31)) - 1u));
+                    }
+                window_accumulate<T, FLAGS, COUNT>(r, s, cb, o, S, vals, flags);
+                return;
+            }
             uint32_t w[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) w[u] = filt[__builtin_amdgcn_ubfe((uint32_t)j[u], 5, (uint32_t)fwb)];
