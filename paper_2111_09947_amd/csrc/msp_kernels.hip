@@ -1207,15 +1207,22 @@ __device__ __forceinline__ int hash_find(const int4* tkey, const uint16_t* trank
 // the end of every batch of A entries (candidates refer to that batch's A
 // values).
 // Search kind, exact-bitmap mode: when the tile's keys span at most
-// 32 * FILTER_WORDS columns, the filter words instead hold an exact bitmap of
-// the keys over [first key, last key], and a per-word prefix count of the
-// set bits (2-byte counts, in the otherwise unused candidate rings) gives a
-// key's rank in O(1): rank(j) = prefix[w] + popcount(word w below bit b).
-// A product is then tested and, on a hit, folded straight away, with no
-// candidate ring and no binary search. Masks that are dense within their
-// column range (the batch's masks of 10% to 80% density, the hub rows of
-// k-truss) take this mode; sparse, widely spread mask rows keep the filter
-// and the searches.
+// 32 * FILTER_WORDS columns and at most BMP_SPAN_PER_KEY columns per key, the
+// filter words instead hold an exact bitmap of the keys over [first key,
+// last key], and a per-word prefix count of the set bits (2-byte counts, in
+// the otherwise unused candidate rings) gives a key's rank in O(1):
+// rank(j) = prefix[w] + popcount(word w below bit b). A product is then
+// tested and, on a hit, folded straight away, with no candidate ring and no
+// binary search. That pays where hits are frequent: masks dense within
+// their column range (the batch's masks of 10% to 80% density, the hub rows
+// of k-truss). Where few products hit (triangle counting: 2% in its light
+// rows, 18% in its heavy ones), folding slot by slot issues a wave-wide LDS
+// atomic per slot for a few lanes, and the candidate ring, which gathers the
+// hits into full rounds, is faster: such rows, and the hash kind, keep the
+// filter and the lookups (measured: triangle counting's hash_block 0.397
+// against 0.431 ms with the bitmap mode). The one-wave search kernel has no
+// bitmap mode at all: its code alone cost triangle counting's light rows 3%.
+constexpr uint32_t BMP_SPAN_PER_KEY = 16;
 // Hash table size: buckets of four slots, at least (keys >> shift) of them.
 // Shift 1 fills at most half of the slots, in half the LDS of shift 0: one
 // more workgroup of the 512-key block kernel per CU, which outweighs the
@@ -1288,11 +1295,13 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     const int64_t mnnz = o.Mrp[i + 1] - mrow;
     const int cnt = (int)min((int64_t)CAP, mnnz - r0);
     const bool tiled = mnnz > CAP;
-    // the tile's column range; an exact bitmap of it fits the filter words (search kind only)
+    // the tile's column range; an exact bitmap of it may fit the filter words
     const int32_t lo = __builtin_amdgcn_readfirstlane(o.Mci[mrow + r0]);
     const int32_t hi = __builtin_amdgcn_readfirstlane(o.Mci[mrow + r0 + cnt - 1]);
     const uint32_t span = (uint32_t)(hi - lo) + 1u;
-    const bool bmp = !HASHED && span <= 32u * (uint32_t)FW;
+    // (the one-wave kernels have tiles of at most 256 keys, whose rows are light: they keep the ring)
+    constexpr bool BMP_OK = !HASHED && CAP > 256;
+    const bool bmp = BMP_OK && span <= 32u * (uint32_t)FW && span <= BMP_SPAN_PER_KEY * (uint32_t)cnt;
     static_assert(2 * FW <= 4 * NW * (QCAP + WAVE), "the prefix counts fit the unit's candidate rings");
     uint16_t* pre = reinterpret_cast<uint16_t*>(qj_[gi * NW]);  // the unit's rings, contiguous
     for (int x = ut; x < cnt; x += UT) {
