@@ -326,10 +326,23 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
 // two blocks update one address: k_segoff adds them up.
 __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
     static_assert(ANA_T == ANA_ROWS, "one row per thread and chunk");
+    static_assert(MSP_KIND_CLASSES % 4 == 0 && MSP_KIND_CLASSES / 4 <= ANA_T, "the kind table: whole words");
     __shared__ unsigned long long sst[ST_COUNT];
+    __shared__ uint32_t table_w[MSP_KIND_CLASSES / 4];
     const Operands& o = a.op;
     for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) sst[x] = 0;
+    // the kind table moves to LDS word by word with constant indices: indexing the argument
+    // block with a lane-dependent index would copy all of it to per-lane scratch memory
+    if (a.has_table) {
+#pragma unroll
+        for (int x = 0; x < MSP_KIND_CLASSES / 4; ++x) {
+            uint32_t w;
+            __builtin_memcpy(&w, &a.kind_table[4 * x], 4);
+            if (threadIdx.x == x) table_w[x] = w;
+        }
+    }
     __syncthreads();
+    const int8_t* table = a.has_table ? reinterpret_cast<const int8_t*>(table_w) : nullptr;
     for (int64_t r0 = (int64_t)blockIdx.x * ANA_T; r0 < o.m; r0 += (int64_t)gridDim.x * ANA_T) {
         const int64_t r1 = min(r0 + ANA_T, o.m);
         const int64_t i = r0 + threadIdx.x;
@@ -346,7 +359,7 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
             if (ub > 0) {
                 classify(mnnz, flops, o.Arp[i + 1] - o.Arp[i], o.n, o.complement, a.force_kind, a.inner_ratio,
                          a.maskidx_max, a.block_flops, a.split_flops, a.heap_flops, icost,
-                         a.has_table ? a.kind_table : nullptr, bin, tiles);
+                         table, bin, tiles);
                 if (bin == BIN_DENSE_SPLIT) atomicAdd(&sst[ST_SPLITROWS], 1ull);
                 if (bin == BIN_HEAP_L && o.complement) atomicAdd(&sst[ST_HEAP_APART], 1ull);
                 if (bin == BIN_HEAP_LM && mnnz > MASKIDX_B_CAP) atomicAdd(&sst[ST_HEAPLM_APART], 1ull);
