@@ -242,7 +242,10 @@ enum {
                                         row of A, merged into a per-row accumulator */
     MSP_BIN_HEAP_LANE = 9,           /* one lane per row, k-way merge (HEAP kind) */
     MSP_BIN_HEAP_LANE_LONG_MASK = 10,  /* the same, normal mask rows of more than 256 entries */
-    MSP_NBINS = 11
+    MSP_BIN_MASKIDX_PACKED = 11,     /* eight lanes per row: normal mask rows of <= 16 entries,
+                                        <= 256 products, <= 32 entries in the row of A
+                                        (automatic choice only) */
+    MSP_NBINS = 12
 };
 
 /* Stage slots of msp_execute_profiled: 0..15 = numeric kernel of bin b,

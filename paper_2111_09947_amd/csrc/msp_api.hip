@@ -810,11 +810,17 @@ struct StageTimer {
         }
         auto& pool = event_pool();
         if (pool.empty()) {
-            MSP_HIP(hipEventCreate(e));
-        } else {
-            *e = pool.back();
-            pool.pop_back();
+            // the events of a whole execution are created at once, before the first of them is
+            // recorded: creating one between a stage's start and stop events would count the
+            // host's creation time in that stage
+            for (int x = 0; x < 2 * MSP_NSTAGES; ++x) {
+                hipEvent_t f = nullptr;
+                MSP_HIP(hipEventCreate(&f));
+                pool.push_back(f);
+            }
         }
+        *e = pool.back();
+        pool.pop_back();
         held.push_back(*e);
         return MSP_OK;
     }
@@ -1351,7 +1357,8 @@ msp_status msp_batch_info(const msp_plan* P, int64_t p, msp_plan_info_t* info) {
         info->kind_units[MSP_KIND_DENSE] += pr.bin_units[BIN_DENSE_W] + pr.bin_units[BIN_DENSE_B] +
                                             pr.bin_units[BIN_DENSE_BN] + pr.bin_units[BIN_DENSE_SPLIT];
         info->kind_units[MSP_KIND_HASH] += pr.bin_units[BIN_HASH_W] + pr.bin_units[BIN_HASH_B];
-        info->kind_units[MSP_KIND_MASKIDX] += pr.bin_units[BIN_MASKIDX_W] + pr.bin_units[BIN_MASKIDX_B];
+        info->kind_units[MSP_KIND_MASKIDX] +=
+            pr.bin_units[BIN_MASKIDX_W] + pr.bin_units[BIN_MASKIDX_B] + pr.bin_units[BIN_MASKIDX_P];
         info->kind_units[MSP_KIND_INNER] += pr.bin_units[BIN_INNER_W];
         info->kind_units[MSP_KIND_HEAP] += pr.bin_units[BIN_HEAP_L] + pr.bin_units[BIN_HEAP_LM];
         for (int b = 0; b < NBINS; ++b) info->bin_units[b] += pr.bin_units[b];

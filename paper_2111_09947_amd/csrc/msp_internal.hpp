@@ -28,7 +28,9 @@ enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_HEAP_L = 9,     // one lane per row, k-way merge of <= HEAP_CAP rows of B by a heap in LDS
                         // (normal masks of <= MASKIDX_W_CAP entries, and complemented masks)
     BIN_HEAP_LM = 10,   // the same for normal masks of more than MASKIDX_W_CAP entries
-    NBINS = 11
+    BIN_MASKIDX_P = 11,  // eight lanes per row, eight rows per wave: short normal mask rows
+                         // (<= PACK_MASK entries), few products (<= PACK_FLOPS), short rows of A
+    NBINS = 12
 };
 
 constexpr int DENSE_W_COLS = 512;
@@ -49,6 +51,15 @@ constexpr int MASKIDX_W_CAP = 256;
 #endif
 constexpr int MASKIDX_B_CAP = MSP_MASKIDX_B_CAP;
 constexpr int INNER_CAP = 256;
+// The packed mask-indexed bin (automatic choice only): a row fits it with a
+// normal mask row of at most PACK_MASK entries, at most PACK_FLOPS products
+// and at most PACK_ALEN entries in its row of A. Such rows take PACK_G lanes
+// each; a wave per row would leave most of its 64 lanes idle on them (an
+// Erdos-Renyi row of degree 8 has 64 products and 8 mask entries).
+constexpr int PACK_G = 8;
+constexpr int PACK_MASK = 16;
+constexpr int PACK_ALEN = 32;
+constexpr int64_t PACK_FLOPS = 256;
 constexpr int INNER_ACAP = 1024;  // A row (column indices) staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 #ifndef MSP_MASKIDX_B_NW
@@ -84,9 +95,11 @@ constexpr int64_t HEAP_LM_FOLD_MAX = 4096;
 // Position x of the unit list holds the units of bin bin_at(x): the bins in
 // numeric order, except that the two heap bins sit between the mask-indexed
 // wave and block bins (wave, heap, heap with long masks, block), so that each
-// heap bin and its mask-indexed neighbour form one contiguous range of units.
+// heap bin and its mask-indexed neighbour form one contiguous range of units;
+// the packed bin comes last.
 __host__ __device__ inline int bin_at(int x) {
-    return x <= BIN_MASKIDX_W ? x
+    return x == BIN_MASKIDX_P ? x
+           : x <= BIN_MASKIDX_W ? x
            : x == BIN_MASKIDX_W + 1 ? (int)BIN_HEAP_L
            : x == BIN_MASKIDX_W + 2 ? (int)BIN_HEAP_LM
            : x - 2;

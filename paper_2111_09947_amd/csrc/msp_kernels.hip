@@ -234,6 +234,9 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
                         int64_t icost, const int8_t* table, int& bin, int64_t& tiles) {
     // the heap holds one iterator per entry of A's row; other rows take the automatic choice
     const bool heap_fits = alen <= HEAP_CAP && flops <= HEAP_MAX_FLOPS;
+    // a light row with a short normal mask row fits eight lanes of a wave (automatic choice only)
+    const bool pack_fits = !comp && mnnz <= PACK_MASK && flops <= PACK_FLOPS && alen <= PACK_ALEN;
+    bool pack = false;
     int kind = force == MSP_KIND_HEAP && !heap_fits ? (int)MSP_KIND_AUTO : force;
     // a tuned kind for the row's class (products bucket x mask-length bucket), where it fits the row
     if (kind == MSP_KIND_AUTO && table) {
@@ -242,13 +245,14 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
                           (t != MSP_KIND_HEAP || heap_fits);
         if (fits) kind = t;
     }
-    // Auto: very light rows are merged one row per lane (a wave-wide kind would leave most of its
-    // lanes idle on them), and so are somewhat heavier rows whose mask row is much longer than
-    // their product count (the other kinds spend time per mask entry). Matrices of at most 512
+    // Auto: light rows with a short normal mask row take eight lanes each in the packed
+    // mask-indexed kernel. Other very light rows are merged one row per lane (a wave-wide kind
+    // would leave most of its lanes idle on them), and so are somewhat heavier rows whose mask row
+    // is much longer than their product count (the other kinds spend time per mask entry). Matrices of at most 512
     // columns keep the one-wave dense tile. Under a complemented mask light rows of a wider one go
     // to the heap, and every fitting row of one wider than a 4096-column tile, which the dense
     // kind would restream once per tile.
-    if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0 && n > DENSE_W_COLS) {
+    if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0 && n > DENSE_W_COLS && !pack_fits) {
         const bool light = flops <= heap_flops;
         if (comp ? (n > DENSE_B_COLS || light)
                  : (light || (flops <= HEAP_LONG_MASK_FLOPS * heap_flops && mnnz >= HEAP_LONG_MASK_RATIO * flops)))
@@ -262,6 +266,7 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
         // has more candidates per lookup round and takes the hash table of a workgroup.
         if (inner_ratio > 0 && icost * (int64_t)inner_ratio < flops) kind = MSP_KIND_INNER;
         else if (n <= DENSE_W_COLS) kind = MSP_KIND_DENSE;
+        else if (pack_fits) { kind = MSP_KIND_MASKIDX; pack = true; }
         else if (mnnz <= maskidx_max || (mnnz <= MASKIDX_W_CAP && !heavy)) kind = MSP_KIND_MASKIDX;
         else if (mnnz <= HASH_B_CAP) kind = MSP_KIND_HASH;
         else kind = MSP_KIND_MASKIDX;
@@ -279,7 +284,8 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
         else { bin = BIN_HASH_B; tiles = cdiv(mnnz, HASH_B_CAP); }
         break;
     case MSP_KIND_MASKIDX:
-        if (mnnz <= MASKIDX_W_CAP && !heavy) { bin = BIN_MASKIDX_W; tiles = 1; }
+        if (pack) { bin = BIN_MASKIDX_P; tiles = 1; }
+        else if (mnnz <= MASKIDX_W_CAP && !heavy) { bin = BIN_MASKIDX_W; tiles = 1; }
         else { bin = BIN_MASKIDX_B; tiles = cdiv(mnnz, MASKIDX_B_CAP); }
         break;
     case MSP_KIND_HEAP:
@@ -313,7 +319,7 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
         break;
     }
     case BIN_HEAP_L: case BIN_HEAP_LM: adm = o.complement ? o.n - mnnz : mnnz; break;
-    case BIN_HASH_W: case BIN_MASKIDX_W: adm = mnnz; break;
+    case BIN_HASH_W: case BIN_MASKIDX_W: case BIN_MASKIDX_P: adm = mnnz; break;
     case BIN_HASH_B: adm = min((int64_t)HASH_B_CAP, mnnz - t * HASH_B_CAP); break;
     case BIN_MASKIDX_B: adm = min((int64_t)MASKIDX_B_CAP, mnnz - t * MASKIDX_B_CAP); break;
     default: adm = min((int64_t)INNER_CAP, mnnz - t * INNER_CAP); break;
@@ -1759,6 +1765,180 @@ __global__ __launch_bounds__(HEAP_T) void k_heap(NumArgs g) {
     if (MODE != MODE_DIRECT) g.cnt[u] = cnt;
 }
 
+// ------------------------------------------------------ packed light rows
+// Rows of the packed bin (a normal mask row of at most PACK_MASK entries, at
+// most PACK_FLOPS products, at most PACK_ALEN entries in the row of A) take a
+// group of PACK_G lanes each, PACK_RPW rows to a wave. The row's mask keys
+// sit sorted in LDS, padded with INT32_MAX to PACK_MASK entries, and a
+// product's rank among them comes from a four-step branch-free binary search
+// (the mask-indexed kind). The row's products, numbered in the order of A's
+// row and then of each B row, go to the group's lanes round-robin (product p
+// to lane p mod PACK_G), PACK_UNR of them in flight per lane; the A entry of
+// product p is the last one whose first product is at most p, found by
+// walking forward a prefix of the B row lengths kept in LDS. A hit folds
+// A's and B's values into the key's slot with an LDS atomic; emission walks
+// the keys in order (two per lane). Each wave works alone: its groups only
+// synchronize through the wave's own LDS accesses.
+constexpr int PACK_RPW = WAVE / PACK_G;  // rows per wave
+constexpr int PACK_WPB = 2;              // waves per block
+constexpr int PACK_UNR = 4;              // products in flight per lane
+static_assert(PACK_MASK == 2 * PACK_G, "two keys per lane; the search takes four steps over 16 keys");
+static_assert(PACK_ALEN % PACK_G == 0, "A entries are dealt to the group's lanes in whole rounds");
+
+// inclusive prefix sum over the PACK_G lanes of a group
+__device__ __forceinline__ int group_incl_scan(int v, int q) {
+#pragma unroll
+    for (int d = 1; d < PACK_G; d <<= 1) {
+        const int y = __shfl_up(v, d, PACK_G);
+        if (q >= d) v += y;
+    }
+    return v;
+}
+
+template <int SR, int MODE, bool BATCH>
+__global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    constexpr bool FLAGS = COUNT || T::sep_flag;
+    constexpr int R = PACK_WPB * PACK_RPW;  // rows per block
+    constexpr int NT = PACK_ALEN / PACK_G;  // A entries per lane
+    __shared__ int32_t keys_[R][PACK_MASK];
+    __shared__ acc_t vals_[COUNT ? 1 : R][COUNT ? 1 : PACK_MASK];
+    __shared__ uint8_t flags_[FLAGS ? R : 1][FLAGS ? PACK_MASK : 1];
+    __shared__ int32_t pre_[R][PACK_ALEN + 1];  // first product of each A entry; pre[alen] = products
+    __shared__ int64_t shift_[R][PACK_ALEN];    // B position of the row's product p in entry s: shift[s] + p
+    const int ln = lane();
+    const int q = ln & (PACK_G - 1);
+    const int r = (int)threadIdx.x / PACK_G;
+    const int64_t uix = (int64_t)blockIdx.x * R + r;
+    const bool live = uix < g.nunits;  // no early exit: the emission takes wave-wide ballots
+    int u = 0;
+    int64_t i = 0;
+    if (live) {
+        u = g.units[uix];
+        i = g.unit_row[u];
+    }
+    // the row's operands (the groups of one wave may belong to different products of a batch)
+    const int64_t* Arp;
+    const int32_t* Aci;
+    const void* Av;
+    const int64_t* Brp;
+    const int32_t* Bci;
+    const void* Bv;
+    const int64_t* Mrp;
+    const int32_t* Mci;
+    if constexpr (BATCH) {
+        const Operands& o = g.ops[live ? g.unit_prob[u] : 0];
+        Arp = o.Arp; Aci = o.Aci; Av = o.Av; Brp = o.Brp; Bci = o.Bci; Bv = o.Bv; Mrp = o.Mrp; Mci = o.Mci;
+    } else {
+        Arp = g.op.Arp; Aci = g.op.Aci; Av = g.op.Av; Brp = g.op.Brp; Bci = g.op.Bci; Bv = g.op.Bv;
+        Mrp = g.op.Mrp; Mci = g.op.Mci;
+    }
+    int64_t pa0 = 0, m0 = 0;
+    int alen = 0, mcnt = 0;  // <= PACK_ALEN and <= PACK_MASK by classification
+    if (live) {
+        pa0 = Arp[i];
+        alen = (int)(Arp[i + 1] - pa0);
+        m0 = Mrp[i];
+        mcnt = (int)(Mrp[i + 1] - m0);
+    }
+    int32_t* keys = keys_[r];
+    acc_t* vals = vals_[COUNT ? 0 : r];
+    uint8_t* flags = flags_[FLAGS ? r : 0];
+    int32_t* pre = pre_[r];
+    int64_t* shift = shift_[r];
+#pragma unroll
+    for (int t = 0; t < PACK_MASK / PACK_G; ++t) {
+        const int x = q + t * PACK_G;
+        keys[x] = x < mcnt ? Mci[m0 + x] : INT32_MAX;
+        if (!COUNT) vals[x] = T::identity();
+        if (FLAGS) flags[x] = 0;
+    }
+    // entry e = q + PACK_G * t of A's row: its B row [b0, b0 + len)
+    int len[NT];
+    int64_t b0[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int e = q + t * PACK_G;
+        int32_t k = 0;
+        if (e < alen) k = Aci[pa0 + e];
+        b0[t] = e < alen ? Brp[k] : 0;
+        len[t] = e < alen ? (int)(Brp[k + 1] - b0[t]) : 0;
+    }
+    int total = 0;  // products of the row (<= PACK_FLOPS)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int incl = group_incl_scan(len[t], q);
+        const int e = q + t * PACK_G;
+        const int start = total + incl - len[t];
+        if (e < alen) {
+            pre[e] = start;
+            shift[e] = b0[t] - start;
+        }
+        total += __shfl(incl, PACK_G - 1, PACK_G);
+    }
+    if (q == 0) pre[alen] = total;
+    wave_lds_sync();
+    int s = 0;  // A entry of this lane's current product (products only move forward)
+    for (int p0 = q; p0 < total; p0 += PACK_G * PACK_UNR) {
+        int sx[PACK_UNR];
+        int64_t bpos[PACK_UNR];
+        int32_t j[PACK_UNR];
+#pragma unroll
+        for (int x = 0; x < PACK_UNR; ++x) {
+            const int p = p0 + x * PACK_G;
+            if (p < total)
+                while (pre[s + 1] <= p) ++s;
+            sx[x] = s;
+            bpos[x] = p < total ? shift[s] + p : -1;
+        }
+#pragma unroll
+        for (int x = 0; x < PACK_UNR; ++x) j[x] = bpos[x] >= 0 ? Bci[bpos[x]] : -1;  // -1: below every key
+        int rk[PACK_UNR];
+#pragma unroll
+        for (int x = 0; x < PACK_UNR; ++x) {
+            // rank of the first key >= j (at most PACK_MASK - 1); a hit if that key is j
+            int pos = keys[7] < j[x] ? 8 : 0;
+            pos += keys[pos + 3] < j[x] ? 4 : 0;
+            pos += keys[pos + 1] < j[x] ? 2 : 0;
+            pos += keys[pos] < j[x] ? 1 : 0;
+            rk[x] = keys[pos] == j[x] ? pos : -1;
+        }
+#pragma unroll
+        for (int x = 0; x < PACK_UNR; ++x) {
+            if (rk[x] >= 0) {
+                if (FLAGS) flags[rk[x]] = 1;
+                if (!COUNT) T::lds_add(&vals[rk[x]], T::term(T::load(Av, pa0 + sx[x]), T::load(Bv, bpos[x])));
+            }
+        }
+    }
+    wave_lds_sync();
+    const int x0 = q, x1 = q + PACK_G;
+    const bool k0 = x0 < mcnt && (FLAGS ? flags[x0] != 0 : T::is_set(vals[x0]));
+    const bool k1 = x1 < mcnt && (FLAGS ? flags[x1] != 0 : T::is_set(vals[x1]));
+    const uint64_t gm = 0xFFull << (ln & ~(PACK_G - 1));  // this group's lanes
+    static_assert(PACK_G == 8, "the group mask holds eight lanes");
+    const uint64_t m0b = __ballot(k0) & gm, m1b = __ballot(k1) & gm;
+    const uint64_t below = (1ull << ln) - 1ull;
+    const int n0 = __popcll(m0b);
+    if (!COUNT && live) {
+        const int64_t ob = g.out_off[u];
+        typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+        if (k0) {
+            const int64_t pos = ob + __popcll(m0b & below);
+            g.out_col[pos] = keys[x0];
+            ov[pos] = T::finish(vals[x0]);
+        }
+        if (k1) {
+            const int64_t pos = ob + n0 + __popcll(m1b & below);
+            g.out_col[pos] = keys[x1];
+            ov[pos] = T::finish(vals[x1]);
+        }
+    }
+    if (MODE != MODE_DIRECT && live && q == 0) g.cnt[u] = n0 + __popcll(m1b);
+}
+
 #ifndef MSP_HASH_LOOKUP
 #define MSP_HASH_LOOKUP 1
 #endif
@@ -1816,6 +1996,12 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
         MSP_LAUNCH((k_heap<SR, MODE, BATCH>), dim3((unsigned)((a.nunits + HEAP_T - 1) / HEAP_T)), dim3(HEAP_T), 0,
                    s, a);
         break;
+    case BIN_MASKIDX_P: {
+        constexpr int64_t rows = PACK_WPB * PACK_RPW;
+        MSP_LAUNCH((k_pack<SR, MODE, BATCH>), dim3((unsigned)((a.nunits + rows - 1) / rows)), dim3(PACK_WPB * WAVE),
+                   0, s, a);
+        break;
+    }
     default:
         return hipErrorInvalidValue;
     }
