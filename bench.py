@@ -158,9 +158,10 @@ def main():
                     "(and at most 8 entries in A's row) use the heap kind (0: never; default: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="all",
-                    choices=("all", "tc", "er", "batch", "bfs", "serve", "bc", "ktruss", "heatmap", "copy"),
+                    choices=("all", "tc", "er", "er_batch", "batch", "bfs", "serve", "bc", "ktruss", "heatmap", "copy"),
                     help="all (default): the multi-source BFS step (headline), triangle counting and the "
-                         "Erdos-Renyi n=4096 product in one line; tc, er, bfs: one of them; batch: 64 mixed FP64 "
+                         "Erdos-Renyi n=4096 product in one line; tc, er, bfs: one of them; er_batch: 256 "
+                         "Erdos-Renyi n=4096 products as one batch; batch: 64 mixed FP64 "
                          "products, batched and graph-replayed vs one launch per product")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mask-cap", type=int, default=0,
@@ -203,6 +204,8 @@ def main():
         return run_tc(args)
     if args.workload == "er":
         return run_er(args)
+    if args.workload == "er_batch":
+        return print(json.dumps(headline(measure_er_batched(args), args)), flush=True)
     run_all(args)
 
 

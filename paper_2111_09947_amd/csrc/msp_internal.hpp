@@ -56,7 +56,10 @@ constexpr int INNER_CAP = 256;
 // and at most PACK_ALEN entries in its row of A. Such rows take PACK_G lanes
 // each; a wave per row would leave most of its 64 lanes idle on them (an
 // Erdos-Renyi row of degree 8 has 64 products and 8 mask entries).
-constexpr int PACK_G = 8;
+#ifndef MSP_PACK_G
+#define MSP_PACK_G 8
+#endif
+constexpr int PACK_G = MSP_PACK_G;
 constexpr int PACK_MASK = 16;
 constexpr int PACK_ALEN = 32;
 constexpr int64_t PACK_FLOPS = 256;

@@ -1777,13 +1777,18 @@ __global__ __launch_bounds__(HEAP_T) void k_heap(NumArgs g) {
 // product p is the last one whose first product is at most p, found by
 // walking forward a prefix of the B row lengths kept in LDS. A hit folds
 // A's and B's values into the key's slot with an LDS atomic; emission walks
-// the keys in order (two per lane). Each wave works alone: its groups only
+// the keys in order (PACK_MASK / PACK_G per lane). Each wave works alone: its groups only
 // synchronize through the wave's own LDS accesses.
 constexpr int PACK_RPW = WAVE / PACK_G;  // rows per wave
 constexpr int PACK_WPB = 2;              // waves per block
-constexpr int PACK_UNR = 4;              // products in flight per lane
-static_assert(PACK_MASK == 2 * PACK_G, "two keys per lane; the search takes four steps over 16 keys");
-static_assert(PACK_ALEN % PACK_G == 0, "A entries are dealt to the group's lanes in whole rounds");
+#ifndef MSP_PACK_UNR
+#define MSP_PACK_UNR 4
+#endif
+constexpr int PACK_UNR = MSP_PACK_UNR;   // products in flight per lane
+static_assert(PACK_MASK == 16, "the search takes four steps over 16 keys");
+static_assert(PACK_G >= 2 && PACK_G <= 16 && (PACK_G & (PACK_G - 1)) == 0 && PACK_MASK % PACK_G == 0 &&
+                  PACK_ALEN % PACK_G == 0,
+              "keys and A entries are dealt to the group's lanes in whole rounds");
 
 // inclusive prefix sum over the PACK_G lanes of a group
 __device__ __forceinline__ int group_incl_scan(int v, int q) {
@@ -1914,29 +1919,25 @@ __global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
         }
     }
     wave_lds_sync();
-    const int x0 = q, x1 = q + PACK_G;
-    const bool k0 = x0 < mcnt && (FLAGS ? flags[x0] != 0 : T::is_set(vals[x0]));
-    const bool k1 = x1 < mcnt && (FLAGS ? flags[x1] != 0 : T::is_set(vals[x1]));
-    const uint64_t gm = 0xFFull << (ln & ~(PACK_G - 1));  // this group's lanes
-    static_assert(PACK_G == 8, "the group mask holds eight lanes");
-    const uint64_t m0b = __ballot(k0) & gm, m1b = __ballot(k1) & gm;
+    // emission in key order: round t holds keys t * PACK_G .. t * PACK_G + PACK_G - 1, one per lane
+    const uint64_t gm = ((1ull << PACK_G) - 1ull) << (ln & ~(PACK_G - 1));  // this group's lanes
     const uint64_t below = (1ull << ln) - 1ull;
-    const int n0 = __popcll(m0b);
-    if (!COUNT && live) {
-        const int64_t ob = g.out_off[u];
-        typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
-        if (k0) {
-            const int64_t pos = ob + __popcll(m0b & below);
-            g.out_col[pos] = keys[x0];
-            ov[pos] = T::finish(vals[x0]);
+    const int64_t ob = (!COUNT && live) ? g.out_off[u] : 0;
+    typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+    int emitted = 0;
+#pragma unroll
+    for (int t = 0; t < PACK_MASK / PACK_G; ++t) {
+        const int x = q + t * PACK_G;
+        const bool kp = x < mcnt && (FLAGS ? flags[x] != 0 : T::is_set(vals[x]));
+        const uint64_t mb = __ballot(kp) & gm;
+        if (!COUNT && kp) {  // kp implies live
+            const int64_t pos = ob + emitted + __popcll(mb & below);
+            g.out_col[pos] = keys[x];
+            ov[pos] = T::finish(vals[x]);
         }
-        if (k1) {
-            const int64_t pos = ob + n0 + __popcll(m1b & below);
-            g.out_col[pos] = keys[x1];
-            ov[pos] = T::finish(vals[x1]);
-        }
+        emitted += __popcll(mb);
     }
-    if (MODE != MODE_DIRECT && live && q == 0) g.cnt[u] = n0 + __popcll(m1b);
+    if (MODE != MODE_DIRECT && live && q == 0) g.cnt[u] = emitted;
 }
 
 #ifndef MSP_HASH_LOOKUP
