@@ -173,7 +173,7 @@ def main():
                     help="turn the FETCH_SIZE / WRITE_SIZE counter runs under DIR (copy_FETCH_SIZE, copy_WRITE_SIZE, "
                          "KEY_FETCH_SIZE, KEY_WRITE_SIZE) into profiles/traffic_KEY.json for --bin/--kernel")
     ap.add_argument("--traffic-key", default="tc_rmat18", help="with --summarize-traffic: the workload key "
-                    "(tc_rmat18, bfs_rmat20_i32, bfs_rmat20_bool, er4096)")
+                    "(tc_rmat18, bfs_rmat20_i32, bfs_rmat20_bool, er4096, er4096_x256)")
     ap.add_argument("--bin", default="hash_block", help="with --summarize-traffic: the kernel bin")
     ap.add_argument("--kernel", default="k_maskkey<1, 1, 4, 512, true, 1, false>",
                     help="with --summarize-traffic: the kernel name (substring) of that bin")
@@ -552,15 +552,21 @@ def measure_er_batched(args, count=256):
     dom_bytes = int(per_row[bins == dom].sum())
     achieved = dom_bytes / (bin_ms[dom] * 1e-3) / 1e9 if bin_ms[dom] > 0 else 0.0
     total = int(per_row.sum())
+    roof = {"bound": "hbm", "achieved": sig(achieved), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": sig(achieved / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic(os.path.join(ROOT, "profiles", "traffic_er4096_x256.json"), kernel_source_hash(),
+                                    msp.BIN_NAMES[dom]),
+            "kernel": f"numeric bin {msp.BIN_NAMES[dom]}", "kernel_ms": round(float(bin_ms[dom]), 5),
+            "alg_bytes": dom_bytes}
+    if roof["traffic"] and bin_ms[dom] > 0:
+        roof["traffic_gbs"] = round(roof["traffic"] / (bin_ms[dom] * 1e-3) / 1e9, 1)
+        roof["traffic_frac"] = round(roof["traffic_gbs"] / HBM_PEAK_GBS, 4)
     return {"workload": f"{count} independent Erdos-Renyi products of the n = 4096, average degree 8, FP64 "
                         "plus-times shape (product p: seeds 101+10p, 102+10p, 103+10p) as one batch",
             "dtype": "f64", "products": products, "useful_products": useful, "bin_units": bin_units,
             "ms_per_step": round(ms_step, 4), "value": sig(2 * useful / (ms_step * 1e-3) / 1e9), "unit": "GFLOP/s",
             "graph_replay_ms": round(ms_graph, 4),
-            "roofline": {"bound": "hbm", "achieved": sig(achieved), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": sig(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                         "kernel": f"numeric bin {msp.BIN_NAMES[dom]}", "kernel_ms": round(float(bin_ms[dom]), 5),
-                         "alg_bytes": dom_bytes},
+            "roofline": roof,
             "path": {"alg_bytes_total": total,
                      "hbm_frac_whole_step": sig(total / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "hbm_frac_graph_replay": sig(total / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
