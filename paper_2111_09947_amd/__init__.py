@@ -124,12 +124,39 @@ def _workspace(nbytes: int, device):
     return ws
 
 
+_WIDTH = {}
+
+
 def _carve(alloc, n: int, dtype):
     """n elements of dtype from a byte allocator (alloc(nbytes) -> uint8
     device tensor starting on a 256-byte boundary)."""
-    t = _torch()
-    width = t.empty(0, dtype=dtype).element_size()
-    return alloc(max(int(n), 1) * width)[:max(int(n), 1) * width].view(dtype)
+    width = _WIDTH.get(dtype)
+    if width is None:
+        width = _WIDTH[dtype] = _torch().empty(0, dtype=dtype).element_size()
+    nb = max(int(n), 1) * width
+    return alloc(nb)[:nb].view(dtype)
+
+
+class _Slab:
+    """A byte allocator over one device tensor: consecutive slices, each on a
+    256-byte boundary (the views keep the whole tensor alive)."""
+
+    def __init__(self, nbytes: int, device):
+        t = _torch()
+        self.buf = t.empty(max(int(nbytes), 1), dtype=t.uint8, device=device)
+        self.off = 0
+
+    @staticmethod
+    def size(n: int) -> int:
+        return (max(int(n), 1) + 255) // 256 * 256
+
+    def __call__(self, nbytes: int):
+        n = self.size(nbytes)
+        if self.off + n > self.buf.numel():
+            raise RuntimeError("output slab exhausted")
+        v = self.buf[self.off:self.off + n]
+        self.off += n
+        return v
 
 
 class _TorchAllocator:
@@ -628,10 +655,19 @@ class Batch:
     def bind_new_outputs(self, out_alloc=None, keep=None):
         """Allocates every output with its upper-bound capacity and binds it.
         `out_alloc(nbytes)`: optional source of the output buffers, except
-        for the products p with keep[p] true, which get their own."""
+        for the products p with keep[p] true, which get their own. By default
+        all outputs are views into one device allocation (one allocation
+        instead of three per product; a kept result keeps that allocation
+        alive)."""
         t = _torch()
         outs = (L.MspCsrOut * self.count)()
         self.outputs = []
+        if out_alloc is None and self.count:
+            w = t.empty(0, dtype=out_dtype(self.semiring)).element_size()
+            total = sum(_Slab.size((A.nrows + 1) * 8) + _Slab.size(max(self.upper_bounds[p], 1) * 4) +
+                        _Slab.size(max(self.upper_bounds[p], 1) * w)
+                        for p, (A, _, _, _) in enumerate(self.problems))
+            out_alloc, keep = _Slab(total, self.problems[0][0].rowptr.device), None
         for p, (A, B, M, _) in enumerate(self.problems):
             dev = A.rowptr.device
             cap = max(self.upper_bounds[p], 1)

@@ -184,6 +184,12 @@ struct msp_plan {
     unsigned int* gacc = nullptr;  // [nsplit] x (inserted bits, slots)
     // batch tables (plan workspace)
     Operands* ops_d = nullptr;
+    ProdMeta* meta_d = nullptr;            // [P + 1] per-product entries of the batch launches
+    int64_t* nnz_d = nullptr;              // [P] output counts gathered for msp_batch_nnz
+    bool batch_launch = false;             // analysis and unit placement: one launch for all products
+    std::vector<Operands> ops_h;           // host copies of the uploaded tables (kept while the plan lives)
+    std::vector<ProdMeta> meta_h;
+    std::vector<int64_t> ent_h;
     OutBind* outs_d = nullptr;
     int64_t* ent_off_d = nullptr;
     std::vector<OutBind> outs;
@@ -344,6 +350,8 @@ static size_t plan_layout(msp_plan* P, char* base) {
         L.take(&P->ops_d, count);
         L.take(&P->outs_d, count);
         L.take(&P->ent_off_d, count + 1);
+        L.take(&P->meta_d, count + 1);
+        L.take(&P->nnz_d, count);
     }
     if (P->inner_any && !P->opt.b_transpose) {
         const int vb = in_bytes(P->sr);
@@ -524,7 +532,52 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
             MSP_CHECK(build_transpose(P, pr, o.force_kind == MSP_KIND_INNER));
         }
     }
-    for (int64_t p = 0; p < count; ++p) {
+    // a batch without pull costs: the row sums and the analysis of all products in one launch each
+    P->batch_launch = count > 1 && !P->inner_any;
+    if (P->batch_launch) {
+        P->ops_h.resize((size_t)count);
+        P->meta_h.assign((size_t)count + 1, ProdMeta{});
+        int64_t chunks = 0;
+        for (int64_t p = 0; p < count; ++p) {
+            const Product& pr = P->prods[(size_t)p];
+            P->ops_h[(size_t)p] = pr.op;
+            P->meta_h[(size_t)p] = ProdMeta{pr.bdeg, pr.row_off, pr.gblk0, chunks, pr.nnzA};
+            chunks += rowsum_chunks(pr.nnzA);
+        }
+        P->meta_h[(size_t)count] = ProdMeta{nullptr, R, P->gtot, chunks, 0};
+        P->ent_h.assign((size_t)count + 1, 0);
+        for (int64_t p = 0; p < count; ++p)
+            P->ent_h[(size_t)p + 1] = P->ent_h[(size_t)p] + P->prods[(size_t)p].op.m + 1;
+        // the tables go up before the plan's synchronization below, which also ends the copies' reads
+        // of the host vectors
+        MSP_HIP(hipMemcpyAsync(P->ops_d, P->ops_h.data(), sizeof(Operands) * count, hipMemcpyHostToDevice, s));
+        MSP_HIP(hipMemcpyAsync(P->meta_d, P->meta_h.data(), sizeof(ProdMeta) * (count + 1), hipMemcpyHostToDevice,
+                               s));
+        MSP_HIP(hipMemcpyAsync(P->ent_off_d, P->ent_h.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
+                               s));
+        for (int64_t p = 0; p < count; ++p) {
+            const Product& pr = P->prods[(size_t)p];
+            if (pr.bdeg) MSP_HIP(launch_deg16(pr.op.Brp, pr.op.k, pr.bdeg, s));
+        }
+        AnalysisArgs aa{};
+        aa.force_kind = o.force_kind;
+        aa.inner_ratio = 0;
+        aa.maskidx_max = o.maskidx_max;
+        aa.block_flops = o.block_flops;
+        aa.split_flops = o.split_flops;
+        aa.heap_flops = o.heap_flops;
+        aa.has_table = P->has_table && o.force_kind == MSP_KIND_AUTO;
+        std::memcpy(aa.kind_table, P->kind_table, sizeof(aa.kind_table));
+        aa.icost = nullptr;
+        aa.flops = P->flops;
+        aa.flops_zeroed = true;
+        aa.tiles = P->unit_base;
+        aa.bin = P->bin;
+        aa.part = P->part;
+        aa.gtot = P->gtot;
+        MSP_HIP(launch_analysis_batch(aa, P->ops_d, P->meta_d, count, chunks, P->gtot, s));
+    }
+    for (int64_t p = 0; p < count && !P->batch_launch; ++p) {
         Product& pr = P->prods[(size_t)p];
         AnalysisArgs aa{};
         aa.op = pr.op;
@@ -621,16 +674,17 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
         Product& pr = P->prods[(size_t)p];
         if (pr.bin_units[BIN_INNER_W] > 0 && !o.b_transpose) MSP_CHECK(build_transpose(P, pr, true));
     }
-    if (count > 1) {
-        std::vector<Operands> ops((size_t)count);
-        std::vector<int64_t> ent((size_t)count + 1, 0);
+    if (count > 1 && !P->batch_launch) {  // the operand table (B^T may have been built since) and the row offsets
+        P->ops_h.resize((size_t)count);
+        P->ent_h.assign((size_t)count + 1, 0);
         for (int64_t p = 0; p < count; ++p) {
-            ops[(size_t)p] = P->prods[(size_t)p].op;
-            ent[(size_t)p + 1] = ent[(size_t)p] + P->prods[(size_t)p].op.m + 1;
+            P->ops_h[(size_t)p] = P->prods[(size_t)p].op;
+            P->ent_h[(size_t)p + 1] = P->ent_h[(size_t)p] + P->prods[(size_t)p].op.m + 1;
         }
-        MSP_HIP(hipMemcpyAsync(P->ops_d, ops.data(), sizeof(Operands) * count, hipMemcpyHostToDevice, s));
-        MSP_HIP(hipMemcpyAsync(P->ent_off_d, ent.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s));
-        MSP_HIP(hipStreamSynchronize(s));  // the host staging vectors go out of scope
+        MSP_HIP(hipMemcpyAsync(P->ops_d, P->ops_h.data(), sizeof(Operands) * count, hipMemcpyHostToDevice, s));
+        MSP_HIP(hipMemcpyAsync(P->ent_off_d, P->ent_h.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
+                               s));
+        MSP_HIP(hipStreamSynchronize(s));  // the copies have read the host vectors
     }
     return MSP_OK;
 }
@@ -648,9 +702,9 @@ static msp_status place_units(msp_plan* P, void* ws, size_t ws_bytes, bool stagi
     P->placed_ws = nullptr;
     // the split-row counter starts at zero
     MSP_HIP(launch_fill_i64(reinterpret_cast<int64_t*>(P->split_counter), 1, 0, s));
-    for (int64_t p = 0; p < P->P; ++p) {
+    for (int64_t p = 0; p < (P->batch_launch ? 1 : P->P); ++p) {
         Product& pr = P->prods[(size_t)p];
-        if (pr.op.m == 0) continue;
+        if (pr.op.m == 0 && !P->batch_launch) continue;
         UnitArgs ua{};
         ua.op = pr.op;
         ua.row_off = pr.row_off;
@@ -671,7 +725,10 @@ static msp_status place_units(msp_plan* P, void* ws, size_t ws_bytes, bool stagi
         ua.unit_aux = P->unit_aux;
         ua.split_first = P->split_first;
         ua.split_nchunk = P->split_nchunk;
-        MSP_HIP(launch_units(ua, pr.op.m, s));
+        if (P->batch_launch)  // every product's units in one launch (per-product fields from the tables)
+            MSP_HIP(launch_units_batch(ua, P->ops_d, P->meta_d, P->P, P->gtot, s));
+        else
+            MSP_HIP(launch_units(ua, pr.op.m, s));
     }
     if (staging) MSP_HIP(launch_scan(P->stg_off, P->stg_off, P->U, P->xpart, s));
     P->placed_ws = ws;
@@ -1441,9 +1498,12 @@ msp_status msp_batch_graph_launch(msp_plan* P, void* stream) {
 msp_status msp_batch_nnz(const msp_plan* P, int64_t* nnz, void* stream) {
     if (!P || !nnz || !P->bound) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument or unbound batch");
     hipStream_t s = (hipStream_t)stream;
-    for (int64_t p = 0; p < P->P; ++p) {
-        const OutBind& ob = P->outs[(size_t)p];
-        MSP_HIP(hipMemcpyAsync(&nnz[p], ob.rowptr + ob.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (P->P > 1) {  // one gather kernel and one copy for all products
+        MSP_HIP(launch_batch_nnz(P->outs_d, P->P, P->nnz_d, s));
+        MSP_HIP(hipMemcpyAsync(nnz, P->nnz_d, sizeof(int64_t) * P->P, hipMemcpyDeviceToHost, s));
+    } else {
+        const OutBind& ob = P->outs[0];
+        MSP_HIP(hipMemcpyAsync(&nnz[0], ob.rowptr + ob.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     }
     MSP_HIP(hipStreamSynchronize(s));
     return MSP_OK;

@@ -187,6 +187,16 @@ __host__ __device__ inline int64_t analysis_blocks(int64_t m) {
     return b < ANA_MAXB ? b : ANA_MAXB;
 }
 constexpr int NSEG = NBINS * NBUCKET;  // (bin, flops bucket) segments of the unit list
+// Per-product entries of a batch's analysis launches (a device table of
+// count + 1 entries; the last holds the totals), so that the row sums, the
+// analysis and the unit placement run as one launch each for all products.
+struct ProdMeta {
+    const uint16_t* bdeg;  // B's 2-byte row lengths, or null
+    int64_t row_off;       // first global row
+    int64_t blk0;          // first analysis block
+    int64_t chunk0;        // first row-sum chunk
+    int64_t a_nnz;         // nnz(A)
+};
 // When B has more rows than this, its row pointers (8 bytes a row) exceed
 // 2 MB, half of one XCD's L2: the product count per row then gathers B's row
 // lengths from a 2-byte copy instead.
@@ -269,6 +279,20 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_zero2(int64_t* a, int64_t na, int64_t* b, int64_t nb, hipStream_t s);
 hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s);
 hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s);
+// nnz(C_p) of every product of a bound batch into dst[count] (device).
+hipError_t launch_batch_nnz(const OutBind* outs, int64_t count, int64_t* dst, hipStream_t s);
+// Row-sum chunks of a row of A with nnz entries (one workgroup each).
+int64_t rowsum_chunks(int64_t nnz);
+// The row sums and the analysis of all products of a batch, one launch each:
+// `a` holds the fields common to the products (no pull costs: icost null,
+// inner_ratio 0); ops and meta are device tables of count and count + 1
+// entries; chunks and blocks are the totals (meta[count].chunk0, .blk0).
+hipError_t launch_analysis_batch(const AnalysisArgs& a, const Operands* ops, const ProdMeta* meta, int64_t count,
+                                 int64_t chunks, int64_t blocks, hipStream_t s);
+// The unit placement of all products of a batch in one launch (`a` without
+// its per-product fields).
+hipError_t launch_units_batch(const UnitArgs& a, const Operands* ops, const ProdMeta* meta, int64_t count,
+                              int64_t blocks, hipStream_t s);
 __host__ __device__ inline int flops_bucket(int64_t flops) {
     int b = 0;
     while (b < NBUCKET - 1 && flops >= (int64_t(4) << (2 * b))) ++b;

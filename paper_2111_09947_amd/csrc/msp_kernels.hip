@@ -169,14 +169,45 @@ __device__ int64_t row_of(const int64_t* __restrict__ rp, int64_t nrows, int64_t
 // into LDS, prefix-sums them, and every row overlapping the range adds its
 // overlap (a plain store when the row lies wholly in the range, an atomic add
 // when it spans blocks).
+// The last product p with key(p) <= x, for a key that does not decrease over
+// the count + 1 entries of a batch table, starts at 0 and ends above x:
+// the product of a batch launch's workgroup x (empty products are skipped).
+template <class K>
+__device__ __forceinline__ int64_t product_of(int64_t count, int64_t x, K key) {
+    int64_t lo = 0, hi = count;  // key(lo) <= x < key(hi)
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key(mid) <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// BATCHED: one launch for all products of a batch; workgroup b takes chunk
+// b - meta[p].chunk0 of product p (the arguments before `ops` are unused).
+template <bool BATCHED>
 __global__ __launch_bounds__(ANA_T) void k_rowsum(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                   int64_t nrows, int64_t nnz, const int64_t* __restrict__ grp,
-                                                  const uint16_t* __restrict__ gdeg, int64_t* __restrict__ out) {
+                                                  const uint16_t* __restrict__ gdeg, int64_t* __restrict__ out,
+                                                  const Operands* ops, const ProdMeta* meta, int64_t count) {
     __shared__ int64_t lds[RS_CHUNK + RS_CHUNK / 8];
     __shared__ int64_t tmp[ANA_T / WAVE];
     __shared__ int64_t rows[2];
     const int tid = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * RS_CHUNK;
+    int64_t chunk = blockIdx.x;
+    if constexpr (BATCHED) {
+        const int64_t p = product_of(count, chunk, [&](int64_t q) { return meta[q].chunk0; });
+        const Operands& o = ops[p];
+        rp = o.Arp;
+        ci = o.Aci;
+        nrows = o.m;
+        grp = o.Brp;
+        nnz = meta[p].a_nnz;
+        gdeg = meta[p].bdeg;
+        out += meta[p].row_off;
+        chunk -= meta[p].chunk0;
+    }
+    const int64_t c0 = chunk * RS_CHUNK;
     const int64_t c1 = min(c0 + (int64_t)RS_CHUNK, nnz);
     const int w = tid / WAVE;
     if (w < 2) {  // wave 0 finds the row of the first entry, wave 1 that of the last
@@ -327,33 +358,15 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
     return min(adm, flops);
 }
 
-// Each block walks the chunks of 256 rows blockIdx.x, blockIdx.x + gridDim.x,
-// ... (gridDim.x = analysis_blocks(m)) and writes its own statistics, so no
-// two blocks update one address: k_segoff adds them up.
-__global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
-    static_assert(ANA_T == ANA_ROWS, "one row per thread and chunk");
-    static_assert(MSP_KIND_CLASSES % 4 == 0 && MSP_KIND_CLASSES / 4 <= ANA_T, "the kind table: whole words");
-    __shared__ unsigned long long sst[ST_COUNT];
-    __shared__ uint32_t table_w[MSP_KIND_CLASSES / 4];
-    const Operands& o = a.op;
-    for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) sst[x] = 0;
-    // the kind table moves to LDS word by word with constant indices: indexing the argument
-    // block with a lane-dependent index would copy all of it to per-lane scratch memory
-    if (a.has_table) {
-#pragma unroll
-        for (int x = 0; x < MSP_KIND_CLASSES / 4; ++x) {
-            uint32_t w;
-            __builtin_memcpy(&w, &a.kind_table[4 * x], 4);
-            if (threadIdx.x == x) table_w[x] = w;
-        }
-    }
-    __syncthreads();
-    const int8_t* table = a.has_table ? reinterpret_cast<const int8_t*>(table_w) : nullptr;
-    for (int64_t r0 = (int64_t)blockIdx.x * ANA_T; r0 < o.m; r0 += (int64_t)gridDim.x * ANA_T) {
+// The rows of one analysis block: rows blk * ANA_T.., then every nblk-th chunk
+// of ANA_T rows, classified and counted into the block's statistics sst.
+__device__ __forceinline__ void analysis_rows(const AnalysisArgs& a, const Operands& o, int64_t row_off, int64_t blk,
+                                              int64_t nblk, const int8_t* table, unsigned long long* sst) {
+    for (int64_t r0 = blk * ANA_T; r0 < o.m; r0 += nblk * ANA_T) {
         const int64_t r1 = min(r0 + ANA_T, o.m);
         const int64_t i = r0 + threadIdx.x;
         // products per row (and the pull cost), summed beforehand by k_rowsum
-        const int64_t flops = i < r1 ? a.flops[a.row_off + i] : 0;
+        const int64_t flops = i < r1 ? a.flops[row_off + i] : 0;
         const int64_t icost = (i < r1 && a.icost) ? a.icost[i] : 0;
         int64_t ub = 0, tiles = 0, stg = 0, mnnz = 0;
         int seg = -1;
@@ -372,8 +385,8 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
                 for (int64_t t = 0; t < tiles; ++t) stg += unit_staging(o, i, bin, t, tiles, mnnz, flops);
                 seg = bin * NBUCKET + flops_bucket(flops);
             }
-            a.tiles[a.row_off + i] = tiles;
-            a.bin[a.row_off + i] = (int8_t)bin;
+            a.tiles[row_off + i] = tiles;
+            a.bin[row_off + i] = (int8_t)bin;
         }
         // per-segment unit counts: one LDS atomic per distinct segment per wave
         bool pending = seg >= 0;
@@ -403,9 +416,43 @@ __global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a) {
             atomicMax(&sst[ST_MAXFLOPS], (unsigned long long)v_max);
         }
     }
+}
+
+// Each block walks the chunks of 256 rows blk, blk + nblk, ... of its product
+// (nblk = analysis_blocks(m)) and writes its own statistics, so no two blocks
+// update one address: k_segoff adds them up. BATCHED: one launch for all
+// products of a batch, workgroup g taking block g - meta[p].blk0 of product p.
+template <bool BATCHED>
+__global__ __launch_bounds__(ANA_T) void k_analysis(AnalysisArgs a, const Operands* ops, const ProdMeta* meta,
+                                                    int64_t count) {
+    static_assert(ANA_T == ANA_ROWS, "one row per thread and chunk");
+    static_assert(MSP_KIND_CLASSES % 4 == 0 && MSP_KIND_CLASSES / 4 <= ANA_T, "the kind table: whole words");
+    __shared__ unsigned long long sst[ST_COUNT];
+    __shared__ uint32_t table_w[MSP_KIND_CLASSES / 4];
+    for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) sst[x] = 0;
+    // the kind table moves to LDS word by word with constant indices: indexing the argument
+    // block with a lane-dependent index would copy all of it to per-lane scratch memory
+    if (a.has_table) {
+#pragma unroll
+        for (int x = 0; x < MSP_KIND_CLASSES / 4; ++x) {
+            uint32_t w;
+            __builtin_memcpy(&w, &a.kind_table[4 * x], 4);
+            if (threadIdx.x == x) table_w[x] = w;
+        }
+    }
+    __syncthreads();
+    const int8_t* table = a.has_table ? reinterpret_cast<const int8_t*>(table_w) : nullptr;
+    int64_t g;  // the block's column of the statistics table
+    if constexpr (BATCHED) {
+        g = blockIdx.x;
+        const int64_t p = product_of(count, g, [&](int64_t q) { return meta[q].blk0; });
+        analysis_rows(a, ops[p], meta[p].row_off, g - meta[p].blk0, meta[p + 1].blk0 - meta[p].blk0, table, sst);
+    } else {
+        g = a.gblk0 + blockIdx.x;
+        analysis_rows(a, a.op, a.row_off, blockIdx.x, gridDim.x, table, sst);
+    }
     __syncthreads();
     // this block's statistics, every one of them (the buffer is not cleared beforehand)
-    const int64_t g = a.gblk0 + blockIdx.x;
     for (int x = threadIdx.x; x < ST_COUNT; x += ANA_T) a.part[(int64_t)x * a.gtot + g] = sst[x];
 }
 
@@ -442,17 +489,34 @@ hipError_t launch_analysis(const AnalysisArgs& a, hipStream_t s) {
     // products per row: sum over A(i,:) of nnz(B(k,:)); pull cost: sum over M(i,:) of nnz(B(:,j))
     hipError_t e = a.flops_zeroed ? hipSuccess : launch_fill_i64(a.flops + a.row_off, a.op.m, 0, s);
     if (e != hipSuccess) return e;
+    const Operands* no_ops = nullptr;
+    const ProdMeta* no_meta = nullptr;
     if (a.a_nnz > 0)
-        MSP_LAUNCH(k_rowsum, dim3(grid_for(a.a_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Arp, a.op.Aci,
-                   a.op.m, a.a_nnz, a.op.Brp, a.bdeg, a.flops + a.row_off);
+        MSP_LAUNCH(k_rowsum<false>, dim3(grid_for(a.a_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Arp, a.op.Aci,
+                   a.op.m, a.a_nnz, a.op.Brp, a.bdeg, a.flops + a.row_off, no_ops, no_meta, (int64_t)0);
     if (a.icost) {
         e = launch_fill_i64(a.icost, a.op.m, 0, s);
         if (e != hipSuccess) return e;
         if (a.m_nnz > 0)
-            MSP_LAUNCH(k_rowsum, dim3(grid_for(a.m_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Mrp,
-                       a.op.Mci, a.op.m, a.m_nnz, a.colcnt_rp, (const uint16_t*)nullptr, a.icost);
+            MSP_LAUNCH(k_rowsum<false>, dim3(grid_for(a.m_nnz, RS_CHUNK, INT32_MAX)), dim3(ANA_T), 0, s, a.op.Mrp,
+                       a.op.Mci, a.op.m, a.m_nnz, a.colcnt_rp, (const uint16_t*)nullptr, a.icost, no_ops, no_meta,
+                       (int64_t)0);
     }
-    MSP_LAUNCH(k_analysis, dim3(analysis_blocks(a.op.m)), dim3(ANA_T), 0, s, a);
+    MSP_LAUNCH(k_analysis<false>, dim3(analysis_blocks(a.op.m)), dim3(ANA_T), 0, s, a, no_ops, no_meta, (int64_t)0);
+    return hipGetLastError();
+}
+
+int64_t rowsum_chunks(int64_t nnz) { return nnz > 0 ? (nnz + RS_CHUNK - 1) / RS_CHUNK : 0; }
+
+hipError_t launch_analysis_batch(const AnalysisArgs& a, const Operands* ops, const ProdMeta* meta, int64_t count,
+                                 int64_t chunks, int64_t blocks, hipStream_t s) {
+    if (a.icost || a.inner_ratio) return hipErrorInvalidValue;  // pull costs: one product at a time
+    if (chunks > INT32_MAX || blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (chunks > 0)
+        MSP_LAUNCH(k_rowsum<true>, dim3((unsigned)chunks), dim3(ANA_T), 0, s, (const int64_t*)nullptr,
+                   (const int32_t*)nullptr, (int64_t)0, (int64_t)0, (const int64_t*)nullptr, (const uint16_t*)nullptr,
+                   a.flops, ops, meta, count);
+    if (blocks > 0) MSP_LAUNCH(k_analysis<true>, dim3((unsigned)blocks), dim3(ANA_T), 0, s, a, ops, meta, count);
     return hipGetLastError();
 }
 
@@ -471,10 +535,9 @@ __global__ __launch_bounds__(SEG_T) void k_segoff(unsigned long long* __restrict
     unsigned long long* row = part + (int64_t)x * gtot;
     const bool is_max = x == ST_MAXFLOPS;
     const int w = threadIdx.x / WAVE;
-    for (int64_t p = 0; p < count; ++p) {
-        const int64_t g0 = blk_off ? blk_off[p] : 0, g1 = blk_off ? blk_off[p + 1] : gtot;
+    if (count == 1) {  // one product: the whole block adds up its blocks
         unsigned long long v = 0;
-        for (int64_t g = g0 + threadIdx.x; g < g1; g += SEG_T) v = is_max ? max(v, row[g]) : v + row[g];
+        for (int64_t g = threadIdx.x; g < gtot; g += SEG_T) v = is_max ? max(v, row[g]) : v + row[g];
 #pragma unroll
         for (int d = WAVE / 2; d >= 1; d >>= 1) {
             const unsigned long long o = __shfl_xor(v, d, WAVE);
@@ -485,11 +548,26 @@ __global__ __launch_bounds__(SEG_T) void k_segoff(unsigned long long* __restrict
         if (threadIdx.x == 0) {
             unsigned long long t = 0;
             for (int k = 0; k < SEG_T / WAVE; ++k) t = is_max ? max(t, red[k]) : t + red[k];
-            stats[p * ST_COUNT + x] = t;
-            if (host_stats) host_stats[p * ST_COUNT + x] = t;
+            stats[x] = t;
+            if (host_stats) host_stats[x] = t;
         }
-        __syncthreads();
+    } else {  // a batch: one wave per product (most products have few blocks)
+        for (int64_t p = w; p < count; p += SEG_T / WAVE) {
+            const int64_t g0 = blk_off[p], g1 = blk_off[p + 1];
+            unsigned long long v = 0;
+            for (int64_t g = g0 + lane(); g < g1; g += WAVE) v = is_max ? max(v, row[g]) : v + row[g];
+#pragma unroll
+            for (int d = WAVE / 2; d >= 1; d >>= 1) {
+                const unsigned long long o = __shfl_xor(v, d, WAVE);
+                v = is_max ? max(v, o) : v + o;
+            }
+            if (lane() == 0) {
+                stats[p * ST_COUNT + x] = v;
+                if (host_stats) host_stats[p * ST_COUNT + x] = v;
+            }
+        }
     }
+    __syncthreads();  // every read of `row` above comes before the prefix below rewrites it
     if (x < ST_BIN0 || x >= ST_BIN0 + NSEG) return;
     // segment counts -> exclusive prefix over all blocks, chunk by chunk
     unsigned long long carry = 0;
@@ -523,6 +601,19 @@ hipError_t launch_segoff(unsigned long long* part, int64_t gtot, const int64_t* 
     return hipGetLastError();
 }
 
+// The output count of every product of a batch, nnz(C_p) = rowptr_p[nrows_p],
+// gathered into one device array (one copy to the host instead of one per product).
+__global__ void k_batch_nnz(const OutBind* __restrict__ outs, int64_t count, int64_t* __restrict__ dst) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < count; p += (int64_t)gridDim.x * blockDim.x)
+        dst[p] = outs[p].rowptr[outs[p].nrows];
+}
+
+hipError_t launch_batch_nnz(const OutBind* outs, int64_t count, int64_t* dst, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    MSP_LAUNCH(k_batch_nnz, dim3(grid_for(count, 256, 1024)), dim3(256), 0, s, outs, count, dst);
+    return hipGetLastError();
+}
+
 // One int64 from device memory into a device-visible page-locked host word.
 __global__ void k_peek(const int64_t* __restrict__ src, int64_t* dst) { *dst = *src; }
 
@@ -536,12 +627,13 @@ hipError_t launch_peek(const int64_t* src, int64_t* host_dst, hipStream_t s) {
 // Same blocks and row chunks as k_analysis. A block's units of segment s go
 // to positions segment start + the block's prefix (from k_segoff) + a rank
 // taken with an LDS atomic; the counts match the analysis's, so the ranges
-// of the blocks tile every segment exactly.
-__global__ __launch_bounds__(ANA_ROWS) void k_units(UnitArgs a, int64_t m) {
+// of the blocks tile every segment exactly. units_rows places the units of
+// the rows of analysis block blk (of nblk) of one product (g: the block's
+// column of the statistics table).
+__device__ __forceinline__ void units_rows(const UnitArgs& a, const Operands& o, int64_t m, int64_t row_off,
+                                           int32_t prob, int64_t g, int64_t blk, int64_t nblk) {
     __shared__ unsigned int hist[NSEG];
     __shared__ int64_t sbase[NSEG];
-    const Operands& o = a.op;
-    const int64_t g = a.gblk0 + blockIdx.x;
     for (int x = threadIdx.x; x < NSEG; x += blockDim.x) hist[x] = 0;
     if (threadIdx.x < WAVE) {  // segment starts: bins in order, inside a bin the buckets from the heaviest down
         constexpr int PER = (NSEG + WAVE - 1) / WAVE;  // consecutive list positions per lane
@@ -565,10 +657,10 @@ __global__ __launch_bounds__(ANA_ROWS) void k_units(UnitArgs a, int64_t m) {
     __syncthreads();
     for (int x = threadIdx.x; x < NSEG; x += blockDim.x) sbase[x] += (int64_t)a.part[(int64_t)(ST_BIN0 + x) * a.gtot + g];
     __syncthreads();
-    for (int64_t r0 = (int64_t)blockIdx.x * ANA_ROWS; r0 < m; r0 += (int64_t)gridDim.x * ANA_ROWS) {
+    for (int64_t r0 = blk * ANA_ROWS; r0 < m; r0 += nblk * ANA_ROWS) {
         const int64_t i = r0 + threadIdx.x;
         if (i >= m) continue;
-        const int64_t gr = a.row_off + i;
+        const int64_t gr = row_off + i;
         const int64_t base = a.unit_base[gr];
         const int64_t tiles = a.unit_base[gr + 1] - base;
         if (tiles <= 0) continue;
@@ -578,7 +670,7 @@ __global__ __launch_bounds__(ANA_ROWS) void k_units(UnitArgs a, int64_t m) {
         for (int64_t t = 0; t < tiles; ++t) {
             a.unit_row[base + t] = (int32_t)i;
             a.unit_tile[base + t] = (int32_t)t;
-            a.unit_prob[base + t] = a.prob;
+            a.unit_prob[base + t] = prob;
             a.stg_size[base + t] = unit_staging(o, i, bin, t, tiles, mnnz, flops);
         }
         const int seg = bin * NBUCKET + flops_bucket(flops);
@@ -593,9 +685,33 @@ __global__ __launch_bounds__(ANA_ROWS) void k_units(UnitArgs a, int64_t m) {
     }
 }
 
+// BATCHED: one launch for all products of a batch, workgroup g taking block
+// g - meta[p].blk0 of product p (a's op, row_off, prob, gblk0 and m unused).
+template <bool BATCHED>
+__global__ __launch_bounds__(ANA_ROWS) void k_units(UnitArgs a, int64_t m, const Operands* ops, const ProdMeta* meta,
+                                                    int64_t count) {
+    if constexpr (BATCHED) {
+        const int64_t g = blockIdx.x;
+        const int64_t p = product_of(count, g, [&](int64_t q) { return meta[q].blk0; });
+        const Operands& o = ops[p];
+        units_rows(a, o, o.m, meta[p].row_off, (int32_t)p, g, g - meta[p].blk0, meta[p + 1].blk0 - meta[p].blk0);
+    } else {
+        units_rows(a, a.op, m, a.row_off, a.prob, a.gblk0 + blockIdx.x, blockIdx.x, gridDim.x);
+    }
+}
+
 hipError_t launch_units(const UnitArgs& a, int64_t m, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    MSP_LAUNCH(k_units, dim3(analysis_blocks(m)), dim3(ANA_ROWS), 0, s, a, m);
+    MSP_LAUNCH(k_units<false>, dim3(analysis_blocks(m)), dim3(ANA_ROWS), 0, s, a, m, (const Operands*)nullptr,
+               (const ProdMeta*)nullptr, (int64_t)0);
+    return hipGetLastError();
+}
+
+hipError_t launch_units_batch(const UnitArgs& a, const Operands* ops, const ProdMeta* meta, int64_t count,
+                              int64_t blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    MSP_LAUNCH(k_units<true>, dim3((unsigned)blocks), dim3(ANA_ROWS), 0, s, a, (int64_t)0, ops, meta, count);
     return hipGetLastError();
 }
 
