@@ -91,3 +91,60 @@ def test_batch_rebind_changes_outputs():
             b.graph_launch()
             for (ci, v), C in zip(first, b.results()):
                 assert torch.equal(ci, C.colidx) and torch.equal(v, C.values)
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64"])
+def test_batch_with_pull_costs_plans_product_by_product(sr):
+    """With inner_ratio > 0 (pull costs per row, B^T built by the plan) the
+    batch plan analyses its products one launch each; the results must be
+    the oracle's either way, and the same as with the one-launch analysis."""
+    torch = torch_or_skip()
+    m = msp()
+    probs = _mixed_problems(17, sr)
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    with m.Batch(dev, semiring=sr, inner_ratio=4) as b:
+        b.bind_new_outputs()
+        b.execute()
+        pulled = b.results()
+    with m.Batch(dev, semiring=sr) as b:
+        b.bind_new_outputs()
+        b.execute()
+        pushed = b.results()
+    for (A, B, M, c), C, D in zip(probs, pulled, pushed):
+        R = oracle.masked_spgemm(A, B, M, c, sr)
+        assert_same(C, R, sr)
+        assert_same(D, R, sr)
+        assert torch.equal(C.rowptr, D.rowptr) and torch.equal(C.colidx, D.colidx)
+
+
+def test_batch_with_long_b_and_empty_products():
+    """One-launch batch analysis over products of very different shapes: a B
+    with more than 2^18 rows (its row lengths come from the 2-byte copy), a
+    product with no rows, one with no entries in A, and ordinary ones."""
+    torch = torch_or_skip()
+    m = msp()
+    sr = "plus_times_i32"
+    rng = np.random.default_rng(23)
+    probs = []
+    kbig = (1 << 18) + 1000
+    A = mspgen.er(500, kbig, 40.0, 31, "i32")
+    B = mspgen.er(kbig, 3000, 3.0, 32, "i32")
+    M = mspgen.er(500, 3000, 60.0, 33, None)
+    probs.append((A, B, M, False))
+    probs.append((mspgen.er(0, 10, 1.0, 34, "i32"), mspgen.er(10, 10, 1.0, 35, "i32"), mspgen.er(0, 10, 1.0, 36, None),
+                  False))
+    probs.append((mspgen.er(50, 40, 0.0, 37, "i32"), mspgen.er(40, 700, 5.0, 38, "i32"),
+                  mspgen.er(50, 700, 9.0, 39, None), False))
+    for t in range(3):
+        s = int(rng.integers(1, 10**6))
+        probs.append((mspgen.er(2000, 2000, 6.0, s, "i32"), mspgen.er(2000, 2000, 6.0, s + 1, "i32"),
+                      mspgen.er(2000, 2000, 6.0, s + 2, None), t == 2))
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr) as b:
+            b.bind_new_outputs()
+            for _ in range(2):
+                b.graph_launch()
+                for (A, B, M, c), C in zip(probs, b.results()):
+                    assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
