@@ -478,7 +478,9 @@ msp_status msp_batch_workspace_size(const msp_problem* problems, int64_t count, 
 
 /* Analyses and bins all products (one synchronization) in the plan
    workspace (device, at least msp_batch_workspace_size bytes), which the
-   batch holds until msp_plan_destroy. */
+   batch holds until msp_plan_destroy. Without pull costs (inner_ratio 0)
+   the row sums, the analysis and the unit placement run as one launch each
+   for all products; with them, one product at a time. */
 msp_status msp_batch_create(msp_plan** batch, const msp_problem* problems, int64_t count,
                             msp_semiring semiring, const msp_options* opt, void* workspace,
                             size_t workspace_bytes, void* stream);
