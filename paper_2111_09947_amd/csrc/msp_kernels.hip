@@ -1074,6 +1074,42 @@ __device__ __forceinline__ int64_t ordered_emit(int len, int64_t* tmp, int ut, K
     return running;
 }
 
+// ordered_emit for at most MAXLEN entries with one block barrier instead of
+// two per round of NW * 64 entries: every wave ballots all of its rounds
+// first (the masks stay in scalar registers) and publishes its per-round
+// counts to `cnt` (LDS, MAXLEN / 64 entries); after the one barrier each
+// thread adds up the counts before its (round, wave) and writes its entries
+// in the same order, with the same coalesced stores, as ordered_emit.
+template <int NW, int MAXLEN, class K, class W>
+__device__ __forceinline__ int64_t ordered_emit_1b(int len, int32_t* cnt, int ut, K keep, W write) {
+    constexpr int UT = NW * WAVE;
+    constexpr int MAXR = (MAXLEN + UT - 1) / UT;
+    static_assert(NW > 1 && MAXR <= 8, "for block units of at most eight rounds");
+    const int w = ut / WAVE;
+    uint64_t bm[MAXR];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+        const int idx = r * UT + ut;
+        bm[r] = __ballot(idx < len && keep(idx));
+        if (lane() == 0) cnt[r * NW + w] = __popcll(bm[r]);
+    }
+    __syncthreads();
+    int64_t base = 0;
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+        int before = 0, round = 0;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) {
+            const int c = cnt[r * NW + x];
+            before += x < w ? c : 0;
+            round += c;
+        }
+        if ((bm[r] >> lane()) & 1ull) write(r * UT + ut, base + before + rank_below(bm[r]));
+        base += round;
+    }
+    return base;
+}
+
 // Barrier among the waves that work on one unit: the whole block when a unit
 // spans NW > 1 waves, only the wave itself otherwise (several independent
 // one-wave units may share a block).
@@ -1586,15 +1622,20 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? MSP_MINW_BLOCK : MSP_MINW
     unit_sync<NW>();
     const int64_t ob = COUNT ? 0 : g.out_off[u];
     typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
-    const int64_t total = ordered_emit<NW>(
-        cnt, tmp, ut,
-        [&](int r) { return FLAGS ? (flags[r] != 0) : T::is_set(vals[r]); },
-        [&](int r, int64_t pos) {
-            if (!COUNT) {
-                g.out_col[ob + pos] = keys[r];
-                ov[ob + pos] = T::finish(vals[r]);
-            }
-        });
+    auto keep = [&](int r) { return FLAGS ? (flags[r] != 0) : T::is_set(vals[r]); };
+    auto put = [&](int r, int64_t pos) {
+        if (!COUNT) {
+            g.out_col[ob + pos] = keys[r];
+            ov[ob + pos] = T::finish(vals[r]);
+        }
+    };
+    int64_t total;
+    if constexpr (NW > 1 && CAP / (NW * WAVE) <= 8) {
+        // the unit's candidate rings are free again: they hold the per-round counts
+        total = ordered_emit_1b<NW, CAP>(cnt, reinterpret_cast<int32_t*>(qj_[gi * NW]), ut, keep, put);
+    } else {
+        total = ordered_emit<NW>(cnt, tmp, ut, keep, put);
+    }
     if (ut == 0 && MODE != MODE_DIRECT) g.cnt[u] = total;
 }
 
