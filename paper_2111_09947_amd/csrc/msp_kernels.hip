@@ -1934,8 +1934,8 @@ __global__ __launch_bounds__(HEAP_T) void k_heap(NumArgs g) {
 // product p is the last one whose first product is at most p, found by
 // walking forward a prefix of the B row lengths kept in LDS. A hit folds
 // A's and B's values into the key's slot with an LDS atomic; emission walks
-// the keys in order (PACK_MASK / PACK_G per lane). Each wave works alone: its groups only
-// synchronize through the wave's own LDS accesses.
+// the keys in order (PACK_MASK / PACK_G per lane). Each wave works alone:
+// its groups only synchronize through the wave's own LDS accesses.
 constexpr int PACK_RPW = WAVE / PACK_G;  // rows per wave
 constexpr int PACK_WPB = 2;              // waves per block
 #ifndef MSP_PACK_UNR
