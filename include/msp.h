@@ -219,7 +219,7 @@ typedef struct msp_plan_info_t {
     int64_t units;           /* work units (rows or row tiles) */
     int64_t staging;         /* staging entries used by one-phase execution */
     int64_t mask_nnz;        /* nnz(M) */
-    int64_t kind_units[8];   /* units per msp_kind (5 used) */
+    int64_t kind_units[8];   /* units per msp_kind (0..4), and [5]: units of the sorting bin */
     int64_t bin_units[16];   /* units per kernel bin (MSP_BIN_*; MSP_NBINS used) */
 } msp_plan_info_t;
 
@@ -245,7 +245,11 @@ enum {
     MSP_BIN_MASKIDX_PACKED = 11,     /* eight lanes per row: normal mask rows of <= 16 entries,
                                         <= 256 products, <= 32 entries in the row of A
                                         (automatic choice only) */
-    MSP_NBINS = 12
+    MSP_BIN_SORT_BLOCK = 12,         /* one workgroup per row: complemented mask rows of matrices
+                                        wider than 4096 columns with more than 8 entries of A and
+                                        <= 4096 products: products expanded, sorted by column,
+                                        folded and filtered (automatic choice only) */
+    MSP_NBINS = 13
 };
 
 /* Stage slots of msp_execute_profiled: 0..15 = numeric kernel of bin b,

@@ -271,7 +271,8 @@ class Plan:
         self.units = info.units
         self.staging = info.staging
         self.mask_nnz = info.mask_nnz
-        self.kind_units = {k: info.kind_units[i] for i, k in enumerate(["dense", "hash", "maskidx", "inner", "heap"])}
+        self.kind_units = {k: info.kind_units[i]
+                           for i, k in enumerate(["dense", "hash", "maskidx", "inner", "heap", "sort"])}
         self.bin_units = {k: info.bin_units[i] for i, k in enumerate(L.BIN_NAMES)}
 
     def workspace(self):

@@ -48,7 +48,7 @@ class MspKtrussInfo(ctypes.Structure):
 
 BIN_NAMES = ["dense_wave", "dense_block", "hash_wave", "hash_block", "maskidx_wave", "maskidx_block",
              "inner_wave", "dense_block_narrow", "dense_split", "heap_lane", "heap_lane_long_mask",
-             "maskidx_packed"]
+             "maskidx_packed", "sort_block"]
 STAGE_NAMES = BIN_NAMES + [f"bin{b}" for b in range(len(BIN_NAMES), 16)] + [
     "symbolic", "scan", "rowptr", "compact", "split_emit", "place"]
 NSTAGES = len(STAGE_NAMES)

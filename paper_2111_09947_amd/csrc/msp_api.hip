@@ -952,6 +952,24 @@ static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream
             ab.units = P->bin_units + P->bin_off[b] + wide;
             ab.nunits = P->bin_count[b] - wide;
         }
+        if (b == BIN_ESC) {
+            // the sorting bin's lighter units (its last buckets) in smaller workgroups
+            const int64_t e_end = P->bin_off[b] + P->bin_count[b];
+            const int64_t e_mid = P->seg_off[b * NBUCKET + ESC_MID_FROM_BUCKET];
+            const int64_t e_light = P->seg_off[b * NBUCKET + ESC_LIGHT_FROM_BUCKET];
+            ab.nunits = e_mid - P->bin_off[b];
+            NumArgs am = a, al = a;
+            am.units = P->bin_units + e_mid;
+            am.nunits = e_light - e_mid;
+            al.units = P->bin_units + e_light;
+            al.nunits = e_end - e_light;
+            if (am.nunits > 0) MSP_HIP(launch_numeric(P->sr, LAUNCH_ESC_MID, mode, am, s));
+            if (al.nunits > 0) MSP_HIP(launch_numeric(P->sr, LAUNCH_ESC_LIGHT, mode, al, s));
+            if (ab.nunits <= 0) {
+                if (tm) MSP_CHECK(tm->end());
+                continue;
+            }
+        }
         MSP_HIP(launch_numeric(P->sr, b, mode, ab, s));
         if (tm) MSP_CHECK(tm->end());
     }
@@ -1418,6 +1436,7 @@ msp_status msp_batch_info(const msp_plan* P, int64_t p, msp_plan_info_t* info) {
             pr.bin_units[BIN_MASKIDX_W] + pr.bin_units[BIN_MASKIDX_B] + pr.bin_units[BIN_MASKIDX_P];
         info->kind_units[MSP_KIND_INNER] += pr.bin_units[BIN_INNER_W];
         info->kind_units[MSP_KIND_HEAP] += pr.bin_units[BIN_HEAP_L] + pr.bin_units[BIN_HEAP_LM];
+        info->kind_units[MSP_KIND_HEAP + 1] += pr.bin_units[BIN_ESC];
         for (int b = 0; b < NBINS; ++b) info->bin_units[b] += pr.bin_units[b];
     }
     return MSP_OK;

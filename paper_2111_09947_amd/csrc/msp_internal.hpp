@@ -30,7 +30,9 @@ enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_HEAP_LM = 10,   // the same for normal masks of more than MASKIDX_W_CAP entries
     BIN_MASKIDX_P = 11,  // eight lanes per row, eight rows per wave: short normal mask rows
                          // (<= PACK_MASK entries), few products (<= PACK_FLOPS), short rows of A
-    NBINS = 12
+    BIN_ESC = 12,        // one block per row: complemented rows of matrices wider than DENSE_B_COLS
+                         // that the heap cannot take, with <= ESC_MAX products: expand, sort, fold
+    NBINS = 13
 };
 
 constexpr int DENSE_W_COLS = 512;
@@ -63,6 +65,12 @@ constexpr int PACK_G = MSP_PACK_G;
 constexpr int PACK_MASK = 16;
 constexpr int PACK_ALEN = 32;
 constexpr int64_t PACK_FLOPS = 256;
+// Complemented rows of matrices wider than one dense tile (DENSE_B_COLS
+// columns) that the heap cannot take (more than HEAP_CAP entries of A) would
+// make the dense kind stream the row once per 4096-column tile. With at most
+// ESC_MAX products such a row is expanded into LDS, sorted by column, folded
+// and filtered against its mask row instead (automatic choice only).
+constexpr int64_t ESC_MAX = 4096;
 constexpr int INNER_ACAP = 1024;  // A row (column indices) staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 #ifndef MSP_MASKIDX_B_NW
@@ -80,6 +88,12 @@ constexpr int MASKIDX_B_NW = MSP_MASKIDX_B_NW;  // waves per block of the mask-i
 constexpr int MASKIDX_B_WIDE_BUCKET = MSP_MASKIDX_B_WIDE_BUCKET;
 constexpr int MASKIDX_B_WIDE_NW = 8;
 constexpr int LAUNCH_MASKIDX_B_WIDE = NBINS;  // launch id (not a bin) of that kernel
+// The sorting bin's units of fewer than 4^5 products run in a launch of two
+// waves per unit, and those of fewer than 4^4 in one of a wave per unit.
+constexpr int ESC_MID_FROM_BUCKET = 4;
+constexpr int ESC_LIGHT_FROM_BUCKET = 3;
+constexpr int LAUNCH_ESC_MID = NBINS + 1;
+constexpr int LAUNCH_ESC_LIGHT = NBINS + 2;
 constexpr int HEAP_CAP = 8;       // heap kind: iterators per row (entries of the row of A)
 constexpr int64_t HEAP_MAX_FLOPS = (int64_t(1) << 24) - 1;  // heap keys hold a B row's remaining length in 24 bits
 constexpr int64_t HEAP_LONG_MASK_RATIO = 8;  // auto HEAP also when the mask row has >= this many entries per product
@@ -99,9 +113,9 @@ constexpr int64_t HEAP_LM_FOLD_MAX = 4096;
 // numeric order, except that the two heap bins sit between the mask-indexed
 // wave and block bins (wave, heap, heap with long masks, block), so that each
 // heap bin and its mask-indexed neighbour form one contiguous range of units;
-// the packed bin comes last.
+// the packed and the sorting bins come last.
 __host__ __device__ inline int bin_at(int x) {
-    return x == BIN_MASKIDX_P ? x
+    return x >= BIN_MASKIDX_P ? x
            : x <= BIN_MASKIDX_W ? x
            : x == BIN_MASKIDX_W + 1 ? (int)BIN_HEAP_L
            : x == BIN_MASKIDX_W + 2 ? (int)BIN_HEAP_LM

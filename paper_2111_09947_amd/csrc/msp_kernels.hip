@@ -269,6 +269,7 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
     const bool pack_fits = !comp && mnnz <= PACK_MASK && flops <= PACK_FLOPS && alen <= PACK_ALEN;
     bool pack = false;
     int kind = force == MSP_KIND_HEAP && !heap_fits ? (int)MSP_KIND_AUTO : force;
+    const bool forced = kind != MSP_KIND_AUTO;  // a forced kind keeps its own kernels
     // a tuned kind for the row's class (products bucket x mask-length bucket), where it fits the row
     if (kind == MSP_KIND_AUTO && table) {
         const int t = table[flops_bucket(flops) * NBUCKET + flops_bucket(mnnz)];
@@ -276,13 +277,15 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
                           (t != MSP_KIND_HEAP || heap_fits);
         if (fits) kind = t;
     }
+    const bool chosen = forced || kind != MSP_KIND_AUTO;  // forced or tabled
     // Auto: light rows with a short normal mask row take eight lanes each in the packed
     // mask-indexed kernel. Other very light rows are merged one row per lane (a wave-wide kind
-    // would leave most of its lanes idle on them), and so are somewhat heavier rows whose mask row
-    // is much longer than their product count (the other kinds spend time per mask entry). Matrices of at most 512
-    // columns keep the one-wave dense tile. Under a complemented mask light rows of a wider one go
-    // to the heap, and every fitting row of one wider than a 4096-column tile, which the dense
-    // kind would restream once per tile.
+    // would leave most of its lanes idle on them), and so are somewhat heavier rows whose mask
+    // row is much longer than their product count (the other kinds spend time per mask entry).
+    // Matrices of at most 512 columns keep the one-wave dense tile. Under a complemented mask
+    // light rows of a wider one go to the heap, and every fitting row of one wider than a
+    // 4096-column tile, which the dense kind would restream once per tile; there, rows that do not
+    // fit the heap are expanded and sorted (at most ESC_MAX products).
     if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0 && n > DENSE_W_COLS && !pack_fits) {
         const bool light = flops <= heap_flops;
         if (comp ? (n > DENSE_B_COLS || light)
@@ -308,6 +311,7 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
         tiles = 1;
         if (n <= DENSE_B_COLS && split) { bin = BIN_DENSE_SPLIT; tiles = min(cdiv(flops, split_flops), alen); }
         else if (n <= DENSE_W_COLS) bin = flops > DENSE_NARROW_BLOCK_MULT * block_flops ? BIN_DENSE_BN : BIN_DENSE_W;
+        else if (comp && !chosen && n > DENSE_B_COLS && flops <= ESC_MAX) { bin = BIN_ESC; tiles = 1; }
         else { bin = BIN_DENSE_B; tiles = cdiv(n, DENSE_B_COLS); }
         break;
     case MSP_KIND_HASH:
@@ -349,7 +353,7 @@ __device__ int64_t unit_staging(const Operands& o, int64_t i, int bin, int64_t t
         adm = o.complement ? (c1 - c0) - mt : mt;
         break;
     }
-    case BIN_HEAP_L: case BIN_HEAP_LM: adm = o.complement ? o.n - mnnz : mnnz; break;
+    case BIN_HEAP_L: case BIN_HEAP_LM: case BIN_ESC: adm = o.complement ? o.n - mnnz : mnnz; break;
     case BIN_HASH_W: case BIN_MASKIDX_W: case BIN_MASKIDX_P: adm = mnnz; break;
     case BIN_HASH_B: adm = min((int64_t)HASH_B_CAP, mnnz - t * HASH_B_CAP); break;
     case BIN_MASKIDX_B: adm = min((int64_t)MASKIDX_B_CAP, mnnz - t * MASKIDX_B_CAP); break;
@@ -2097,6 +2101,160 @@ __global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
     if (MODE != MODE_DIRECT && live && q == 0) g.cnt[u] = emitted;
 }
 
+// ----------------------------------- expand, sort, fold (complemented rows)
+// One workgroup of NT threads per row of the sorting bin (a complemented mask
+// over more than DENSE_B_COLS columns, more entries of A than the heap holds,
+// at most CAP products), product-driven instead of tile by tile:
+//  1. expand: every product of the row goes to LDS as the key
+//     (column << 12 | its index in the row's product order: A's row, then
+//     each B row) and, unless counting, its term a * b; the entries of A are
+//     taken NT at a time, and a product finds its entry by a binary search
+//     over the chunk's prefix of B row lengths;
+//  2. sort the keys (a bitonic network in LDS, padded to a power of two);
+//  3. fold: the first key of each column is a candidate; it is kept when the
+//     mask admits the column (a binary search in the mask row, staged in LDS
+//     when it has at most 4 NT entries), and its value is the fold of
+//     its column's terms in key order, which is the order of A's row (the
+//     Gustavson order);
+//  4. emit the kept columns in order (each thread takes a contiguous run of
+//     sorted keys; a block scan gives the positions).
+// Work per row is O(flops log^2 flops) in LDS, independent of the width n.
+// The bin runs as three launches by product count (heaviest units first in
+// the unit list), so that light rows take small workgroups with little LDS
+// and many of them fit a CU: a wave for rows under 256 products, two waves
+// with room for 1024, four waves with room for ESC_MAX.
+// units of bucket b have fewer than 4^(b+1) products
+static_assert((int64_t(4) << (2 * ESC_LIGHT_FROM_BUCKET)) <= 256 && (int64_t(4) << (2 * ESC_MID_FROM_BUCKET)) <= 1024,
+              "the light and middle launches hold 256 and 1024 products");
+static_assert(ESC_MAX <= 4096, "product index in 12 bits");
+constexpr int esc_mcap(int nt) { return 4 * nt; }  // mask entries staged in LDS
+
+template <int SR, int MODE, bool BATCH, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
+    using T = SRT<SR>;
+    using acc_t = typename T::acc_t;
+    using in_t = typename T::in_t;
+    constexpr bool COUNT = MODE == MODE_COUNT;
+    constexpr int NW = NT / WAVE;
+    constexpr int PER = CAP / NT;  // sorted keys per thread at most
+    constexpr int MCAP = esc_mcap(NT);
+    static_assert(CAP <= 4096 && CAP % NT == 0 && PER <= 32 && (CAP & (CAP - 1)) == 0,
+                  "product index in 12 bits; whole rounds per thread; one bit per key of a run");
+    __shared__ unsigned long long key_[CAP];
+    __shared__ acc_t val_[COUNT ? 1 : CAP];
+    __shared__ int32_t off_[NT + 1];
+    __shared__ int64_t bpos_[NT];
+    __shared__ in_t aval_[T::needs_values ? NT : 1];
+    __shared__ int32_t mrow_[MCAP];
+    __shared__ int64_t tmp[NW];
+    const int t = threadIdx.x;
+    const int u = __builtin_amdgcn_readfirstlane(g.units[blockIdx.x]);
+    const Operands& o = BATCH ? g.ops[__builtin_amdgcn_readfirstlane(g.unit_prob[u])] : g.op;
+    const int64_t i = g.unit_row[u];
+    const int64_t pa0 = o.Arp[i], pa1 = o.Arp[i + 1];
+    const int64_t m0 = o.Mrp[i], m1 = o.Mrp[i + 1];
+    const bool mstaged = m1 - m0 <= MCAP;
+    if (mstaged)
+        for (int64_t q = m0 + t; q < m1; q += NT) mrow_[q - m0] = o.Mci[q];
+    // 1. expand
+    int total = 0;  // products so far (<= CAP by classification and launch)
+    for (int64_t c0 = pa0; c0 < pa1; c0 += NT) {
+        const int64_t p = c0 + t;
+        int64_t b0 = 0, len = 0;
+        in_t a = T::one();
+        if (p < pa1) {
+            const int32_t k = o.Aci[p];
+            b0 = o.Brp[k];
+            len = o.Brp[k + 1] - b0;
+            if (T::needs_values) a = T::load(o.Av, p);
+        }
+        int64_t ctot;
+        const int64_t ex = block_excl_scan<NW>(len, tmp, ctot);
+        off_[t] = (int)ex;
+        if (t == 0) off_[NT] = (int)ctot;
+        bpos_[t] = b0;
+        if (T::needs_values) aval_[t] = a;
+        __syncthreads();
+        for (int q = t; q < (int)ctot; q += NT) {
+            int lo = 0, hi = NT;  // off_[lo] <= q < off_[hi]: the last entry starting at or before q
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off_[mid] <= q) lo = mid;
+                else hi = mid;
+            }
+            const int64_t bp = bpos_[lo] + (q - off_[lo]);
+            const int slot = total + q;
+            key_[slot] = ((unsigned long long)(uint32_t)o.Bci[bp] << 12) | (unsigned long long)slot;
+            if (!COUNT) val_[slot] = T::term(T::needs_values ? aval_[lo] : T::one(), T::load(o.Bv, bp));
+        }
+        total += (int)ctot;
+        __syncthreads();  // the chunk's tables are rewritten by the next chunk
+    }
+    // 2. sort
+    int nsort = 1;
+    while (nsort < total) nsort <<= 1;
+    for (int x = total + t; x < nsort; x += NT) key_[x] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= nsort; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int x = t; x < nsort; x += NT) {
+                const int y = x ^ jj;
+                if (y > x) {
+                    const unsigned long long kx = key_[x], ky = key_[y];
+                    if ((kx > ky) == ((x & k) == 0)) {
+                        key_[x] = ky;
+                        key_[y] = kx;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // 3. candidates and the mask: thread t takes the sorted keys [e0, e1)
+    const int per = (total + NT - 1) / NT;  // <= PER
+    const int e0 = min(t * per, total), e1 = min(e0 + per, total);
+    uint32_t keepbits = 0;
+    int kept = 0;
+    int64_t ms = 0;  // the search starts past the previous candidate's position (columns ascend)
+    const int64_t mlen = m1 - m0;
+    for (int e = e0; e < e1; ++e) {
+        const uint32_t col = (uint32_t)(key_[e] >> 12);
+        if (e > 0 && (uint32_t)(key_[e - 1] >> 12) == col) continue;  // not the first of its column
+        int64_t lo = ms, hi = mlen;
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            const int32_t mc = mstaged ? mrow_[mid] : o.Mci[m0 + mid];
+            if ((uint32_t)mc < col) lo = mid + 1;
+            else hi = mid;
+        }
+        ms = lo;
+        const bool in_mask = lo < mlen && (uint32_t)(mstaged ? mrow_[lo] : o.Mci[m0 + lo]) == col;
+        if (in_mask != (o.complement != 0)) {
+            keepbits |= 1u << (e - e0);
+            ++kept;
+        }
+    }
+    int64_t ktot;
+    const int64_t pos0 = block_excl_scan<NW>(kept, tmp, ktot);
+    // 4. emit
+    if (!COUNT) {
+        const int64_t ob = g.out_off[u];
+        typename T::out_t* ov = static_cast<typename T::out_t*>(g.out_val);
+        int64_t pos = ob + pos0;
+        for (int e = e0; e < e1; ++e) {
+            if (!((keepbits >> (e - e0)) & 1u)) continue;
+            const uint32_t col = (uint32_t)(key_[e] >> 12);
+            acc_t acc = T::identity();
+            for (int f = e; f < total && (uint32_t)(key_[f] >> 12) == col; ++f)
+                acc = T::add(acc, val_[(int)(key_[f] & 0xFFFull)]);
+            g.out_col[pos] = (int32_t)col;
+            ov[pos] = T::finish(acc);
+            ++pos;
+        }
+    }
+    if (t == 0 && MODE != MODE_DIRECT) g.cnt[u] = ktot;
+}
+
 #ifndef MSP_HASH_LOOKUP
 #define MSP_HASH_LOOKUP 1
 #endif
@@ -2153,6 +2311,15 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
     case BIN_HEAP_L: case BIN_HEAP_LM:
         MSP_LAUNCH((k_heap<SR, MODE, BATCH>), dim3((unsigned)((a.nunits + HEAP_T - 1) / HEAP_T)), dim3(HEAP_T), 0,
                    s, a);
+        break;
+    case BIN_ESC:  // the heaviest units of the sorting bin
+        MSP_LAUNCH((k_esc<SR, MODE, BATCH, 4 * WAVE, (int)ESC_MAX>), gb, dim3(4 * WAVE), 0, s, a);
+        break;
+    case LAUNCH_ESC_MID:
+        MSP_LAUNCH((k_esc<SR, MODE, BATCH, 2 * WAVE, 1024>), gb, dim3(2 * WAVE), 0, s, a);
+        break;
+    case LAUNCH_ESC_LIGHT:
+        MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 256>), gb, dim3(WAVE), 0, s, a);
         break;
     case BIN_MASKIDX_P: {
         constexpr int64_t rows = PACK_WPB * PACK_RPW;

@@ -1,0 +1,150 @@
+"""GPU parity of the sorting bin: rows under a complemented mask of a matrix
+wider than one 4096-column dense tile, with more entries of A than the heap
+holds and at most 4096 products, are expanded, sorted by column, folded and
+filtered against the mask row (automatic choice only). Each case checks the
+bin ran and compares with the oracle: patterns and integer values bit-exact,
+FP64 within 1e-12 relative."""
+import numpy as np
+import pytest
+
+import mspgen
+import oracle
+from tests.gpu_util import VKIND, assert_same, msp, torch_or_skip, up
+
+pytestmark = pytest.mark.gpu
+
+SEMIRINGS = ["plus_times_f64", "plus_pair_i64", "lor_land_bool", "plus_times_i32", "plus_times_i64"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch_or_skip()
+
+
+def _plan_check(A, B, M, sr, complement=True, phase=1, **kw):
+    m = msp()
+    with m.Plan(up(A, sr), up(B, sr), up(M), complement, sr, phase=phase, **kw) as p:
+        C = p.execute()
+        bins = dict(p.bin_units)
+    assert_same(C, oracle.masked_spgemm(A, B, M, complement, sr), sr)
+    return bins
+
+
+def _limits_problem(sr, seed=5):
+    """Rows on both sides of each limit of the sorting bin, n = 20000. B row b
+    < 6000 has b % 65 entries; rows 6000..6099 all hold the same 34 columns,
+    0 and n - 1 among them. Row types (cycled): 9 entries of A with 256
+    products (sorted); 8 entries of A (heap); 64 entries with 4096 products
+    (sorted); 65 entries with 4097 products (dense tiles); 40 entries of which
+    most have empty B rows, under a mask row that holds all but five product
+    columns (sorted); 20 entries whose 680 products fold into 34 columns
+    (sorted); entries whose B rows are all empty (no products)."""
+    rng = np.random.default_rng(seed)
+    n, k = 20000, 6100
+    blen = np.arange(k) % 65
+    bcols = [np.sort(rng.choice(n, size=blen[b], replace=False)) for b in range(k)]
+    shared = np.sort(np.concatenate([[0, n - 1], rng.choice(np.arange(1, n - 1), size=32, replace=False)]))
+    for b in range(6000, k):
+        bcols[b] = shared
+    B = mspgen.from_coo(k, n, np.concatenate([np.full(len(c), b) for b, c in enumerate(bcols)]),
+                        np.concatenate(bcols))
+    by_len = {L: np.nonzero(blen[:6000] == L)[0] for L in range(65)}
+    pick = lambda L, c: rng.choice(by_len[L], size=c, replace=False)  # noqa: E731
+    arows, acols, mrows, mcols = [], [], [], []
+    m = 140
+    for i in range(m):
+        t = i % 7
+        ent = [
+            lambda: np.concatenate([pick(32, 8), pick(0, 1)]),
+            lambda: pick(20, 8),
+            lambda: pick(64, 64),
+            lambda: np.concatenate([pick(64, 64), pick(1, 1)]),
+            lambda: np.concatenate([pick(0, 36), pick(25, 4)]),
+            lambda: 6000 + rng.choice(100, size=20, replace=False),
+            lambda: pick(0, 12),
+        ][t]()
+        ent = np.unique(ent.astype(np.int64))
+        arows.append(np.full(len(ent), i))
+        acols.append(ent)
+        prod = np.unique(np.concatenate([bcols[b] for b in ent]))
+        if t == 4:
+            mc = prod[: len(prod) - 5]
+        else:
+            third = rng.choice(prod, size=len(prod) // 3, replace=False) if len(prod) else prod
+            mc = np.unique(np.concatenate([third, rng.choice(n, size=50, replace=False)]))
+        mrows.append(np.full(len(mc), i))
+        mcols.append(mc)
+    A = mspgen.from_coo(m, k, np.concatenate(arows), np.concatenate(acols))
+    M = mspgen.from_coo(m, n, np.concatenate(mrows), np.concatenate(mcols))
+    vk = VKIND[sr]
+    A = A.with_values(mspgen.random_values(A.nnz, vk, np.random.default_rng(seed + 10)))
+    B = B.with_values(mspgen.random_values(B.nnz, vk, np.random.default_rng(seed + 20)))
+    return A, B, M
+
+
+def _row_classes(A, B):
+    alen = np.diff(A.rowptr)
+    bl = np.diff(B.rowptr)
+    fl = np.array([bl[A.colidx[A.rowptr[i]:A.rowptr[i + 1]]].sum() for i in range(A.nrows)])
+    return alen, fl
+
+
+@pytest.mark.parametrize("phase", [1, 2])
+@pytest.mark.parametrize("sr", SEMIRINGS)
+def test_sorting_limits(sr, phase):
+    A, B, M = _limits_problem(sr)
+    alen, fl = _row_classes(A, B)
+    expect = int(((alen > 8) & (fl <= 4096) & (fl > 0)).sum())
+    bins = _plan_check(A, B, M, sr, phase=phase)
+    assert bins["sort_block"] == expect and expect > 0, (bins, expect)
+    assert bins["heap_lane"] > 0 and bins["dense_block"] > 0
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_i32"])
+def test_forced_dense_never_sorts(sr):
+    A, B, M = _limits_problem(sr, seed=6)
+    bins = _plan_check(A, B, M, sr, force_kind="dense")
+    assert bins["sort_block"] == 0
+
+
+def test_normal_mask_never_sorts():
+    A, B, M = _limits_problem("plus_times_f64", seed=7)
+    bins = _plan_check(A, B, M, "plus_times_f64", complement=False)
+    assert bins["sort_block"] == 0
+
+
+def test_wide_complement_heavy_rows():
+    """2000 rows of about 16 entries over a graph of 2^20 vertices under a
+    complemented mask of degree 8: every row with more than 8 entries sorts
+    (the tiled dense kind would restream each such row 256 times)."""
+    n = 1 << 20
+    A = mspgen.er(2000, n, 16.0, 41, "f64")
+    B = mspgen.er(n, n, 16.0, 42, "f64")
+    M = mspgen.er(2000, n, 8.0, 43, None)
+    m = msp()
+    dA, dB, dM = up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M)
+    with m.Plan(dA, dB, dM, True, "plus_times_f64") as p:
+        C = p.execute()
+        alen = np.diff(A.rowptr)
+        assert p.bin_units["sort_block"] == int((alen > 8).sum()) > 1500
+    assert_same(C, oracle.masked_spgemm(A, B, M, True, "plus_times_f64"), "plus_times_f64")
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "lor_land_bool"])
+def test_sorting_rows_in_a_batch(sr):
+    torch = torch_or_skip()
+    m = msp()
+    probs = [(*_limits_problem(sr, seed=8), True), (*_limits_problem(sr, seed=9), True)]
+    n = 1 << 16
+    probs.append((mspgen.er(500, n, 12.0, 51, VKIND[sr]), mspgen.er(n, n, 12.0, 52, VKIND[sr]),
+                  mspgen.er(500, n, 8.0, 53, None), True))
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr) as b:
+            assert b.bin_units["sort_block"] > 0
+            b.bind_new_outputs()
+            for _ in range(2):
+                b.graph_launch()
+                for (A, B, M, c), C in zip(probs, b.results()):
+                    assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
