@@ -163,6 +163,7 @@ struct msp_plan {
     int64_t bin_off[NBINS + 1] = {};
     bool heap_fold = false;     // BIN_HEAP_L units run in the mask-indexed wave kernel's launch
     bool heap_lm_fold = false;  // BIN_HEAP_LM units run in the mask-indexed block kernel's launch
+    bool heap_sort = false;     // BIN_HEAP_L units run in the one-wave sorting kernel
     int64_t seg_off[NBINS * NBUCKET] = {};
     int64_t nsplit = 0;
     // execution workspace: valid for the workspace the units were last placed in
@@ -669,6 +670,12 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
                    P->bin_count[BIN_HEAP_L] <= HEAP_FOLD_MAX && heap_apart == 0;
     P->heap_lm_fold = o.force_kind == MSP_KIND_AUTO && P->bin_count[BIN_HEAP_LM] > 0 &&
                       P->bin_count[BIN_HEAP_LM] <= HEAP_LM_FOLD_MAX && heap_lm_apart == 0;
+    // A small heap bin that no mask-indexed launch takes (complemented rows) is as slow as its
+    // longest lane's serial merge; when each of its rows has fewer than 256 products, the
+    // one-wave sorting kernel runs them side by side instead.
+    P->heap_sort = o.force_kind == MSP_KIND_AUTO && !P->heap_fold && P->bin_count[BIN_HEAP_L] > 0 &&
+                   P->bin_count[BIN_HEAP_L] <= HEAP_FOLD_MAX &&
+                   P->seg_off[BIN_HEAP_L * NBUCKET + ESC_LIGHT_FROM_BUCKET] == P->bin_off[BIN_HEAP_L];
     if (P->U >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many work units");
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
@@ -970,7 +977,7 @@ static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream
                 continue;
             }
         }
-        MSP_HIP(launch_numeric(P->sr, b, mode, ab, s));
+        MSP_HIP(launch_numeric(P->sr, P->heap_sort && b == BIN_HEAP_L ? LAUNCH_ESC_LIGHT : b, mode, ab, s));
         if (tm) MSP_CHECK(tm->end());
     }
     return MSP_OK;

@@ -283,12 +283,12 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
     // would leave most of its lanes idle on them), and so are somewhat heavier rows whose mask
     // row is much longer than their product count (the other kinds spend time per mask entry).
     // Matrices of at most 512 columns keep the one-wave dense tile. Under a complemented mask
-    // light rows of a wider one go to the heap, and every fitting row of one wider than a
-    // 4096-column tile, which the dense kind would restream once per tile; there, rows that do not
-    // fit the heap are expanded and sorted (at most ESC_MAX products).
+    // light rows of a wider one go to the heap. Rows of one wider than a 4096-column tile, which
+    // the dense kind would restream once per tile, are expanded and sorted when they have at most
+    // ESC_MAX products, and otherwise go to the heap where they fit it.
     if (kind == MSP_KIND_AUTO && heap_fits && heap_flops > 0 && n > DENSE_W_COLS && !pack_fits) {
         const bool light = flops <= heap_flops;
-        if (comp ? (n > DENSE_B_COLS || light)
+        if (comp ? (light || (n > DENSE_B_COLS && flops > ESC_MAX))
                  : (light || (flops <= HEAP_LONG_MASK_FLOPS * heap_flops && mnnz >= HEAP_LONG_MASK_RATIO * flops)))
             kind = MSP_KIND_HEAP;
     }

@@ -157,12 +157,19 @@ def test_auto_picks_heap_for_light_rows():
     C, R, bins, _ = run_plan(A, B, Mc, True, sr)
     assert_same(C, R, sr)
     assert bins["heap"] > 1000
-    # a complemented mask wider than one 4096-column dense tile: every fitting row, however
-    # many products it has
+    # a complemented mask wider than one 4096-column dense tile: rows of at most heap_flops
+    # products take the heap, heavier ones are sorted; with a large heap_flops every fitting
+    # row takes the heap, however many products it has
     A2 = clip_rows(mspgen.er(2000, 500, 4.0, 95, "f64"), HEAP_CAP)
     B2 = mspgen.er(500, 10000, 20.0, 96, "f64")
     M2 = mspgen.er(2000, 10000, 50.0, 97, None)
+    deg_b = np.diff(B2.rowptr)
+    flops = np.array([deg_b[A2.colidx[A2.rowptr[i]:A2.rowptr[i + 1]]].sum() for i in range(A2.nrows)])
     C, R, bins, _ = run_plan(A2, B2, M2, True, sr)
+    assert_same(C, R, sr)
+    assert bins["heap"] == int(((flops > 0) & (flops <= 32)).sum()) > 0
+    assert bins["sort_block"] == int((flops > 32).sum()) > 0
+    C, R, bins, _ = run_plan(A2, B2, M2, True, sr, heap_flops=1 << 20)
     assert_same(C, R, sr)
     assert bins["heap"] == rows_with_output_bound(A2, B2, M2, True)
 

@@ -1,9 +1,9 @@
 """GPU parity of the sorting bin: rows under a complemented mask of a matrix
-wider than one 4096-column dense tile, with more entries of A than the heap
-holds and at most 4096 products, are expanded, sorted by column, folded and
-filtered against the mask row (automatic choice only). Each case checks the
-bin ran and compares with the oracle: patterns and integer values bit-exact,
-FP64 within 1e-12 relative."""
+wider than one 4096-column dense tile, with more products than the heap
+takes automatically (heap_flops, 32 by default) and at most 4096, are
+expanded, sorted by column, folded and filtered against the mask row
+(automatic choice only). Each case checks the bin ran and compares with the
+oracle: patterns and integer values bit-exact, FP64 within 1e-12 relative."""
 import numpy as np
 import pytest
 
@@ -34,11 +34,13 @@ def _limits_problem(sr, seed=5):
     """Rows on both sides of each limit of the sorting bin, n = 20000. B row b
     < 6000 has b % 65 entries; rows 6000..6099 all hold the same 34 columns,
     0 and n - 1 among them. Row types (cycled): 9 entries of A with 256
-    products (sorted); 8 entries of A (heap); 64 entries with 4096 products
-    (sorted); 65 entries with 4097 products (dense tiles); 40 entries of which
-    most have empty B rows, under a mask row that holds all but five product
-    columns (sorted); 20 entries whose 680 products fold into 34 columns
-    (sorted); entries whose B rows are all empty (no products)."""
+    products (sorted); 8 entries of A with 160 products (sorted); 64 entries
+    with 4096 products (sorted); 65 entries with 4097 products (dense tiles);
+    40 entries of which most have empty B rows, under a mask row that holds
+    all but five product columns (sorted); 20 entries whose 680 products
+    fold into 34 columns (sorted); entries whose B rows are all empty (no
+    products); 4 entries with 32 products (heap); 3 entries with 33 products
+    (sorted)."""
     rng = np.random.default_rng(seed)
     n, k = 20000, 6100
     blen = np.arange(k) % 65
@@ -51,9 +53,9 @@ def _limits_problem(sr, seed=5):
     by_len = {L: np.nonzero(blen[:6000] == L)[0] for L in range(65)}
     pick = lambda L, c: rng.choice(by_len[L], size=c, replace=False)  # noqa: E731
     arows, acols, mrows, mcols = [], [], [], []
-    m = 140
+    m = 180
     for i in range(m):
-        t = i % 7
+        t = i % 9
         ent = [
             lambda: np.concatenate([pick(32, 8), pick(0, 1)]),
             lambda: pick(20, 8),
@@ -62,6 +64,8 @@ def _limits_problem(sr, seed=5):
             lambda: np.concatenate([pick(0, 36), pick(25, 4)]),
             lambda: 6000 + rng.choice(100, size=20, replace=False),
             lambda: pick(0, 12),
+            lambda: pick(8, 4),
+            lambda: np.concatenate([pick(11, 3)]),
         ][t]()
         ent = np.unique(ent.astype(np.int64))
         arows.append(np.full(len(ent), i))
@@ -94,10 +98,11 @@ def _row_classes(A, B):
 def test_sorting_limits(sr, phase):
     A, B, M = _limits_problem(sr)
     alen, fl = _row_classes(A, B)
-    expect = int(((alen > 8) & (fl <= 4096) & (fl > 0)).sum())
+    expect = int(((fl > 32) & (fl <= 4096)).sum())
     bins = _plan_check(A, B, M, sr, phase=phase)
     assert bins["sort_block"] == expect and expect > 0, (bins, expect)
-    assert bins["heap_lane"] > 0 and bins["dense_block"] > 0
+    assert bins["heap_lane"] == int(((fl > 0) & (fl <= 32)).sum()) > 0
+    assert bins["dense_block"] == int((fl > 4096).sum()) * 5  # 20000 columns: five 4096-column tiles
 
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_i32"])
@@ -115,8 +120,8 @@ def test_normal_mask_never_sorts():
 
 def test_wide_complement_heavy_rows():
     """2000 rows of about 16 entries over a graph of 2^20 vertices under a
-    complemented mask of degree 8: every row with more than 8 entries sorts
-    (the tiled dense kind would restream each such row 256 times)."""
+    complemented mask of degree 8: every row with more than 32 products
+    sorts (the tiled dense kind would restream each such row 256 times)."""
     n = 1 << 20
     A = mspgen.er(2000, n, 16.0, 41, "f64")
     B = mspgen.er(n, n, 16.0, 42, "f64")
@@ -125,8 +130,8 @@ def test_wide_complement_heavy_rows():
     dA, dB, dM = up(A, "plus_times_f64"), up(B, "plus_times_f64"), up(M)
     with m.Plan(dA, dB, dM, True, "plus_times_f64") as p:
         C = p.execute()
-        alen = np.diff(A.rowptr)
-        assert p.bin_units["sort_block"] == int((alen > 8).sum()) > 1500
+        _, fl = _row_classes(A, B)
+        assert p.bin_units["sort_block"] == int((fl > 32).sum()) > 1900
     assert_same(C, oracle.masked_spgemm(A, B, M, True, "plus_times_f64"), "plus_times_f64")
 
 
