@@ -164,6 +164,9 @@ struct msp_plan {
     bool heap_fold = false;     // BIN_HEAP_L units run in the mask-indexed wave kernel's launch
     bool heap_lm_fold = false;  // BIN_HEAP_LM units run in the mask-indexed block kernel's launch
     bool heap_sort = false;     // BIN_HEAP_L units run in the one-wave sorting kernel
+    bool narrow = false;        // the dense kernels read a 16-bit copy of B's column indices
+    int64_t narrow_n = 0;       // entries of that copy (nnz(B) when narrow)
+    uint16_t* bci16 = nullptr;  // that copy (execution workspace), made by every execution
     int64_t seg_off[NBINS * NBUCKET] = {};
     int64_t nsplit = 0;
     // execution workspace: valid for the workspace the units were last placed in
@@ -385,6 +388,8 @@ static size_t exec_layout(msp_plan* P, char* base, bool staging) {
     L.take(&P->xpart, scan_partial_elems(U + 1));
     L.take(&P->split_first, P->nsplit);
     L.take(&P->split_nchunk, P->nsplit);
+    if (P->narrow_n > 0) L.take(&P->bci16, P->narrow_n);
+    else P->bci16 = nullptr;
     L.bytes(reinterpret_cast<void**>(&P->gacc), (size_t)(P->nsplit > 0 ? P->nsplit : 1) * split_acc_bytes(P->sr));
     if (staging) {
         L.take(&P->stg_col, P->S);
@@ -397,6 +402,18 @@ static size_t exec_layout(msp_plan* P, char* base, bool staging) {
 }
 
 static bool exec_staging(const msp_plan* P) { return P->opt.phase == 1; }
+
+// Bytes of the execution workspace: a size-only walk of exec_layout on a copy
+// of the sizes, which leaves the plan's placed pointers alone.
+static size_t exec_size(const msp_plan* P, bool staging) {
+    msp_plan tmp;
+    tmp.U = P->U;
+    tmp.S = P->S;
+    tmp.nsplit = P->nsplit;
+    tmp.sr = P->sr;
+    tmp.narrow_n = P->narrow_n;
+    return exec_layout(&tmp, nullptr, staging);
+}
 
 // B^T of product `pr`: column counts and their prefix sum (always), rows
 // scattered (when `scatter`). Rows of B^T come out in no particular order.
@@ -676,6 +693,18 @@ static msp_status plan_create_impl(msp_plan* P, const msp_problem* probs, int64_
     P->heap_sort = o.force_kind == MSP_KIND_AUTO && !P->heap_fold && P->bin_count[BIN_HEAP_L] > 0 &&
                    P->bin_count[BIN_HEAP_L] <= HEAP_FOLD_MAX &&
                    P->seg_off[BIN_HEAP_L * NBUCKET + ESC_LIGHT_FROM_BUCKET] == P->bin_off[BIN_HEAP_L];
+    // The one-tile dense kernels of a single product over at most 512 columns re-read B's rows
+    // once per entry of A that selects them: when their products (a lower bound from the flops
+    // buckets) come to NARROW_REUSE times nnz(B) or more, each execution first copies B's column
+    // indices to 16 bits, halving the bytes of the column stream.
+    if (P->P == 1 && P->prods[0].op.n <= DENSE_W_COLS && P->prods[0].nnzB > 0) {
+        int64_t dense_flops = 0;
+        for (int b : {BIN_DENSE_W, BIN_DENSE_BN, BIN_DENSE_SPLIT})
+            for (int q = 0; q < NBUCKET; ++q)
+                dense_flops += segc[(size_t)(b * NBUCKET + q)] * (q == 0 ? 1 : (int64_t(1) << (2 * q)));
+        P->narrow = dense_flops >= NARROW_REUSE * P->prods[0].nnzB;
+    }
+    P->narrow_n = P->narrow ? P->prods[0].nnzB : 0;
     if (P->U >= INT32_MAX) return fail(MSP_ERR_UNSUPPORTED, "too many work units");
     for (int64_t p = 0; p < count; ++p) {
         Product& pr = P->prods[(size_t)p];
@@ -787,6 +816,7 @@ static NumArgs num_args(const msp_plan* P, int b) {
     a.nsplit = P->nsplit;
     a.gset = P->gacc;
     a.gval = P->gacc + (size_t)P->nsplit * (DENSE_B_COLS / 32);
+    if (P->narrow) a.op.Bci16 = P->bci16;
     return a;
 }
 
@@ -932,6 +962,11 @@ struct StageTimer {
 // mask-indexed neighbour's launch: BIN_HEAP_L's units directly follow the
 // wave bin's, BIN_HEAP_LM's directly precede the block bin's.
 static msp_status launch_bins(msp_plan* P, int mode, const NumArgs& a, hipStream_t s, StageTimer* tm) {
+    if (P->narrow) {  // the 16-bit copy of B's column indices that the dense kernels read
+        if (tm) MSP_CHECK(tm->begin(MSP_STAGE_PLACE));
+        MSP_HIP(launch_narrow_cols(P->prods[0].op.Bci, P->bci16, P->prods[0].nnzB, s));
+        if (tm) MSP_CHECK(tm->end());
+    }
     for (int b = 0; b < NBINS; ++b) {
         if ((P->heap_fold && b == BIN_HEAP_L) || (P->heap_lm_fold && b == BIN_HEAP_LM)) continue;
         const int64_t after = P->heap_fold && b == BIN_MASKIDX_W ? P->bin_count[BIN_HEAP_L] : 0;
@@ -1214,14 +1249,7 @@ msp_status msp_plan_create(msp_plan** plan, const msp_csr* A, const msp_csr* B, 
 
 msp_status msp_workspace_size(const msp_plan* P, size_t* bytes) {
     if (!P || !bytes) return fail(MSP_ERR_INVALID_ARGUMENT, "NULL argument");
-    msp_plan* Q = const_cast<msp_plan*>(P);
-    // a size-only walk: the layout with no base leaves the placed pointers alone
-    msp_plan tmp;
-    tmp.U = Q->U;
-    tmp.S = Q->S;
-    tmp.nsplit = Q->nsplit;
-    tmp.sr = Q->sr;
-    *bytes = exec_layout(&tmp, nullptr, exec_staging(Q));
+    *bytes = exec_size(P, exec_staging(P));
     return MSP_OK;
 }
 
@@ -1241,13 +1269,8 @@ msp_status msp_numeric(msp_plan* P, msp_csr_out* C, void* workspace, size_t work
     MSP_CHECK(check_out(P->prods[0], C));
     size_t need = 0;
     MSP_CHECK(msp_workspace_size(P, &need));
-    if (P->opt.phase == 1) {  // a one-phase plan's size includes staging that the two-phase steps leave unused
-        msp_plan tmp;
-        tmp.U = P->U;
-        tmp.nsplit = P->nsplit;
-        tmp.sr = P->sr;
-        need = exec_layout(&tmp, nullptr, false);
-    }
+    if (P->opt.phase == 1) need = exec_size(P, false);  // a one-phase plan's size includes staging
+                                                         // that the two-phase steps leave unused
     if (workspace_bytes < need) return fail(MSP_ERR_INSUFFICIENT_CAPACITY, "execution workspace too small");
     StageTimer none;
     return numeric_impl(P, C, workspace, (hipStream_t)stream, none);

@@ -71,6 +71,9 @@ constexpr int64_t PACK_FLOPS = 256;
 // ESC_MAX products such a row is expanded into LDS, sorted by column, folded
 // and filtered against its mask row instead (automatic choice only).
 constexpr int64_t ESC_MAX = 4096;
+// Dense kernels read a 16-bit copy of B's column indices when their products
+// come to at least this many times nnz(B) (single products, n <= 512).
+constexpr int64_t NARROW_REUSE = 4;
 constexpr int INNER_ACAP = 1024;  // A row (column indices) staged in LDS up to this length
 constexpr int BLOCK_NW = 4;       // waves per block for the block kinds
 #ifndef MSP_MASKIDX_B_NW
@@ -161,6 +164,7 @@ struct Operands {
     const int64_t* Brp; const int32_t* Bci; const void* Bv;
     const int64_t* Mrp; const int32_t* Mci;
     const int64_t* BTrp; const int32_t* BTci; const void* BTv;  // B^T (inner kind)
+    const uint16_t* Bci16;  // B's column indices in 16 bits (single products, n <= 65536), or null
     int complement;
 };
 
@@ -322,6 +326,7 @@ hipError_t launch_split_emit(int semiring, int mode, const NumArgs& a, hipStream
 // Bytes of the global accumulator per split row.
 size_t split_acc_bytes(int semiring);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, hipStream_t s);
+hipError_t launch_narrow_cols(const int32_t* in, uint16_t* out, int64_t n, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 // Row pointers of every product: C_p.rowptr[i] = out_off[unit_base[row_off_p + i]] - out_off[unit_first_p].
 // `outs` (device, P entries) or `one` (P == 1); `ent_off` (device, P + 1) = row_off_p + p.

@@ -848,21 +848,44 @@ constexpr int STREAM_U = MSP_STREAM_U;
 // An int32 in global memory (addresses rebuilt from integers keep their
 // address space, so the loads stay global rather than flat).
 typedef __attribute__((address_space(1))) const int32_t gint32_t;
+typedef __attribute__((address_space(1))) const uint16_t guint16_t;
+
+// B's column indices as the dense kernels read them: int32, or the 16-bit
+// copy that an execution makes when B has at most 65536 columns.
+template <class CI>
+__device__ __forceinline__ const CI* bcols(const Operands& o) {
+    static_assert(std::is_same<CI, int32_t>::value || std::is_same<CI, uint16_t>::value, "int32 or uint16 columns");
+    if constexpr (std::is_same<CI, uint16_t>::value) return o.Bci16;
+    else return o.Bci;
+}
+
+// First position p in [lo, hi) with a[p] >= key (a sorted ascending).
+template <class CI>
+__device__ __forceinline__ int64_t lower_bound_c(const CI* __restrict__ a, int64_t lo, int64_t hi, int64_t key) {
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
 
 // B's values are parallel to its column indices: the value of the product
-// whose column index sits at byte address cb is at Bv + (cb - Bci) / 4 * w
-// for values of w bytes. With a per-operand constant this is one shift-add.
-template <int W>
+// whose column index (of CW bytes) sits at byte address cb is at
+// Bv + (cb - Bci) / CW * w for values of w bytes. With a per-operand constant
+// this is one shift-add.
+template <int W, int CW = 4>
 struct ValAddr {
-    uint64_t d;
-    __device__ ValAddr(const void* Bv, const int32_t* Bci)
-        : d(W == 8 ? (uint64_t)Bv - 2ull * (uint64_t)Bci
-            : W == 4 ? (uint64_t)Bv - (uint64_t)Bci
-                     : (uint64_t)Bv - ((uint64_t)Bci >> 2)) {}
-    __device__ uint64_t at(uint64_t cb) const {
-        static_assert(W == 8 || W == 4 || W == 1, "value widths 1, 4 or 8");
-        return (W == 8 ? cb << 1 : W == 4 ? cb : cb >> 2) + d;  // Bci and cb are 4-byte aligned
+    static_assert(W == 8 || W == 4 || W == 1, "value widths 1, 4 or 8");
+    static_assert(CW == 4 || CW == 2, "column widths 4 or 2");
+    static constexpr int L = (W == 8 ? 3 : W == 4 ? 2 : 0) - (CW == 4 ? 2 : 1);  // log2(W / CW)
+    // byte address scaled by W / CW (exact: Bci and cb are CW-byte aligned)
+    __device__ static uint64_t scale(uint64_t x) {
+        if constexpr (L >= 0) return x << L;
+        else return x >> (-L);
     }
+    uint64_t d;
+    __device__ ValAddr(const void* Bv, const void* Bci) : d((uint64_t)Bv - scale((uint64_t)Bci)) {}
+    __device__ uint64_t at(uint64_t cb) const { return scale(cb) + d; }
 };
 
 // Per-wave LDS for one batch of up to 64 A entries: for the s-th stanza with
@@ -901,7 +924,7 @@ struct StanzaLds {
 //   + popcount(map bits 0 .. 64u + lane) - 1.
 // The STREAM_U loads of a lane are issued back to back before any of them is
 // consumed, so a wave keeps STREAM_U stanza reads outstanding.
-template <class T, class F, class E>
+template <class T, class CI = int32_t, class F, class E>
 __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, int64_t pa1, bool window, int32_t lo,
                                                 int32_t hi, int wv, int nw, StanzaLds<T>& st, F&& f, E&& batch_end,
                                                 int* claim = nullptr) {
@@ -927,8 +950,8 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
             b1 = o.Brp[k + 1];
             if (T::needs_values) a = T::load(o.Av, p);
             if (window) {
-                b0 = lower_bound_g(o.Bci, b0, b1, lo);
-                b1 = lower_bound_g(o.Bci, b0, b1, (int64_t)hi + 1);
+                b0 = lower_bound_c(bcols<CI>(o), b0, b1, lo);
+                b1 = lower_bound_c(bcols<CI>(o), b0, b1, (int64_t)hi + 1);
             }
         }
         const int64_t len = b1 - b0;
@@ -940,7 +963,7 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
         if (len > 0) {
             const int sl = rank_below(nzm);
             st.start[sl] = incl - len;
-            st.ptr[sl] = (uint64_t)(o.Bci + b0) - 4ull * (uint64_t)(incl - len);
+            st.ptr[sl] = (uint64_t)(bcols<CI>(o) + b0) - sizeof(CI) * (uint64_t)(incl - len);
             if constexpr (T::needs_values) st.a[sl] = a;
         }
         wave_lds_sync();
@@ -973,12 +996,13 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
                 sidx[u] = cum + (int)(Sw[u] & 1ull) + rank_below(Sw[u] >> 1);
                 cum += __popcll(Sw[u]);
             }
-            // the product at flattened position x of stanza s sits at byte st.ptr[s] + 4x
+            // the product at flattened position x of stanza s sits at byte st.ptr[s] + x * sizeof(CI)
             // (slot u adds 64u entries: an immediate offset of the load)
-            const uint64_t pos4 = 4ull * (uint64_t)(base + ln);
-            const gint32_t* bp[STREAM_U];
+            using gci_t = typename std::conditional<sizeof(CI) == 2, guint16_t, gint32_t>::type;
+            const uint64_t pos4 = sizeof(CI) * (uint64_t)(base + ln);
+            const gci_t* bp[STREAM_U];
 #pragma unroll
-            for (int u = 0; u < STREAM_U; ++u) bp[u] = reinterpret_cast<const gint32_t*>(st.ptr[sidx[u]] + pos4);
+            for (int u = 0; u < STREAM_U; ++u) bp[u] = reinterpret_cast<const gci_t*>(st.ptr[sidx[u]] + pos4);
             uint64_t cb[STREAM_U];
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u) cb[u] = (uint64_t)(bp[u] + u * WAVE);
@@ -991,7 +1015,7 @@ __device__ __forceinline__ void stream_products(const Operands& o, int64_t pa0, 
                 for (int u = 0; u < STREAM_U; ++u) act[u] = FULL || u * WAVE + ln < lim;
                 int32_t j[STREAM_U];
 #pragma unroll
-                for (int u = 0; u < STREAM_U; ++u) j[u] = (FULL || act[u]) ? bp[u][u * WAVE] : 0;
+                for (int u = 0; u < STREAM_U; ++u) j[u] = (FULL || act[u]) ? (int32_t)bp[u][u * WAVE] : 0;
                 f(j, sidx, cb, act);
             };
             if (lim == WIN) run(std::integral_constant<bool, true>{});
@@ -1020,7 +1044,7 @@ __device__ __forceinline__ int* batch_claim(int* counter, int64_t alen) {
 // u goes to vals[slot[u]] when slot[u] >= 0 (-1: not admitted). B values are
 // loaded only for admitted products; all loads of the window are issued
 // before the first LDS update.
-template <class T, bool FLAGS, bool COUNT>
+template <class T, bool FLAGS, bool COUNT, class CI = int32_t>
 __device__ __forceinline__ void window_accumulate(const int* slot, const int* s, const uint64_t* cb,
                                                   const Operands& o, const StanzaLds<T>& st,
                                                   typename T::acc_t* vals, uint8_t* flags) {
@@ -1029,7 +1053,7 @@ __device__ __forceinline__ void window_accumulate(const int* slot, const int* s,
 #pragma unroll
         for (int u = 0; u < STREAM_U; ++u) b[u] = T::one();
         if (T::needs_values && o.Bv) {  // one uniform test per window (iso-valued B: all ones)
-            const ValAddr<T::vbytes> va(o.Bv, o.Bci);
+            const ValAddr<T::vbytes, (int)sizeof(CI)> va(o.Bv, bcols<CI>(o));
 #pragma unroll
             for (int u = 0; u < STREAM_U; ++u)
                 if (slot[u] >= 0) b[u] = T::load_at(va.at(cb[u]));
@@ -1129,7 +1153,7 @@ __device__ __forceinline__ void unit_sync() {
 // the mask row), values and (where the value cannot tell) inserted flags.
 // Emission scans the tile in column order, so rows come out sorted for both
 // mask modes.
-template <int SR, int MODE, int NW, int W, int WPB, bool BATCH>
+template <int SR, int MODE, int NW, int W, int WPB, bool BATCH, class CI = int32_t>
 __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SRT<SR>::sep_flag ? 5 : MSP_MINW_BLOCK)
                                                     : MSP_MINW_WAVE) void k_dense(NumArgs g) {
     static_assert(NW == 1 || WPB == 1, "a block holds one multi-wave unit or several one-wave units");
@@ -1186,7 +1210,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
     // the waves share every batch's windows: claiming whole batches measured slower with the
     // 512-column tile (the waves' concurrent LDS updates of the same few columns) and no faster
     // with the 4096-column one
-    stream_products<T>(o, o.Arp[i], o.Arp[i + 1], tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
+    stream_products<T, CI>(o, o.Arp[i], o.Arp[i + 1], tiled, (int32_t)c0, (int32_t)(c0 + wt - 1), wv, NW, S,
                        [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
                            uint32_t w[STREAM_U];
@@ -1199,7 +1223,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u)
                                c[u] = act[u] && __builtin_amdgcn_ubfe(w[u], (uint32_t)c[u], 1) ? c[u] : -1;
-                           window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
+                           window_accumulate<T, FLAGS, COUNT, CI>(c, s, cb, o, S, vals, flags);
                        },
                        [] {});
     unit_sync<NW>();
@@ -1224,7 +1248,7 @@ __global__ __launch_bounds__(NW * WPB * WAVE, NW > 1 ? (W <= DENSE_W_COLS && !SR
 // in global memory with atomics (inserted bits, and values with the
 // semiring's (+)); a second kernel emits every split row in column order.
 // Integer semirings stay exact; FP64 sums are reordered (within tolerance).
-template <int SR, int MODE, bool BATCH, int LW>
+template <int SR, int MODE, bool BATCH, int LW, class CI = int32_t>
 __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split(NumArgs g) {
     // LW: the LDS tile (n <= LW); the global accumulator of a split row keeps DENSE_B_COLS columns
     using T = SRT<SR>;
@@ -1269,7 +1293,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
     const int64_t chunk = (alen + nchunk - 1) / nchunk;
     const int64_t a0 = ra0 + min((int64_t)t * chunk, alen), a1 = ra0 + min((int64_t)(t + 1) * chunk, alen);
     StanzaLds<T>& S = st[wv];
-    stream_products<T>(o, a0, a1, false, 0, 0, wv, NW, S,
+    stream_products<T, CI>(o, a0, a1, false, 0, 0, wv, NW, S,
                        [&](const int32_t* j, const int* s, const uint64_t* cb, const bool* act) {
                            int c[STREAM_U];
                            uint32_t w[STREAM_U];
@@ -1281,7 +1305,7 @@ __global__ __launch_bounds__(BLOCK_NW * WAVE, MSP_MINW_BLOCK) void k_dense_split
 #pragma unroll
                            for (int u = 0; u < STREAM_U; ++u)
                                c[u] = act[u] && __builtin_amdgcn_ubfe(w[u], (uint32_t)c[u], 1) ? c[u] : -1;
-                           window_accumulate<T, FLAGS, COUNT>(c, s, cb, o, S, vals, flags);
+                           window_accumulate<T, FLAGS, COUNT, CI>(c, s, cb, o, S, vals, flags);
                        },
                        [] {}, batch_claim<NW>(&claim, a1 - a0));
     __syncthreads();
@@ -2274,7 +2298,8 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
     const dim3 bw(WPB * WAVE), bb(BLOCK_NW * WAVE);
     switch (bin) {
     case BIN_DENSE_W:
-        MSP_LAUNCH((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB, BATCH>), gw, bw, 0, s, a);
+        if (!BATCH && a.op.Bci16) MSP_LAUNCH((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB, BATCH, uint16_t>), gw, bw, 0, s, a);
+        else MSP_LAUNCH((k_dense<SR, MODE, 1, DENSE_W_COLS, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_DENSE_B:
         MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_B_COLS, 1, BATCH>), gb, bb, 0, s, a);
@@ -2300,10 +2325,13 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
         MSP_LAUNCH((k_inner<SR, MODE, INNER_CAP, INNER_ACAP, WPB, BATCH>), gw, bw, 0, s, a);
         break;
     case BIN_DENSE_BN:
-        MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH>), gb, bb, 0, s, a);
+        if (!BATCH && a.op.Bci16) MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH, uint16_t>), gb, bb, 0, s, a);
+        else MSP_LAUNCH((k_dense<SR, MODE, BLOCK_NW, DENSE_W_COLS, 1, BATCH>), gb, bb, 0, s, a);
         break;
     case BIN_DENSE_SPLIT:  // a narrow LDS tile (more blocks per CU) when every column fits it
-        if (!BATCH && a.op.n <= DENSE_W_COLS)
+        if (!BATCH && a.op.n <= DENSE_W_COLS && a.op.Bci16)
+            MSP_LAUNCH((k_dense_split<SR, MODE, BATCH, DENSE_W_COLS, uint16_t>), gb, bb, 0, s, a);
+        else if (!BATCH && a.op.n <= DENSE_W_COLS)
             MSP_LAUNCH((k_dense_split<SR, MODE, BATCH, DENSE_W_COLS>), gb, bb, 0, s, a);
         else
             MSP_LAUNCH((k_dense_split<SR, MODE, BATCH, DENSE_B_COLS>), gb, bb, 0, s, a);
@@ -2390,6 +2418,35 @@ size_t split_acc_bytes(int) {
 __global__ void k_fill_u32(unsigned int* p, int64_t n) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
         p[x] = 0u;
+}
+
+// B's column indices narrowed to 16 bits (B has at most 65536 columns), four
+// per thread when the input is 16-byte aligned.
+__global__ __launch_bounds__(256) void k_narrow_cols(const int32_t* __restrict__ in, uint16_t* __restrict__ out,
+                                                     int64_t n, int vec) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vec) {
+        const int64_t n4 = n / 4;
+        for (int64_t q = t0; q < n4; q += stride) {
+            const int4 v = reinterpret_cast<const int4*>(in)[q];
+            const uint2 w = make_uint2(((uint32_t)v.y << 16) | ((uint32_t)v.x & 0xFFFFu),
+                                       ((uint32_t)v.w << 16) | ((uint32_t)v.z & 0xFFFFu));
+            reinterpret_cast<uint2*>(out)[q] = w;  // out is 256-byte aligned
+        }
+        for (int64_t q = n4 * 4 + t0; q < n; q += stride) out[q] = (uint16_t)in[q];
+    } else {
+        for (int64_t q = t0; q < n; q += stride) out[q] = (uint16_t)in[q];
+    }
+}
+
+hipError_t launch_narrow_cols(const int32_t* in, uint16_t* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int vec = ((uintptr_t)in % 16) == 0;
+    const int64_t work = vec ? (n + 3) / 4 : n;
+    const unsigned grid = (unsigned)std::min<int64_t>((work + 255) / 256, 8192);
+    MSP_LAUNCH(k_narrow_cols, dim3(grid), dim3(256), 0, s, in, out, n, vec);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, hipStream_t s) {
