@@ -281,8 +281,11 @@ typedef struct msp_plan msp_plan;
  *    lists (placed at the start of each such call), per-unit counts and
  *    prefix sums, the one-phase staging (Section "Symbolic and Numeric
  *    Phases": the output of the one-phase method is written to storage sized
- *    by an upper bound and then copied), and the accumulators of rows split
- *    over several workgroups. Its size depends on the binning, known after
+ *    by an upper bound and then copied), the accumulators of rows split
+ *    over several workgroups, and, for a single product over at most 512
+ *    columns whose dense rows re-read B at least 4 times over, a 16-bit copy
+ *    of B's column indices that each call makes before its numeric kernels.
+ *    Its size depends on the binning, known after
  *    msp_plan_create: msp_workspace_size. Its contents matter only within a
  *    call, except from msp_symbolic to msp_numeric, and from msp_batch_bind
  *    to the batch's executions.
