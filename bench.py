@@ -158,11 +158,13 @@ def main():
                     "(and at most 8 entries in A's row) use the heap kind (0: never; default: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="all",
-                    choices=("all", "tc", "er", "er_batch", "batch", "bfs", "serve", "bc", "ktruss", "heatmap", "copy"),
+                    choices=("all", "tc", "er", "er_batch", "batch", "bfs", "complement", "serve", "bc", "ktruss",
+                             "heatmap", "copy"),
                     help="all (default): the multi-source BFS step (headline), triangle counting and the "
                          "Erdos-Renyi n=4096 product in one line; tc, er, bfs: one of them; er_batch: 256 "
                          "Erdos-Renyi n=4096 products as one batch; batch: 64 mixed FP64 "
-                         "products, batched and graph-replayed vs one launch per product")
+                         "products, batched and graph-replayed vs one launch per product; complement: "
+                         "an Erdos-Renyi product over 2^20 columns under a complemented mask")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mask-cap", type=int, default=0,
                     help="batch: cap on one product's mask entries (0: none, the full-size masks)")
@@ -204,6 +206,8 @@ def main():
         return run_tc(args)
     if args.workload == "er":
         return run_er(args)
+    if args.workload == "complement":
+        return print(json.dumps(headline(measure_complement(args), args)), flush=True)
     if args.workload == "er_batch":
         return print(json.dumps(headline(measure_er_batched(args), args)), flush=True)
     run_all(args)
@@ -475,6 +479,49 @@ def measure_er(args):
         rec["parity"] = {"checked": "every row against the oracle", "identical_within_tolerance": ok}
         if not ok:
             print("[bench] MISMATCH: Erdos-Renyi n=4096 differs from the oracle", file=sys.stderr)
+            sys.exit(1)
+        rec["cpu_baseline"] = baseline_record(rep, "the whole product")
+    return rec
+
+
+def measure_complement(args):
+    """Erdos-Renyi A (2^16 x 2^20) and B (2^20 x 2^20) of average degree 16,
+    FP64 U(0,1) values, plus-times, under a complemented Erdos-Renyi mask of
+    degree 8 (seeds 41, 42, 43): the regime of complemented masks wider than
+    one dense tile, where rows of more than heap_flops products are sorted.
+    Every 4th row checked against the oracle."""
+    import torch
+
+    import mspgen
+    import paper_2111_09947_amd as msp
+    dev = torch.device("cuda:0")
+    m, n, d, dm = 1 << 16, 1 << 20, 16.0, 8.0
+    A = mspgen.er(m, n, d, 41, "f64")
+    B = mspgen.er(n, n, d, 42, "f64")
+    M = mspgen.er(m, n, dm, 43, None)
+    sr = "plus_times_f64"
+    dA = msp.DeviceCSR.from_host(A, dev, torch.float64)
+    dB = msp.DeviceCSR.from_host(B, dev, torch.float64)
+    dM = msp.DeviceCSR.from_host(M, dev)
+    t = time_steps(dA, dB, dM, True, sr, args.steps, args.warmup, tuning_kw(args))
+    rp, ci, v = t["out"]
+    nnz = int(rp[-1].item())
+    got = (rp.cpu().numpy(), ci[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+    del t["out"], rp, ci, v
+    useful_row = useful_rows(dA, dB, dM, True)
+    per_row = alg_bytes(np.diff(A.rowptr), row_flops(A, np.diff(B.rowptr)), np.diff(M.rowptr), useful_row,
+                        np.diff(got[0]), wA=8, wB=8, wC=8)
+    rec = {"workload": "Erdos-Renyi A 2^16 x 2^20 and B 2^20 x 2^20, average degree 16, FP64 U(0,1), plus-times, "
+                       "complemented Erdos-Renyi mask of degree 8; seeds 41, 42, 43",
+           "dtype": "f64", "m": m, "n": n, "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_M": M.nnz, "nnz_C": nnz,
+           **product_record(t, per_row, int(useful_row.sum()), "complement_er2p20",
+                            8 * (m + 1) * 3 + 8 * (n + 1) + 12 * (A.nnz + B.nnz) + 4 * M.nnz + 12 * nnz)}
+    if not args.no_cpu_baseline:
+        rep = cpu_leg(A, B, M, True, sr, reps=3, sample=True)
+        ok = same_rows(got, rep["C"], True)
+        rec["parity"] = {"checked": "every row against the oracle", "identical_within_tolerance": ok}
+        if not ok:
+            print("[bench] MISMATCH: the complemented product differs from the oracle", file=sys.stderr)
             sys.exit(1)
         rec["cpu_baseline"] = baseline_record(rep, "the whole product")
     return rec

@@ -153,3 +153,30 @@ def test_sorting_rows_in_a_batch(sr):
                 b.graph_launch()
                 for (A, B, M, c), C in zip(probs, b.results()):
                     assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_i32"])
+def test_small_heap_bin_of_mixed_masks_runs_sorted(sr):
+    """A batch whose light rows (heap bin) come from products with normal and
+    with complemented masks: no mask-indexed launch can take the complemented
+    ones, so the small bin runs in the one-wave sorting kernel, which filters
+    each row by its own product's mask mode."""
+    torch = torch_or_skip()
+    m = msp()
+    probs = []
+    for t, (rows, n, d, dm, comp) in enumerate([(3000, 3000, 1.5, 64.0, False), (2000, 9000, 1.5, 10.0, True),
+                                               (1500, 1500, 2.0, 30.0, False), (1200, 70000, 1.2, 6.0, True)]):
+        A = mspgen.er(rows, n, d, 600 + 3 * t, VKIND[sr])
+        B = mspgen.er(n, n, d, 601 + 3 * t, VKIND[sr])
+        M = mspgen.er(rows, n, dm, 602 + 3 * t, None)
+        probs.append((A, B, M, comp))
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with m.Batch(dev, semiring=sr) as b:
+            assert 0 < b.bin_units["heap_lane"] <= 32768
+            b.bind_new_outputs()
+            for _ in range(2):
+                b.graph_launch()
+                for (A, B, M, c), C in zip(probs, b.results()):
+                    assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
