@@ -91,8 +91,9 @@ constexpr int MASKIDX_B_NW = MSP_MASKIDX_B_NW;  // waves per block of the mask-i
 constexpr int MASKIDX_B_WIDE_BUCKET = MSP_MASKIDX_B_WIDE_BUCKET;
 constexpr int MASKIDX_B_WIDE_NW = 8;
 constexpr int LAUNCH_MASKIDX_B_WIDE = NBINS;  // launch id (not a bin) of that kernel
-// The sorting bin's units of fewer than 4^5 products run in a launch of two
-// waves per unit, and those of fewer than 4^4 in one of a wave per unit.
+// The sorting bin's units of fewer than 4^5 products run in a launch of one
+// wave per unit with room for 1024 products, and those of fewer than 4^4 in
+// one of a wave per unit with room for 256.
 constexpr int ESC_MID_FROM_BUCKET = 4;
 constexpr int ESC_LIGHT_FROM_BUCKET = 3;
 constexpr int LAUNCH_ESC_MID = NBINS + 1;

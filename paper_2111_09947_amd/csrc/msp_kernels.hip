@@ -2134,7 +2134,9 @@ __global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
 //     each B row) and, unless counting, its term a * b; the entries of A are
 //     taken NT at a time, and a product finds its entry by a binary search
 //     over the chunk's prefix of B row lengths;
-//  2. sort the keys (a bitonic network in LDS, padded to a power of two);
+//  2. sort the keys with a bitonic network over the next power of two: in
+//     registers and lane shuffles in a one-wave workgroup (no barriers), in
+//     LDS with a block barrier per stage in a larger one;
 //  3. fold: the first key of each column is a candidate; it is kept when the
 //     mask admits the column (a binary search in the mask row, staged in LDS
 //     when it has at most 4 NT entries), and its value is the fold of
@@ -2145,16 +2147,19 @@ __global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
 // Work per row is O(flops log^2 flops) in LDS, independent of the width n.
 // The bin runs as three launches by product count (heaviest units first in
 // the unit list), so that light rows take small workgroups with little LDS
-// and many of them fit a CU: a wave for rows under 256 products, two waves
-// with room for 1024, four waves with room for ESC_MAX.
+// and many of them fit a CU: a wave for rows under 256 products (4 keys per
+// lane), a wave for rows under 1024 (16 keys per lane), four waves with room
+// for ESC_MAX.
 // units of bucket b have fewer than 4^(b+1) products
 static_assert((int64_t(4) << (2 * ESC_LIGHT_FROM_BUCKET)) <= 256 && (int64_t(4) << (2 * ESC_MID_FROM_BUCKET)) <= 1024,
               "the light and middle launches hold 256 and 1024 products");
 static_assert(ESC_MAX <= 4096, "product index in 12 bits");
 constexpr int esc_mcap(int nt) { return 4 * nt; }  // mask entries staged in LDS
 
+constexpr int ESC_EU = 4;  // expansion: products per lane with their loads in flight together
+
 template <int SR, int MODE, bool BATCH, int NT, int CAP>
-__global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
+__global__ __launch_bounds__(NT, NT == WAVE ? 4 : 1) void k_esc(NumArgs g) {
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     using in_t = typename T::in_t;
@@ -2199,17 +2204,43 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
         bpos_[t] = b0;
         if (T::needs_values) aval_[t] = a;
         __syncthreads();
-        for (int q = t; q < (int)ctot; q += NT) {
-            int lo = 0, hi = NT;  // off_[lo] <= q < off_[hi]: the last entry starting at or before q
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (off_[mid] <= q) lo = mid;
-                else hi = mid;
+        // ESC_EU products per lane a round: their entries found first, then all their loads issued
+        for (int q0 = t; q0 < (int)ctot; q0 += NT * ESC_EU) {
+            int lo[ESC_EU];
+            int64_t bp[ESC_EU];
+#pragma unroll
+            for (int x = 0; x < ESC_EU; ++x) {
+                const int q = q0 + x * NT;
+                lo[x] = 0;
+                bp[x] = 0;
+                if (q < (int)ctot) {
+                    int l = 0, h = NT;  // off_[l] <= q < off_[h]: the last entry starting at or before q
+                    while (h - l > 1) {
+                        const int mid = (l + h) >> 1;
+                        if (off_[mid] <= q) l = mid;
+                        else h = mid;
+                    }
+                    lo[x] = l;
+                    bp[x] = bpos_[l] + (q - off_[l]);
+                }
             }
-            const int64_t bp = bpos_[lo] + (q - off_[lo]);
-            const int slot = total + q;
-            key_[slot] = ((unsigned long long)(uint32_t)o.Bci[bp] << 12) | (unsigned long long)slot;
-            if (!COUNT) val_[slot] = T::term(T::needs_values ? aval_[lo] : T::one(), T::load(o.Bv, bp));
+            int32_t jc[ESC_EU];
+            in_t bv[ESC_EU];
+#pragma unroll
+            for (int x = 0; x < ESC_EU; ++x) {
+                const bool ok = q0 + x * NT < (int)ctot;
+                jc[x] = ok ? o.Bci[bp[x]] : 0;
+                bv[x] = (!COUNT && ok) ? T::load(o.Bv, bp[x]) : T::one();
+            }
+#pragma unroll
+            for (int x = 0; x < ESC_EU; ++x) {
+                const int q = q0 + x * NT;
+                if (q < (int)ctot) {
+                    const int slot = total + q;
+                    key_[slot] = ((unsigned long long)(uint32_t)jc[x] << 12) | (unsigned long long)slot;
+                    if (!COUNT) val_[slot] = T::term(T::needs_values ? aval_[lo[x]] : T::one(), bv[x]);
+                }
+            }
         }
         total += (int)ctot;
         __syncthreads();  // the chunk's tables are rewritten by the next chunk
@@ -2217,21 +2248,65 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
     // 2. sort
     int nsort = 1;
     while (nsort < total) nsort <<= 1;
-    for (int x = total + t; x < nsort; x += NT) key_[x] = ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= nsort; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int x = t; x < nsort; x += NT) {
-                const int y = x ^ jj;
-                if (y > x) {
-                    const unsigned long long kx = key_[x], ky = key_[y];
-                    if ((kx > ky) == ((x & k) == 0)) {
-                        key_[x] = ky;
-                        key_[y] = kx;
+    if constexpr (NT == WAVE) {
+        // one wave: the keys in registers, element t * PER + r in register r of lane t; partners
+        // closer than PER are in the lane's own registers, farther ones a lane shuffle away
+        unsigned long long kr[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) kr[r] = t * PER + r < total ? key_[t * PER + r] : ~0ull;
+        for (int k = 2; k <= nsort; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                if (jj >= PER) {
+                    const bool lower = (t & (jj / PER)) == 0;
+#pragma unroll
+                    for (int r = 0; r < PER; ++r) {
+                        const unsigned long long o = __shfl_xor(kr[r], jj / PER, WAVE);
+                        const bool asc = ((t * PER + r) & k) == 0;
+                        kr[r] = (lower == asc) ? (kr[r] < o ? kr[r] : o) : (kr[r] < o ? o : kr[r]);
+                    }
+                } else {
+                    // partners in the lane's own registers: one unrolled body per distance, so that
+                    // every register index is a constant
+#pragma unroll
+                    for (int lj = 0; (1 << lj) < PER; ++lj) {
+                        if (jj == (1 << lj)) {
+#pragma unroll
+                            for (int r = 0; r < PER; ++r) {
+                                if ((r & (1 << lj)) == 0) {
+                                    const int y = r | (1 << lj);
+                                    const bool asc = ((t * PER + r) & k) == 0;
+                                    const unsigned long long a = kr[r], b = kr[y];
+                                    const bool sw = (a > b) == asc;
+                                    kr[r] = sw ? b : a;
+                                    kr[y] = sw ? a : b;
+                                }
+                            }
+                        }
                     }
                 }
             }
-            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r)
+            if (t * PER + r < nsort) key_[t * PER + r] = kr[r];
+        wave_lds_sync();
+    } else {
+        for (int x = total + t; x < nsort; x += NT) key_[x] = ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= nsort; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int x = t; x < nsort; x += NT) {
+                    const int y = x ^ jj;
+                    if (y > x) {
+                        const unsigned long long kx = key_[x], ky = key_[y];
+                        if ((kx > ky) == ((x & k) == 0)) {
+                            key_[x] = ky;
+                            key_[y] = kx;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
     // 3. candidates and the mask: thread t takes the sorted keys [e0, e1)
@@ -2344,7 +2419,7 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
         MSP_LAUNCH((k_esc<SR, MODE, BATCH, 4 * WAVE, (int)ESC_MAX>), gb, dim3(4 * WAVE), 0, s, a);
         break;
     case LAUNCH_ESC_MID:
-        MSP_LAUNCH((k_esc<SR, MODE, BATCH, 2 * WAVE, 1024>), gb, dim3(2 * WAVE), 0, s, a);
+        MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 1024>), gb, dim3(WAVE), 0, s, a);
         break;
     case LAUNCH_ESC_LIGHT:
         MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 256>), gb, dim3(WAVE), 0, s, a);
