@@ -168,16 +168,18 @@ typedef struct msp_options {
                              when they have at most this many products, or at
                              most twice as many and a mask row with at least 8
                              entries per product; under a complemented mask,
-                             when they have at most this many products, or
-                             whatever their product count with more than 4096
-                             columns (-1 = default 32;
-                             0 = never). An automatic heap bin runs in the
-                             MASKIDX wave kernel instead when it has at most
-                             32768 rows, all with normal mask rows of at most
-                             256 entries, or in the MASKIDX block kernel when
-                             it has at most 4096 rows, all with normal mask
-                             rows of 257 to 2048 entries: a small heap launch
-                             costs more than it saves. */
+                             when they have at most this many products, or,
+                             with more than 4096 columns, more than 4096
+                             (rows between go to the sorting bin) (-1 =
+                             default 32; 0 = never). An automatic heap bin
+                             runs in the MASKIDX wave kernel instead when it
+                             has at most 32768 rows, all with normal mask rows
+                             of at most 256 entries, or in the MASKIDX block
+                             kernel when it has at most 4096 rows, all with
+                             normal mask rows of 257 to 2048 entries; another
+                             bin of at most 32768 rows, all under 256
+                             products, runs in the one-wave sorting kernel: a
+                             small heap launch costs more than it saves. */
     int64_t block_flops;  /* rows with more products than this run on a whole
                              workgroup (256 threads; 512 for mask-indexed
                              rows of at least 65536 products) instead of
@@ -246,7 +248,7 @@ enum {
                                         <= 256 products, <= 32 entries in the row of A
                                         (automatic choice only) */
     MSP_BIN_SORT_BLOCK = 12,         /* one workgroup per row: complemented mask rows of matrices
-                                        wider than 4096 columns with more than 8 entries of A and
+                                        wider than 4096 columns with more than heap_flops and
                                         <= 4096 products: products expanded, sorted by column,
                                         folded and filtered (automatic choice only) */
     MSP_NBINS = 13
