@@ -31,7 +31,7 @@ enum Bin : int {  // same numbering as MSP_BIN_* in msp.h
     BIN_MASKIDX_P = 11,  // eight lanes per row, eight rows per wave: short normal mask rows
                          // (<= PACK_MASK entries), few products (<= PACK_FLOPS), short rows of A
     BIN_ESC = 12,        // one block per row: complemented rows of matrices wider than DENSE_B_COLS
-                         // that the heap cannot take, with <= ESC_MAX products: expand, sort, fold
+                         // with more than heap_flops and <= ESC_MAX products: expand, sort, fold
     NBINS = 13
 };
 
@@ -66,10 +66,11 @@ constexpr int PACK_MASK = 16;
 constexpr int PACK_ALEN = 32;
 constexpr int64_t PACK_FLOPS = 256;
 // Complemented rows of matrices wider than one dense tile (DENSE_B_COLS
-// columns) that the heap cannot take (more than HEAP_CAP entries of A) would
-// make the dense kind stream the row once per 4096-column tile. With at most
-// ESC_MAX products such a row is expanded into LDS, sorted by column, folded
-// and filtered against its mask row instead (automatic choice only).
+// columns) would make the dense kind stream the row once per 4096-column tile.
+// A row of more than heap_flops and at most ESC_MAX products is expanded into
+// LDS, sorted by column, folded and filtered against its mask row instead
+// (automatic choice only); lighter rows, and heavier ones that fit it, take
+// the heap.
 constexpr int64_t ESC_MAX = 4096;
 // Dense kernels read a 16-bit copy of B's column indices when their products
 // come to at least this many times nnz(B) (single products, n <= 512).

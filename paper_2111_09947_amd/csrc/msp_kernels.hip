@@ -2127,8 +2127,9 @@ __global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
 
 // ----------------------------------- expand, sort, fold (complemented rows)
 // One workgroup of NT threads per row of the sorting bin (a complemented mask
-// over more than DENSE_B_COLS columns, more entries of A than the heap holds,
-// at most CAP products), product-driven instead of tile by tile:
+// over more than DENSE_B_COLS columns, more than heap_flops and at most CAP
+// products; also a small heap bin of rows under 256 products, either mask
+// mode), product-driven instead of tile by tile:
 //  1. expand: every product of the row goes to LDS as the key
 //     (column << 12 | its index in the row's product order: A's row, then
 //     each B row) and, unless counting, its term a * b; the entries of A are
