@@ -2160,7 +2160,7 @@ constexpr int esc_mcap(int nt) { return 4 * nt; }  // mask entries staged in LDS
 constexpr int ESC_EU = 4;  // expansion: products per lane with their loads in flight together
 
 template <int SR, int MODE, bool BATCH, int NT, int CAP>
-__global__ __launch_bounds__(NT, NT == WAVE ? 4 : 1) void k_esc(NumArgs g) {
+__global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
     using in_t = typename T::in_t;
