@@ -816,6 +816,7 @@ static NumArgs num_args(const msp_plan* P, int b) {
     a.nsplit = P->nsplit;
     a.gset = P->gacc;
     a.gval = P->gacc + (size_t)P->nsplit * (DENSE_B_COLS / 32);
+    for (const Product& pr : P->prods) a.max_n = std::max(a.max_n, pr.op.n);
     if (P->narrow) a.op.Bci16 = P->bci16;
     return a;
 }

@@ -267,6 +267,7 @@ struct NumArgs {
     int64_t split_off;         // first split row of this launch (split emission)
     unsigned int* gset;        // [nsplit][DENSE_B_COLS / 32] inserted bits
     void* gval;                // [nsplit][DENSE_B_COLS] accumulator slots
+    int64_t max_n;             // the largest column count of the launch's products (sort-key width)
 };
 
 // Per-product output binding (device table entry when batched).

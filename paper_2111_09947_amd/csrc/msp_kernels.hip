@@ -2159,7 +2159,7 @@ constexpr int esc_mcap(int nt) { return 4 * nt; }  // mask entries staged in LDS
 
 constexpr int ESC_EU = 4;  // expansion: products per lane with their loads in flight together
 
-template <int SR, int MODE, bool BATCH, int NT, int CAP>
+template <int SR, int MODE, bool BATCH, int NT, int CAP, class KT>
 __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
     using T = SRT<SR>;
     using acc_t = typename T::acc_t;
@@ -2170,7 +2170,12 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
     constexpr int MCAP = esc_mcap(NT);
     static_assert(CAP <= 4096 && CAP % NT == 0 && PER <= 32 && (CAP & (CAP - 1)) == 0,
                   "product index in 12 bits; whole rounds per thread; one bit per key of a run");
-    __shared__ unsigned long long key_[CAP];
+    static_assert(std::is_same<KT, uint32_t>::value || std::is_same<KT, unsigned long long>::value, "key width");
+    // key = column << SB | product index: 64-bit keys keep 12 index bits; 32-bit keys (launched
+    // only when every column is below 2^(32 - log2 CAP)) keep log2 CAP
+    constexpr int SB = sizeof(KT) == 8 ? 12 : __builtin_ctz(CAP);
+    constexpr KT SMASK = (KT(1) << SB) - 1;
+    __shared__ KT key_[CAP];
     __shared__ acc_t val_[COUNT ? 1 : CAP];
     __shared__ int32_t off_[NT + 1];
     __shared__ int64_t bpos_[NT];
@@ -2238,7 +2243,7 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
                 const int q = q0 + x * NT;
                 if (q < (int)ctot) {
                     const int slot = total + q;
-                    key_[slot] = ((unsigned long long)(uint32_t)jc[x] << 12) | (unsigned long long)slot;
+                    key_[slot] = ((KT)(uint32_t)jc[x] << SB) | (KT)slot;
                     if (!COUNT) val_[slot] = T::term(T::needs_values ? aval_[lo[x]] : T::one(), bv[x]);
                 }
             }
@@ -2252,16 +2257,16 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
     if constexpr (NT == WAVE) {
         // one wave: the keys in registers, element t * PER + r in register r of lane t; partners
         // closer than PER are in the lane's own registers, farther ones a lane shuffle away
-        unsigned long long kr[PER];
+        KT kr[PER];
 #pragma unroll
-        for (int r = 0; r < PER; ++r) kr[r] = t * PER + r < total ? key_[t * PER + r] : ~0ull;
+        for (int r = 0; r < PER; ++r) kr[r] = t * PER + r < total ? key_[t * PER + r] : ~KT(0);
         for (int k = 2; k <= nsort; k <<= 1) {
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
                 if (jj >= PER) {
                     const bool lower = (t & (jj / PER)) == 0;
 #pragma unroll
                     for (int r = 0; r < PER; ++r) {
-                        const unsigned long long o = __shfl_xor(kr[r], jj / PER, WAVE);
+                        const KT o = __shfl_xor(kr[r], jj / PER, WAVE);
                         const bool asc = ((t * PER + r) & k) == 0;
                         kr[r] = (lower == asc) ? (kr[r] < o ? kr[r] : o) : (kr[r] < o ? o : kr[r]);
                     }
@@ -2276,7 +2281,7 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
                                 if ((r & (1 << lj)) == 0) {
                                     const int y = r | (1 << lj);
                                     const bool asc = ((t * PER + r) & k) == 0;
-                                    const unsigned long long a = kr[r], b = kr[y];
+                                    const KT a = kr[r], b = kr[y];
                                     const bool sw = (a > b) == asc;
                                     kr[r] = sw ? b : a;
                                     kr[y] = sw ? a : b;
@@ -2292,14 +2297,14 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
             if (t * PER + r < nsort) key_[t * PER + r] = kr[r];
         wave_lds_sync();
     } else {
-        for (int x = total + t; x < nsort; x += NT) key_[x] = ~0ull;
+        for (int x = total + t; x < nsort; x += NT) key_[x] = ~KT(0);
         __syncthreads();
         for (int k = 2; k <= nsort; k <<= 1) {
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
                 for (int x = t; x < nsort; x += NT) {
                     const int y = x ^ jj;
                     if (y > x) {
-                        const unsigned long long kx = key_[x], ky = key_[y];
+                        const KT kx = key_[x], ky = key_[y];
                         if ((kx > ky) == ((x & k) == 0)) {
                             key_[x] = ky;
                             key_[y] = kx;
@@ -2318,8 +2323,8 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
     int64_t ms = 0;  // the search starts past the previous candidate's position (columns ascend)
     const int64_t mlen = m1 - m0;
     for (int e = e0; e < e1; ++e) {
-        const uint32_t col = (uint32_t)(key_[e] >> 12);
-        if (e > 0 && (uint32_t)(key_[e - 1] >> 12) == col) continue;  // not the first of its column
+        const uint32_t col = (uint32_t)(key_[e] >> SB);
+        if (e > 0 && (uint32_t)(key_[e - 1] >> SB) == col) continue;  // not the first of its column
         int64_t lo = ms, hi = mlen;
         while (lo < hi) {
             const int64_t mid = lo + ((hi - lo) >> 1);
@@ -2343,10 +2348,10 @@ __global__ __launch_bounds__(NT) void k_esc(NumArgs g) {
         int64_t pos = ob + pos0;
         for (int e = e0; e < e1; ++e) {
             if (!((keepbits >> (e - e0)) & 1u)) continue;
-            const uint32_t col = (uint32_t)(key_[e] >> 12);
+            const uint32_t col = (uint32_t)(key_[e] >> SB);
             acc_t acc = T::identity();
-            for (int f = e; f < total && (uint32_t)(key_[f] >> 12) == col; ++f)
-                acc = T::add(acc, val_[(int)(key_[f] & 0xFFFull)]);
+            for (int f = e; f < total && (uint32_t)(key_[f] >> SB) == col; ++f)
+                acc = T::add(acc, val_[(int)(key_[f] & SMASK)]);
             g.out_col[pos] = (int32_t)col;
             ov[pos] = T::finish(acc);
             ++pos;
@@ -2417,13 +2422,20 @@ static hipError_t launch_numeric_one(int bin, const NumArgs& a, hipStream_t s) {
                    s, a);
         break;
     case BIN_ESC:  // the heaviest units of the sorting bin
-        MSP_LAUNCH((k_esc<SR, MODE, BATCH, 4 * WAVE, (int)ESC_MAX>), gb, dim3(4 * WAVE), 0, s, a);
+        MSP_LAUNCH((k_esc<SR, MODE, BATCH, 4 * WAVE, (int)ESC_MAX, unsigned long long>), gb, dim3(4 * WAVE), 0, s,
+                   a);
         break;
-    case LAUNCH_ESC_MID:
-        MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 1024>), gb, dim3(WAVE), 0, s, a);
+    case LAUNCH_ESC_MID:  // 32-bit keys when every column is below 2^22
+        if (a.max_n > 0 && a.max_n <= (int64_t(1) << 22))
+            MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 1024, uint32_t>), gb, dim3(WAVE), 0, s, a);
+        else
+            MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 1024, unsigned long long>), gb, dim3(WAVE), 0, s, a);
         break;
-    case LAUNCH_ESC_LIGHT:
-        MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 256>), gb, dim3(WAVE), 0, s, a);
+    case LAUNCH_ESC_LIGHT:  // 32-bit keys when every column is below 2^24
+        if (a.max_n > 0 && a.max_n <= (int64_t(1) << 24))
+            MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 256, uint32_t>), gb, dim3(WAVE), 0, s, a);
+        else
+            MSP_LAUNCH((k_esc<SR, MODE, BATCH, WAVE, 256, unsigned long long>), gb, dim3(WAVE), 0, s, a);
         break;
     case BIN_MASKIDX_P: {
         constexpr int64_t rows = PACK_WPB * PACK_RPW;

@@ -180,3 +180,30 @@ def test_small_heap_bin_of_mixed_masks_runs_sorted(sr):
                 b.graph_launch()
                 for (A, B, M, c), C in zip(probs, b.results()):
                     assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64"])
+def test_columns_beyond_32_bit_keys(sr):
+    """Over 2^25 columns the one-wave sorting kernels keep 64-bit keys (below
+    2^22 columns, or 2^24 for rows under 256 products, a key fits 32 bits):
+    rows under 256 and under 1024 products, columns 2^24 - 1, 2^24 and
+    n - 1 among B's. The oracle runs on one thread (its accumulator spans
+    all n columns)."""
+    rng = np.random.default_rng(70)
+    n, k, m = 1 << 25, 3000, 300
+    B = mspgen.er(k, n, 24.0, 71, VKIND[sr])
+    extra = np.array([(1 << 24) - 1, 1 << 24, n - 1], np.int64)
+    rows = np.concatenate([np.repeat(np.arange(B.nrows), np.diff(B.rowptr)), rng.integers(0, k, size=60)])
+    cols = np.concatenate([B.colidx.astype(np.int64), rng.choice(extra, size=60)])
+    B = mspgen.from_coo(k, n, rows, cols)
+    B = B.with_values(mspgen.random_values(B.nnz, VKIND[sr], np.random.default_rng(72)))
+    alen = np.where(np.arange(m) % 2 == 0, 6, 30)  # about 150 and about 750 products
+    A = mspgen.from_coo(m, k, np.repeat(np.arange(m), alen),
+                        np.concatenate([np.sort(rng.choice(k, size=a, replace=False)) for a in alen]))
+    A = A.with_values(mspgen.random_values(A.nnz, VKIND[sr], np.random.default_rng(73)))
+    M = mspgen.er(m, n, 5.0, 74, None)
+    mm = msp()
+    with mm.Plan(up(A, sr), up(B, sr), up(M), True, sr) as p:
+        assert p.bin_units["sort_block"] == m
+        C = p.execute()
+    assert_same(C, oracle.masked_spgemm(A, B, M, True, sr, nthreads=1), sr)
