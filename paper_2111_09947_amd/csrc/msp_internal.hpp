@@ -72,6 +72,11 @@ constexpr int64_t PACK_FLOPS = 256;
 // (automatic choice only); lighter rows, and heavier ones that fit it, take
 // the heap.
 constexpr int64_t ESC_MAX = 4096;
+// Rows of at least ESC_WAVE_MAX products take the four-wave sorting shape,
+// whose LDS sort costs more than restreaming the row over fewer than
+// ESC_BLOCK_MIN_TILES dense tiles: those rows keep the dense tiles.
+constexpr int64_t ESC_WAVE_MAX = 1024;
+constexpr int64_t ESC_BLOCK_MIN_TILES = 10;
 // Dense kernels read a 16-bit copy of B's column indices when their products
 // come to at least this many times nnz(B) (single products, n <= 512).
 constexpr int64_t NARROW_REUSE = 4;

@@ -311,7 +311,11 @@ __device__ void classify(int64_t mnnz, int64_t flops, int64_t alen, int64_t n, i
         tiles = 1;
         if (n <= DENSE_B_COLS && split) { bin = BIN_DENSE_SPLIT; tiles = min(cdiv(flops, split_flops), alen); }
         else if (n <= DENSE_W_COLS) bin = flops > DENSE_NARROW_BLOCK_MULT * block_flops ? BIN_DENSE_BN : BIN_DENSE_W;
-        else if (comp && !chosen && n > DENSE_B_COLS && flops <= ESC_MAX) { bin = BIN_ESC; tiles = 1; }
+        else if (comp && !chosen && n > DENSE_B_COLS && flops <= ESC_MAX &&
+                 (flops < ESC_WAVE_MAX || cdiv(n, DENSE_B_COLS) >= ESC_BLOCK_MIN_TILES)) {
+            bin = BIN_ESC;
+            tiles = 1;
+        }
         else { bin = BIN_DENSE_B; tiles = cdiv(n, DENSE_B_COLS); }
         break;
     case MSP_KIND_HASH:

@@ -31,7 +31,9 @@ def _plan_check(A, B, M, sr, complement=True, phase=1, **kw):
 
 
 def _limits_problem(sr, seed=5):
-    """Rows on both sides of each limit of the sorting bin, n = 20000. B row b
+    """Rows on both sides of each limit of the sorting bin, n = 45000 (eleven
+    4096-column tiles: rows of 1024 products or more are sorted only from ten
+    tiles on, fewer stream the dense tiles). B row b
     < 6000 has b % 65 entries; rows 6000..6099 all hold the same 34 columns,
     0 and n - 1 among them. Row types (cycled): 9 entries of A with 256
     products (sorted); 8 entries of A with 160 products (sorted); 64 entries
@@ -42,7 +44,7 @@ def _limits_problem(sr, seed=5):
     products); 4 entries with 32 products (heap); 3 entries with 33 products
     (sorted)."""
     rng = np.random.default_rng(seed)
-    n, k = 20000, 6100
+    n, k = 45000, 6100
     blen = np.arange(k) % 65
     bcols = [np.sort(rng.choice(n, size=blen[b], replace=False)) for b in range(k)]
     shared = np.sort(np.concatenate([[0, n - 1], rng.choice(np.arange(1, n - 1), size=32, replace=False)]))
@@ -102,7 +104,7 @@ def test_sorting_limits(sr, phase):
     bins = _plan_check(A, B, M, sr, phase=phase)
     assert bins["sort_block"] == expect and expect > 0, (bins, expect)
     assert bins["heap_lane"] == int(((fl > 0) & (fl <= 32)).sum()) > 0
-    assert bins["dense_block"] == int((fl > 4096).sum()) * 5  # 20000 columns: five 4096-column tiles
+    assert bins["dense_block"] == int((fl > 4096).sum()) * 11  # 45000 columns: eleven 4096-column tiles
 
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_i32"])
@@ -207,3 +209,22 @@ def test_columns_beyond_32_bit_keys(sr):
         assert p.bin_units["sort_block"] == m
         C = p.execute()
     assert_same(C, oracle.masked_spgemm(A, B, M, True, sr, nthreads=1), sr)
+
+
+@pytest.mark.parametrize("n", [8192, 40960])
+def test_heavy_rows_sort_only_over_many_tiles(n):
+    """Rows of 1024 to 4096 products under a complemented mask: over 2 tiles
+    they stream the dense tiles, over 10 tiles they are sorted."""
+    sr = "plus_times_f64"
+    A = mspgen.er(400, n, 40.0, 81, VKIND[sr])
+    B = mspgen.er(n, n, 40.0, 82, VKIND[sr])
+    M = mspgen.er(400, n, 30.0, 83, None)
+    _, fl = _row_classes(A, B)
+    heavy = int(((fl >= 1024) & (fl <= 4096)).sum())
+    assert heavy > 300
+    bins = _plan_check(A, B, M, sr)
+    if n == 8192:
+        assert bins["sort_block"] == int(((fl > 32) & (fl < 1024)).sum())
+        assert bins["dense_block"] == 2 * int((fl >= 1024).sum())
+    else:
+        assert bins["sort_block"] == int(((fl > 32) & (fl <= 4096)).sum())
