@@ -249,8 +249,9 @@ enum {
                                         (automatic choice only) */
     MSP_BIN_SORT_BLOCK = 12,         /* one workgroup per row: complemented mask rows of matrices
                                         wider than 4096 columns with more than heap_flops and
-                                        <= 4096 products: products expanded, sorted by column,
-                                        folded and filtered (automatic choice only) */
+                                        < 1024 products (<= 4096 from 40961 columns on):
+                                        products expanded, sorted by column, folded and
+                                        filtered (automatic choice only) */
     MSP_NBINS = 13
 };
 
