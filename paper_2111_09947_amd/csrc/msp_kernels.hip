@@ -2135,8 +2135,9 @@ __global__ __launch_bounds__(PACK_WPB * WAVE) void k_pack(NumArgs g) {
 // products; also a small heap bin of rows under 256 products, either mask
 // mode), product-driven instead of tile by tile:
 //  1. expand: every product of the row goes to LDS as the key
-//     (column << 12 | its index in the row's product order: A's row, then
-//     each B row) and, unless counting, its term a * b; the entries of A are
+//     (column << SB | its index in the row's product order: A's row, then
+//     each B row; SB = 12 in 64-bit keys, log2 CAP in 32-bit ones) and,
+//     unless counting, its term a * b; the entries of A are
 //     taken NT at a time, and a product finds its entry by a binary search
 //     over the chunk's prefix of B row lengths;
 //  2. sort the keys with a bitonic network over the next power of two: in
