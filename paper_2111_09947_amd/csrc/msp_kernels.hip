@@ -819,8 +819,44 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down_fused(const int64_t* in, i
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = off + tot;
 }
 
+// A short scan in one workgroup of 1024 threads, one chunk of SCAN1_CHUNK
+// entries after another with a running carry: one launch instead of two for
+// the small unit lists of small products. Each chunk is read whole before any
+// of it is written, so in may equal out.
+constexpr int SCAN1_T = 1024, SCAN1_CHUNK = SCAN1_T * SCAN_I;
+constexpr int64_t SCAN1_MAX = 4 * (int64_t)SCAN1_CHUNK;
+
+__global__ __launch_bounds__(SCAN1_T) void k_scan_single(const int64_t* in, int64_t* out, int64_t n) {
+    __shared__ int64_t tmp[SCAN1_T / WAVE];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += SCAN1_CHUNK) {
+        const int64_t base = c0 + (int64_t)threadIdx.x * SCAN_I;
+        int64_t v[SCAN_I];
+        int64_t run = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_I; ++j) {
+            v[j] = (base + j < n) ? in[base + j] : 0;
+            run += v[j];
+        }
+        int64_t tot;
+        const int64_t ex = block_excl_scan<SCAN1_T / WAVE>(run, tmp, tot);  // every thread has read its entries
+        int64_t acc = carry + ex;
+#pragma unroll
+        for (int j = 0; j < SCAN_I; ++j) {
+            if (base + j < n) out[base + j] = acc;
+            acc += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* partial, hipStream_t s) {
     if (n <= 0) return launch_fill_i64(out, 1, 0, s);
+    if (n <= SCAN1_MAX) {
+        MSP_LAUNCH(k_scan_single, dim3(1), dim3(SCAN1_T), 0, s, in, out, n);
+        return hipGetLastError();
+    }
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     MSP_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, partial);
     if (nb <= SCAN_FUSE_TILES) {
