@@ -184,13 +184,9 @@ def test_small_heap_bin_of_mixed_masks_runs_sorted(sr):
                     assert_same(C, oracle.masked_spgemm(A, B, M, c, sr), sr)
 
 
-@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_pair_i64"])
-def test_columns_beyond_32_bit_keys(sr):
-    """Over 2^25 columns the one-wave sorting kernels keep 64-bit keys (below
-    2^22 columns, or 2^24 for rows under 256 products, a key fits 32 bits):
-    rows under 256 and under 1024 products, columns 2^24 - 1, 2^24 and
-    n - 1 among B's. The oracle runs on one thread (its accumulator spans
-    all n columns)."""
+def _wide_problem(sr):
+    """300 rows over 2^25 columns: even rows about 150 products, odd rows
+    about 750; B holds columns 2^24 - 1, 2^24 and n - 1 among others."""
     rng = np.random.default_rng(70)
     n, k, m = 1 << 25, 3000, 300
     B = mspgen.er(k, n, 24.0, 71, VKIND[sr])
@@ -199,16 +195,44 @@ def test_columns_beyond_32_bit_keys(sr):
     cols = np.concatenate([B.colidx.astype(np.int64), rng.choice(extra, size=60)])
     B = mspgen.from_coo(k, n, rows, cols)
     B = B.with_values(mspgen.random_values(B.nnz, VKIND[sr], np.random.default_rng(72)))
-    alen = np.where(np.arange(m) % 2 == 0, 6, 30)  # about 150 and about 750 products
+    alen = np.where(np.arange(m) % 2 == 0, 6, 30)
     A = mspgen.from_coo(m, k, np.repeat(np.arange(m), alen),
                         np.concatenate([np.sort(rng.choice(k, size=a, replace=False)) for a in alen]))
     A = A.with_values(mspgen.random_values(A.nnz, VKIND[sr], np.random.default_rng(73)))
     M = mspgen.er(m, n, 5.0, 74, None)
+    return A, B, M
+
+
+@pytest.mark.parametrize("sr,phase", [("plus_times_f64", 1), ("plus_pair_i64", 1), ("plus_times_i32", 2),
+                                      ("lor_land_bool", 2)])
+def test_columns_beyond_32_bit_keys(sr, phase):
+    """Over 2^25 columns the one-wave sorting kernels keep 64-bit keys (below
+    2^22 columns, or 2^24 for rows under 256 products, a key fits 32 bits).
+    The oracle runs on one thread (its accumulator spans all n columns)."""
+    A, B, M = _wide_problem(sr)
     mm = msp()
-    with mm.Plan(up(A, sr), up(B, sr), up(M), True, sr) as p:
-        assert p.bin_units["sort_block"] == m
+    with mm.Plan(up(A, sr), up(B, sr), up(M), True, sr, phase=phase) as p:
+        assert p.bin_units["sort_block"] == A.nrows
         C = p.execute()
     assert_same(C, oracle.masked_spgemm(A, B, M, True, sr, nthreads=1), sr)
+
+
+def test_key_width_of_a_batch_follows_its_widest_product():
+    """A batch holding a 2^16-column product and the 2^25-column one sorts
+    both with 64-bit keys (the width is chosen per launch)."""
+    torch = torch_or_skip()
+    sr = "plus_times_f64"
+    m = msp()
+    n = 1 << 16
+    probs = [(mspgen.er(800, n, 16.0, 91, VKIND[sr]), mspgen.er(n, n, 16.0, 92, VKIND[sr]),
+              mspgen.er(800, n, 8.0, 93, None), True), (*_wide_problem(sr), True)]
+    dev = [(up(A, sr), up(B, sr), up(M), c) for (A, B, M, c) in probs]
+    with m.Batch(dev, semiring=sr) as b:
+        assert b.bin_units["sort_block"] > 1000
+        b.bind_new_outputs()
+        b.execute()
+        for (A, B, M, c), C in zip(probs, b.results()):
+            assert_same(C, oracle.masked_spgemm(A, B, M, c, sr, nthreads=1), sr)
 
 
 @pytest.mark.parametrize("n", [8192, 40960])
